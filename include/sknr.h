@@ -1,0 +1,249 @@
+/*
+ * sknr.h -- C ABI of libsknr: entropic optimal transport on one AMD MI355X
+ * (gfx950) by log-domain Sinkhorn-Knopp (SK) and SK-NR(l), the spectral
+ * warm start of Chhaibi, Gratton and Vaiter (arXiv 2506.14780).
+ *
+ * Problem (paper, Sec. 2).  Two discrete measures alpha = a (length n) and
+ * beta = b (length m), probability vectors; a cost C (n x m), either stored
+ * or built from point clouds x (n x d), y (m x d) as
+ * C_ij = cost_scale * ||x_i - y_j||^2; a regularisation eps > 0 or an eps
+ * schedule; a tolerance omega on the L1 marginal error
+ * ||pi 1_m - a||_1 + ||pi^T 1_n - b||_1 (the convergence test of
+ * Algorithm 4.1).
+ *
+ * Potentials follow the paper's convention (eq. Optimal_P_epsilon): they
+ * are relative to a (x) b, so pi_ij = a_i b_j exp((f_i + g_j - C_ij)/eps).
+ * Returned potentials are gauge-normalised to <f,a> = <g,b> (the dual is
+ * invariant under (f,g) -> (f,g) + c(1,-1), Sec. 2).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns an int status (SKNR_OK = 0, SKNR_NOT_CONVERGED
+ *     = 1 as a warning, negative values are errors) and never throws.
+ *     On error, sknr_last_error() gives a message (thread-local).
+ *   - Array pointers marked [device] are HIP device pointers of the
+ *     context's device; pointers marked [host] are host memory.
+ *   - Arrays are dense and row-major unless stated; the caller owns every
+ *     input and output buffer.  The library never frees caller memory and
+ *     does not keep pointers to it after the call returns, except where
+ *     sknr_submit documents a copy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are synchronous with respect to the host: when a call returns,
+ *     its outputs are written and the stream is idle.
+ *   - A context is not thread-safe; use one per host thread.
+ *
+ * Precision: the O(nm) sweeps run in FP32 with compensated (double-float)
+ * potentials; FP64 is used for the small projected Newton / eigen systems,
+ * for the scalar objective values that decide the Newton acceptance test,
+ * and for the final marginal-error check and reported values.
+ */
+#ifndef SKNR_H_
+#define SKNR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define SKNR_OK 0
+#define SKNR_NOT_CONVERGED 1   /* warning: outputs valid, tolerance not reached */
+#define SKNR_EINVAL (-1)       /* invalid argument (message in sknr_last_error) */
+#define SKNR_ENOMEM (-2)       /* device allocation failed / over budget */
+#define SKNR_EDEVICE (-3)      /* HIP runtime error */
+#define SKNR_EBUSY (-4)        /* serving queue full */
+#define SKNR_ECANCELED (-5)    /* request cancelled */
+#define SKNR_EINTERNAL (-6)    /* internal failure */
+
+#define SKNR_MAX_STAGES 32     /* maximum length of an eps schedule */
+#define SKNR_MAX_ELL 32        /* maximum number of low-frequency modes l */
+
+/* --------------------------------------------------------------- problem */
+enum sknr_cost_kind {
+  SKNR_COST_STORED = 0,   /* C given as an n x m FP32 matrix */
+  SKNR_COST_SQEUCLID = 1  /* C_ij = cost_scale * ||x_i - y_j||^2 built per tile */
+};
+
+/* How the cross term of the squared distance is formed when the cost is
+ * built from points.  FP32 evaluates sum_k (x_ik - y_jk)^2 in FP32 in the
+ * order k = 0..d-1; BF16 / BF16X3 form ||x||^2 + ||y||^2 - 2 x.y with the
+ * x.y products on bf16 matrix cores with FP32 accumulation, from one bf16
+ * term per coordinate (BF16) or a hi/lo bf16 split keeping hi*hi + hi*lo +
+ * lo*hi (BF16X3).  AUTO picks FP32 for d < 16 and BF16X3 for d >= 16. */
+enum sknr_xterm { SKNR_XTERM_AUTO = 0, SKNR_XTERM_FP32 = 1, SKNR_XTERM_BF16 = 2, SKNR_XTERM_BF16X3 = 3 };
+
+typedef struct sknr_problem {
+  int64_t n;            /* number of source points / size of a (n >= 1) */
+  int64_t m;            /* number of target points / size of b (m >= 1) */
+  int32_t d;            /* point dimension (SQEUCLID only, 1 <= d <= 1024) */
+  int32_t kind;         /* enum sknr_cost_kind */
+  int32_t xterm;        /* enum sknr_xterm (SQEUCLID only) */
+  int32_t reserved0;
+  const float* C;       /* [device] STORED: n x m FP32, row stride ldc */
+  int64_t ldc;          /* STORED: row stride in elements (>= m) */
+  const float* x;       /* [device] SQEUCLID: n x d FP32 */
+  const float* y;       /* [device] SQEUCLID: m x d FP32 */
+  double cost_scale;    /* SQEUCLID: positive multiplier (0 means 1) */
+  const double* a;      /* [device] n FP64 weights, positive, sum 1 */
+  const double* b;      /* [device] m FP64 weights, positive, sum 1 */
+} sknr_problem;
+
+/* ------------------------------------------------------------ solve opts */
+enum sknr_warm_mode {
+  SKNR_WARM_SEQUENTIAL = 0, /* V_l of stage s from the optimum of stage s-1 */
+  SKNR_WARM_STATIC = 1,     /* V_l from a plain SK solve at eps_prime */
+  SKNR_WARM_USER = 2        /* V_l given in opts.V0 for every stage */
+};
+
+typedef struct sknr_opts {
+  const double* eps;      /* [host] eps schedule, n_eps values, each > 0 */
+  int32_t n_eps;          /* 1 .. SKNR_MAX_STAGES */
+  int32_t max_iter;       /* SK iterations allowed per stage (>= 1) */
+  double tol;             /* omega: L1 marginal error target per stage (> 0) */
+  int32_t ell;            /* l: number of low-frequency modes (0 = plain SK) */
+  int32_t warm_mode;      /* enum sknr_warm_mode */
+  double eps_prime;       /* STATIC: eps' of the warm-start solve */
+  int32_t eig_oversample; /* extra subspace columns (0 -> 8) */
+  int32_t eig_max_iter;   /* subspace iterations cap (0 -> 200) */
+  double eig_tol;         /* Ritz-value stagnation tolerance (0 -> 1e-7) */
+  int32_t check_every;    /* iterations per host convergence poll (0 -> auto) */
+  int32_t first_stage_nr; /* 1: allow SK-NR on stage 0 (needs WARM_USER) */
+  const double* f0;       /* [device] optional n FP64 initial f at eps[0] (NULL -> 0) */
+  const double* V0;       /* [device] optional n x ell FP64 basis (WARM_USER) */
+  uint64_t seed;          /* seed of the subspace-iteration start block */
+  void* stream;           /* hipStream_t */
+} sknr_opts;
+
+typedef struct sknr_stage_stats {
+  double eps;
+  int32_t iters;          /* SK iterations of Algorithm 4.1 in this stage */
+  int32_t newton_tried;   /* projected Newton steps attempted */
+  int32_t newton_accepted;/* ... and accepted by the Q^semi test */
+  int32_t eig_iters;      /* subspace iterations of the warm start feeding this stage */
+  double marginal_err;    /* FP64 L1 marginal error at the end of the stage */
+  double seconds;         /* wall time of the stage (incl. its warm start) */
+} sknr_stage_stats;
+
+typedef struct sknr_result {
+  int32_t status;
+  int32_t n_stages;
+  int32_t total_iters;
+  int32_t transposed;       /* 1 when solved on the transpose (n > m) */
+  sknr_stage_stats stage[SKNR_MAX_STAGES];
+  double marginal_err;      /* FP64 L1 marginal error vs the solver's cost */
+  double row_err;           /* ||pi 1 - a||_1 (FP64) */
+  double col_err;           /* ||pi^T 1 - b||_1 (FP64) */
+  double transport_cost;    /* <C, pi> (FP64) */
+  double dual_value;        /* Q_eps(f, g), eq. def_Q (FP64) */
+  double primal_value;      /* <C,pi> + eps KL(pi || a(x)b) (FP64) */
+  double mass;              /* sum_ij pi_ij */
+  double seconds;
+} sknr_result;
+
+/* --------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory the context may hold for workspaces and queued serving
+ * requests (0 = 90% of the free memory at creation).  *out receives the
+ * context.  Errors: EINVAL (bad device), EDEVICE. */
+int sknr_ctx_create(int device, uint64_t hbm_budget_bytes, void** out);
+
+/* Destroy a context, waiting for outstanding work and freeing its memory. */
+int sknr_ctx_destroy(void* ctx);
+
+/* ----------------------------------------------------------- full solves */
+
+/* Solve the EOT problem along the eps schedule of `opts` (Sec. 5 "sequential
+ * warm start"): stage s starts from the potentials of stage s-1; with
+ * ell > 0 stages run Algorithm 4.1 with V_l from the spectral warm start
+ * (Sec. 4) chosen by warm_mode, otherwise plain SK (eq. SK_iterations).
+ * The first stage is plain SK unless first_stage_nr is set with WARM_USER.
+ * f_out [device] n FP64 and g_out [device] m FP64 receive the potentials of
+ * the last stage, res [host] the statistics.  When n > m the solve runs on
+ * the transposed problem (semi-dual on the smaller side, Sec. 2); outputs
+ * are always in the caller's orientation.
+ * Returns OK, NOT_CONVERGED (some stage hit max_iter), or an error. */
+int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts,
+               double* f_out, double* g_out, sknr_result* res);
+
+/* ------------------------------------------- single steps of the path */
+
+/* Row c-transform f = g^{C,eps} (eq. foc_f), one FP32 sweep with
+ * compensated accumulation:  f_i = -eps log sum_j b_j exp((g_j - C_ij)/eps).
+ * g [device] m FP64 in, f_out [device] n FP64 out. */
+int sknr_c_transform_row(void* ctx, const sknr_problem* prob, double eps,
+                         const double* g, double* f_out, void* stream);
+
+/* Column c-transform g = f^{C,eps} (eq. foc_g), fused with the marginal
+ * error of the pair (f, g_prev):  err = sum_j b_j |exp((g_prev_j - g_j)/eps)
+ * - 1| = ||pi(f,g_prev)^T 1 - b||_1 when f = g_prev^{C,eps} (the test of
+ * Algorithm 4.1), and with <g, b>.  f [device] n FP64, g_prev [device] m
+ * FP64 or NULL (err then 0), g_out [device] m FP64; err_out and gdot_out
+ * [host] scalars or NULL. */
+int sknr_c_transform_col(void* ctx, const sknr_problem* prob, double eps,
+                         const double* f, const double* g_prev, double* g_out,
+                         double* err_out, double* gdot_out, void* stream);
+
+/* Semi-dual value and its gradient / Hessian restricted to span(V)
+ * (eq. def_Q_semi, dQ_semi, d2Q_semi; Algorithm 4.1, computing the value
+ * and the derivatives on V_l):
+ *   qsemi = <f,a> + <f^{C,eps}, b>,
+ *   grad  = V^T (a - P~ 1_m),               P~ = pi(f, f^{C,eps}),
+ *   G     = -eps V^T (grad^2 Q^semi) V = V^T diag(P~ 1) V - W^T diag(b)^-1 W,
+ *           W = P~^T V.
+ * f [device] n FP64, V [device] n x ell FP64 (1 <= ell <= 32);
+ * G_out [host] ell x ell, grad_out [host] ell, qsemi_out [host] scalar. */
+int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps,
+                          const double* f, const double* V, int32_t ell,
+                          double* G_out, double* grad_out, double* qsemi_out,
+                          void* stream);
+
+/* One projected Newton-Raphson step with the acceptance test of Algorithm
+ * 4.1: Delta f = eps V G^-1 grad (Cholesky, FP64), f' = f + Delta f, kept
+ * iff Q^semi(f') > Q^semi(f).  f_inout [device] n FP64 is replaced by f'
+ * when accepted.  accepted/q0/q1 [host] may be NULL. */
+int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps,
+                     double* f_inout, const double* V, int32_t ell,
+                     int32_t* accepted, double* q0, double* q1, void* stream);
+
+/* Spectral warm-start basis (Sec. 4): at the pair (f, f^{C,eps}) the top
+ * ell non-constant eigenvectors of M = diag(a)^-1 P diag(b)^-1 P^T (the
+ * semi-dual Hessian at the optimum is -(1/eps) diag(a) (Id - M), eq.
+ * semidual_Hessian) by block subspace iteration with ell + oversample
+ * columns and FP64 Rayleigh-Ritz.  V_out [device] n x ell FP64 (columns
+ * orthonormal in L2(a), orthogonal to constants, descending rho);
+ * rho_out [host] ell+1 values sqrt(eigenvalue), rho_out[0] = 1 for the
+ * constant mode; iters_out [host] subspace iterations used (may be NULL). */
+int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps,
+                        const double* f, int32_t ell, int32_t oversample,
+                        int32_t max_iter, double tol, uint64_t seed,
+                        double* V_out, double* rho_out, int32_t* iters_out,
+                        void* stream);
+
+typedef struct sknr_eval {
+  double row_err, col_err, marginal_err;   /* L1 marginal errors */
+  double transport_cost, dual_value, primal_value, mass;
+} sknr_eval;
+
+/* FP64 evaluation of a pair (f, g) on the solver's cost: marginal errors,
+ * <C,pi>, Q_eps (eq. def_Q) and the primal value <C,pi> + eps KL(pi||a(x)b)
+ * (eq. primal_EOT).  f, g [device] FP64; out [host]. */
+int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps,
+                  const double* f, const double* g, sknr_eval* out, void* stream);
+
+/* The coupling pi (eq. Optimal_P_epsilon) as FP32: P_out [device] n x m
+ * row-major.  Diagnostic; O(nm) memory. */
+int sknr_coupling(void* ctx, const sknr_problem* prob, double eps,
+                  const double* f, const double* g, float* P_out, void* stream);
+
+/* ---------------------------------------------------------------- errors */
+const char* sknr_status_str(int status);
+const char* sknr_last_error(void);
+
+/* Library version string. */
+const char* sknr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKNR_H_ */

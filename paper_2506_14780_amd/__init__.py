@@ -1,0 +1,307 @@
+"""Python binding of libsknr (C ABI in include/sknr.h).
+
+Argument marshalling only: every computation runs in the HIP library.
+Device arrays are torch tensors on the HIP device (torch supplies device
+memory and streams); their data pointers cross the ABI.  The library is
+built in-tree by ``paper_2506_14780_amd.build``; importing this module
+fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+__all__ = [
+    "lib", "Context", "Problem", "solve", "c_transform_row", "c_transform_col",
+    "projected_system", "newton_step", "spectral_basis", "evaluate", "coupling",
+    "SknrError", "COST_STORED", "COST_SQEUCLID", "XTERM_AUTO", "XTERM_FP32",
+    "XTERM_BF16", "XTERM_BF16X3", "WARM_SEQUENTIAL", "WARM_STATIC", "WARM_USER",
+    "LIB_PATH", "MAX_STAGES", "MAX_ELL",
+]
+
+# torch ships its own HIP runtime; importing it first makes libsknr bind to
+# that same runtime (one HIP runtime per process).
+import torch  # noqa: E402,F401
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsknr.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libsknr.so not built ({LIB_PATH}); run `python -m paper_2506_14780_amd.build`")
+lib = ctypes.CDLL(LIB_PATH)
+
+MAX_STAGES = 32
+MAX_ELL = 32
+COST_STORED, COST_SQEUCLID = 0, 1
+XTERM_AUTO, XTERM_FP32, XTERM_BF16, XTERM_BF16X3 = 0, 1, 2, 3
+WARM_SEQUENTIAL, WARM_STATIC, WARM_USER = 0, 1, 2
+OK, NOT_CONVERGED = 0, 1
+
+_p = ctypes.c_void_p
+_d = ctypes.c_double
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n", _i64), ("m", _i64), ("d", _i32), ("kind", _i32), ("xterm", _i32),
+                ("reserved0", _i32), ("C", _p), ("ldc", _i64), ("x", _p), ("y", _p),
+                ("cost_scale", _d), ("a", _p), ("b", _p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.POINTER(_d)), ("n_eps", _i32), ("max_iter", _i32), ("tol", _d),
+                ("ell", _i32), ("warm_mode", _i32), ("eps_prime", _d), ("eig_oversample", _i32),
+                ("eig_max_iter", _i32), ("eig_tol", _d), ("check_every", _i32),
+                ("first_stage_nr", _i32), ("f0", _p), ("V0", _p), ("seed", ctypes.c_uint64),
+                ("stream", _p)]
+
+
+class _Stage(ctypes.Structure):
+    _fields_ = [("eps", _d), ("iters", _i32), ("newton_tried", _i32), ("newton_accepted", _i32),
+                ("eig_iters", _i32), ("marginal_err", _d), ("seconds", _d)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", _i32), ("n_stages", _i32), ("total_iters", _i32), ("transposed", _i32),
+                ("stage", _Stage * MAX_STAGES), ("marginal_err", _d), ("row_err", _d),
+                ("col_err", _d), ("transport_cost", _d), ("dual_value", _d),
+                ("primal_value", _d), ("mass", _d), ("seconds", _d)]
+
+
+class _Eval(ctypes.Structure):
+    _fields_ = [("row_err", _d), ("col_err", _d), ("marginal_err", _d), ("transport_cost", _d),
+                ("dual_value", _d), ("primal_value", _d), ("mass", _d)]
+
+
+def _sig(name, args):
+    fn = getattr(lib, name)
+    fn.argtypes = args
+    fn.restype = ctypes.c_int
+    return fn
+
+
+_P = ctypes.POINTER
+lib.sknr_status_str.restype = ctypes.c_char_p
+lib.sknr_status_str.argtypes = [ctypes.c_int]
+lib.sknr_last_error.restype = ctypes.c_char_p
+lib.sknr_version.restype = ctypes.c_char_p
+_sig("sknr_ctx_create", [ctypes.c_int, ctypes.c_uint64, _P(_p)])
+_sig("sknr_ctx_destroy", [_p])
+_sig("sknr_solve", [_p, _P(_Problem), _P(_Opts), _p, _p, _P(_Result)])
+_sig("sknr_c_transform_row", [_p, _P(_Problem), _d, _p, _p, _p])
+_sig("sknr_c_transform_col", [_p, _P(_Problem), _d, _p, _p, _p, _P(_d), _P(_d), _p])
+_sig("sknr_projected_system", [_p, _P(_Problem), _d, _p, _p, _i32, _P(_d), _P(_d), _P(_d), _p])
+_sig("sknr_newton_step", [_p, _P(_Problem), _d, _p, _p, _i32, _P(_i32), _P(_d), _P(_d), _p])
+_sig("sknr_spectral_basis", [_p, _P(_Problem), _d, _p, _i32, _i32, _i32, _d, ctypes.c_uint64, _p,
+                             _P(_d), _P(_i32), _p])
+_sig("sknr_evaluate", [_p, _P(_Problem), _d, _p, _p, _P(_Eval), _p])
+_sig("sknr_coupling", [_p, _P(_Problem), _d, _p, _p, _p, _p])
+
+
+class SknrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib.sknr_last_error().decode(errors="replace")
+        super().__init__(f"{where}: status {status} ({lib.sknr_status_str(status).decode()}): {msg}")
+        self.status = status
+
+
+def _check(st: int, where: str, allow_not_converged: bool = True) -> int:
+    if st < 0 or (st == NOT_CONVERGED and not allow_not_converged):
+        raise SknrError(st, where)
+    return st
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A libsknr context on one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        try:  # torch owns the device memory and streams: let it set up HIP first
+            import torch
+            torch.cuda.init()
+        except ImportError:  # pragma: no cover
+            pass
+        h = ctypes.c_void_p()
+        _check(lib.sknr_ctx_create(device, hbm_budget_bytes, ctypes.byref(h)), "sknr_ctx_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _check(lib.sknr_ctx_destroy(self.handle), "sknr_ctx_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class Problem:
+    """Device-resident problem: a, b float64 tensors; either C (n x m
+    float32, row stride ldc) or x (n x d), y (m x d) float32 tensors."""
+
+    a: object
+    b: object
+    C: object = None
+    x: object = None
+    y: object = None
+    cost_scale: float = 1.0
+    xterm: int = XTERM_AUTO
+    ldc: int | None = None
+
+    def c_struct(self) -> _Problem:
+        p = _Problem()
+        p.n = int(self.a.shape[0])
+        p.m = int(self.b.shape[0])
+        p.a = _ptr(self.a)
+        p.b = _ptr(self.b)
+        p.xterm = self.xterm
+        if self.C is not None:
+            p.kind = COST_STORED
+            p.C = _ptr(self.C)
+            p.ldc = self.ldc if self.ldc is not None else int(self.C.stride(0))
+            p.d = 0
+        else:
+            p.kind = COST_SQEUCLID
+            p.x = _ptr(self.x)
+            p.y = _ptr(self.y)
+            p.d = int(self.x.shape[1])
+            p.cost_scale = self.cost_scale
+        return p
+
+
+def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,
+          warm_mode: int = WARM_USER, V0=None, f0=None, eps_prime: float = 0.0, check_every: int = 0,
+          first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
+          eig_tol: float = 0.0, seed: int = 0, stream=None, f_out=None, g_out=None):
+    """sknr_solve.  Returns (f, g, result dict); f, g are float64 device
+    tensors in the caller's orientation."""
+    import torch
+    eps = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
+    dev = prob.a.device
+    n, m = int(prob.a.shape[0]), int(prob.b.shape[0])
+    f = f_out if f_out is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    g = g_out if g_out is not None else torch.empty(m, dtype=torch.float64, device=dev)
+    earr = (_d * len(eps))(*eps)
+    o = _Opts()
+    o.eps = ctypes.cast(earr, _P(_d))
+    o.n_eps = len(eps)
+    o.max_iter = max_iter
+    o.tol = tol
+    o.ell = ell
+    o.warm_mode = warm_mode
+    o.eps_prime = eps_prime
+    o.eig_oversample = eig_oversample
+    o.eig_max_iter = eig_max_iter
+    o.eig_tol = eig_tol
+    o.check_every = check_every
+    o.first_stage_nr = 1 if first_stage_nr else 0
+    o.f0 = _ptr(f0)
+    o.V0 = _ptr(V0)
+    o.seed = seed
+    o.stream = _stream(stream)
+    r = _Result()
+    ps = prob.c_struct()
+    st = lib.sknr_solve(ctx.handle, ctypes.byref(ps), ctypes.byref(o), _ptr(f), _ptr(g), ctypes.byref(r))
+    _check(st, "sknr_solve")
+    res = {k: getattr(r, k) for k in ("status", "n_stages", "total_iters", "transposed", "marginal_err",
+                                       "row_err", "col_err", "transport_cost", "dual_value",
+                                       "primal_value", "mass", "seconds")}
+    res["stages"] = [{k: getattr(r.stage[i], k) for k, _ in _Stage._fields_} for i in range(r.n_stages)]
+    return f, g, res
+
+
+def c_transform_row(ctx, prob: Problem, eps: float, g, stream=None):
+    import torch
+    f = torch.empty(int(prob.a.shape[0]), dtype=torch.float64, device=g.device)
+    ps = prob.c_struct()
+    _check(lib.sknr_c_transform_row(ctx.handle, ctypes.byref(ps), eps, _ptr(g), _ptr(f), _stream(stream)),
+           "sknr_c_transform_row")
+    return f
+
+
+def c_transform_col(ctx, prob: Problem, eps: float, f, g_prev=None, stream=None):
+    """Returns (g, err, <g,b>)."""
+    import torch
+    g = torch.empty(int(prob.b.shape[0]), dtype=torch.float64, device=f.device)
+    err, gdot = _d(), _d()
+    ps = prob.c_struct()
+    _check(lib.sknr_c_transform_col(ctx.handle, ctypes.byref(ps), eps, _ptr(f), _ptr(g_prev), _ptr(g),
+                                    ctypes.byref(err), ctypes.byref(gdot), _stream(stream)),
+           "sknr_c_transform_col")
+    return g, err.value, gdot.value
+
+
+def projected_system(ctx, prob: Problem, eps: float, f, V, stream=None):
+    """Returns (G, grad, qsemi) as numpy arrays / float."""
+    import numpy as np
+    ell = int(V.shape[1])
+    G = (_d * (ell * ell))()
+    gr = (_d * ell)()
+    q = _d()
+    ps = prob.c_struct()
+    _check(lib.sknr_projected_system(ctx.handle, ctypes.byref(ps), eps, _ptr(f), _ptr(V), ell, G, gr,
+                                     ctypes.byref(q), _stream(stream)), "sknr_projected_system")
+    return np.array(G[:]).reshape(ell, ell), np.array(gr[:]), q.value
+
+
+def newton_step(ctx, prob: Problem, eps: float, f, V, stream=None):
+    """In-place on f; returns (accepted, q0, q1)."""
+    acc = _i32()
+    q0, q1 = _d(), _d()
+    ps = prob.c_struct()
+    _check(lib.sknr_newton_step(ctx.handle, ctypes.byref(ps), eps, _ptr(f), _ptr(V), int(V.shape[1]),
+                                ctypes.byref(acc), ctypes.byref(q0), ctypes.byref(q1), _stream(stream)),
+           "sknr_newton_step")
+    return bool(acc.value), q0.value, q1.value
+
+
+def spectral_basis(ctx, prob: Problem, eps: float, f, ell: int, oversample: int = 8, max_iter: int = 200,
+                   tol: float = 1e-7, seed: int = 0, stream=None):
+    """Returns (V [n x ell float64 device], rho [ell+1], iters)."""
+    import numpy as np
+    import torch
+    n = int(prob.a.shape[0])
+    V = torch.empty((n, ell), dtype=torch.float64, device=f.device)
+    rho = (_d * (ell + 1))()
+    it = _i32()
+    ps = prob.c_struct()
+    _check(lib.sknr_spectral_basis(ctx.handle, ctypes.byref(ps), eps, _ptr(f), ell, oversample, max_iter, tol,
+                                   seed, _ptr(V), rho, ctypes.byref(it), _stream(stream)), "sknr_spectral_basis")
+    return V, np.array(rho[:]), it.value
+
+
+def evaluate(ctx, prob: Problem, eps: float, f, g, stream=None) -> dict:
+    e = _Eval()
+    ps = prob.c_struct()
+    _check(lib.sknr_evaluate(ctx.handle, ctypes.byref(ps), eps, _ptr(f), _ptr(g), ctypes.byref(e),
+                             _stream(stream)), "sknr_evaluate")
+    return {k: getattr(e, k) for k, _ in _Eval._fields_}
+
+
+def coupling(ctx, prob: Problem, eps: float, f, g, stream=None):
+    import torch
+    n, m = int(prob.a.shape[0]), int(prob.b.shape[0])
+    P = torch.empty((n, m), dtype=torch.float32, device=f.device)
+    ps = prob.c_struct()
+    _check(lib.sknr_coupling(ctx.handle, ctypes.byref(ps), eps, _ptr(f), _ptr(g), _ptr(P), _stream(stream)),
+           "sknr_coupling")
+    return P

@@ -1,0 +1,1109 @@
+// Host engine and C ABI of libsknr (see include/sknr.h).
+//
+// The engine keeps one problem resident on the device in a fixed
+// orientation: side X (size n) carries the semi-dual potential f and is the
+// smaller side (Sec. 2: the semi-dual is taken over the smaller space);
+// side Y (size m) carries g.  Each Sinkhorn iteration is a fixed sequence of
+// kernel launches gated by a small device state block, so chunks of
+// iterations run without host round trips; the host polls the state once
+// per chunk.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sknr.h"
+#include "sknr_internal.h"
+
+using namespace sknr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Err {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) throw Err{SKNR_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+#define REQUIRE(cond, msg)                                   \
+  do {                                                       \
+    if (!(cond)) throw Err{SKNR_EINVAL, std::string(msg)};   \
+  } while (0)
+
+float2 split_df(double v) {
+  float hi = (float)v;
+  float lo = (float)(v - (double)hi);
+  return make_float2(hi, lo);
+}
+
+// ------------------------------------------------------------------ arena
+// One device allocation carved into aligned buffers; grown (reallocated)
+// when a larger problem arrives.  Counters inside are zeroed at growth.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  void reset() { off = 0; }
+  void* take(size_t bytes) {
+    size_t a = (off + 255) & ~size_t(255);
+    if (a + bytes > cap) throw Err{SKNR_EINTERNAL, "arena overflow"};
+    off = a + bytes;
+    return base + a;
+  }
+};
+
+struct Ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  Arena arena;
+  DevState* st_host = nullptr;  // pinned mirror of the state
+};
+
+struct Prepared {
+  // caller orientation
+  int n0, m0;
+  // engine orientation
+  int n, m;
+  bool transposed;
+  int kind;
+  const float* C;
+  long long ldc;
+  bool ctrans;  // engine element (i, j) is C[j*ldc + i]
+  const float* X;  // points of side X (n x d)
+  const float* Y;  // points of side Y (m x d)
+  int d;
+  float cscale;
+  float cmax;
+  const double* wX;  // device FP64 weights
+  const double* wY;
+  std::vector<double> hX, hY;  // host copies
+};
+
+struct WS {
+  float2 *F, *Fsk, *Fp, *G[2], *Gt, *Gp;
+  float* mdiff;
+  float *V, *W;
+  int ellp;
+  float* part;
+  unsigned* cnt_cb;
+  double *blk_err, *blk_dot;
+  float* blk_max;
+  double* nrpart;
+  int nr_rows_blk, nr_cols_blk;
+  float* coef32;
+  double* coef64;
+  DevState* st;
+  float *wX32, *wY32;
+  double *lX64, *lY64;
+  float2 *lXdf, *lYdf;
+  double *fX64, *gY64;
+  double* scratch;
+  double *evrow, *evcol, *evscal, *evout;
+  double* Gout;
+  double* gout;
+  // warm start (block width up to 32)
+  float *Vw, *Zw, *Uw, *Utw;
+  double *Rw, *sw, *Qw, *lamw;
+  int* okw;
+  bool have_Vw;
+  // sweep geometry
+  int ns_c, rps_c, nb_c, ns_r, rps_r, nb_r, ns_cw, rps_cw, nb_cw;
+};
+
+int ell_pad(int ell) { return ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32)); }
+
+bool col_is_stream(const Prepared& P) { return P.kind == SKNR_COST_SQEUCLID || !P.ctrans; }
+bool row_is_stream(const Prepared& P) { return P.kind == SKNR_COST_SQEUCLID || P.ctrans; }
+// float4 access along the output axis of a streaming sweep over a stored cost
+bool stream_vec(const Prepared& P, int n_out) {
+  return P.kind == SKNR_COST_STORED && n_out % 4 == 0 && P.ldc % 4 == 0 && ((uintptr_t)P.C % 16) == 0;
+}
+
+// --------------------------------------------------------------- prepare
+Prepared prepare(const sknr_problem* pr, hipStream_t s) {
+  REQUIRE(pr, "problem is NULL");
+  REQUIRE(pr->n >= 1 && pr->m >= 1, "n and m must be >= 1");
+  REQUIRE(pr->n <= (1 << 26) && pr->m <= (1 << 26), "n, m too large");
+  REQUIRE(pr->kind == SKNR_COST_STORED || pr->kind == SKNR_COST_SQEUCLID, "unknown cost kind");
+  REQUIRE(pr->a && pr->b, "weights a, b are required");
+  Prepared P;
+  P.n0 = (int)pr->n;
+  P.m0 = (int)pr->m;
+  P.kind = pr->kind;
+  P.transposed = pr->n > pr->m;
+  P.n = P.transposed ? P.m0 : P.n0;
+  P.m = P.transposed ? P.n0 : P.m0;
+  P.C = pr->C;
+  P.ldc = pr->ldc;
+  P.ctrans = P.transposed;
+  P.d = pr->d;
+  P.cscale = 1.0f;
+  if (pr->kind == SKNR_COST_STORED) {
+    REQUIRE(pr->C, "stored cost C is NULL");
+    REQUIRE(pr->ldc >= pr->m, "ldc < m");
+    P.X = P.Y = nullptr;
+  } else {
+    REQUIRE(pr->x && pr->y, "points x, y are required");
+    REQUIRE(pr->d >= 1 && pr->d <= 1024, "d must be in [1, 1024]");
+    double sc = pr->cost_scale == 0.0 ? 1.0 : pr->cost_scale;
+    REQUIRE(sc > 0 && std::isfinite(sc), "cost_scale must be positive");
+    P.cscale = (float)sc;
+    P.X = P.transposed ? pr->y : pr->x;
+    P.Y = P.transposed ? pr->x : pr->y;
+  }
+  // weights: validate on the host
+  std::vector<double> ha(P.n0), hb(P.m0);
+  HIPCHK(hipMemcpyAsync(ha.data(), pr->a, sizeof(double) * P.n0, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hb.data(), pr->b, sizeof(double) * P.m0, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto check_w = [](const std::vector<double>& w, const char* name) {
+    double sum = 0;
+    for (double v : w) {
+      if (!(v > 0) || !std::isfinite(v)) throw Err{SKNR_EINVAL, std::string(name) + " has a non-positive or non-finite entry"};
+      sum += v;
+    }
+    if (std::fabs(sum - 1.0) > 1e-9 * std::max<double>(1.0, (double)w.size()))
+      throw Err{SKNR_EINVAL, std::string(name) + " does not sum to 1"};
+  };
+  check_w(ha, "a");
+  check_w(hb, "b");
+  P.wX = P.transposed ? pr->b : pr->a;
+  P.wY = P.transposed ? pr->a : pr->b;
+  P.hX = P.transposed ? hb : ha;
+  P.hY = P.transposed ? ha : hb;
+  // cost bound
+  if (pr->kind == SKNR_COST_STORED) {
+    float* dmax;
+    HIPCHK(hipMallocAsync((void**)&dmax, sizeof(float), s));
+    HIPCHK(hipMemsetAsync(dmax, 0, sizeof(float), s));
+    HIPCHK(launch_cost_max(0, pr->C, pr->ldc, P.n0, P.m0, nullptr, nullptr, 0, dmax, s));
+    float hm = 0;
+    HIPCHK(hipMemcpyAsync(&hm, dmax, sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipFreeAsync(dmax, s));
+    HIPCHK(hipStreamSynchronize(s));
+    REQUIRE(std::isfinite(hm), "cost has non-finite entries");
+    P.cmax = hm;
+  } else {
+    int d = pr->d;
+    std::vector<float> hx((size_t)P.n0 * d), hy((size_t)P.m0 * d);
+    HIPCHK(hipMemcpyAsync(hx.data(), pr->x, hx.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hy.data(), pr->y, hy.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double bound = 0;
+    for (int k = 0; k < d; ++k) {
+      double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY;
+      for (int i = 0; i < P.n0; ++i) {
+        double v = hx[(size_t)i * d + k];
+        REQUIRE(std::isfinite(v), "x has non-finite entries");
+        xl = std::min(xl, v);
+        xh = std::max(xh, v);
+      }
+      for (int j = 0; j < P.m0; ++j) {
+        double v = hy[(size_t)j * d + k];
+        REQUIRE(std::isfinite(v), "y has non-finite entries");
+        yl = std::min(yl, v);
+        yh = std::max(yh, v);
+      }
+      double span = std::max(std::fabs(xh - yl), std::fabs(yh - xl));
+      bound += span * span;
+    }
+    P.cmax = (float)(bound * P.cscale * 1.001 + 1e-30);
+  }
+  return P;
+}
+
+// --------------------------------------------------------------- workspace
+size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
+  int n = P.n, m = P.m;
+  size_t b = 0;
+  auto add = [&](size_t x) { b += (x + 255) & ~size_t(255); };
+  int ns, rps, nb, nbmax = 0;
+  size_t pmax = 0;
+  // T_c (output Y), with and without weights
+  for (int e : {0, ellp}) {
+    size_t p = sweep_part_floats(m, n, e, P.kind, P.d, stream_vec(P, m), &ns, &rps, &nb, col_is_stream(P));
+    pmax = std::max(pmax, p);
+    nbmax = std::max(nbmax, nb);
+    p = sweep_part_floats(n, m, e, P.kind, P.d, stream_vec(P, n), &ns, &rps, &nb, row_is_stream(P));
+    pmax = std::max(pmax, p);
+    nbmax = std::max(nbmax, nb);
+  }
+  nbmax = std::max(nbmax, (std::max(n, m) + 255) / 256 + 1);
+  add(sizeof(float2) * n * 3);
+  add(sizeof(float2) * m);
+  add(sizeof(float2) * m);
+  add(sizeof(float2) * m * 2);
+  add(sizeof(float) * n);
+  add(sizeof(float) * (size_t)n * std::max(ellp, 1));
+  add(sizeof(float) * (size_t)m * std::max(ellp, 1));
+  add(sizeof(float) * pmax + 16);
+  add(sizeof(unsigned) * (size_t)(std::max(n, m) / 64 + 16));
+  add(sizeof(double) * nbmax * 2);
+  add(sizeof(float) * nbmax);
+  int nrb = 64, ncb = 64;
+  add(sizeof(double) * (nrb + ncb) * (size_t)(std::max(ellp, 1) * std::max(ellp, 1) + std::max(ellp, 1)));
+  add(sizeof(float) * 32);
+  add(sizeof(double) * 32);
+  add(sizeof(DevState));
+  add(sizeof(float) * (n + m));
+  add(sizeof(double) * (n + m));
+  add(sizeof(float2) * (n + m));
+  add(sizeof(double) * (n + m));
+  add(sizeof(double) * ((std::max(n, m) + 255) / 256 + 64));
+  int ecb = (P.m0 + 255) / 256, erb = (P.n0 + 63) / 64;
+  add(sizeof(double) * (size_t)ecb * P.n0);
+  add(sizeof(double) * (size_t)erb * P.m0);
+  add(sizeof(double) * (size_t)ecb * erb * 3);
+  add(sizeof(double) * 16);
+  add(sizeof(double) * 32 * 32);
+  add(sizeof(double) * 32);
+  if (ellp > 0) {
+    add(sizeof(float) * (size_t)n * 32 * 2);
+    add(sizeof(float) * (size_t)m * 32 * 2);
+    add(sizeof(double) * 32 * 32 * 2 + sizeof(double) * 64 + 64);
+  }
+  if (geo) *geo = nbmax;
+  return b + 4096;
+}
+
+WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
+  size_t need = ws_bytes(P, ellp, nullptr);
+  if (need > c->arena.cap) {
+    HIPCHK(hipStreamSynchronize(s));
+    if (c->arena.base) HIPCHK(hipFree(c->arena.base));
+    c->arena.base = nullptr;
+    c->arena.cap = 0;
+    size_t cap = need + need / 4;
+    hipError_t e = hipMalloc((void**)&c->arena.base, cap);
+    if (e != hipSuccess) throw Err{SKNR_ENOMEM, "device allocation of the workspace failed"};
+    c->arena.cap = cap;
+    HIPCHK(hipMemsetAsync(c->arena.base, 0, cap, s));
+  }
+  Arena& A = c->arena;
+  A.reset();
+  int n = P.n, m = P.m;
+  WS w{};
+  w.ellp = ellp;
+  w.F = (float2*)A.take(sizeof(float2) * n);
+  w.Fsk = (float2*)A.take(sizeof(float2) * n);
+  w.Fp = (float2*)A.take(sizeof(float2) * n);
+  w.G[0] = (float2*)A.take(sizeof(float2) * m);
+  w.G[1] = (float2*)A.take(sizeof(float2) * m);
+  w.Gt = (float2*)A.take(sizeof(float2) * m);
+  w.Gp = (float2*)A.take(sizeof(float2) * m);
+  w.mdiff = (float*)A.take(sizeof(float) * n);
+  w.V = (float*)A.take(sizeof(float) * (size_t)n * std::max(ellp, 1));
+  w.W = (float*)A.take(sizeof(float) * (size_t)m * std::max(ellp, 1));
+  int ns, rps, nb, nbmax = 0;
+  size_t pmax = 0;
+  for (int e : {0, ellp}) {
+    pmax = std::max(pmax, sweep_part_floats(m, n, e, P.kind, P.d, stream_vec(P, m), &ns, &rps, &nb,
+                                            col_is_stream(P)));
+    nbmax = std::max(nbmax, nb);
+    pmax = std::max(pmax, sweep_part_floats(n, m, e, P.kind, P.d, stream_vec(P, n), &ns, &rps, &nb,
+                                            row_is_stream(P)));
+    nbmax = std::max(nbmax, nb);
+  }
+  nbmax = std::max(nbmax, (std::max(n, m) + 255) / 256 + 1);
+  w.part = (float*)A.take(sizeof(float) * pmax + 16);
+  const size_t ncnt = (size_t)(std::max(n, m) / 64 + 16);
+  w.cnt_cb = (unsigned*)A.take(sizeof(unsigned) * ncnt);
+  // the split-K "last block" counters must start at zero; the arena layout
+  // depends on the problem shape, so clear them every time it is carved
+  HIPCHK(hipMemsetAsync(w.cnt_cb, 0, sizeof(unsigned) * ncnt, s));
+  w.blk_err = (double*)A.take(sizeof(double) * nbmax);
+  w.blk_dot = (double*)A.take(sizeof(double) * nbmax);
+  w.blk_max = (float*)A.take(sizeof(float) * nbmax);
+  w.nr_rows_blk = std::min(64, std::max(1, (n + 255) / 256));
+  w.nr_cols_blk = std::min(64, std::max(1, (m + 255) / 256));
+  int e1 = std::max(ellp, 1);
+  w.nrpart = (double*)A.take(sizeof(double) * (128) * (size_t)(e1 * e1 + e1));
+  w.coef32 = (float*)A.take(sizeof(float) * 32);
+  w.coef64 = (double*)A.take(sizeof(double) * 32);
+  w.st = (DevState*)A.take(sizeof(DevState));
+  w.wX32 = (float*)A.take(sizeof(float) * n);
+  w.wY32 = (float*)A.take(sizeof(float) * m);
+  w.lX64 = (double*)A.take(sizeof(double) * n);
+  w.lY64 = (double*)A.take(sizeof(double) * m);
+  w.lXdf = (float2*)A.take(sizeof(float2) * n);
+  w.lYdf = (float2*)A.take(sizeof(float2) * m);
+  w.fX64 = (double*)A.take(sizeof(double) * n);
+  w.gY64 = (double*)A.take(sizeof(double) * m);
+  w.scratch = (double*)A.take(sizeof(double) * ((std::max(n, m) + 255) / 256 + 64));
+  int ecb = (P.m0 + 255) / 256, erb = (P.n0 + 63) / 64;
+  w.evrow = (double*)A.take(sizeof(double) * (size_t)ecb * P.n0);
+  w.evcol = (double*)A.take(sizeof(double) * (size_t)erb * P.m0);
+  w.evscal = (double*)A.take(sizeof(double) * (size_t)ecb * erb * 3);
+  w.evout = (double*)A.take(sizeof(double) * 16);
+  w.Gout = (double*)A.take(sizeof(double) * 32 * 32);
+  w.gout = (double*)A.take(sizeof(double) * 32);
+  w.have_Vw = false;
+  if (ellp > 0) {
+    w.Vw = (float*)A.take(sizeof(float) * (size_t)n * 32);
+    w.Zw = (float*)A.take(sizeof(float) * (size_t)n * 32);
+    w.Uw = (float*)A.take(sizeof(float) * (size_t)m * 32);
+    w.Utw = (float*)A.take(sizeof(float) * (size_t)m * 32);
+    w.Rw = (double*)A.take(sizeof(double) * 32 * 32);
+    w.Qw = (double*)A.take(sizeof(double) * 32 * 32);
+    w.sw = (double*)A.take(sizeof(double) * 32);
+    w.lamw = (double*)A.take(sizeof(double) * 32);
+    w.okw = (int*)A.take(64);
+  }
+  // weights and log-weights (host FP64 log, uploaded)
+  std::vector<float> fx(n), fy(m);
+  std::vector<double> lx(n), ly(m);
+  std::vector<float2> dx(n), dy(m);
+  for (int i = 0; i < n; ++i) {
+    fx[i] = (float)P.hX[i];
+    lx[i] = std::log(P.hX[i]);
+    dx[i] = split_df(lx[i]);
+  }
+  for (int j = 0; j < m; ++j) {
+    fy[j] = (float)P.hY[j];
+    ly[j] = std::log(P.hY[j]);
+    dy[j] = split_df(ly[j]);
+  }
+  HIPCHK(hipMemcpyAsync(w.wX32, fx.data(), 4 * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.wY32, fy.data(), 4 * m, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.lX64, lx.data(), 8 * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.lY64, ly.data(), 8 * m, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.lXdf, dx.data(), 8 * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.lYdf, dy.data(), 8 * m, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));  // host vectors go out of scope
+  return w;
+}
+
+// ------------------------------------------------------------------ engine
+struct Engine {
+  Ctx* c;
+  Prepared& P;
+  WS& w;
+  hipStream_t s;
+  double eps = 1.0;
+  double tol = 1e-6;
+
+  Engine(Ctx* c_, Prepared& P_, WS& w_, hipStream_t s_) : c(c_), P(P_), w(w_), s(s_) {}
+
+  void fill_common(SweepArgs& a) const {
+    a.C = P.C;
+    a.ldc = P.ldc;
+    a.d = P.d;
+    a.cscale = P.cscale;
+    a.cmax = P.cmax;
+    a.K = (float)(1.4426950408889634 / eps);
+    a.inv_eps = (float)(1.0 / eps);
+    a.eps_df = split_df(eps);
+    a.eln2_df = split_df(eps * 0.6931471805599453);
+    a.tol = tol;
+    a.part = w.part;
+    a.cnt_cb = w.cnt_cb;
+    a.blk_err = w.blk_err;
+    a.blk_dot = w.blk_dot;
+    a.blk_max = w.blk_max;
+    a.st = w.st;
+  }
+
+  // g_out = T_c(U_in) on side Y (eq. foc_g), hat form
+  void sweep_col(const float2* Fin, int ma_in, const float2* Gold, float2* Gout, int dot_slot, int ma_out, int ell,
+                 const float* Vred, float* Wout, int wmode, int gate, int flags, int gsel_val = 0) {
+    SweepArgs a{};
+    fill_common(a);
+    a.n_out = P.m;
+    a.n_red = P.n;
+    a.Pred = P.X;
+    a.Pout = P.Y;
+    a.Uin = Fin;
+    a.ma_in = ma_in;
+    a.lw_out = w.lYdf;
+    a.w_out = w.wY32;
+    a.w_out64 = P.wY;
+    a.Uold = Gold;
+    a.Uout = Gout;
+    a.mdiff = nullptr;
+    a.dot_slot = dot_slot;
+    a.ma_out = ma_out;
+    a.ell = ell;
+    a.Vred = Vred;
+    a.Wout = Wout;
+    a.wmode = wmode;
+    a.gate = gate;
+    a.flags = flags;
+    a.gsel_val = gsel_val;
+    a.cnt_id = 0;
+    bool st = col_is_stream(P);
+    bool vec = stream_vec(P, a.n_out);
+    sweep_part_floats(a.n_out, a.n_red, ell, P.kind, P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
+    if (st) HIPCHK(launch_sweep_stream(a, P.kind, vec, s));
+    else HIPCHK(launch_sweep_rows(a, s));
+  }
+
+  // f_out = T_r(U_in) on side X (eq. foc_f)
+  void sweep_row(const float2* Gin, int ma_in, const float2* Fold, float2* Fout, float* mdiff, int dot_slot,
+                 int ma_out, int ell, const float* Vred, float* Wout, int wmode, int gate, int flags) {
+    SweepArgs a{};
+    fill_common(a);
+    a.n_out = P.n;
+    a.n_red = P.m;
+    a.Pred = P.Y;
+    a.Pout = P.X;
+    a.Uin = Gin;
+    a.ma_in = ma_in;
+    a.lw_out = w.lXdf;
+    a.w_out = w.wX32;
+    a.w_out64 = P.wX;
+    a.Uold = Fold;
+    a.Uout = Fout;
+    a.mdiff = mdiff;
+    a.dot_slot = dot_slot;
+    a.ma_out = ma_out;
+    a.ell = ell;
+    a.Vred = Vred;
+    a.Wout = Wout;
+    a.wmode = wmode;
+    a.gate = gate;
+    a.flags = flags;
+    a.cnt_id = 1;
+    bool st = row_is_stream(P);
+    bool vec = stream_vec(P, a.n_out);
+    sweep_part_floats(a.n_out, a.n_red, ell, P.kind, P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
+    if (st) HIPCHK(launch_sweep_stream(a, P.kind, vec, s));
+    else HIPCHK(launch_sweep_rows(a, s));
+  }
+
+  void init_state() {
+    DevState z{};
+    std::memcpy(c->st_host, &z, sizeof(DevState));
+    HIPCHK(hipMemcpyAsync(w.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  DevState read_state() {
+    HIPCHK(hipMemcpyAsync(c->st_host, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    DevState r;
+    std::memcpy(&r, c->st_host, sizeof(DevState));
+    return r;
+  }
+
+  // load FP64 potentials (engine orientation) into hat form
+  void load_f(const double* f /*nullable*/) {
+    HIPCHK(launch_to_hat(f, w.lX64, eps, w.F, P.n, w.st, MA_F, P.wX, DOT_F, w.scratch, s));
+  }
+  void load_g(const double* g, float2* dst, int ma, int dot) {
+    HIPCHK(launch_to_hat(g, w.lY64, eps, dst, P.m, w.st, ma, P.wY, dot, w.scratch, s));
+  }
+
+  // ---- Newton pieces for one iteration (after Gt, Fsk, mdiff, W exist)
+  void newton(int ell, int gate_base) {
+    HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
+                              w.st, gate_base, s));
+    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, eps, w.coef32, w.coef64, w.Gout, w.gout,
+                           w.st, gate_base, s));
+    HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.blk_dot, w.blk_max, w.st,
+                           gate_base | G_CHOL_OK, DOT_FP, MA_FP, s));
+  }
+
+  // One SK iteration (ping-pong on G[p]).
+  void sk_iter(int p) {
+    sweep_col(w.F, MA_F, w.G[p], w.G[1 - p], DOT_G, MA_G, 0, nullptr, nullptr, W_NONE, G_NOT_DONE,
+              F_CHECK | F_COUNT | F_GSEL, p);
+    sweep_row(w.G[1 - p], MA_G, nullptr, w.F, nullptr, DOT_F, MA_F, 0, nullptr, nullptr, W_NONE, G_NOT_DONE, 0);
+  }
+  // One SK-NR iteration; first == true skips the Newton step (first SK
+  // iteration of Algorithm 4.1 from f_0).
+  void sknr_iter(int ell, bool first) {
+    const int ellp = w.ellp;
+    sweep_col(w.F, MA_F, w.G[0], w.Gt, DOT_GT, MA_GT, first ? 0 : ellp, w.V, w.W, W_SCALE_WEIGHT, G_NOT_DONE,
+              F_CHECK | F_COUNT);
+    sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, G_NOT_DONE, 0);
+    if (!first) {
+      newton(ell, G_NOT_DONE);
+      sweep_col(w.Fp, MA_FP, nullptr, w.Gp, DOT_GP, MA_GP, 0, nullptr, nullptr, W_NONE, G_NOT_DONE | G_CHOL_OK,
+                F_ACCEPT_TEST);
+    }
+    HIPCHK(launch_select(w.Fp, w.Fsk, w.F, P.n, w.Gp, w.Gt, w.G[0], P.m, w.st, G_NOT_DONE, s));
+    if (!first)
+      sweep_row(w.G[0], MA_G, nullptr, w.F, nullptr, DOT_F, MA_F, 0, nullptr, nullptr, W_NONE,
+                G_NOT_DONE | G_ACCEPT, 0);
+  }
+
+  // Run one stage of Algorithm 4.1 from the current (F, G[0]); returns
+  // iterations and sets *converged.  G ends in w.G[0].
+  int run_stage(int ell, int max_iter, int check_every, bool resume, bool* converged, int* tried, int* accepted) {
+    init_state_keep();
+    int launched = 0;  // iterations launched (each = one column sweep)
+    int p = 0;
+    int chunk = check_every > 0 ? check_every : 4;
+    bool done = false;
+    DevState st{};
+    while (true) {
+      int remaining = max_iter + 1 - launched;  // +1: the final sweep only checks
+      if (remaining <= 0) break;
+      int k = std::min(chunk, remaining);
+      for (int t = 0; t < k; ++t) {
+        bool last_check_only = (launched == max_iter);
+        if (last_check_only) {
+          // the (max_iter+1)-th column sweep: convergence test of f_max_iter
+          sweep_col(w.F, MA_F, w.G[ell > 0 ? 0 : p], ell > 0 ? w.Gt : w.G[1 - p], ell > 0 ? DOT_GT : DOT_G,
+                    ell > 0 ? MA_GT : MA_G, 0, nullptr, nullptr, W_NONE, G_NOT_DONE, F_CHECK | F_COUNT | F_GSEL, p);
+        } else if (ell > 0) {
+          sknr_iter(ell, launched == 0 && !resume);
+        } else {
+          sk_iter(p);
+          p = 1 - p;
+        }
+        ++launched;
+      }
+      st = read_state();
+      if (st.done) {
+        done = true;
+        break;
+      }
+      if (check_every <= 0) chunk = std::min(chunk * 2, ell > 0 ? 16 : 64);
+    }
+    if (!done) st = read_state();
+    *converged = st.done != 0;
+    *tried = st.newton_tried;
+    *accepted = st.newton_accepted;
+    // bring g_k into G[0]
+    int gidx = ell > 0 ? 0 : (st.done ? st.gsel : p);
+    if (gidx != 0) HIPCHK(hipMemcpyAsync(w.G[0], w.G[gidx], sizeof(float2) * P.m, hipMemcpyDeviceToDevice, s));
+    return std::max(0, st.npass - 1);
+  }
+
+  // state re-initialisation that keeps the maxabs / dot slots of (F, G[0])
+  void init_state_keep() {
+    DevState cur = read_state();
+    DevState z{};
+    z.maxabs[MA_F] = cur.maxabs[MA_F];
+    z.maxabs[MA_G] = cur.maxabs[MA_G];
+    z.dots[DOT_F] = cur.dots[DOT_F];
+    z.dots[DOT_G] = cur.dots[DOT_G];
+    std::memcpy(c->st_host, &z, sizeof(DevState));
+    HIPCHK(hipMemcpyAsync(w.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+
+  // FP64 potentials in the caller's orientation -> f_out, g_out (device)
+  void export_fg(double* f_out, double* g_out) {
+    HIPCHK(launch_from_hat(w.F, w.lX64, eps, w.fX64, P.n, s));
+    HIPCHK(launch_from_hat(w.G[0], w.lY64, eps, w.gY64, P.m, s));
+    double* fo = P.transposed ? g_out : f_out;
+    double* go = P.transposed ? f_out : g_out;
+    HIPCHK(hipMemcpyAsync(fo, w.fX64, 8 * (size_t)P.n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(go, w.gY64, 8 * (size_t)P.m, hipMemcpyDeviceToDevice, s));
+  }
+
+  // FP64 evaluation in the caller's orientation
+  sknr_eval evaluate(const sknr_problem* pr, const double* f, const double* g) {
+    SweepArgs geo{};
+    geo.C = pr->C;
+    geo.ldc = pr->ldc;
+    geo.Pred = pr->x;
+    geo.Pout = pr->y;
+    geo.d = pr->d;
+    geo.cscale = P.cscale;
+    int nrb, ncb;
+    HIPCHK(launch_eval(geo, P.kind, f, g, pr->a, pr->b, eps, w.evrow, w.evcol, w.evscal, P.n0, P.m0, &nrb, &ncb, s));
+    HIPCHK(launch_eval_finish(w.evrow, w.evcol, w.evscal, pr->a, pr->b, P.n0, P.m0, nrb, ncb, w.evout, s));
+    HIPCHK(launch_dot64(f, pr->a, P.n0, w.evout + 8, s));
+    HIPCHK(launch_dot64(g, pr->b, P.m0, w.evout + 9, s));
+    double h[16];
+    HIPCHK(hipMemcpyAsync(h, w.evout, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    sknr_eval e{};
+    e.row_err = h[0];
+    e.col_err = h[1];
+    e.marginal_err = h[0] + h[1];
+    e.transport_cost = h[2];
+    e.mass = h[3];
+    e.dual_value = h[8] + h[9] - eps * (h[3] - 1.0);
+    e.primal_value = h[2] + eps * (h[4] - h[3] + 1.0);
+    return e;
+  }
+
+  void gauge(const sknr_problem* pr, double* f, double* g) {
+    HIPCHK(launch_dot64(f, pr->a, P.n0, w.evout + 10, s));
+    HIPCHK(launch_dot64(g, pr->b, P.m0, w.evout + 11, s));
+    HIPCHK(launch_shift64(f, P.n0, w.evout + 10, +1.0, s));
+    HIPCHK(launch_shift64(g, P.m0, w.evout + 10, -1.0, s));
+  }
+
+  // Spectral warm start (Sec. 4) at the current (F, eps): block subspace
+  // iteration on M = D_a^-1 P~ D_b^-1 P~^T, P~ = pi(f, f^{C,eps}), with a
+  // block of kp = pad(min(32, ell + oversample)) columns kept orthonormal in
+  // L2(a) and orthogonal to the constants (rho_0 = 1 is excluded), FP64
+  // Rayleigh-Ritz each iteration, stop when the leading ell Ritz values
+  // move by less than tol.  Leaves the Ritz vectors in w.Vw (n x kp,
+  // descending) and returns the iterations; lam gets the kp Ritz values.
+  int spectral(int ell, int oversample, int max_it, double tol, uint64_t seed, std::vector<double>* lam) {
+    int kp = ell_pad(std::min(32, ell + std::max(0, oversample)));
+    if (kp < ell_pad(ell)) kp = ell_pad(ell);
+    const int n = P.n, m = P.m;
+    const int nbn = std::min(64, std::max(1, (n + 255) / 256));
+    const int nbm = std::min(64, std::max(1, (m + 255) / 256));
+    if (w.have_Vw) HIPCHK(hipMemcpyAsync(w.Zw, w.Vw, sizeof(float) * (size_t)n * kp, hipMemcpyDeviceToDevice, s));
+    else HIPCHK(launch_random_block(kp, w.Zw, n, 0, seed, s));
+    std::vector<double> lp(kp, 0.0), lc(kp, 0.0);
+    int it = 0;
+    for (it = 1; it <= max_it; ++it) {
+      // V = orthonormalised (Z - 1 s^T) in L2(a)
+      HIPCHK(launch_wgram(kp, w.Zw, P.wX, 0, n, w.nrpart, nbn, s));
+      HIPCHK(launch_orth(kp, w.nrpart, nbn, w.Rw, w.sw, w.okw, s));
+      HIPCHK(launch_affine(kp, w.Zw, w.sw, w.Rw, nullptr, 0, n, w.Vw, s));
+      // U = P~^T V (and G~ = T_c(F))
+      sweep_col(w.F, MA_F, nullptr, w.Gt, DOT_GT, MA_GT, kp, w.Vw, w.Uw, W_SCALE_WEIGHT, 0, 0);
+      // Rayleigh-Ritz: T = U^T D_b^-1 U = V^T D_a M V
+      HIPCHK(launch_wgram(kp, w.Uw, P.wY, 1, m, w.nrpart, nbm, s));
+      HIPCHK(launch_jacobi(kp, w.nrpart, nbm, w.Qw, w.lamw, s));
+      HIPCHK(launch_affine(kp, w.Vw, nullptr, w.Qw, nullptr, 0, n, w.Zw, s));
+      std::swap(w.Vw, w.Zw);  // V <- V Q (Ritz vectors)
+      HIPCHK(launch_affine(kp, w.Uw, nullptr, w.Qw, P.wY, 1, m, w.Utw, s));  // D_b^-1 U Q
+      HIPCHK(hipMemcpyAsync(lc.data(), w.lamw, sizeof(double) * kp, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double dmax = 0;
+      for (int i = 0; i < ell; ++i) dmax = std::max(dmax, std::fabs(lc[i] - lp[i]));
+      lp = lc;
+      if (it >= 2 && dmax < tol) break;
+      if (it == max_it) break;
+      // Z = M V = D_a^-1 P~ (D_b^-1 U Q)
+      sweep_row(w.Gt, MA_GT, w.F, w.Fsk, nullptr, DOT_FSK, MA_FSK, kp, w.Utw, w.Zw, W_SCALE_RATIO, 0, 0);
+    }
+    w.have_Vw = true;
+    if (lam) *lam = lc;
+    return std::min(it, max_it);
+  }
+  int spectral_kp(int ell, int oversample) const {
+    int kp = ell_pad(std::min(32, ell + std::max(0, oversample)));
+    return std::max(kp, ell_pad(ell));
+  }
+  // Newton basis from the warm-start block: first ell columns, padded
+  void use_warm_V(int ell, int oversample) {
+    HIPCHK(launch_repack(w.Vw, spectral_kp(ell, oversample), P.n, ell, w.ellp, w.V, s));
+  }
+
+  // V (engine orientation, n x ell FP64 device) -> padded FP32 V
+  void load_V(const double* V, int ell) {
+    std::vector<double> hv((size_t)P.n * ell);
+    HIPCHK(hipMemcpyAsync(hv.data(), V, 8 * hv.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<float> pv((size_t)P.n * w.ellp, 0.f);
+    for (int i = 0; i < P.n; ++i)
+      for (int l = 0; l < ell; ++l) pv[(size_t)i * w.ellp + l] = (float)hv[(size_t)i * ell + l];
+    HIPCHK(hipMemcpyAsync(w.V, pv.data(), 4 * pv.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+};
+
+Prepared prepare_caller_orientation(const sknr_problem* prob, hipStream_t s) {
+  Prepared P = prepare(prob, s);
+  if (P.transposed) {
+    P.transposed = false;
+    P.n = P.n0;
+    P.m = P.m0;
+    P.ctrans = false;
+    P.X = prob->x;
+    P.Y = prob->y;
+    P.wX = prob->a;
+    P.wY = prob->b;
+    std::swap(P.hX, P.hY);
+  }
+  return P;
+}
+
+hipStream_t as_stream(void* p) { return reinterpret_cast<hipStream_t>(p); }
+
+template <typename Fn>
+int guarded(Fn fn) {
+  try {
+    return fn();
+  } catch (const Err& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return SKNR_EINTERNAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return SKNR_EINTERNAL;
+  }
+}
+
+Ctx* as_ctx(void* p) {
+  if (!p) throw Err{SKNR_EINVAL, "context is NULL"};
+  Ctx* c = reinterpret_cast<Ctx*>(p);
+  HIPCHK(hipSetDevice(c->device));
+  return c;
+}
+
+void check_eps(double eps) { REQUIRE(eps > 0 && std::isfinite(eps), "eps must be positive and finite"); }
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* sknr_version(void) { return "sknr 0.1 (gfx950)"; }
+
+const char* sknr_status_str(int status) {
+  switch (status) {
+    case SKNR_OK: return "ok";
+    case SKNR_NOT_CONVERGED: return "not converged (tolerance not reached within max_iter)";
+    case SKNR_EINVAL: return "invalid argument";
+    case SKNR_ENOMEM: return "out of device memory or over budget";
+    case SKNR_EDEVICE: return "HIP runtime error";
+    case SKNR_EBUSY: return "busy";
+    case SKNR_ECANCELED: return "cancelled";
+    case SKNR_EINTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+const char* sknr_last_error(void) { return g_last_error.c_str(); }
+
+int sknr_ctx_create(int device, uint64_t hbm_budget_bytes, void** out) {
+  return guarded([&]() -> int {
+    REQUIRE(out, "out is NULL");
+    int cnt = 0;
+    HIPCHK(hipGetDeviceCount(&cnt));
+    REQUIRE(device >= 0 && device < cnt, "no such device");
+    HIPCHK(hipSetDevice(device));
+    Ctx* c = new Ctx();
+    c->device = device;
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * fr);
+    HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault));
+    *out = c;
+    return SKNR_OK;
+  });
+}
+
+int sknr_ctx_destroy(void* ctx) {
+  return guarded([&]() -> int {
+    if (!ctx) return SKNR_OK;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipDeviceSynchronize());
+    if (c->arena.base) HIPCHK(hipFree(c->arena.base));
+    if (c->st_host) HIPCHK(hipHostFree(c->st_host));
+    delete c;
+    return SKNR_OK;
+  });
+}
+
+int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts, double* f_out, double* g_out,
+               sknr_result* res) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    REQUIRE(opts && res && f_out && g_out, "opts, res, f_out, g_out are required");
+    REQUIRE(opts->n_eps >= 1 && opts->n_eps <= SKNR_MAX_STAGES && opts->eps, "eps schedule length out of range");
+    for (int s = 0; s < opts->n_eps; ++s) check_eps(opts->eps[s]);
+    REQUIRE(opts->tol > 0 && std::isfinite(opts->tol), "tol must be positive");
+    REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
+    REQUIRE(opts->ell >= 0 && opts->ell <= SKNR_MAX_ELL, "ell out of range");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = as_stream(opts->stream);
+    Prepared P = prepare(prob, s);
+    REQUIRE(opts->ell < std::min(P.n0, P.m0), "ell must be < min(n, m)");
+    if (opts->ell > 0) {
+      REQUIRE(opts->warm_mode == SKNR_WARM_USER || opts->warm_mode == SKNR_WARM_SEQUENTIAL ||
+                  opts->warm_mode == SKNR_WARM_STATIC, "unknown warm_mode");
+      if (opts->warm_mode == SKNR_WARM_USER) {
+        REQUIRE(opts->V0, "WARM_USER needs V0");
+        REQUIRE(!P.transposed, "WARM_USER needs n <= m");
+      }
+      if (opts->warm_mode == SKNR_WARM_STATIC) check_eps(opts->eps_prime);
+      REQUIRE(!opts->first_stage_nr || opts->warm_mode != SKNR_WARM_SEQUENTIAL,
+              "first_stage_nr needs WARM_USER or WARM_STATIC");
+    }
+    if (opts->f0) REQUIRE(!P.transposed, "f0 needs n <= m");
+    int ellp = ell_pad(opts->ell);
+    WS w = make_ws(c, P, ellp, s);
+    Engine E(c, P, w, s);
+    const int eig_os = opts->eig_oversample > 0 ? opts->eig_oversample : 8;
+    const int eig_it = opts->eig_max_iter > 0 ? opts->eig_max_iter : 200;
+    const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 1e-9;
+    std::memset(res, 0, sizeof(*res));
+    E.tol = opts->tol;
+    int static_eig_iters = 0;
+    if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) {
+      // plain SK at eps' from the initial potential, then V_l once
+      E.eps = opts->eps_prime;
+      E.init_state();
+      E.load_f(opts->f0);
+      E.load_g(nullptr, w.G[0], MA_G, DOT_G);
+      bool cv;
+      int tr, ac;
+      E.run_stage(0, opts->max_iter, opts->check_every, false, &cv, &tr, &ac);
+      static_eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed, nullptr);
+      E.use_warm_V(opts->ell, eig_os);
+    }
+    E.eps = opts->eps[0];
+    E.init_state();
+    E.load_f(opts->f0);
+    E.load_g(nullptr, w.G[0], MA_G, DOT_G);
+    if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_USER) E.load_V(opts->V0, opts->ell);
+    res->n_stages = opts->n_eps;
+    res->transposed = P.transposed ? 1 : 0;
+    int status = SKNR_OK;
+    for (int st = 0; st < opts->n_eps; ++st) {
+      auto ts = std::chrono::steady_clock::now();
+      double eps = opts->eps[st];
+      int eig_iters = 0;
+      if (st > 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_SEQUENTIAL) {
+        // V_l from the optimum of the previous stage (its eps), Sec. 4
+        eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed + st, nullptr);
+        E.use_warm_V(opts->ell, eig_os);
+      }
+      if (st == 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) eig_iters = static_eig_iters;
+      if (st > 0) {
+        double de = eps - E.eps;
+        E.init_state();
+        HIPCHK(launch_rebase(w.F, w.lXdf, split_df(de), P.n, w.st, MA_F, s));
+        HIPCHK(launch_rebase(w.G[0], w.lYdf, split_df(de), P.m, w.st, MA_G, s));
+        E.eps = eps;
+      }
+      bool use_nr = opts->ell > 0 && (st > 0 || opts->first_stage_nr);
+      bool conv = false;
+      int tried = 0, acc = 0, it = 0;
+      sknr_eval ev{};
+      // The sweeps estimate the error in FP32 (column marginal via the next
+      // c-transform); the FP64 check decides.  If it disagrees, continue
+      // the stage with a tighter FP32 threshold.
+      E.tol = opts->tol;
+      for (int attempt = 0; attempt < 8; ++attempt) {
+        int tr = 0, ac = 0;
+        bool cv = false;
+        it += E.run_stage(use_nr ? opts->ell : 0, opts->max_iter - it, opts->check_every, attempt > 0, &cv, &tr, &ac);
+        tried += tr;
+        acc += ac;
+        E.export_fg(f_out, g_out);
+        ev = E.evaluate(prob, f_out, g_out);
+        conv = cv && ev.marginal_err < opts->tol;
+        if (conv || !cv || it >= opts->max_iter) break;
+        E.tol = E.tol * std::min(0.9, opts->tol / ev.marginal_err);
+      }
+      if (!conv) status = SKNR_NOT_CONVERGED;
+      sknr_stage_stats& ss = res->stage[st];
+      ss.eps = eps;
+      ss.iters = it;
+      ss.newton_tried = tried;
+      ss.newton_accepted = acc;
+      ss.eig_iters = eig_iters;
+      ss.marginal_err = ev.marginal_err;
+      ss.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+      res->total_iters += it;
+      if (st == opts->n_eps - 1) {
+        E.gauge(prob, f_out, g_out);
+        res->marginal_err = ev.marginal_err;
+        res->row_err = ev.row_err;
+        res->col_err = ev.col_err;
+        res->transport_cost = ev.transport_cost;
+        res->dual_value = ev.dual_value;
+        res->primal_value = ev.primal_value;
+        res->mass = ev.mass;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    res->status = status;
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+  });
+}
+
+int sknr_c_transform_col(void* ctx, const sknr_problem* prob, double eps, const double* f, const double* g_prev,
+                         double* g_out, double* err_out, double* gdot_out, void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(f && g_out, "f and g_out are required");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    WS w = make_ws(c, P, 0, s);
+    Engine E(c, P, w, s);
+    E.eps = eps;
+    E.init_state();
+    E.load_f(f);
+    if (g_prev) E.load_g(g_prev, w.G[1], MA_G2, DOT_TMP);
+    E.sweep_col(w.F, MA_F, g_prev ? w.G[1] : nullptr, w.G[0], DOT_G, MA_G, 0, nullptr, nullptr, W_NONE, 0, 0);
+    HIPCHK(launch_from_hat(w.G[0], w.lY64, eps, g_out, P.m, s));
+    DevState st = E.read_state();
+    if (err_out) *err_out = g_prev ? st.err : 0.0;
+    if (gdot_out) {
+      double h;
+      HIPCHK(launch_dot64(g_out, prob->b, P.m, w.evout, s));
+      HIPCHK(hipMemcpyAsync(&h, w.evout, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      *gdot_out = h;
+    }
+    return SKNR_OK;
+  });
+}
+
+int sknr_c_transform_row(void* ctx, const sknr_problem* prob, double eps, const double* g, double* f_out,
+                         void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(g && f_out, "g and f_out are required");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    WS w = make_ws(c, P, 0, s);
+    Engine E(c, P, w, s);
+    E.eps = eps;
+    E.init_state();
+    E.load_g(g, w.G[0], MA_G, DOT_G);
+    E.sweep_row(w.G[0], MA_G, nullptr, w.F, nullptr, DOT_F, MA_F, 0, nullptr, nullptr, W_NONE, 0, 0);
+    HIPCHK(launch_from_hat(w.F, w.lX64, eps, f_out, P.n, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SKNR_OK;
+  });
+}
+
+int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps, const double* f, const double* V,
+                          int32_t ell, double* G_out, double* grad_out, double* qsemi_out, void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(f && V && ell >= 1 && ell <= SKNR_MAX_ELL, "f, V and 1 <= ell <= 32 are required");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    int ellp = ell_pad(ell);
+    WS w = make_ws(c, P, ellp, s);
+    Engine E(c, P, w, s);
+    E.eps = eps;
+    E.init_state();
+    E.load_f(f);
+    E.load_V(V, ell);
+    E.sweep_col(w.F, MA_F, nullptr, w.Gt, DOT_GT, MA_GT, ellp, w.V, w.W, W_SCALE_WEIGHT, 0, 0);
+    E.sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, 0, 0);
+    HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
+                              w.st, 0, s));
+    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, eps, w.coef32, w.coef64, w.Gout, w.gout,
+                           w.st, 0, s));
+    std::vector<double> hG((size_t)ell * ell), hg(ell);
+    HIPCHK(hipMemcpyAsync(hG.data(), w.Gout, 8 * hG.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hg.data(), w.gout, 8 * hg.size(), hipMemcpyDeviceToHost, s));
+    DevState st = E.read_state();
+    if (G_out) std::memcpy(G_out, hG.data(), 8 * hG.size());
+    if (grad_out) std::memcpy(grad_out, hg.data(), 8 * hg.size());
+    if (qsemi_out) {
+      // <f,a> + <g~,b> in paper convention: hat dots minus eps (<log a,a> + <log b,b>)
+      double ca = 0, cb = 0;
+      for (int i = 0; i < P.n; ++i) ca += P.hX[i] * std::log(P.hX[i]);
+      for (int j = 0; j < P.m; ++j) cb += P.hY[j] * std::log(P.hY[j]);
+      *qsemi_out = st.dots[DOT_F] + st.dots[DOT_GT] - eps * (ca + cb);
+    }
+    return SKNR_OK;
+  });
+}
+
+int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps, double* f_inout, const double* V, int32_t ell,
+                     int32_t* accepted, double* q0, double* q1, void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(f_inout && V && ell >= 1 && ell <= SKNR_MAX_ELL, "f, V and 1 <= ell <= 32 are required");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    int ellp = ell_pad(ell);
+    WS w = make_ws(c, P, ellp, s);
+    Engine E(c, P, w, s);
+    E.eps = eps;
+    E.init_state();
+    E.load_f(f_inout);
+    E.load_V(V, ell);
+    E.sweep_col(w.F, MA_F, nullptr, w.Gt, DOT_GT, MA_GT, ellp, w.V, w.W, W_SCALE_WEIGHT, 0, 0);
+    E.sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, 0, 0);
+    E.newton(ell, 0);
+    E.sweep_col(w.Fp, MA_FP, nullptr, w.Gp, DOT_GP, MA_GP, 0, nullptr, nullptr, W_NONE, G_CHOL_OK, F_ACCEPT_TEST);
+    DevState st = E.read_state();
+    double ca = 0, cb = 0;
+    for (int i = 0; i < P.n; ++i) ca += P.hX[i] * std::log(P.hX[i]);
+    for (int j = 0; j < P.m; ++j) cb += P.hY[j] * std::log(P.hY[j]);
+    if (q0) *q0 = st.dots[DOT_F] + st.dots[DOT_GT] - eps * (ca + cb);
+    if (q1) *q1 = st.chol_ok ? st.dots[DOT_FP] + st.dots[DOT_GP] - eps * (ca + cb) : NAN;
+    if (accepted) *accepted = st.accept;
+    if (st.accept) HIPCHK(launch_from_hat(w.Fp, w.lX64, eps, f_inout, P.n, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SKNR_OK;
+  });
+}
+
+int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps, const double* f, const double* g, sknr_eval* out,
+                  void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(f && g && out, "f, g, out are required");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    WS w = make_ws(c, P, 0, s);
+    Engine E(c, P, w, s);
+    E.eps = eps;
+    *out = E.evaluate(prob, f, g);
+    return SKNR_OK;
+  });
+}
+
+int sknr_coupling(void* ctx, const sknr_problem* prob, double eps, const double* f, const double* g, float* P_out,
+                  void* stream) {
+  return guarded([&]() -> int {
+    as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(f && g && P_out, "f, g, P_out are required");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    SweepArgs geo{};
+    geo.C = prob->C;
+    geo.ldc = prob->ldc;
+    geo.Pred = prob->x;
+    geo.Pout = prob->y;
+    geo.d = prob->d;
+    geo.cscale = P.cscale;
+    HIPCHK(launch_coupling(geo, P.kind, f, g, prob->a, prob->b, eps, P_out, P.n0, P.m0, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SKNR_OK;
+  });
+}
+
+int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps, const double* f, int32_t ell,
+                        int32_t oversample, int32_t max_iter, double tol, uint64_t seed, double* V_out,
+                        double* rho_out, int32_t* iters_out, void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(f && V_out && rho_out, "f, V_out, rho_out are required");
+    REQUIRE(ell >= 1 && ell <= SKNR_MAX_ELL, "1 <= ell <= 32 required");
+    REQUIRE(max_iter >= 1 && tol > 0, "max_iter >= 1 and tol > 0 required");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    REQUIRE(ell < std::min(P.n, P.m), "ell must be < min(n, m)");
+    WS w = make_ws(c, P, ell_pad(ell), s);
+    Engine E(c, P, w, s);
+    E.eps = eps;
+    E.init_state();
+    E.load_f(f);
+    std::vector<double> lam;
+    int it = E.spectral(ell, oversample, max_iter, tol, seed, &lam);
+    int kp = E.spectral_kp(ell, oversample);
+    HIPCHK(launch_take_cols(w.Vw, kp, P.n, ell, V_out, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rho_out[0] = 1.0;
+    for (int i = 0; i < ell; ++i) rho_out[i + 1] = std::sqrt(std::max(0.0, lam[i]));
+    if (iters_out) *iters_out = it;
+    return SKNR_OK;
+  });
+}
+
+}  // extern "C"

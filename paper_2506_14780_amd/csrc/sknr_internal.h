@@ -1,0 +1,155 @@
+// Internal declarations shared by the HIP kernels and the host engine of
+// libsknr.  Not part of the public ABI (include/sknr.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sknr {
+
+// ----------------------------------------------------------------- state
+// Small device-resident control block of one solver instance.  Kernels of
+// one iteration read the gating flags at entry and the "last block" of a
+// sweep updates the scalars, so a whole chunk of iterations can be queued
+// (or captured in a graph) without host round trips.
+enum DotSlot { DOT_F = 0, DOT_G = 1, DOT_GT = 2, DOT_FSK = 3, DOT_FP = 4, DOT_GP = 5, DOT_TMP = 6, NDOT = 8 };
+enum MaxSlot { MA_F = 0, MA_G = 1, MA_GT = 2, MA_FSK = 3, MA_FP = 4, MA_GP = 5, MA_G2 = 6, NMA = 8 };
+
+struct DevState {
+  int done;             // stage converged: every gated kernel returns at entry
+  int npass;            // column sweeps executed in this stage
+  int armed;            // the next checking sweep may declare convergence
+  int accept;           // last Newton candidate accepted
+  int chol_ok;          // last projected system factorised
+  int newton_tried;
+  int newton_accepted;
+  int gsel;             // SK ping-pong: which g buffer holds g_k at convergence
+  double err;           // last L1 marginal error estimate (output side)
+  double err_aux;       // sum |mdiff| of the last row sweep (row marginal of P~)
+  double dots[NDOT];    // <U, w> of hat potentials (FP64 sums)
+  float maxabs[NMA];    // max |U.hi| of hat potentials (for the Fast2Sum offset)
+  unsigned cnt[8];      // global "last block" counters, one per sweep kind
+  int pad[8];
+};
+
+// gating bits: a kernel returns immediately unless all requested hold
+enum Gate { G_NOT_DONE = 1, G_CHOL_OK = 2, G_ACCEPT = 4, G_NOT_ACCEPT = 8 };
+// sweep flags
+enum SweepFlag {
+  F_CHECK = 1,       // compare the L1 error with tol and set done (col sweeps)
+  F_COUNT = 2,       // count this sweep in npass
+  F_GSEL = 4,        // record gsel_val into state->gsel when setting done
+  F_ACCEPT_TEST = 8  // after this sweep decide the Newton acceptance test
+};
+enum WMode { W_NONE = 0, W_SCALE_WEIGHT = 1, W_SCALE_RATIO = 2 };
+
+// ---------------------------------------------------------- sweep arguments
+// One c-transform sweep: out_o = eps*lw_o - eps*log sum_r exp((Uin_r - C_ro)/eps)
+// over the "reduce" side r, for every "output" o, with hat potentials
+// U = potential + eps*log(weight) kept as (hi, lo) float pairs.
+struct SweepArgs {
+  int n_out, n_red;
+  // cost: STORED element (r, o) is C[r*ldc + o] for the streaming kernel
+  // (output = columns of C) and C[o*ldc + r] for the row kernel.
+  const float* C;
+  long long ldc;
+  // point clouds (SQEUCLID): reduce-side points and output-side points
+  const float* Pred;
+  const float* Pout;
+  int d;
+  float cscale;
+  float cmax;            // upper bound of |C| (Fast2Sum offset)
+  // potentials
+  const float2* Uin;     // reduce-side hat potential (n_red)
+  int ma_in;             // maxabs slot of Uin
+  const float2* lw_out;  // output-side log weights (double-float)
+  const float* w_out;    // output-side weights FP32
+  const double* w_out64; // output-side weights FP64 (dots)
+  const float2* Uold;    // previous output-side hat potential (error / ratio) or null
+  float2* Uout;          // new output-side hat potential
+  float* mdiff;          // optional: w_o * expm1((Uold_o - Uout_o)/eps)
+  int dot_slot;          // slot for <Uout, w_out> (or -1)
+  int ma_out;            // slot for max|Uout.hi| (or -1)
+  // weighted averages (l-wide): Wout_o = scale_o * sum_r P_ro V_r / sum_r P_ro
+  int ell;               // 0 or the compile-time width
+  const float* Vred;     // n_red x ell, row-major
+  float* Wout;           // n_out x ell
+  int wmode;
+  // constants
+  float K;               // log2(e)/eps
+  float inv_eps;
+  float2 eps_df;         // eps as double-float
+  float2 eln2_df;        // eps*ln2 as double-float
+  double tol;
+  // split-K bookkeeping
+  int nsplit;
+  int rows_per_split;
+  float* part;           // [nsplit][3+ell][n_out]
+  unsigned* cnt_cb;      // per column block counters (zeroed, self-resetting)
+  double* blk_err;       // per output-block partial scalars
+  double* blk_dot;
+  float* blk_max;
+  int nblk;              // number of output blocks
+  int cnt_id;            // which global counter
+  DevState* st;
+  int gate;
+  int flags;
+  int gsel_val;
+};
+
+// ----------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return hipSuccess or the launch error.
+// vec: the stored cost allows float4 access along the output axis
+hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t stream);
+hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t stream);
+size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bool vec, int* nsplit, int* rps,
+                         int* nblk, bool stream_kernel);
+
+// conversions between FP64 paper-convention potentials and hat double-floats
+hipError_t launch_to_hat(const double* f, const double* logw, double eps, float2* U, int n,
+                         DevState* st, int ma_slot, const double* w, int dot_slot, double* scratch, hipStream_t s);
+hipError_t launch_from_hat(const float2* U, const double* logw, double eps, double* f, int n, hipStream_t s);
+hipError_t launch_rebase(float2* U, const float2* lw, float2 deps_df, int n, DevState* st, int ma, hipStream_t s);
+hipError_t launch_copy_state_slot(DevState* st, int dst_dot, int src_dot, int dst_ma, int src_ma, hipStream_t s);
+
+// Newton step pieces (FP64 small system)
+hipError_t launch_nr_assemble(int ell, const float* V, const float* rdiff, const double* a, int n,
+                              const float* W, const double* b, int m, double* part, int nrow_blk,
+                              int ncol_blk, DevState* st, int gate, hipStream_t s);
+hipError_t launch_nr_solve(int ell, const double* part, int nblk, double eps, float* coef32,
+                           double* coef64, double* Gout, double* gout, DevState* st, int gate,
+                           hipStream_t s);
+hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a,
+                           float2* Fp, int n, double* blk, float* blkmax, DevState* st, int gate,
+                           int dot_slot, int ma_slot, hipStream_t s);
+hipError_t launch_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp,
+                         const float2* Gt, float2* G, int m, DevState* st, int gate, hipStream_t s);
+
+// FP64 evaluation (final check)
+hipError_t launch_eval(const SweepArgs& geo, int cost_kind, const double* f, const double* g,
+                       const double* a, const double* b, double eps, double* rowpart, double* colpart,
+                       double* scal, int n, int m, int* nrb, int* ncb, hipStream_t s);
+hipError_t launch_eval_finish(const double* rowpart, const double* colpart, const double* scal,
+                              const double* a, const double* b, int n, int m, int nrb, int ncb,
+                              double* out8, hipStream_t s);
+
+// spectral warm start: block subspace iteration helpers (k = kp <= 32)
+hipError_t launch_wgram(int kp, const float* Z, const double* w, int invert, int n, double* part, int nblk,
+                        hipStream_t s);
+hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok, hipStream_t s);
+hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, hipStream_t s);
+hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
+                         int n, float* out, hipStream_t s);
+hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, hipStream_t s);
+hipError_t launch_take_cols(const float* V, int kp, int n, int ell, double* out, hipStream_t s);
+hipError_t launch_repack(const float* V, int kp, int n, int ell, int ellp, float* out, hipStream_t s);
+hipError_t launch_f32_to_f64(const float* src, double* dst, long long count, hipStream_t s);
+hipError_t launch_f64_to_f32(const double* src, float* dst, long long count, hipStream_t s);
+hipError_t launch_coupling(const SweepArgs& geo, int cost_kind, const double* f, const double* g,
+                           const double* a, const double* b, double eps, float* P, int n, int m,
+                           hipStream_t s);
+hipError_t launch_dot64(const double* x, const double* w, int n, double* out, hipStream_t s);
+hipError_t launch_shift64(double* x, int n, const double* dots, double sign, hipStream_t s);
+hipError_t launch_cost_max(int cost_kind, const float* C, long long ldc, int n, int m, const float* x,
+                           const float* y, int d, float* out2, hipStream_t s);
+
+}  // namespace sknr

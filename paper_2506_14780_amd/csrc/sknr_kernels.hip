@@ -1,0 +1,1297 @@
+// HIP kernels of libsknr for gfx950 (MI355X).
+//
+// The hot path is the c-transform sweep (paper Sec. 2, eq. foc_f / foc_g):
+//   out_o = eps*log(w_o) - eps*log sum_r exp((U_r - C_ro)/eps),
+// with hat potentials U = potential + eps*log(weight), so that the weights
+// fold into the exponent.  A sweep reads (or builds) every cost element once
+// and runs an online max-shifted log-sum-exp in FP32.  Precision (the FP32
+// exponent (U_r - C_ro)/eps cancels O(|C|) terms down to O(eps)) is kept by:
+//   * double-float potentials (hi, lo FP32 pairs);
+//   * an exact subtraction U_r - C_ro: Fast2Sum after offsetting U by a
+//     constant L >= |C| (streaming sweep) or TwoSum (row sweep of a stored
+//     cost), the error term joining the small argument;
+//   * compensated accumulation of the exponentials and of the split merges;
+//   * log of the sum split into exponent + log2 of the mantissa.
+// Everything else (cross-block merges, epilogues) works on O(n + m) data.
+#include "sknr_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace sknr {
+
+#define SIG0 (-3.0e38f)
+constexpr int TPB = 256;
+constexpr int WAVES = TPB / 64;
+
+// ------------------------------------------------------- double-float
+__device__ __forceinline__ float2 two_sum(float a, float b) {
+  float s = a + b;
+  float bb = s - a;
+  float e = (a - (s - bb)) + (b - bb);
+  return make_float2(s, e);
+}
+__device__ __forceinline__ float2 fast_two_sum(float a, float b) {
+  float s = a + b;
+  float e = b - (s - a);
+  return make_float2(s, e);
+}
+__device__ __forceinline__ float2 df_add(float2 a, float2 b) {
+  float2 s = two_sum(a.x, b.x);
+  float2 t = two_sum(a.y, b.y);
+  s.y += t.x;
+  s = fast_two_sum(s.x, s.y);
+  s.y += t.y;
+  return fast_two_sum(s.x, s.y);
+}
+__device__ __forceinline__ float2 df_add_f(float2 a, float b) {
+  float2 s = two_sum(a.x, b);
+  s.y += a.y;
+  return fast_two_sum(s.x, s.y);
+}
+__device__ __forceinline__ float2 df_mul(float2 a, float2 b) {
+  float p = a.x * b.x;
+  float e = fmaf(a.x, b.x, -p);
+  e = fmaf(a.x, b.y, e);
+  e = fmaf(a.y, b.x, e);
+  return fast_two_sum(p, e);
+}
+__device__ __forceinline__ float2 df_neg(float2 a) { return make_float2(-a.x, -a.y); }
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
+
+__device__ __forceinline__ bool gate_closed(const DevState* st, int gate) {
+  if (!gate) return false;
+  const volatile DevState* v = st;
+  if ((gate & G_NOT_DONE) && v->done) return true;
+  if ((gate & G_CHOL_OK) && !v->chol_ok) return true;
+  if ((gate & G_ACCEPT) && !v->accept) return true;
+  if ((gate & G_NOT_ACCEPT) && v->accept) return true;
+  return false;
+}
+
+// squared distance in the fixed order k = 0..d-1 (the defined FP32 cost;
+// symmetric in its arguments bit for bit since (p-q)^2 == (q-p)^2)
+template <int D>
+__device__ __forceinline__ float sqdist(const float* p, const float* q) {
+  float t = p[0] - q[0];
+  float acc = t * t;
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    t = p[k] - q[k];
+    acc = fmaf(t, t, acc);
+  }
+  return acc;
+}
+__device__ __forceinline__ float sqdist_rt(const float* p, const float* q, int d) {
+  float t = p[0] - q[0];
+  float acc = t * t;
+  for (int k = 1; k < d; ++k) {
+    t = p[k] - q[k];
+    acc = fmaf(t, t, acc);
+  }
+  return acc;
+}
+
+// ------------------------------------------------------ block reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+// deterministic block sum (fixed tree): result valid in thread 0
+__device__ __forceinline__ double block_sum_d(double v, double* sbuf) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sbuf[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sbuf[i];
+  }
+  return r;
+}
+__device__ __forceinline__ float block_max_f(float v, float* sbuf) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sbuf[w] = v;
+  __syncthreads();
+  float r = 0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = fmaxf(r, sbuf[i]);
+  }
+  return r;
+}
+
+__device__ __forceinline__ unsigned atomic_ticket(unsigned* p) {
+  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ----------------------------------------------------- LSE state merging
+// (sig, S, Sc): the partial sum  sum exp2((t - sig)*K) = S + Sc.
+__device__ __forceinline__ void lse_merge(float& sig, float& S, float& Sc, float sig2, float S2, float Sc2,
+                                          float K, float& f1, float& f2) {
+  float mx = fmaxf(sig, sig2);
+  f1 = ex2((sig - mx) * K);
+  f2 = ex2((sig2 - mx) * K);
+  float p1 = S * f1, p2 = S2 * f2;
+  float e1 = fmaf(S, f1, -p1), e2 = fmaf(S2, f2, -p2);
+  float2 s = two_sum(p1, p2);
+  Sc = fmaf(Sc, f1, fmaf(Sc2, f2, e1 + e2 + s.y));
+  S = s.x;
+  sig = mx;
+}
+
+// Finalise one output of a sweep from its merged (sig, S, Sc) and write the
+// potential, the marginal-ratio term and the weighted average.
+// Returns |mdiff| (error contribution), accumulates dot and max.
+template <int ELL>
+__device__ __forceinline__ void finalize_output(const SweepArgs& A, int o, float L, float sig, float S, float Sc,
+                                                const float* acc, double& err, double& dot, float& mx) {
+  // log2(S + Sc) = k + log2(mant) + Sc/(S ln 2), S = mant * 2^k, mant in [0.5, 1)
+  int k;
+  float mant = frexpf(S, &k);
+  float lm = lg2(mant);
+  float corr = (Sc / S) * 1.4426950408889634f;
+  float2 l2 = fast_two_sum((float)k, lm);
+  l2.y += corr;
+  float2 t = df_mul(A.eln2_df, l2);
+  float2 out = df_mul(A.eps_df, A.lw_out[o]);
+  out = df_add_f(out, -sig);
+  out = df_add_f(out, L);
+  out = df_add(out, df_neg(t));
+  A.Uout[o] = out;
+  float ratio_m1 = 0.f;
+  if (A.Uold) {
+    float2 dlt = df_add(A.Uold[o], df_neg(out));
+    ratio_m1 = expm1f((dlt.x + dlt.y) * A.inv_eps);
+    float md = A.w_out[o] * ratio_m1;
+    if (A.mdiff) A.mdiff[o] = md;
+    err += fabs((double)md);
+  }
+  dot += A.w_out64[o] * ((double)out.x + (double)out.y);
+  mx = fmaxf(mx, fabsf(out.x));
+  if (ELL > 0) {
+    float inv = 1.f / (S + Sc);
+    float scale = A.wmode == W_SCALE_WEIGHT ? A.w_out[o] : (A.wmode == W_SCALE_RATIO ? 1.f + ratio_m1 : 1.f);
+    scale *= inv;
+#pragma unroll
+    for (int l = 0; l < ELL; ++l) A.Wout[(size_t)o * ELL + l] = acc[l] * scale;
+  }
+}
+
+// Global "last block" reduction of the per-block scalars and the state
+// update.  Called by every block after its own outputs are written; (err,
+// dot, mx) are valid in thread 0.
+__device__ void finish_global(const SweepArgs& A, int bid, double err, double dot, float mx, double* sbd,
+                              float* sbf) {
+  __shared__ unsigned s_ticket;
+  if (threadIdx.x == 0) {
+    A.blk_err[bid] = err;
+    A.blk_dot[bid] = dot;
+    A.blk_max[bid] = mx;
+    __threadfence();
+    s_ticket = atomic_ticket(&A.st->cnt[A.cnt_id]);
+  }
+  __syncthreads();
+  if (s_ticket != (unsigned)(A.nblk - 1)) return;
+  __threadfence();
+  double e = 0, d = 0;
+  float m = 0;
+  for (int b = threadIdx.x; b < A.nblk; b += blockDim.x) {
+    e += __builtin_nontemporal_load(&A.blk_err[b]);
+    d += __builtin_nontemporal_load(&A.blk_dot[b]);
+    m = fmaxf(m, __builtin_nontemporal_load(&A.blk_max[b]));
+  }
+  e = block_sum_d(e, sbd);
+  d = block_sum_d(d, sbd + 8);
+  m = block_max_f(m, sbf);
+  if (threadIdx.x == 0) {
+    DevState* st = A.st;
+    st->cnt[A.cnt_id] = 0;
+    if (A.Uold) {
+      if (A.mdiff) st->err_aux = e; else st->err = e;
+    }
+    if (A.dot_slot >= 0) st->dots[A.dot_slot] = d;
+    if (A.ma_out >= 0) st->maxabs[A.ma_out] = m;
+    if (A.flags & F_COUNT) st->npass += 1;
+    if (A.flags & F_CHECK) {
+      if (st->armed && e < A.tol) {
+        st->done = 1;
+        if (A.flags & F_GSEL) st->gsel = A.gsel_val;
+      }
+      st->armed = 1;
+    }
+    if (A.flags & F_ACCEPT_TEST) {
+      double q1 = st->dots[DOT_FP] + st->dots[DOT_GP];
+      double q0 = st->dots[DOT_F] + st->dots[DOT_GT];
+      int acc = (st->chol_ok && q1 > q0) ? 1 : 0;
+      st->accept = acc;
+      st->newton_accepted += acc;
+    }
+    __threadfence();
+  }
+}
+
+// ============================================================================
+// Streaming sweep: each workgroup owns NC = 64*CPT outputs (lane-contiguous
+// groups of CPT) and a contiguous range of the reduce side (split-K).  Its 4
+// waves take interleaved reduce rows; per row the reduce-side data
+// (offset potential, point) is a wave-uniform LDS broadcast.  For a stored
+// cost the outputs are columns of the row-major C, so each wave reads
+// 64*CPT*4 contiguous bytes per row.  Per-wave states merge through LDS, the
+// workgroup writes its (sig, S, Sc, acc) partial, and the last workgroup of
+// each column block merges the splits in split order (deterministic).
+// ============================================================================
+template <int CPT, int ELL, int COST, int D, int R, bool SCALE>
+__global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
+  if (gate_closed(A.st, A.gate)) return;
+  extern __shared__ float4 smem4[];
+  char* smem = reinterpret_cast<char*>(smem4);
+  constexpr int NC = 64 * CPT;
+  constexpr int DD = (COST == 1) ? (D > 0 ? D : 1) : 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r0 = blockIdx.y * A.rows_per_split;
+  const int nr = min(A.rows_per_split, A.n_red - r0);
+  const int d = (COST == 1 && D > 0) ? D : A.d;
+  const float K = A.K;
+  const float L = 2.f * (A.cmax + A.st->maxabs[A.ma_in]);
+
+  float2* sU = reinterpret_cast<float2*>(smem);
+  float* sX = reinterpret_cast<float*>(smem + (size_t)A.rows_per_split * sizeof(float2));
+  for (int t = threadIdx.x; t < nr; t += TPB) {
+    float2 u = A.Uin[r0 + t];
+    float2 s = two_sum(L, u.x);
+    s.y += u.y;
+    sU[t] = fast_two_sum(s.x, s.y);
+    if (COST == 1) {
+      for (int k = 0; k < d; ++k) sX[t * d + k] = A.Pred[(size_t)(r0 + t) * d + k];
+    }
+  }
+  __syncthreads();
+
+  const int colbase = blockIdx.x * NC + lane * CPT;
+  float q[CPT][DD];
+  const float* crow0 = nullptr;
+  int ccol[CPT];
+  if (COST == 1) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      int col = min(colbase + c, A.n_out - 1);
+      if (D > 0) {
+#pragma unroll
+        for (int k = 0; k < DD; ++k) q[c][k] = A.Pout[(size_t)col * DD + k];
+      }
+      ccol[c] = col;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) ccol[c] = min(colbase + c, A.n_out - 1);
+    if (CPT == 4) ccol[0] = min(colbase, A.n_out - 4);  // vector path: n_out % 4 == 0
+    crow0 = A.C + ccol[0];
+  }
+
+  float sig[CPT], S[CPT], Sc[CPT];
+  float acc[CPT][ELL > 0 ? ELL : 1];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    sig[c] = SIG0;
+    S[c] = 0.f;
+    Sc[c] = 0.f;
+#pragma unroll
+    for (int l = 0; l < (ELL > 0 ? ELL : 1); ++l) acc[c][l] = 0.f;
+  }
+
+  for (int rb = wave; rb < nr; rb += WAVES * R) {
+    float s[R][CPT], e[R][CPT];
+    int rowl[R];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      int rl = rb + rr * WAVES;
+      bool ok = rl < nr;
+      int rlc = ok ? rl : (nr - 1);
+      rowl[rr] = rlc;
+      float2 u = sU[rlc];
+      float cv[CPT];
+      if (COST == 0) {
+        const float* crow = crow0 + (size_t)(r0 + rlc) * A.ldc;
+        if (CPT == 4) {
+          float4 v = *reinterpret_cast<const float4*>(crow);
+          cv[0] = v.x; cv[1 % CPT] = v.y; cv[2 % CPT] = v.z; cv[3 % CPT] = v.w;
+        } else {
+#pragma unroll
+          for (int c = 0; c < CPT; ++c) cv[c] = A.C[(size_t)(r0 + rlc) * A.ldc + ccol[c]];
+        }
+      } else {
+        const float* xp = &sX[rlc * d];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          float cc;
+          if (D > 0) cc = sqdist<DD>(xp, q[c]);
+          else cc = sqdist_rt(xp, A.Pout + (size_t)ccol[c] * d, d);
+          cv[c] = SCALE ? cc * A.cscale : cc;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        // Fast2Sum: |u.x| >= |C| because u carries the offset L >= 2 max|C|
+        float sv = u.x - cv[c];
+        float ev = ((u.x - sv) - cv[c]) + u.y;
+        s[rr][c] = ok ? sv : SIG0;
+        e[rr][c] = ok ? ev : 0.f;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      float mx = s[0][c];
+#pragma unroll
+      for (int rr = 1; rr < R; ++rr) mx = fmaxf(mx, s[rr][c]);
+      if (mx > sig[c]) {
+        float sc = ex2((sig[c] - mx) * K);
+        S[c] *= sc;
+        Sc[c] *= sc;
+#pragma unroll
+        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[c][l] *= sc;
+        sig[c] = mx;
+      }
+      float p[R];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) p[rr] = ex2(((s[rr][c] - sig[c]) + e[rr][c]) * K);
+      // pairwise sum of the chunk, then a compensated add
+      float t[R];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) t[rr] = p[rr];
+#pragma unroll
+      for (int w = 1; w < R; w <<= 1) {
+#pragma unroll
+        for (int rr = 0; rr + w < R; rr += 2 * w) t[rr] += t[rr + w];
+      }
+      float2 ts = two_sum(S[c], t[0]);
+      S[c] = ts.x;
+      Sc[c] += ts.y;
+      if (ELL > 0) {
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+          const float* vr = A.Vred + (size_t)(r0 + rowl[rr]) * (ELL > 0 ? ELL : 1);
+#pragma unroll
+          for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[c][l] = fmaf(p[rr], vr[l], acc[c][l]);
+        }
+      }
+    }
+  }
+
+  // ---- merge the 4 waves through LDS, in wave order (deterministic)
+  __syncthreads();
+  constexpr int ELLZ = ELL > 0 ? ELL : 0;
+  constexpr int NQ = 3 + ELLZ;
+  float* cmb = reinterpret_cast<float*>(smem);  // [NQ][NC]
+  for (int w = 0; w < WAVES; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int idx = lane * CPT + c;
+        if (w > 0) {
+          float sg = cmb[0 * NC + idx], Ss = cmb[1 * NC + idx], Sx = cmb[2 * NC + idx];
+          float f1, f2;
+          lse_merge(sg, Ss, Sx, sig[c], S[c], Sc[c], K, f1, f2);
+#pragma unroll
+          for (int l = 0; l < ELLZ; ++l) acc[c][l] = cmb[(3 + l) * NC + idx] * f1 + acc[c][l] * f2;
+          sig[c] = sg;
+          S[c] = Ss;
+          Sc[c] = Sx;
+        }
+        cmb[0 * NC + idx] = sig[c];
+        cmb[1 * NC + idx] = S[c];
+        cmb[2 * NC + idx] = Sc[c];
+#pragma unroll
+        for (int l = 0; l < ELLZ; ++l) cmb[(3 + l) * NC + idx] = acc[c][l];
+      }
+    }
+    __syncthreads();
+  }
+  const int n_out = A.n_out;
+  for (int t = threadIdx.x; t < NC; t += TPB) {
+    int col = blockIdx.x * NC + t;
+    if (col < n_out) {
+      size_t base = (size_t)blockIdx.y * NQ * n_out + col;
+#pragma unroll
+      for (int q2 = 0; q2 < NQ; ++q2) A.part[base + q2 * (size_t)n_out] = cmb[q2 * NC + t];
+    }
+  }
+
+  // ---- last workgroup of this column block merges the splits
+  __threadfence();
+  __syncthreads();
+  __shared__ unsigned s_ticket;
+  if (threadIdx.x == 0) s_ticket = atomic_ticket(&A.cnt_cb[blockIdx.x]);
+  __syncthreads();
+  if (s_ticket != (unsigned)(A.nsplit - 1)) return;
+  __threadfence();
+  if (threadIdx.x == 0) A.cnt_cb[blockIdx.x] = 0;
+
+  double err = 0, dot = 0;
+  float mxo = 0.f;
+  for (int t = threadIdx.x; t < NC; t += TPB) {
+    int col = blockIdx.x * NC + t;
+    if (col >= n_out) continue;
+    const float* pp = A.part + col;
+    const size_t stride = (size_t)n_out;
+    float sg = __builtin_nontemporal_load(pp), Ss = __builtin_nontemporal_load(pp + stride),
+          Sx = __builtin_nontemporal_load(pp + 2 * stride);
+    float ac[ELL > 0 ? ELL : 1];
+#pragma unroll
+    for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = __builtin_nontemporal_load(pp + (3 + l) * stride);
+    for (int sp = 1; sp < A.nsplit; ++sp) {
+      const float* q2 = pp + (size_t)sp * NQ * stride;
+      float f1, f2;
+      lse_merge(sg, Ss, Sx, __builtin_nontemporal_load(q2), __builtin_nontemporal_load(q2 + stride),
+                __builtin_nontemporal_load(q2 + 2 * stride), K, f1, f2);
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l)
+        ac[l] = ac[l] * f1 + __builtin_nontemporal_load(q2 + (3 + l) * stride) * f2;
+    }
+    finalize_output<ELL>(A, col, L, sg, Ss, Sx, ac, err, dot, mxo);
+  }
+  __shared__ double sbd[16];
+  __shared__ float sbf[8];
+  err = block_sum_d(err, sbd);
+  dot = block_sum_d(dot, sbd + 8);
+  mxo = block_max_f(mxo, sbf);
+  finish_global(A, blockIdx.x, err, dot, mxo, sbd, sbf);
+}
+
+// ============================================================================
+// Row sweep of a stored cost: the outputs are rows of C (n_out = rows), the
+// reduce side runs along each row.  A workgroup owns RPW rows; its threads
+// stride over the row in float4 groups (coalesced), each thread keeps an
+// online (sig, S, Sc) per row, then wave shuffles and LDS merge them.
+// The subtraction U_r - C_ro uses TwoSum (no precondition).
+// ============================================================================
+template <int RPW, int ELL, bool VEC4>
+__global__ __launch_bounds__(TPB) void k_sweep_rows(SweepArgs A) {
+  if (gate_closed(A.st, A.gate)) return;
+  const float K = A.K;
+  const int o0 = blockIdx.x * RPW;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int EL = ELL > 0 ? ELL : 1;
+  float sig[RPW], S[RPW], Sc[RPW], acc[RPW][EL];
+  const float* crow[RPW];
+#pragma unroll
+  for (int rr = 0; rr < RPW; ++rr) {
+    sig[rr] = SIG0;
+    S[rr] = 0.f;
+    Sc[rr] = 0.f;
+#pragma unroll
+    for (int l = 0; l < EL; ++l) acc[rr][l] = 0.f;
+    int o = min(o0 + rr, A.n_out - 1);
+    crow[rr] = A.C + (size_t)o * A.ldc;
+  }
+  const int nr = A.n_red;
+  if (VEC4) {
+    const int ng = nr >> 2;
+    const float4* U4 = reinterpret_cast<const float4*>(A.Uin);
+    for (int g = threadIdx.x; g < ng; g += TPB) {
+      float4 ua = U4[2 * g], ub = U4[2 * g + 1];  // (hi0, lo0, hi1, lo1), (hi2, lo2, hi3, lo3)
+      float uh[4] = {ua.x, ua.z, ub.x, ub.z};
+      float ul[4] = {ua.y, ua.w, ub.y, ub.w};
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr) {
+        float4 cv4 = *reinterpret_cast<const float4*>(crow[rr] + 4 * g);
+        float cv[4] = {cv4.x, cv4.y, cv4.z, cv4.w};
+        float s[4], e[4];
+        float mx = SIG0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float2 ts = two_sum(uh[k], -cv[k]);
+          s[k] = ts.x;
+          e[k] = ts.y + ul[k];
+          mx = fmaxf(mx, s[k]);
+        }
+        if (mx > sig[rr]) {
+          float sc = ex2((sig[rr] - mx) * K);
+          S[rr] *= sc;
+          Sc[rr] *= sc;
+#pragma unroll
+          for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[rr][l] *= sc;
+          sig[rr] = mx;
+        }
+        float p[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k] = ex2(((s[k] - sig[rr]) + e[k]) * K);
+        float2 ts = two_sum(S[rr], (p[0] + p[1]) + (p[2] + p[3]));
+        S[rr] = ts.x;
+        Sc[rr] += ts.y;
+        if (ELL > 0) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float* vr = A.Vred + (size_t)(4 * g + k) * EL;
+#pragma unroll
+            for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[rr][l] = fmaf(p[k], vr[l], acc[rr][l]);
+          }
+        }
+      }
+    }
+  } else {
+    for (int j = threadIdx.x; j < nr; j += TPB) {
+      float2 u = A.Uin[j];
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr) {
+        float cvv = crow[rr][j];
+        float2 ts = two_sum(u.x, -cvv);
+        float s = ts.x, e = ts.y + u.y;
+        if (s > sig[rr]) {
+          float sc = ex2((sig[rr] - s) * K);
+          S[rr] *= sc;
+          Sc[rr] *= sc;
+#pragma unroll
+          for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[rr][l] *= sc;
+          sig[rr] = s;
+        }
+        float p = ex2(((s - sig[rr]) + e) * K);
+        float2 t2 = two_sum(S[rr], p);
+        S[rr] = t2.x;
+        Sc[rr] += t2.y;
+        if (ELL > 0) {
+          const float* vr = A.Vred + (size_t)j * EL;
+#pragma unroll
+          for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[rr][l] = fmaf(p, vr[l], acc[rr][l]);
+        }
+      }
+    }
+  }
+  // ---- wave merge (butterfly), then LDS merge across waves
+#pragma unroll
+  for (int rr = 0; rr < RPW; ++rr) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      float sg2 = __shfl_xor(sig[rr], off, 64);
+      float S2 = __shfl_xor(S[rr], off, 64);
+      float Sc2 = __shfl_xor(Sc[rr], off, 64);
+      float f1, f2;
+      float a2[EL];
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) a2[l] = __shfl_xor(acc[rr][l], off, 64);
+      lse_merge(sig[rr], S[rr], Sc[rr], sg2, S2, Sc2, K, f1, f2);
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[rr][l] = acc[rr][l] * f1 + a2[l] * f2;
+    }
+  }
+  constexpr int NQ = 3 + (ELL > 0 ? ELL : 0);
+  __shared__ float cmb[WAVES][RPW][NQ];
+  if (lane == 0) {
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+      cmb[wave][rr][0] = sig[rr];
+      cmb[wave][rr][1] = S[rr];
+      cmb[wave][rr][2] = Sc[rr];
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) cmb[wave][rr][3 + l] = acc[rr][l];
+    }
+  }
+  __syncthreads();
+  double err = 0, dot = 0;
+  float mxo = 0.f;
+  if (threadIdx.x < RPW && o0 + (int)threadIdx.x < A.n_out) {
+    const int rr = threadIdx.x;
+    float sg = cmb[0][rr][0], Ss = cmb[0][rr][1], Sx = cmb[0][rr][2];
+    float ac[EL];
+#pragma unroll
+    for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = cmb[0][rr][3 + l];
+    for (int w = 1; w < WAVES; ++w) {
+      float f1, f2;
+      lse_merge(sg, Ss, Sx, cmb[w][rr][0], cmb[w][rr][1], cmb[w][rr][2], K, f1, f2);
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = ac[l] * f1 + cmb[w][rr][3 + l] * f2;
+    }
+    finalize_output<ELL>(A, o0 + rr, 0.f, sg, Ss, Sx, ac, err, dot, mxo);
+  }
+  __shared__ double sbd[16];
+  __shared__ float sbf[8];
+  err = block_sum_d(err, sbd);
+  dot = block_sum_d(dot, sbd + 8);
+  mxo = block_max_f(mxo, sbf);
+  finish_global(A, blockIdx.x, err, dot, mxo, sbd, sbf);
+}
+
+// ----------------------------------------------------------- launch config
+static int rps_max(int cost_kind, int d) {
+  if (cost_kind == 0) return 4096;                   // 8 B per row of LDS
+  int per = 8 + 4 * d;
+  int cap = (40 * 1024) / per;
+  return cap < 16 ? 16 : cap;
+}
+
+// outputs per thread of the streaming sweep (shared by sizing and launch)
+static int stream_cpt(int cost_kind, int ell, bool vec) {
+  if (cost_kind == 0) {
+    if (ell > 16) return 2;
+    return vec ? 4 : 1;
+  }
+  return ell > 0 ? 2 : 4;
+}
+
+size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bool vec, int* nsplit, int* rps,
+                         int* nblk, bool stream_kernel) {
+  if (!stream_kernel) {
+    int rpw = ell > 0 ? 1 : 4;
+    *nsplit = 1;
+    *rps = n_red;
+    *nblk = (n_out + rpw - 1) / rpw;
+    return 0;
+  }
+  int cpt = stream_cpt(cost_kind, ell, vec);
+  int nc = 64 * cpt;
+  int ncb = (n_out + nc - 1) / nc;
+  int target = 2048;
+  int ns = (target + ncb - 1) / ncb;
+  int r = (n_red + ns - 1) / ns;
+  int rmin = ell > 0 ? 128 : 64;
+  if (r < rmin) r = rmin;
+  int rmx = rps_max(cost_kind, d);
+  if (r > rmx) r = rmx;
+  if (r > n_red) r = n_red;
+  ns = (n_red + r - 1) / r;
+  *nsplit = ns;
+  *rps = r;
+  *nblk = ncb;
+  int ellp = ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32));
+  return (size_t)ns * (3 + ellp) * n_out;
+}
+
+template <int CPT, int ELL, int COST, int D, int R>
+static hipError_t go_stream(const SweepArgs& a, hipStream_t s) {
+  constexpr int NC = 64 * CPT;
+  int ncb = (a.n_out + NC - 1) / NC;
+  dim3 grid(ncb, a.nsplit);
+  size_t rows_bytes = (size_t)a.rows_per_split * (8 + (COST == 1 ? 4 * a.d : 0));
+  size_t cmb_bytes = (size_t)(3 + ELL) * NC * 4;
+  size_t sm = rows_bytes > cmb_bytes ? rows_bytes : cmb_bytes;
+  bool scale = (COST == 1) && a.cscale != 1.0f;
+  if (scale)
+    hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, true>), grid, dim3(TPB), sm, s, a);
+  else
+    hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, false>), grid, dim3(TPB), sm, s, a);
+  return hipGetLastError();
+}
+
+template <int CPT, int ELL>
+static hipError_t go_stream_points(const SweepArgs& a, hipStream_t s) {
+  switch (a.d) {
+    case 1: return go_stream<CPT, ELL, 1, 1, 4>(a, s);
+    case 2: return go_stream<CPT, ELL, 1, 2, 4>(a, s);
+    case 3: return go_stream<CPT, ELL, 1, 3, 4>(a, s);
+    case 4: return go_stream<CPT, ELL, 1, 4, 4>(a, s);
+    case 5: return go_stream<CPT, ELL, 1, 5, 2>(a, s);
+    case 6: return go_stream<CPT, ELL, 1, 6, 2>(a, s);
+    case 7: return go_stream<CPT, ELL, 1, 7, 2>(a, s);
+    case 8: return go_stream<CPT, ELL, 1, 8, 2>(a, s);
+    default: return go_stream<CPT, ELL, 1, 0, 2>(a, s);
+  }
+}
+
+hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t s) {
+  const int cpt = stream_cpt(cost_kind, a.ell, vec);
+  if (cost_kind == 0) {
+    if (a.ell == 0) return cpt == 4 ? go_stream<4, 0, 0, 1, 8>(a, s) : go_stream<1, 0, 0, 1, 8>(a, s);
+    if (a.ell <= 8) return cpt == 4 ? go_stream<4, 8, 0, 1, 4>(a, s) : go_stream<1, 8, 0, 1, 4>(a, s);
+    if (a.ell <= 16) return cpt == 4 ? go_stream<4, 16, 0, 1, 4>(a, s) : go_stream<1, 16, 0, 1, 4>(a, s);
+    return go_stream<2, 32, 0, 1, 4>(a, s);
+  }
+  if (a.ell == 0) return go_stream_points<4, 0>(a, s);
+  if (a.ell <= 8) return go_stream_points<2, 8>(a, s);
+  if (a.ell <= 16) return go_stream_points<2, 16>(a, s);
+  return go_stream_points<2, 32>(a, s);
+}
+
+hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t s) {
+  bool vec = (a.n_red % 4 == 0) && (a.ldc % 4 == 0) && ((uintptr_t)a.C % 16 == 0) && ((uintptr_t)a.Uin % 16 == 0);
+  if (a.ell == 0) {
+    dim3 grid((a.n_out + 3) / 4);
+    if (vec) hipLaunchKernelGGL((k_sweep_rows<4, 0, true>), grid, dim3(TPB), 0, s, a);
+    else hipLaunchKernelGGL((k_sweep_rows<4, 0, false>), grid, dim3(TPB), 0, s, a);
+  } else {
+    dim3 grid(a.n_out);
+    if (a.ell <= 8) {
+      if (vec) hipLaunchKernelGGL((k_sweep_rows<1, 8, true>), grid, dim3(TPB), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_rows<1, 8, false>), grid, dim3(TPB), 0, s, a);
+    } else if (a.ell <= 16) {
+      if (vec) hipLaunchKernelGGL((k_sweep_rows<1, 16, true>), grid, dim3(TPB), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_rows<1, 16, false>), grid, dim3(TPB), 0, s, a);
+    } else {
+      if (vec) hipLaunchKernelGGL((k_sweep_rows<1, 32, true>), grid, dim3(TPB), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_rows<1, 32, false>), grid, dim3(TPB), 0, s, a);
+    }
+  }
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Conversions, rebase, selection
+// ============================================================================
+// U = f + eps*log(w) as double-float; max |U.hi| into st->maxabs[ma] (atomic
+// max on the bit pattern of a non-negative float is order independent);
+// <U, w> partial sums into scratch[blockIdx.x].
+__global__ void k_to_hat(const double* f, const double* logw, double eps, float2* U, int n, DevState* st, int ma,
+                         const double* w, double* scratch) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double dot = 0;
+  float mx = 0.f;
+  if (i < n) {
+    double v = (f ? f[i] : 0.0) + eps * logw[i];
+    float hi = (float)v;
+    float lo = (float)(v - (double)hi);
+    U[i] = make_float2(hi, lo);
+    mx = fabsf(hi);
+    dot = w[i] * v;
+  }
+  __shared__ double sbd[16];
+  __shared__ float sbf[8];
+  dot = block_sum_d(dot, sbd);
+  mx = block_max_f(mx, sbf);
+  if (threadIdx.x == 0) {
+    scratch[blockIdx.x] = dot;
+    atomicMax(reinterpret_cast<unsigned*>(&st->maxabs[ma]), __float_as_uint(mx));
+  }
+}
+__global__ void k_sum_blocks(const double* scratch, int nb, double* out) {
+  __shared__ double sbd[16];
+  double s = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += scratch[b];
+  s = block_sum_d(s, sbd);
+  if (threadIdx.x == 0) *out = s;
+}
+
+hipError_t launch_to_hat(const double* f, const double* logw, double eps, float2* U, int n, DevState* st, int ma,
+                         const double* w, int dot_slot, double* scratch, hipStream_t s) {
+  int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_to_hat, dim3(nb), dim3(256), 0, s, f, logw, eps, U, n, st, ma, w, scratch);
+  hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(256), 0, s, scratch, nb,
+                     dot_slot >= 0 ? &st->dots[dot_slot] : scratch + nb);
+  return hipGetLastError();
+}
+
+__global__ void k_from_hat(const float2* U, const double* logw, double eps, double* f, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float2 u = U[i];
+    f[i] = ((double)u.x + (double)u.y) - eps * logw[i];
+  }
+}
+hipError_t launch_from_hat(const float2* U, const double* logw, double eps, double* f, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_from_hat, dim3((n + 255) / 256), dim3(256), 0, s, U, logw, eps, f, n);
+  return hipGetLastError();
+}
+
+// U += deps * lw (double-float), for a change of eps between stages; the
+// max |U.hi| goes to st->maxabs[ma] by atomic max (slot zeroed beforehand).
+__global__ void k_rebase(float2* U, const float2* lw, float2 deps, int n, DevState* st, int ma) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  float mx = 0.f;
+  if (i < n) {
+    float2 u = df_add(U[i], df_mul(deps, lw[i]));
+    U[i] = u;
+    mx = fabsf(u.x);
+  }
+  __shared__ float sbf[8];
+  mx = block_max_f(mx, sbf);
+  if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned*>(&st->maxabs[ma]), __float_as_uint(mx));
+}
+hipError_t launch_rebase(float2* U, const float2* lw, float2 deps_df, int n, DevState* st, int ma, hipStream_t s) {
+  hipLaunchKernelGGL(k_rebase, dim3((n + 255) / 256), dim3(256), 0, s, U, lw, deps_df, n, st, ma);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_slot(DevState* st, int dd, int sd, int dm, int sm) {
+  if (threadIdx.x == 0) {
+    if (dd >= 0) st->dots[dd] = st->dots[sd];
+    if (dm >= 0) st->maxabs[dm] = st->maxabs[sm];
+  }
+}
+hipError_t launch_copy_state_slot(DevState* st, int dst_dot, int src_dot, int dst_ma, int src_ma, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_slot, dim3(1), dim3(64), 0, s, st, dst_dot, src_dot, dst_ma, src_ma);
+  return hipGetLastError();
+}
+
+// Newton acceptance selection: accepted -> (F, G) = (F', G'); rejected ->
+// (F, G) = (F_sk, G~), i.e. the plain SK iterate.
+__global__ void k_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp, const float2* Gt,
+                         float2* G, int m, DevState* st, int gate) {
+  if (gate_closed(st, gate)) return;
+  const int acc = ((volatile DevState*)st)->accept;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) F[i] = acc ? Fp[i] : Fsk[i];
+  else if (i < n + m) G[i - n] = acc ? Gp[i - n] : Gt[i - n];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->dots[DOT_F] = acc ? st->dots[DOT_FP] : st->dots[DOT_FSK];
+    st->dots[DOT_G] = acc ? st->dots[DOT_GP] : st->dots[DOT_GT];
+    st->maxabs[MA_F] = acc ? st->maxabs[MA_FP] : st->maxabs[MA_FSK];
+    st->maxabs[MA_G] = acc ? st->maxabs[MA_GP] : st->maxabs[MA_GT];
+  }
+}
+hipError_t launch_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp, const float2* Gt,
+                         float2* G, int m, DevState* st, int gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3((n + m + 255) / 256), dim3(256), 0, s, Fp, Fsk, F, n, Gp, Gt, G, m, st, gate);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Projected Newton system (FP64), Algorithm 4.1:
+//   G = V^T diag(r) V - W^T diag(b)^-1 W,  grad = V^T (a - r) = -V^T mdiff,
+//   c = eps G^-1 grad,  Delta f = V c.
+// r = a + mdiff is the row marginal of P~ = pi(f, f^{C,eps}).
+// ============================================================================
+template <int ELL>
+__global__ __launch_bounds__(256) void k_nr_assemble(const float* V, const float* mdiff, const double* a, int n,
+                                                     const float* W, const double* b, int m, double* part,
+                                                     int nrow_blk, int rows_per_blk, DevState* st, int gate) {
+  if (gate_closed(st, gate)) return;
+  constexpr int NE = ELL * ELL;
+  constexpr int PER = (NE + 255) / 256;
+  __shared__ float tile[64][ELL];
+  __shared__ double wrow[64];
+  double accv[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) accv[p] = 0;
+  double gacc = 0;
+  const bool rows = (int)blockIdx.x < nrow_blk;
+  const int blk = rows ? blockIdx.x : blockIdx.x - nrow_blk;
+  const int beg = blk * rows_per_blk;
+  const int cnt = rows ? n : m;
+  const int end = min(beg + rows_per_blk, cnt);
+  for (int t0 = beg; t0 < end; t0 += 64) {
+    int nt = min(64, end - t0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * ELL; q += 256) {
+      int rr = q / ELL, l = q % ELL;
+      float v = 0.f;
+      if (rr < nt) v = rows ? V[(size_t)(t0 + rr) * ELL + l] : W[(size_t)(t0 + rr) * ELL + l];
+      tile[rr][l] = v;
+    }
+    if (threadIdx.x < 64) {
+      int rr = threadIdx.x;
+      double wv = 0;
+      if (rr < nt) wv = rows ? (a[t0 + rr] + (double)mdiff[t0 + rr]) : -1.0 / b[t0 + rr];
+      wrow[rr] = wv;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < nt; ++rr) {
+      double wv = wrow[rr];
+#pragma unroll
+      for (int p = 0; p < PER; ++p) {
+        int e = threadIdx.x + 256 * p;
+        if (e < NE) {
+          int k = e / ELL, l = e % ELL;
+          accv[p] += wv * (double)tile[rr][k] * (double)tile[rr][l];
+        }
+      }
+      if (rows && (int)threadIdx.x < ELL) gacc -= (double)tile[rr][threadIdx.x] * (double)mdiff[t0 + rr];
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * (NE + ELL);
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    int e = threadIdx.x + 256 * p;
+    if (e < NE) out[e] = accv[p];
+  }
+  if ((int)threadIdx.x < ELL) out[NE + threadIdx.x] = gacc;
+}
+
+template <int ELL>
+__global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, int ell_real, double eps,
+                                                  float* coef32, double* coef64, double* Gout, double* gout,
+                                                  DevState* st, int gate) {
+  if (gate_closed(st, gate)) return;
+  constexpr int NE = ELL * ELL;
+  __shared__ double A[ELL][ELL + 1];
+  __shared__ double g[ELL];
+  __shared__ int ok;
+  for (int e = threadIdx.x; e < NE + ELL; e += 256) {
+    double s = 0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (NE + ELL) + e];
+    if (e < NE) A[e / ELL][e % ELL] = s;
+    else g[e - NE] = s;
+  }
+  if (threadIdx.x == 0) ok = 1;
+  __syncthreads();
+  // symmetrise
+  for (int e = threadIdx.x; e < NE; e += 256) {
+    int i = e / ELL, j = e % ELL;
+    if (i < j) {
+      double v = 0.5 * (A[i][j] + A[j][i]);
+      A[i][j] = v;
+      A[j][i] = v;
+    }
+  }
+  __syncthreads();
+  if (Gout) {
+    for (int e = threadIdx.x; e < ell_real * ell_real; e += 256) Gout[e] = A[e / ell_real][e % ell_real];
+    for (int e = threadIdx.x; e < ell_real; e += 256) gout[e] = g[e];
+  }
+  __syncthreads();
+  // padded modes (columns of V beyond ell_real are zero): identity rows
+  for (int e = threadIdx.x; e < NE; e += 256) {
+    int i = e / ELL, j = e % ELL;
+    if (i >= ell_real || j >= ell_real) A[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int e = threadIdx.x; e < ELL; e += 256)
+    if (e >= ell_real) g[e] = 0.0;
+  __syncthreads();
+  double dmax = 0;
+  for (int i = 0; i < ELL; ++i) dmax = fmax(dmax, A[i][i]);
+  // right-looking Cholesky (lower), in place
+  for (int k = 0; k < ELL; ++k) {
+    __syncthreads();
+    double piv = A[k][k];
+    if (!(piv > 1e-300 && piv > 1e-15 * dmax)) {
+      if (threadIdx.x == 0) ok = 0;
+      piv = 1.0;
+    }
+    double dk = sqrt(piv);
+    __syncthreads();
+    if (threadIdx.x == 0) A[k][k] = dk;
+    for (int i = k + 1 + threadIdx.x; i < ELL; i += 256) A[i][k] /= dk;
+    __syncthreads();
+    for (int e = threadIdx.x; e < NE; e += 256) {
+      int i = e / ELL, j = e % ELL;
+      if (j > k && i >= j) A[i][j] -= A[i][k] * A[j][k];
+    }
+  }
+  __syncthreads();
+  // solve L y = g, L^T z = y (single wave, sequential over k)
+  if (threadIdx.x == 0) {
+    double y[ELL];
+    for (int i = 0; i < ELL; ++i) {
+      double s = g[i];
+      for (int j = 0; j < i; ++j) s -= A[i][j] * y[j];
+      y[i] = s / A[i][i];
+    }
+    for (int i = ELL - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int j = i + 1; j < ELL; ++j) s -= A[j][i] * y[j];
+      y[i] = s / A[i][i];
+    }
+    int good = ok;
+    for (int i = 0; i < ELL; ++i) {
+      double c = eps * y[i];
+      if (!(fabs(c) < 1e30)) good = 0;
+      coef64[i] = c;
+    }
+    for (int i = 0; i < ELL; ++i) coef32[i] = good ? (float)coef64[i] : 0.f;
+    st->chol_ok = good;
+    st->accept = 0;
+    st->newton_tried += 1;
+  }
+}
+
+template <int ELL>
+__global__ __launch_bounds__(256) void k_nr_apply(const float2* F, const float* V, const float* coef,
+                                                  const double* a, float2* Fp, int n, double* blk, float* blkmax,
+                                                  DevState* st, int gate, int dot_slot, int ma_slot,
+                                                  unsigned* cnt) {
+  if (gate_closed(st, gate)) return;
+  __shared__ float c[ELL];
+  if (threadIdx.x < ELL) c[threadIdx.x] = coef[threadIdx.x];
+  __syncthreads();
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double dot = 0;
+  float mx = 0.f;
+  if (i < n) {
+    float dl = 0.f;
+    const float* vr = V + (size_t)i * ELL;
+#pragma unroll
+    for (int l = 0; l < ELL; ++l) dl = fmaf(vr[l], c[l], dl);
+    float2 u = df_add_f(F[i], dl);
+    Fp[i] = u;
+    dot = a[i] * ((double)u.x + (double)u.y);
+    mx = fabsf(u.x);
+  }
+  __shared__ double sbd[16];
+  __shared__ float sbf[8];
+  dot = block_sum_d(dot, sbd);
+  mx = block_max_f(mx, sbf);
+  __shared__ unsigned s_ticket;
+  if (threadIdx.x == 0) {
+    blk[blockIdx.x] = dot;
+    blkmax[blockIdx.x] = mx;
+    __threadfence();
+    s_ticket = atomic_ticket(cnt);
+  }
+  __syncthreads();
+  if (s_ticket != gridDim.x - 1) return;
+  __threadfence();
+  double d = 0;
+  float m = 0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+    d += __builtin_nontemporal_load(&blk[b]);
+    m = fmaxf(m, __builtin_nontemporal_load(&blkmax[b]));
+  }
+  d = block_sum_d(d, sbd);
+  m = block_max_f(m, sbf);
+  if (threadIdx.x == 0) {
+    *cnt = 0;
+    st->dots[dot_slot] = d;
+    st->maxabs[ma_slot] = m;
+  }
+}
+
+template <int E>
+static void nr_assemble_e(const float* V, const float* mdiff, const double* a, int n, const float* W, const double* b,
+                          int m, double* part, int nrow_blk, int ncol_blk, int rpb, DevState* st, int gate,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_nr_assemble<E>), dim3(nrow_blk + ncol_blk), dim3(256), 0, s, V, mdiff, a, n, W, b, m, part,
+                     nrow_blk, rpb, st, gate);
+}
+hipError_t launch_nr_assemble(int ell, const float* V, const float* mdiff, const double* a, int n, const float* W,
+                              const double* b, int m, double* part, int nrow_blk, int ncol_blk, DevState* st, int gate,
+                              hipStream_t s) {
+  int rpb_r = (n + nrow_blk - 1) / nrow_blk;
+  int rpb_c = (m + ncol_blk - 1) / ncol_blk;
+  int rpb = rpb_r > rpb_c ? rpb_r : rpb_c;  // one block length for rows and columns
+  if (ell <= 8) nr_assemble_e<8>(V, mdiff, a, n, W, b, m, part, nrow_blk, ncol_blk, rpb, st, gate, s);
+  else if (ell <= 16) nr_assemble_e<16>(V, mdiff, a, n, W, b, m, part, nrow_blk, ncol_blk, rpb, st, gate, s);
+  else nr_assemble_e<32>(V, mdiff, a, n, W, b, m, part, nrow_blk, ncol_blk, rpb, st, gate, s);
+  return hipGetLastError();
+}
+template <int E>
+static void nr_solve_e(const double* part, int nblk, int ell, double eps, float* coef32, double* coef64,
+                       double* Gout, double* gout, DevState* st, int gate, hipStream_t s) {
+  hipLaunchKernelGGL((k_nr_solve<E>), dim3(1), dim3(256), 0, s, part, nblk, ell, eps, coef32, coef64, Gout, gout, st,
+                     gate);
+}
+hipError_t launch_nr_solve(int ell, const double* part, int nblk, double eps, float* coef32, double* coef64,
+                           double* Gout, double* gout, DevState* st, int gate, hipStream_t s) {
+  if (ell <= 8) nr_solve_e<8>(part, nblk, ell, eps, coef32, coef64, Gout, gout, st, gate, s);
+  else if (ell <= 16) nr_solve_e<16>(part, nblk, ell, eps, coef32, coef64, Gout, gout, st, gate, s);
+  else nr_solve_e<32>(part, nblk, ell, eps, coef32, coef64, Gout, gout, st, gate, s);
+  return hipGetLastError();
+}
+template <int E>
+static void nr_apply_e(const float2* F, const float* V, const float* coef, const double* a, float2* Fp, int n,
+                       double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot, hipStream_t s) {
+  int nb = (n + 255) / 256;
+  hipLaunchKernelGGL((k_nr_apply<E>), dim3(nb), dim3(256), 0, s, F, V, coef, a, Fp, n, blk, blkmax, st, gate,
+                     dot_slot, ma_slot, &st->cnt[7]);
+}
+hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a, float2* Fp,
+                           int n, double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot,
+                           hipStream_t s) {
+  if (ell <= 8) nr_apply_e<8>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s);
+  else if (ell <= 16) nr_apply_e<16>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s);
+  else nr_apply_e<32>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// FP64 evaluation of (f, g): row / column sums of pi, <C,pi>, sum pi,
+// sum pi*log(pi/(a b)).  Tiles of 64 rows x 256 columns; deterministic
+// two-stage sums.
+// ============================================================================
+template <int COST, int D>
+__global__ __launch_bounds__(256) void k_eval(SweepArgs G, const double* f, const double* g, const double* a,
+                                              const double* b, double eps, double* rowpart, double* colpart,
+                                              double* scal, int n, int m) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int i0 = blockIdx.y * 64;
+  const int jc = min(j, m - 1);
+  const double inv = 1.0 / eps;
+  const double gj = g[jc], bj = b[jc];
+  float q[D > 0 ? D : 1];
+  if (COST == 1 && D > 0)
+    for (int k = 0; k < D; ++k) q[k] = G.Pout[(size_t)jc * D + k];
+  __shared__ double srow[WAVES][64];
+  double cs = 0, cost = 0, mass = 0, ent = 0;
+  for (int r = 0; r < 64; ++r) {
+    int i = i0 + r;
+    double p = 0, cij = 0;
+    if (i < n && j < m) {
+      float cf;
+      if (COST == 0) cf = G.C[(size_t)i * G.ldc + j];
+      else {
+        const float* xp = G.Pred + (size_t)i * G.d;
+        float cc = (D > 0) ? sqdist<D>(xp, q) : sqdist_rt(xp, G.Pout + (size_t)jc * G.d, G.d);
+        cf = (G.cscale != 1.0f) ? cc * G.cscale : cc;
+      }
+      cij = (double)cf;
+      double t = (f[i] + gj - cij) * inv;
+      p = a[i] * bj * exp(t);
+      cs += p;
+      cost += p * cij;
+      mass += p;
+      ent += p * t;
+    }
+    double rs = wave_sum(p);
+    if (lane == 0) srow[wave][r] = rs;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    int i = i0 + threadIdx.x;
+    if (i < n) rowpart[(size_t)blockIdx.x * n + i] = srow[0][threadIdx.x] + srow[1][threadIdx.x] +
+                                                     srow[2][threadIdx.x] + srow[3][threadIdx.x];
+  }
+  if (j < m) colpart[(size_t)blockIdx.y * m + j] = cs;
+  __shared__ double sbd[16];
+  double c1 = block_sum_d(cost, sbd);
+  double c2 = block_sum_d(mass, sbd);
+  double c3 = block_sum_d(ent, sbd);
+  if (threadIdx.x == 0) {
+    size_t bid = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    scal[bid * 3 + 0] = c1;
+    scal[bid * 3 + 1] = c2;
+    scal[bid * 3 + 2] = c3;
+  }
+}
+
+hipError_t launch_eval(const SweepArgs& geo, int cost_kind, const double* f, const double* g, const double* a,
+                       const double* b, double eps, double* rowpart, double* colpart, double* scal, int n, int m,
+                       int* nrb, int* ncb, hipStream_t s) {
+  dim3 grid((m + 255) / 256, (n + 63) / 64);
+  *ncb = grid.x;
+  *nrb = grid.y;
+  if (cost_kind == 0) {
+    hipLaunchKernelGGL((k_eval<0, 1>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m);
+  } else {
+    switch (geo.d) {
+      case 1: hipLaunchKernelGGL((k_eval<1, 1>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+      case 2: hipLaunchKernelGGL((k_eval<1, 2>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+      case 3: hipLaunchKernelGGL((k_eval<1, 3>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+      case 4: hipLaunchKernelGGL((k_eval<1, 4>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+      case 5: hipLaunchKernelGGL((k_eval<1, 5>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+      case 6: hipLaunchKernelGGL((k_eval<1, 6>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+      case 7: hipLaunchKernelGGL((k_eval<1, 7>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+      case 8: hipLaunchKernelGGL((k_eval<1, 8>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+      default: hipLaunchKernelGGL((k_eval<1, 0>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+// out8 = {row_err, col_err, cost, mass, ent_sum, 0, 0, 0}
+__global__ __launch_bounds__(256) void k_eval_finish(const double* rowpart, const double* colpart,
+                                                     const double* scal, const double* a, const double* b, int n,
+                                                     int m, int nrb, int ncb, double* out8) {
+  __shared__ double sbd[16];
+  double re = 0, ce = 0, c1 = 0, c2 = 0, c3 = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0;
+    for (int cb = 0; cb < ncb; ++cb) s += rowpart[(size_t)cb * n + i];
+    re += fabs(s - a[i]);
+  }
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    double s = 0;
+    for (int rb = 0; rb < nrb; ++rb) s += colpart[(size_t)rb * m + j];
+    ce += fabs(s - b[j]);
+  }
+  for (int q = threadIdx.x; q < nrb * ncb; q += blockDim.x) {
+    c1 += scal[(size_t)q * 3 + 0];
+    c2 += scal[(size_t)q * 3 + 1];
+    c3 += scal[(size_t)q * 3 + 2];
+  }
+  re = block_sum_d(re, sbd);
+  ce = block_sum_d(ce, sbd);
+  c1 = block_sum_d(c1, sbd);
+  c2 = block_sum_d(c2, sbd);
+  c3 = block_sum_d(c3, sbd);
+  if (threadIdx.x == 0) {
+    out8[0] = re;
+    out8[1] = ce;
+    out8[2] = c1;
+    out8[3] = c2;
+    out8[4] = c3;
+  }
+}
+hipError_t launch_eval_finish(const double* rowpart, const double* colpart, const double* scal, const double* a,
+                              const double* b, int n, int m, int nrb, int ncb, double* out8, hipStream_t s) {
+  hipLaunchKernelGGL(k_eval_finish, dim3(1), dim3(256), 0, s, rowpart, colpart, scal, a, b, n, m, nrb, ncb, out8);
+  return hipGetLastError();
+}
+
+// coupling pi_ij = a_i b_j exp((f_i + g_j - C_ij)/eps) as FP32
+template <int COST>
+__global__ void k_coupling(SweepArgs G, const double* f, const double* g, const double* a, const double* b,
+                           double eps, float* P, int n, int m) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (j >= m) return;
+  float cf;
+  if (COST == 0) cf = G.C[(size_t)i * G.ldc + j];
+  else {
+    float cc = sqdist_rt(G.Pred + (size_t)i * G.d, G.Pout + (size_t)j * G.d, G.d);
+    cf = (G.cscale != 1.0f) ? cc * G.cscale : cc;
+  }
+  P[(size_t)i * m + j] = (float)(a[i] * b[j] * exp((f[i] + g[j] - (double)cf) / eps));
+}
+hipError_t launch_coupling(const SweepArgs& geo, int cost_kind, const double* f, const double* g, const double* a,
+                           const double* b, double eps, float* P, int n, int m, hipStream_t s) {
+  dim3 grid((m + 255) / 256, n);
+  if (cost_kind == 0) hipLaunchKernelGGL((k_coupling<0>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
+  else hipLaunchKernelGGL((k_coupling<1>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ small utilities
+__global__ void k_dot64(const double* x, const double* w, int n, double* out) {
+  __shared__ double sbd[16];
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += x[i] * w[i];
+  s = block_sum_d(s, sbd);
+  if (threadIdx.x == 0) *out = s;
+}
+hipError_t launch_dot64(const double* x, const double* w, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot64, dim3(1), dim3(256), 0, s, x, w, n, out);
+  return hipGetLastError();
+}
+// x += sign * 0.5 * (dots[1] - dots[0])  (gauge normalisation <f,a> = <g,b>)
+__global__ void k_shift64(double* x, int n, const double* dots, double sign) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += sign * 0.5 * (dots[1] - dots[0]);
+}
+hipError_t launch_shift64(double* x, int n, const double* dots, double sign, hipStream_t s) {
+  hipLaunchKernelGGL(k_shift64, dim3((n + 255) / 256), dim3(256), 0, s, x, n, dots, sign);
+  return hipGetLastError();
+}
+
+__global__ void k_cost_absmax(const float* C, long long ldc, int n, int m, unsigned* out) {
+  __shared__ float sbf[8];
+  float mx = 0.f;
+  int i = blockIdx.x;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) mx = fmaxf(mx, fabsf(C[(size_t)i * ldc + j]));
+  mx = block_max_f(mx, sbf);
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(mx));
+}
+hipError_t launch_cost_max(int cost_kind, const float* C, long long ldc, int n, int m, const float* x, const float* y,
+                           int d, float* out2, hipStream_t s) {
+  (void)x; (void)y; (void)d;
+  if (cost_kind != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cost_absmax, dim3(n), dim3(256), 0, s, C, ldc, n, m, reinterpret_cast<unsigned*>(out2));
+  return hipGetLastError();
+}
+
+__global__ void k_f32_to_f64(const float* s, double* d, long long cnt) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < cnt) d[i] = s[i];
+}
+__global__ void k_f64_to_f32(const double* s, float* d, long long cnt) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < cnt) d[i] = (float)s[i];
+}
+hipError_t launch_f32_to_f64(const float* src, double* dst, long long count, hipStream_t s) {
+  hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+hipError_t launch_f64_to_f32(const double* src, float* dst, long long count, hipStream_t s) {
+  hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+}  // namespace sknr

@@ -1,0 +1,340 @@
+// Small dense FP64 kernels of the spectral warm start (paper Sec. 4):
+// block subspace iteration for the top eigenvectors of
+//   M = diag(a)^-1 P diag(b)^-1 P^T,
+// self-adjoint in L2(a), whose eigenvalues are rho_k^2 (the semi-dual
+// Hessian at the optimum is -(1/eps) diag(a)(Id - M)).  The two O(nm k)
+// products P^T V and P U run in the weighted c-transform sweeps; what is
+// here works on n x k or m x k blocks (k <= 32) and k x k matrices:
+// weighted Gram matrices, Cholesky orthonormalisation in L2(a) with the
+// constant mode projected out, cyclic Jacobi for the Rayleigh-Ritz step,
+// and the block rotations.
+#include "sknr_internal.h"
+
+#include <math.h>
+
+namespace sknr {
+
+// ----------------------------------------------------------------- Gram
+// part[blk] = ( sum_i w_i Z_i Z_i^T  (k x k),  sum_i w_i Z_i  (k) ),
+// w_i = wgt[i] or 1/wgt[i] (invert), over a contiguous block of rows.
+template <int KP>
+__global__ __launch_bounds__(256) void k_wgram(const float* Z, const double* wgt, int invert, int n, double* part,
+                                               int rows_per_blk) {
+  constexpr int NE = KP * KP;
+  constexpr int PER = (NE + 255) / 256;
+  __shared__ float tile[64][KP];
+  __shared__ double wrow[64];
+  double acc[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) acc[p] = 0;
+  double sacc = 0;
+  const int beg = blockIdx.x * rows_per_blk;
+  const int end = min(beg + rows_per_blk, n);
+  for (int t0 = beg; t0 < end; t0 += 64) {
+    int nt = min(64, end - t0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * KP; q += 256) {
+      int rr = q / KP, l = q % KP;
+      tile[rr][l] = rr < nt ? Z[(size_t)(t0 + rr) * KP + l] : 0.f;
+    }
+    if (threadIdx.x < 64) {
+      int rr = threadIdx.x;
+      double w = 0;
+      if (rr < nt) w = invert ? 1.0 / wgt[t0 + rr] : wgt[t0 + rr];
+      wrow[rr] = w;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < nt; ++rr) {
+      double w = wrow[rr];
+#pragma unroll
+      for (int p = 0; p < PER; ++p) {
+        int e = threadIdx.x + 256 * p;
+        if (e < NE) acc[p] += w * (double)tile[rr][e / KP] * (double)tile[rr][e % KP];
+      }
+      if ((int)threadIdx.x < KP) sacc += w * (double)tile[rr][threadIdx.x];
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * (NE + KP);
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    int e = threadIdx.x + 256 * p;
+    if (e < NE) out[e] = acc[p];
+  }
+  if ((int)threadIdx.x < KP) out[NE + threadIdx.x] = sacc;
+}
+
+// ------------------------------------------- orthonormalisation in L2(a)
+// From the Gram partials of Z with weights a: s = Z^T a, B = Z^T D_a Z.
+// Projecting out the constant (Z - 1 s^T, since sum a = 1) gives
+// B' = B - s s^T; with B' = L L^T, V = (Z - 1 s^T) L^-T is orthonormal in
+// L2(a) and orthogonal to the constants.  Writes R = L^-T (k x k), s.
+template <int KP>
+__global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out) {
+  constexpr int NE = KP * KP;
+  __shared__ double B[KP][KP + 1];
+  __shared__ double s[KP];
+  __shared__ double Li[KP][KP + 1];
+  for (int e = threadIdx.x; e < NE + KP; e += 256) {
+    double v = 0;
+    for (int b = 0; b < nblk; ++b) v += part[(size_t)b * (NE + KP) + e];
+    if (e < NE) B[e / KP][e % KP] = v;
+    else s[e - NE] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NE; e += 256) {
+    int i = e / KP, j = e % KP;
+    B[i][j] -= s[i] * s[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // symmetrise, regularise by a tiny multiple of the trace, Cholesky
+    double tr = 0;
+    for (int i = 0; i < KP; ++i) tr += B[i][i];
+    int ok = tr > 0;
+    for (int i = 0; i < KP; ++i)
+      for (int j = 0; j < i; ++j) B[j][i] = B[i][j] = 0.5 * (B[i][j] + B[j][i]);
+    for (int i = 0; i < KP; ++i) B[i][i] += 1e-13 * tr / KP;
+    for (int k = 0; k < KP; ++k) {
+      double d = B[k][k];
+      for (int j = 0; j < k; ++j) d -= B[k][j] * B[k][j];
+      if (!(d > 1e-30 * tr)) {
+        ok = 0;
+        d = 1e-30 * tr + 1e-300;
+      }
+      double lk = sqrt(d);
+      B[k][k] = lk;
+      for (int i = k + 1; i < KP; ++i) {
+        double v = B[i][k];
+        for (int j = 0; j < k; ++j) v -= B[i][j] * B[k][j];
+        B[i][k] = v / lk;
+      }
+    }
+    // Li = L^-1 (lower)
+    for (int j = 0; j < KP; ++j) {
+      for (int i = 0; i < KP; ++i) Li[i][j] = 0;
+      Li[j][j] = 1.0 / B[j][j];
+      for (int i = j + 1; i < KP; ++i) {
+        double v = 0;
+        for (int t = j; t < i; ++t) v -= B[i][t] * Li[t][j];
+        Li[i][j] = v / B[i][i];
+      }
+    }
+    *ok_out = ok;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NE; e += 256) {
+    int i = e / KP, j = e % KP;
+    R[e] = Li[j][i];  // R = L^-T, row-major
+  }
+  for (int e = threadIdx.x; e < KP; e += 256) s_out[e] = s[e];
+}
+
+// ------------------------------------------------------ Rayleigh-Ritz
+// T = U^T diag(b)^-1 U from Gram partials (U = P^T V, V orthonormal in
+// L2(a), so T = V^T D_a M V).  Cyclic Jacobi with a round-robin pairing
+// (k/2 disjoint rotations per step), then eigenpairs sorted descending:
+// Q (k x k, columns = eigenvectors, row-major), lam (k).
+template <int KP>
+__global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, double* Qout, double* lam, int sweeps) {
+  constexpr int NE = KP * KP;
+  constexpr int NP = KP / 2;
+  __shared__ double A[KP][KP + 1];
+  __shared__ double Q[KP][KP + 1];
+  __shared__ double cs[NP][2];
+  __shared__ int pr[NP][2];
+  __shared__ double off_s;
+  for (int e = threadIdx.x; e < NE; e += 256) {
+    double v = 0;
+    for (int b = 0; b < nblk; ++b) v += part[(size_t)b * (NE + KP) + e];
+    A[e / KP][e % KP] = v;
+    Q[e / KP][e % KP] = (e / KP == e % KP) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NE; e += 256) {
+    int i = e / KP, j = e % KP;
+    if (i < j) {
+      double v = 0.5 * (A[i][j] + A[j][i]);
+      A[i][j] = v;
+      A[j][i] = v;
+    }
+  }
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; ++sw) {
+    if (threadIdx.x == 0) {
+      double off = 0, dia = 0;
+      for (int i = 0; i < KP; ++i) {
+        dia += A[i][i] * A[i][i];
+        for (int j = 0; j < KP; ++j)
+          if (i != j) off += A[i][j] * A[i][j];
+      }
+      off_s = off <= 1e-30 * dia ? -1.0 : off;
+    }
+    __syncthreads();
+    if (off_s < 0) break;
+    for (int step = 0; step < KP - 1; ++step) {
+      if ((int)threadIdx.x < NP) {
+        int r = threadIdx.x;
+        auto pos = [&](int i) { return i == 0 ? 0 : 1 + (i - 1 + step) % (KP - 1); };
+        int p = pos(r), q = pos(KP - 1 - r);
+        if (p > q) { int t = p; p = q; q = t; }
+        pr[r][0] = p;
+        pr[r][1] = q;
+        double apq = A[p][q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > 1e-300) {
+          double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+          double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+        }
+        cs[r][0] = c;
+        cs[r][1] = s;
+      }
+      __syncthreads();
+      // columns: A <- A J, Q <- Q J
+      for (int e = threadIdx.x; e < NP * KP; e += 256) {
+        int r = e / KP, i = e % KP;
+        int p = pr[r][0], q = pr[r][1];
+        double c = cs[r][0], s = cs[r][1];
+        double aip = A[i][p], aiq = A[i][q];
+        A[i][p] = c * aip - s * aiq;
+        A[i][q] = s * aip + c * aiq;
+        double qip = Q[i][p], qiq = Q[i][q];
+        Q[i][p] = c * qip - s * qiq;
+        Q[i][q] = s * qip + c * qiq;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = threadIdx.x; e < NP * KP; e += 256) {
+        int r = e / KP, j = e % KP;
+        int p = pr[r][0], q = pr[r][1];
+        double c = cs[r][0], s = cs[r][1];
+        double apj = A[p][j], aqj = A[q][j];
+        A[p][j] = c * apj - s * aqj;
+        A[q][j] = s * apj + c * aqj;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int idx[KP];
+    for (int i = 0; i < KP; ++i) idx[i] = i;
+    for (int i = 0; i < KP; ++i)
+      for (int j = i + 1; j < KP; ++j)
+        if (A[idx[j]][idx[j]] > A[idx[i]][idx[i]]) {
+          int t = idx[i];
+          idx[i] = idx[j];
+          idx[j] = t;
+        }
+    for (int i = 0; i < KP; ++i) {
+      lam[i] = A[idx[i]][idx[i]];
+      for (int r = 0; r < KP; ++r) Qout[r * KP + i] = Q[r][idx[i]];
+    }
+  }
+}
+
+// out_i = ((Z_i - s) R) * rowscale_i   (k x k transform per row, FP64 math)
+template <int KP>
+__global__ __launch_bounds__(256) void k_affine(const float* Z, const double* s, const double* R, const double* rs,
+                                                int rs_invert, int n, float* out) {
+  __shared__ double Rs[KP][KP];
+  __shared__ double ss[KP];
+  for (int e = threadIdx.x; e < KP * KP; e += 256) Rs[e / KP][e % KP] = R[e];
+  if ((int)threadIdx.x < KP) ss[threadIdx.x] = s ? s[threadIdx.x] : 0.0;
+  __syncthreads();
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double z[KP];
+#pragma unroll
+  for (int l = 0; l < KP; ++l) z[l] = (double)Z[(size_t)i * KP + l] - ss[l];
+  double sc = 1.0;
+  if (rs) sc = rs_invert ? 1.0 / rs[i] : rs[i];
+  float o[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    double v = 0;
+#pragma unroll
+    for (int l = 0; l < KP; ++l) v += z[l] * Rs[l][j];
+    o[j] = (float)(v * sc);
+  }
+#pragma unroll
+  for (int j = 0; j < KP; ++j) out[(size_t)i * KP + j] = o[j];
+}
+
+// counter-based uniform(-1, 1) start block for columns >= col0 (splitmix64)
+__global__ void k_random_block(float* Z, int n, int KP, int col0, unsigned long long seed) {
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)n * KP) return;
+  int l = (int)(e % KP);
+  if (l < col0) return;
+  unsigned long long x = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(e + 1);
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  Z[e] = (float)((double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+}
+
+// out (n x ell FP64) = first ell columns of V (n x KP FP32)
+__global__ void k_take_cols(const float* V, int KP, int n, int ell, double* out) {
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)n * ell) return;
+  int i = (int)(e / ell), l = (int)(e % ell);
+  out[e] = (double)V[(size_t)i * KP + l];
+}
+
+// out (n x ellp) = first ell columns of V (n x kp), zero padded
+__global__ void k_repack(const float* V, int kp, int n, int ell, int ellp, float* out) {
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)n * ellp) return;
+  int i = (int)(e / ellp), l = (int)(e % ellp);
+  out[e] = l < ell ? V[(size_t)i * kp + l] : 0.f;
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_repack(const float* V, int kp, int n, int ell, int ellp, float* out, hipStream_t s) {
+  long long cnt = (long long)n * ellp;
+  hipLaunchKernelGGL(k_repack, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, V, kp, n, ell, ellp, out);
+  return hipGetLastError();
+}
+hipError_t launch_wgram(int kp, const float* Z, const double* w, int invert, int n, double* part, int nblk,
+                        hipStream_t s) {
+  int rpb = (n + nblk - 1) / nblk;
+  if (kp == 8) hipLaunchKernelGGL((k_wgram<8>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb);
+  else if (kp == 16) hipLaunchKernelGGL((k_wgram<16>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb);
+  else hipLaunchKernelGGL((k_wgram<32>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb);
+  return hipGetLastError();
+}
+hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok, hipStream_t s) {
+  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
+  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
+  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
+  return hipGetLastError();
+}
+hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, hipStream_t s) {
+  if (kp == 8) hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 30);
+  else if (kp == 16) hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 30);
+  else hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 30);
+  return hipGetLastError();
+}
+hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
+                         int n, float* out, hipStream_t s) {
+  int nb = (n + 255) / 256;
+  if (kp == 8) hipLaunchKernelGGL((k_affine<8>), dim3(nb), dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  else if (kp == 16) hipLaunchKernelGGL((k_affine<16>), dim3(nb), dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  else hipLaunchKernelGGL((k_affine<32>), dim3(nb), dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, hipStream_t s) {
+  long long cnt = (long long)n * kp;
+  hipLaunchKernelGGL(k_random_block, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, Z, n, kp, col0,
+                     (unsigned long long)seed);
+  return hipGetLastError();
+}
+hipError_t launch_take_cols(const float* V, int kp, int n, int ell, double* out, hipStream_t s) {
+  long long cnt = (long long)n * ell;
+  hipLaunchKernelGGL(k_take_cols, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, V, kp, n, ell, out);
+  return hipGetLastError();
+}
+
+}  // namespace sknr

@@ -1,0 +1,49 @@
+"""C-ABI checks that need no GPU: the library loads and exports every entry
+point the public header declares; status strings and error paths."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sknr.h")
+LIB = os.path.join(ROOT, "paper_2506_14780_amd", "libsknr.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sknr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("sknr_ctx_create", "sknr_ctx_destroy", "sknr_solve", "sknr_c_transform_row",
+                     "sknr_c_transform_col", "sknr_projected_system", "sknr_newton_step",
+                     "sknr_spectral_basis", "sknr_evaluate", "sknr_coupling", "sknr_status_str",
+                     "sknr_last_error"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsknr.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsknr.so not built")
+def test_status_strings_and_null_context():
+    lib = ctypes.CDLL(LIB)
+    lib.sknr_status_str.restype = ctypes.c_char_p
+    lib.sknr_last_error.restype = ctypes.c_char_p
+    lib.sknr_version.restype = ctypes.c_char_p
+    assert lib.sknr_status_str(0) == b"ok"
+    assert b"invalid" in lib.sknr_status_str(-1)
+    assert b"gfx950" in lib.sknr_version()
+    # a NULL context is rejected without touching a device
+    st = lib.sknr_solve(None, None, None, None, None, None)
+    assert st == -1
+    assert lib.sknr_last_error()
+    assert lib.sknr_ctx_destroy(None) == 0

@@ -1,0 +1,144 @@
+"""GPU parity of whole solves (Algorithm 4.1 and eps schedules) against the
+FP64 oracle.
+
+Targets: gauge-invariant potential error e_pot <= 1e-5, transport cost
+within 1e-6 relative, FP64 marginal error of the returned pair below the
+tolerance, iteration counts within 10% of the oracle's (SK-NR given the
+oracle's basis)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests._helpers import e_pot, fp32_sqeuclid, gpu_problem, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2506_14780_amd as sk
+    return sk
+
+
+@pytest.fixture(scope="module")
+def ctx(sk):
+    c = sk.Context(0)
+    yield c
+    c.close()
+
+
+def test_sk_stored_uniform_square(sk, ctx):
+    """256 x 256, eps = 1e-2, stored FP32 cost: plain SK to 1e-6."""
+    prob = W.uniform_square(256, seed=0)
+    C32 = O.sqeuclid_cost(prob.x, prob.y).astype(np.float32)
+    C = C32.astype(np.float64)
+    print("case sk_stored 256 eps=1e-2", flush=True)
+    f, g, res = sk.solve(ctx, gpu_problem(prob, stored=True, C32=C32), [1e-2], tol=1e-6, max_iter=20000)
+    ref = O.sinkhorn(C, prob.a, prob.b, 1e-2, tol=1e-6, max_iter=20000)
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    fr, gr = O.normalize_gauge(ref.f, ref.g, prob.a, prob.b)
+    print(res["total_iters"], ref.iters, res["marginal_err"], flush=True)
+    assert res["status"] == 0
+    assert res["marginal_err"] < 1e-6
+    assert abs(res["total_iters"] - ref.iters) <= max(2, 0.02 * ref.iters)
+    assert e_pot(f, g, fr, gr, C) < 1e-5
+    cost_ref = O.transport_cost(fr, gr, C, prob.a, prob.b, 1e-2)
+    assert res["transport_cost"] == pytest.approx(cost_ref, rel=1e-6)
+    assert abs(f @ prob.a - g @ prob.b) < 1e-12
+
+
+def test_sknr_given_oracle_basis(sk, ctx):
+    """SK-NR(10) at eps = 5e-3 warm-started from eps = 1e-2, with the
+    oracle's V_l(1e-2): iteration counts and the optimum match."""
+    prob = W.uniform_square(256, seed=0)
+    C32 = O.sqeuclid_cost(prob.x, prob.y).astype(np.float32)
+    C = C32.astype(np.float64)
+    r1 = O.sinkhorn(C, prob.a, prob.b, 1e-2, tol=1e-9, max_iter=100000)
+    V, _ = O.spectral_basis(r1.f, r1.g, C, prob.a, prob.b, 1e-2, 10, method="dense")
+    ref = O.sknr(C, prob.a, prob.b, 5e-3, tol=1e-6, max_iter=20000, V=V, f0=r1.f)
+    ref_sk = O.sinkhorn(C, prob.a, prob.b, 5e-3, tol=1e-6, max_iter=20000, f0=r1.f)
+    print("case sknr oracle V: oracle iters", ref.iters, "sk", ref_sk.iters, flush=True)
+    f, g, res = sk.solve(ctx, gpu_problem(prob, stored=True, C32=C32), [5e-3], tol=1e-6, max_iter=20000,
+                         ell=10, warm_mode=sk.WARM_USER, V0=to_dev(V), f0=to_dev(r1.f), first_stage_nr=True)
+    st = res["stages"][0]
+    print("gpu", st, flush=True)
+    assert res["status"] == 0 and res["marginal_err"] < 1e-6
+    assert abs(st["iters"] - ref.iters) <= max(2, 0.1 * ref.iters)
+    fr, gr = O.normalize_gauge(ref.f, ref.g, prob.a, prob.b)
+    assert e_pot(f.cpu().numpy(), g.cpu().numpy(), fr, gr, C) < 1e-5
+    assert st["newton_accepted"] > 0
+
+
+def test_sk_points_schedule(sk, ctx):
+    """Cost from points (FP32 C~), GMM vs uniform, a 4-stage eps ladder."""
+    prob = W.gmm_vs_uniform(1024, seed=1)
+    ladder = [1e-1, 5e-2, 2.5e-2, 1.25e-2]
+    print("case sk_points 1024 ladder", flush=True)
+    f, g, res = sk.solve(ctx, gpu_problem(prob), ladder, tol=1e-6, max_iter=20000)
+    Ct = fp32_sqeuclid(prob.x, prob.y).astype(np.float64)
+    fo, go, rs = O.solve_schedule(Ct, prob.a, prob.b, ladder, 1e-6, 20000)
+    fo, go = O.normalize_gauge(fo, go, prob.a, prob.b)
+    print([s["iters"] for s in res["stages"]], [r.iters for r in rs], res["marginal_err"], flush=True)
+    assert res["status"] == 0 and res["marginal_err"] < 1e-6
+    for s, r in zip(res["stages"], rs):
+        assert abs(s["iters"] - r.iters) <= max(2, 0.05 * r.iters)
+    assert e_pot(f.cpu().numpy(), g.cpu().numpy(), fo, go, Ct) < 1e-5
+    cost_ref = O.transport_cost(fo, go, Ct, prob.a, prob.b, ladder[-1])
+    assert res["transport_cost"] == pytest.approx(cost_ref, rel=1e-6)
+
+
+def test_transposed_problem(sk, ctx):
+    """n > m runs on the transpose internally; outputs come back in the
+    caller's orientation."""
+    prob = _p = W.gmm_vs_uniform(700, 300, seed=3)
+    print("case transposed 700x300", flush=True)
+    f, g, res = sk.solve(ctx, gpu_problem(prob), [5e-2], tol=1e-7, max_iter=20000)
+    assert res["transposed"] == 1
+    Ct = fp32_sqeuclid(prob.x, prob.y).astype(np.float64)
+    ref = O.sinkhorn(Ct, prob.a, prob.b, 5e-2, tol=1e-9, max_iter=100000)
+    fr, gr = O.normalize_gauge(ref.f, ref.g, prob.a, prob.b)
+    assert f.shape[0] == 700 and g.shape[0] == 300
+    assert e_pot(f.cpu().numpy(), g.cpu().numpy(), fr, gr, Ct) < 1e-5
+
+
+def test_sknr_sequential_warm_start_schedule(sk, ctx):
+    """Sequential spectral warm start (Sec. 4-5): each stage after the
+    first runs SK-NR(l) with V_l computed on the GPU at the previous stage's
+    optimum.  Same optimum as the oracle's schedule; fewer iterations than
+    plain SK on the GPU."""
+    prob = W.uniform_square(256, seed=0)
+    C32 = O.sqeuclid_cost(prob.x, prob.y).astype(np.float32)
+    C = C32.astype(np.float64)
+    ladder = [4e-2, 2e-2, 1e-2, 5e-3]
+    gp = gpu_problem(prob, stored=True, C32=C32)
+    print("case sknr sequential", flush=True)
+    f0, g0, r0 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=50000)
+    f1, g1, r1 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=50000, ell=10, warm_mode=sk.WARM_SEQUENTIAL)
+    it0 = [s["iters"] for s in r0["stages"]]
+    it1 = [s["iters"] for s in r1["stages"]]
+    print("SK", it0, "SK-NR", it1, [s["eig_iters"] for s in r1["stages"]],
+          [s["newton_accepted"] for s in r1["stages"]], flush=True)
+    fo, go, ro = O.solve_schedule(C, prob.a, prob.b, ladder, 1e-6, 50000, ell=10)
+    print("oracle SK-NR", [r.iters for r in ro], flush=True)
+    assert r1["status"] == 0 and r1["marginal_err"] < 1e-6
+    fo, go = O.normalize_gauge(fo, go, prob.a, prob.b)
+    assert e_pot(f1.cpu().numpy(), g1.cpu().numpy(), fo, go, C) < 1e-5
+    assert sum(it1[1:]) < sum(it0[1:])
+    for a_, b_ in zip(it1[1:], [r.iters for r in ro][1:]):
+        assert a_ <= 1.25 * b_ + 3
+
+
+def test_sknr_static_warm_start(sk, ctx):
+    """Static warm start (Sec. 5, middle panel of Fig. 5.1): V_l from a
+    plain SK solve at eps' = 2e-2, used at eps = 5e-3 from f = 0."""
+    prob = W.uniform_square(256, seed=0)
+    C32 = O.sqeuclid_cost(prob.x, prob.y).astype(np.float32)
+    gp = gpu_problem(prob, stored=True, C32=C32)
+    print("case sknr static", flush=True)
+    f, g, r = sk.solve(ctx, gp, [5e-3], tol=1e-6, max_iter=50000, ell=10, warm_mode=sk.WARM_STATIC,
+                       eps_prime=2e-2, first_stage_nr=True)
+    f0, g0, r0 = sk.solve(ctx, gp, [5e-3], tol=1e-6, max_iter=50000)
+    print("static SK-NR", r["stages"][0], "SK", r0["stages"][0]["iters"], flush=True)
+    assert r["status"] == 0 and r["marginal_err"] < 1e-6
+    assert r["stages"][0]["iters"] < r0["stages"][0]["iters"]
