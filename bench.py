@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark: entropic OT solves per second to a 1e-6 L1 marginal error on
+one MI355X, SK-NR(l) with the sequential spectral warm start against plain
+log-domain Sinkhorn on the same GPU, with p50/p99 solve latency.
+
+Workload (one "step" = one full solve): n = m = 4096 points in [0,1]^2,
+x from a 3-component Gaussian mixture (sigma 0.05), y uniform, weights
+Dirichlet(5); squared-Euclidean cost built on the fly in FP32; eps annealed
+1e-1 -> 1e-3 by halving (8 stages), each stage run to an FP64-verified L1
+marginal error below 1e-6.  Inputs are resident in HBM before timing.
+
+Prints one JSON line (see the fields below).  `--gpus N` with N > 1 exits:
+the solver runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "OT solves/s to 1e-6 marginal err (SK-NR vs SK); p50/p99 latency"
+
+# MI355X peaks used for the roofline (public figures; the VALU peak is
+# derived from unit counts: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz).
+PEAK_HBM_GBS = 8000.0
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.32 T lane-instructions/s
+
+
+def algorithmic_work(kind: str):
+    """(bound, work per cost element, unit) of a sweep kind.
+
+    Points sweeps ("alu"): per element the squared distance for d = 2 (2
+    sub, 1 mul, 1 fma), the exponent U - C and its scaling by 1/eps, the
+    running max, exp2 (issued at half rate: 2 slots) and the accumulation:
+    10 VALU slots; a weighted sweep adds one FMA per basis column.
+    Stored-cost sweeps ("hbm"): 4 bytes of C read per element."""
+    width = int(kind.rsplit("_l", 1)[1]) if "_l" in kind else 0
+    if "stored" in kind:
+        return "hbm", 4.0, "GB/s"
+    return "alu", 10.0 + width, "TOP/s"
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(prob, ladder, tol, ell, iters_per_stage):
+    """The FP64 oracle, untuned, timed on a bounded sample of the same
+    workload on the host: two plain SK iterations, two SK-NR(l)
+    iterations and one warm-start eigensolve at the 4096 x 4096 size,
+    scaled to one full solve with the per-stage iteration counts of the
+    GPU run (which match the oracle's on smaller instances)."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    try:
+        C = O.sqeuclid_cost(prob.x, prob.y)
+        a, b = prob.a, prob.b
+        eps = ladder[1]
+        f = np.zeros(prob.n)
+        t0 = time.perf_counter()
+        r = O.sinkhorn(C, a, b, ladder[0], tol=0.0, max_iter=2, f0=f)
+        t_sk = (time.perf_counter() - t0) / 2
+        t0 = time.perf_counter()
+        V, _ = O.spectral_basis(r.f, r.g, C, a, b, ladder[0], ell, method="arpack")
+        t_eig = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.sknr(C, a, b, eps, tol=0.0, max_iter=2, V=V, f0=r.f)
+        t_nr = (time.perf_counter() - t0) / 2
+    finally:
+        if limiter is not None:
+            limiter.unregister() if hasattr(limiter, "unregister") else None
+    est = t_sk * iters_per_stage[0] + t_nr * sum(iters_per_stage[1:]) + t_eig * (len(ladder) - 1)
+    return {
+        "value": 1.0 / est,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"FP64 numpy oracle on the {prob.n}x{prob.m} workload, 1 thread: 2 SK iterations "
+                   f"({t_sk:.2f} s each), 2 SK-NR(l={ell}) iterations ({t_nr:.2f} s each), 1 ARPACK "
+                   f"warm-start eigensolve ({t_eig:.2f} s); scaled to one solve with the GPU run's "
+                   f"per-stage iteration counts {iters_per_stage}"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sk-steps", type=int, default=3, help="timed plain-SK solves for the comparison")
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--ell", type=int, default=30)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iter", type=int, default=200000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sk", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(how the path would shard is described in the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2506_14780_amd as sk
+    import workloads as W
+
+    prob = W.gmm_vs_uniform(args.n, seed=1)
+    ladder = list(W.EPS_LADDER_C2)
+    dev = torch.device("cuda:0")
+    gp = sk.Problem(a=torch.from_numpy(prob.a).to(dev), b=torch.from_numpy(prob.b).to(dev),
+                    x=torch.from_numpy(prob.x).to(dev), y=torch.from_numpy(prob.y).to(dev))
+    ctx = sk.Context(0)
+    f_out = torch.empty(prob.n, dtype=torch.float64, device=dev)
+    g_out = torch.empty(prob.m, dtype=torch.float64, device=dev)
+
+    def one(ell):
+        return sk.solve(ctx, gp, ladder, tol=args.tol, max_iter=args.max_iter, ell=ell,
+                        warm_mode=sk.WARM_SEQUENTIAL, f_out=f_out, g_out=g_out)[2]
+
+    def timed(ell, steps, warmup):
+        for _ in range(warmup):
+            one(ell)
+        torch.cuda.synchronize()
+        lat = []
+        res = None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            res = one(ell)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - s0)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        return total, lat, res
+
+    total, lat, res = timed(args.ell, args.steps, args.warmup)
+    iters_nr = [s["iters"] for s in res["stages"]]
+    out = {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"gmm_vs_uniform n=m={args.n} d=2, cost built on the fly, eps 1e-1->1e-3 halving "
+                         f"({len(ladder)} stages), tol {args.tol:g} L1 (FP64-verified), SK-NR(l={args.ell}) "
+                         f"sequential spectral warm start"),
+            "n": prob.n, "m": prob.m, "d": 2, "eps_ladder": ladder, "tol": args.tol, "ell": args.ell,
+        },
+        "p50_ms": 1e3 * percentile(lat, 50),
+        "p99_ms": 1e3 * percentile(lat, 99),
+        "iters_per_stage": iters_nr,
+        "eig_iters_per_stage": [s["eig_iters"] for s in res["stages"]],
+        "newton_accepted_per_stage": [s["newton_accepted"] for s in res["stages"]],
+        "marginal_err": res["marginal_err"],
+        "status": res["status"],
+    }
+    if not args.no_sk:
+        tsk, latsk, rsk = timed(0, args.sk_steps, 1)
+        out["sk"] = {
+            "value": args.sk_steps / tsk, "unit": "solves/s",
+            "p50_ms": 1e3 * percentile(latsk, 50), "p99_ms": 1e3 * percentile(latsk, 99),
+            "iters_per_stage": [s["iters"] for s in rsk["stages"]],
+            "marginal_err": rsk["marginal_err"], "status": rsk["status"],
+        }
+        out["speedup_vs_sk"] = out["value"] / out["sk"]["value"]
+
+    # roofline of the dominant kernel: one more solve with per-kernel HIP
+    # events on the solve's stream
+    ctx.profile(True)
+    one(args.ell)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    dom = max(prof, key=lambda e: e["total_ms"])
+    bound, per_unit, unit = algorithmic_work(dom["name"])
+    avg_s = dom["total_ms"] / dom["launches"] / 1e3
+    per_launch = per_unit * dom["units"] / dom["launches"]
+    if bound == "hbm":
+        achieved, peak = per_launch / avg_s / 1e9, PEAK_HBM_GBS
+    else:
+        achieved, peak = per_launch / avg_s / 1e12, PEAK_VALU_TOPS
+    out["roofline"] = {
+        "bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+        "traffic": None, "kernel": dom["name"], "avg_launch_us": avg_s * 1e6,
+        "launches_per_solve": dom["launches"], "elements_per_launch": dom["units"] / dom["launches"],
+        "share_of_sweep_time": dom["total_ms"] / sum(e["total_ms"] for e in prof),
+    }
+    out["kernel_profile"] = [{"name": e["name"], "launches": e["launches"],
+                              "avg_us": 1e3 * e["total_ms"] / max(1, e["launches"]),
+                              "total_ms": e["total_ms"]} for e in sorted(prof, key=lambda e: -e["total_ms"])]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, ladder, args.tol, args.ell, iters_nr)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -104,10 +104,10 @@ typedef struct sknr_opts {
   int32_t warm_mode;      /* enum sknr_warm_mode */
   double eps_prime;       /* STATIC: eps' of the warm-start solve */
   int32_t eig_oversample; /* extra subspace columns (0 -> 8) */
-  int32_t eig_max_iter;   /* subspace iterations cap (0 -> 200) */
-  double eig_tol;         /* Ritz-value stagnation tolerance (0 -> 1e-7) */
+  int32_t eig_max_iter;   /* subspace iterations cap (0 -> 100) */
+  double eig_tol;         /* Ritz-value stagnation tolerance (0 -> 1e-6) */
   int32_t check_every;    /* iterations per host convergence poll (0 -> auto) */
-  int32_t first_stage_nr; /* 1: allow SK-NR on stage 0 (needs WARM_USER) */
+  int32_t first_stage_nr; /* 1: SK-NR also on stage 0 (WARM_USER or WARM_STATIC) */
   const double* f0;       /* [device] optional n FP64 initial f at eps[0] (NULL -> 0) */
   const double* V0;       /* [device] optional n x ell FP64 basis (WARM_USER) */
   uint64_t seed;          /* seed of the subspace-iteration start block */
@@ -235,6 +235,24 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps,
  * row-major.  Diagnostic; O(nm) memory. */
 int sknr_coupling(void* ctx, const sknr_problem* prob, double eps,
                   const double* f, const double* g, float* P_out, void* stream);
+
+/* ------------------------------------------------------------ profiling */
+typedef struct sknr_kprof {
+  char name[64];        /* kernel kind, e.g. "sweep_stream_points_l0" */
+  int64_t launches;     /* launches timed */
+  double total_ms;      /* summed duration (HIP events on the launch stream) */
+  double units;         /* algorithmic cost elements processed (n_out * n_red per sweep) */
+} sknr_kprof;
+
+/* Enable (1) or disable (0) per-kernel timing: every c-transform sweep
+ * launched by this context is bracketed by HIP events recorded on its
+ * stream, and durations are accumulated per kernel kind.  Resets the
+ * accumulated table.  Adds two event records per sweep. */
+int sknr_profile(void* ctx, int32_t enable);
+
+/* Copy up to max_entries accumulated entries into out [host]; *count
+ * [host] receives the number of kinds recorded. */
+int sknr_profile_read(void* ctx, sknr_kprof* out, int32_t max_entries, int32_t* count);
 
 /* ---------------------------------------------------------------- errors */
 const char* sknr_status_str(int status);

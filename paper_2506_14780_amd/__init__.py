@@ -73,6 +73,10 @@ class _Eval(ctypes.Structure):
                 ("dual_value", _d), ("primal_value", _d), ("mass", _d)]
 
 
+class _KProf(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", _i64), ("total_ms", _d), ("units", _d)]
+
+
 def _sig(name, args):
     fn = getattr(lib, name)
     fn.argtypes = args
@@ -96,6 +100,8 @@ _sig("sknr_spectral_basis", [_p, _P(_Problem), _d, _p, _i32, _i32, _i32, _d, cty
                              _P(_d), _P(_i32), _p])
 _sig("sknr_evaluate", [_p, _P(_Problem), _d, _p, _p, _P(_Eval), _p])
 _sig("sknr_coupling", [_p, _P(_Problem), _d, _p, _p, _p, _p])
+_sig("sknr_profile", [_p, _i32])
+_sig("sknr_profile_read", [_p, _P(_KProf), _i32, _P(_i32)])
 
 
 class SknrError(RuntimeError):
@@ -134,6 +140,18 @@ class Context:
         _check(lib.sknr_ctx_create(device, hbm_budget_bytes, ctypes.byref(h)), "sknr_ctx_create")
         self.handle = h
         self.device = device
+
+    def profile(self, enable: bool = True):
+        """Per-kernel timing with HIP events (resets the table)."""
+        _check(lib.sknr_profile(self.handle, 1 if enable else 0), "sknr_profile")
+
+    def profile_read(self) -> list:
+        cnt = _i32()
+        _check(lib.sknr_profile_read(self.handle, None, 0, ctypes.byref(cnt)), "sknr_profile_read")
+        arr = (_KProf * max(1, cnt.value))()
+        _check(lib.sknr_profile_read(self.handle, arr, cnt.value, ctypes.byref(cnt)), "sknr_profile_read")
+        return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
+                     units=arr[i].units) for i in range(cnt.value)]
 
     def close(self):
         if self.handle:

@@ -1,6 +1,7 @@
 """Build libsknr.so in-tree with hipcc for gfx950.
 
-Usage:  python -m paper_2506_14780_amd.build   (or call build()).
+Usage:  python paper_2506_14780_amd/build.py   (or call build()).
+Run it as a script (not with -m): importing the package loads the library.
 The library lands next to this file; the Python binding loads it from
 there.  Every build recompiles from source.
 """

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -63,11 +64,86 @@ struct Arena {
   }
 };
 
+// Per-kernel-kind timing with HIP events recorded on the launch stream
+// around each sweep (enabled by sknr_profile).
+struct ProfEntry {
+  std::string name;
+  long long launches = 0;
+  double total_ms = 0;
+  double units = 0;  // algorithmic elements (n_out * n_red) processed
+};
+struct Pending {
+  int kind;
+  hipEvent_t e0, e1;
+  double units;
+};
+// A captured chunk of solver iterations.  Every pointer and constant baked
+// into its kernel arguments is part of the key; eps-dependent values live
+// in the device state, so one graph serves all stages of a schedule.
+struct GraphKey {
+  const void* ws;
+  const void* C;
+  const void* X;
+  const void* Y;
+  const void* wX;
+  const void* wY;
+  long long ldc;
+  int n, m, d, kind, ell, ellp, iters, ctrans;
+  float cscale, cmax;
+  void* stream;
+  bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+struct CachedGraph {
+  GraphKey key;
+  hipGraphExec_t exec;
+};
 struct Ctx {
   int device = 0;
   uint64_t budget = 0;
   Arena arena;
+  hipStream_t own = nullptr;     // solver stream (default priority); graphs are captured on it
+  hipEvent_t order_ev = nullptr;  // orders the solver stream after the caller's stream
+  bool use_graphs = true;
+  std::vector<CachedGraph> graphs;
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   DevState* st_host = nullptr;  // pinned mirror of the state
+  bool profile = false;
+  std::vector<ProfEntry> prof;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> evpool;
+  hipEvent_t get_event() {
+    if (!evpool.empty()) {
+      hipEvent_t e = evpool.back();
+      evpool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) throw Err{SKNR_EDEVICE, "hipEventCreate failed"};
+    return e;
+  }
+  int kind_of(const std::string& name) {
+    for (size_t i = 0; i < prof.size(); ++i)
+      if (prof[i].name == name) return (int)i;
+    prof.push_back(ProfEntry{name});
+    return (int)prof.size() - 1;
+  }
+  // after a stream synchronisation: fold completed event pairs
+  void drain() {
+    for (auto& p : pending) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+        prof[p.kind].launches += 1;
+        prof[p.kind].total_ms += ms;
+        prof[p.kind].units += p.units;
+      }
+      evpool.push_back(p.e0);
+      evpool.push_back(p.e1);
+    }
+    pending.clear();
+  }
 };
 
 struct Prepared {
@@ -96,7 +172,6 @@ struct WS {
   float *V, *W;
   int ellp;
   float* part;
-  unsigned* cnt_cb;
   double *blk_err, *blk_dot;
   float* blk_max;
   double* nrpart;
@@ -109,7 +184,7 @@ struct WS {
   float2 *lXdf, *lYdf;
   double *fX64, *gY64;
   double* scratch;
-  double *evrow, *evcol, *evscal, *evout;
+  double *evrow, *evcol, *evscal, *evout, *evblk;
   double* Gout;
   double* gout;
   // warm start (block width up to 32)
@@ -230,8 +305,10 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   auto add = [&](size_t x) { b += (x + 255) & ~size_t(255); };
   int ns, rps, nb, nbmax = 0;
   size_t pmax = 0;
+  // weighted sweeps run l-wide (Newton) or up to 32-wide (warm start)
+  const int ellw = ellp > 0 ? 32 : 0;
   // T_c (output Y), with and without weights
-  for (int e : {0, ellp}) {
+  for (int e : {0, ellp, ellw}) {
     size_t p = sweep_part_floats(m, n, e, P.kind, P.d, stream_vec(P, m), &ns, &rps, &nb, col_is_stream(P));
     pmax = std::max(pmax, p);
     nbmax = std::max(nbmax, nb);
@@ -248,11 +325,10 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   add(sizeof(float) * (size_t)n * std::max(ellp, 1));
   add(sizeof(float) * (size_t)m * std::max(ellp, 1));
   add(sizeof(float) * pmax + 16);
-  add(sizeof(unsigned) * (size_t)(std::max(n, m) / 64 + 16));
   add(sizeof(double) * nbmax * 2);
   add(sizeof(float) * nbmax);
   int nrb = 64, ncb = 64;
-  add(sizeof(double) * (nrb + ncb) * (size_t)(std::max(ellp, 1) * std::max(ellp, 1) + std::max(ellp, 1)));
+  add(sizeof(double) * (nrb + ncb) * (size_t)(std::max(ellw, 1) * std::max(ellw, 1) + std::max(ellw, 1)));
   add(sizeof(float) * 32);
   add(sizeof(double) * 32);
   add(sizeof(DevState));
@@ -266,6 +342,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   add(sizeof(double) * (size_t)erb * P.m0);
   add(sizeof(double) * (size_t)ecb * erb * 3);
   add(sizeof(double) * 16);
+  add(sizeof(double) * ((P.n0 + 255) / 256 + (P.m0 + 255) / 256 + 2));
   add(sizeof(double) * 32 * 32);
   add(sizeof(double) * 32);
   if (ellp > 0) {
@@ -281,6 +358,7 @@ WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
   size_t need = ws_bytes(P, ellp, nullptr);
   if (need > c->arena.cap) {
     HIPCHK(hipStreamSynchronize(s));
+    c->drop_graphs();  // captured kernels point into the old arena
     if (c->arena.base) HIPCHK(hipFree(c->arena.base));
     c->arena.base = nullptr;
     c->arena.cap = 0;
@@ -307,7 +385,8 @@ WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
   w.W = (float*)A.take(sizeof(float) * (size_t)m * std::max(ellp, 1));
   int ns, rps, nb, nbmax = 0;
   size_t pmax = 0;
-  for (int e : {0, ellp}) {
+  const int ellw = ellp > 0 ? 32 : 0;
+  for (int e : {0, ellp, ellw}) {
     pmax = std::max(pmax, sweep_part_floats(m, n, e, P.kind, P.d, stream_vec(P, m), &ns, &rps, &nb,
                                             col_is_stream(P)));
     nbmax = std::max(nbmax, nb);
@@ -317,17 +396,14 @@ WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
   }
   nbmax = std::max(nbmax, (std::max(n, m) + 255) / 256 + 1);
   w.part = (float*)A.take(sizeof(float) * pmax + 16);
-  const size_t ncnt = (size_t)(std::max(n, m) / 64 + 16);
-  w.cnt_cb = (unsigned*)A.take(sizeof(unsigned) * ncnt);
-  // the split-K "last block" counters must start at zero; the arena layout
-  // depends on the problem shape, so clear them every time it is carved
-  HIPCHK(hipMemsetAsync(w.cnt_cb, 0, sizeof(unsigned) * ncnt, s));
   w.blk_err = (double*)A.take(sizeof(double) * nbmax);
   w.blk_dot = (double*)A.take(sizeof(double) * nbmax);
   w.blk_max = (float*)A.take(sizeof(float) * nbmax);
-  w.nr_rows_blk = std::min(64, std::max(1, (n + 255) / 256));
-  w.nr_cols_blk = std::min(64, std::max(1, (m + 255) / 256));
-  int e1 = std::max(ellp, 1);
+  // at most 16 + 16 partial blocks: the one-wave solver sums them with
+  // independent loads
+  w.nr_rows_blk = std::min(16, std::max(1, (n + 255) / 256));
+  w.nr_cols_blk = std::min(16, std::max(1, (m + 255) / 256));
+  int e1 = std::max(ellw, 1);
   w.nrpart = (double*)A.take(sizeof(double) * (128) * (size_t)(e1 * e1 + e1));
   w.coef32 = (float*)A.take(sizeof(float) * 32);
   w.coef64 = (double*)A.take(sizeof(double) * 32);
@@ -346,6 +422,7 @@ WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
   w.evcol = (double*)A.take(sizeof(double) * (size_t)erb * P.m0);
   w.evscal = (double*)A.take(sizeof(double) * (size_t)ecb * erb * 3);
   w.evout = (double*)A.take(sizeof(double) * 16);
+  w.evblk = (double*)A.take(sizeof(double) * ((P.n0 + 255) / 256 + (P.m0 + 255) / 256 + 2));
   w.Gout = (double*)A.take(sizeof(double) * 32 * 32);
   w.gout = (double*)A.take(sizeof(double) * 32);
   w.have_Vw = false;
@@ -401,17 +478,30 @@ struct Engine {
     a.d = P.d;
     a.cscale = P.cscale;
     a.cmax = P.cmax;
-    a.K = (float)(1.4426950408889634 / eps);
-    a.inv_eps = (float)(1.0 / eps);
-    a.eps_df = split_df(eps);
-    a.eln2_df = split_df(eps * 0.6931471805599453);
-    a.tol = tol;
     a.part = w.part;
-    a.cnt_cb = w.cnt_cb;
     a.blk_err = w.blk_err;
     a.blk_dot = w.blk_dot;
     a.blk_max = w.blk_max;
     a.st = w.st;
+  }
+
+  void launch_sweep(const SweepArgs& a, bool stream_kernel, bool vec, int ell) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->profile) {
+      e0 = c->get_event();
+      e1 = c->get_event();
+      HIPCHK(hipEventRecord(e0, s));
+    }
+    if (stream_kernel) HIPCHK(launch_sweep_stream(a, P.kind, vec, s));
+    else HIPCHK(launch_sweep_rows(a, s));
+    if (c->profile) {
+      HIPCHK(hipEventRecord(e1, s));
+      char nm[96];
+      std::snprintf(nm, sizeof nm, "%s_%s_l%d", stream_kernel ? "sweep_stream" : "sweep_rows",
+                    P.kind == SKNR_COST_STORED ? "stored" : (P.d <= 8 ? "points" : "points_gen"),
+                    ell <= 0 ? 0 : ell_pad(ell));
+      c->pending.push_back(Pending{c->kind_of(nm), e0, e1, (double)a.n_out * (double)a.n_red});
+    }
   }
 
   // g_out = T_c(U_in) on side Y (eq. foc_g), hat form
@@ -440,12 +530,10 @@ struct Engine {
     a.gate = gate;
     a.flags = flags;
     a.gsel_val = gsel_val;
-    a.cnt_id = 0;
     bool st = col_is_stream(P);
     bool vec = stream_vec(P, a.n_out);
     sweep_part_floats(a.n_out, a.n_red, ell, P.kind, P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
-    if (st) HIPCHK(launch_sweep_stream(a, P.kind, vec, s));
-    else HIPCHK(launch_sweep_rows(a, s));
+    launch_sweep(a, st, vec, ell);
   }
 
   // f_out = T_r(U_in) on side X (eq. foc_f)
@@ -473,16 +561,23 @@ struct Engine {
     a.wmode = wmode;
     a.gate = gate;
     a.flags = flags;
-    a.cnt_id = 1;
     bool st = row_is_stream(P);
     bool vec = stream_vec(P, a.n_out);
     sweep_part_floats(a.n_out, a.n_red, ell, P.kind, P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
-    if (st) HIPCHK(launch_sweep_stream(a, P.kind, vec, s));
-    else HIPCHK(launch_sweep_rows(a, s));
+    launch_sweep(a, st, vec, ell);
   }
 
+  void set_consts(DevState& z) const {
+    z.eps = eps;
+    z.tol = tol;
+    z.K = (float)(1.4426950408889634 / eps);
+    z.inv_eps = (float)(1.0 / eps);
+    z.eps_df = split_df(eps);
+    z.eln2_df = split_df(eps * 0.6931471805599453);
+  }
   void init_state() {
     DevState z{};
+    set_consts(z);
     std::memcpy(c->st_host, &z, sizeof(DevState));
     HIPCHK(hipMemcpyAsync(w.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -490,6 +585,7 @@ struct Engine {
   DevState read_state() {
     HIPCHK(hipMemcpyAsync(c->st_host, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (c->profile) c->drain();
     DevState r;
     std::memcpy(&r, c->st_host, sizeof(DevState));
     return r;
@@ -507,7 +603,7 @@ struct Engine {
   void newton(int ell, int gate_base) {
     HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
                               w.st, gate_base, s));
-    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, eps, w.coef32, w.coef64, w.Gout, w.gout,
+    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout,
                            w.st, gate_base, s));
     HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.blk_dot, w.blk_max, w.st,
                            gate_base | G_CHOL_OK, DOT_FP, MA_FP, s));
@@ -537,41 +633,93 @@ struct Engine {
                 G_NOT_DONE | G_ACCEPT, 0);
   }
 
+  // k iterations as one captured graph (k even for the SK ping-pong, which
+  // then starts and ends on parity 0)
+  hipGraphExec_t chunk_graph(int ell, int k) {
+    GraphKey key;
+    std::memset(&key, 0, sizeof key);
+    key.ws = c->arena.base;
+    key.C = P.C;
+    key.X = P.X;
+    key.Y = P.Y;
+    key.wX = P.wX;
+    key.wY = P.wY;
+    key.ldc = P.ldc;
+    key.n = P.n;
+    key.m = P.m;
+    key.d = P.d;
+    key.kind = P.kind;
+    key.ell = ell;
+    key.ellp = w.ellp;
+    key.iters = k;
+    key.ctrans = P.ctrans ? 1 : 0;
+    key.cscale = P.cscale;
+    key.cmax = P.cmax;
+    key.stream = (void*)s;
+    for (auto& g : c->graphs)
+      if (g.key == key) return g.exec;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int t = 0; t < k; ++t) {
+      if (ell > 0) sknr_iter(ell, false);
+      else sk_iter(t & 1);
+    }
+    hipGraph_t g;
+    HIPCHK(hipStreamEndCapture(s, &g));
+    hipGraphExec_t ge;
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    if (c->graphs.size() >= 32) c->drop_graphs();
+    c->graphs.push_back(CachedGraph{key, ge});
+    return ge;
+  }
+
   // Run one stage of Algorithm 4.1 from the current (F, G[0]); returns
   // iterations and sets *converged.  G ends in w.G[0].
   int run_stage(int ell, int max_iter, int check_every, bool resume, bool* converged, int* tried, int* accepted) {
     init_state_keep();
+    const bool graphs = c->use_graphs && !c->profile;
     int launched = 0;  // iterations launched (each = one column sweep)
     int p = 0;
     int chunk = check_every > 0 ? check_every : 4;
+    const int chunk_max = check_every > 0 ? check_every : (ell > 0 ? 8 : 32);
     bool done = false;
     DevState st{};
+    if (ell > 0 && !resume && max_iter >= 1) {
+      sknr_iter(ell, true);  // the first iteration of Algorithm 4.1 has no Newton step
+      ++launched;
+    }
     while (true) {
-      int remaining = max_iter + 1 - launched;  // +1: the final sweep only checks
+      int remaining = max_iter - launched;  // full iterations still allowed
       if (remaining <= 0) break;
       int k = std::min(chunk, remaining);
-      for (int t = 0; t < k; ++t) {
-        bool last_check_only = (launched == max_iter);
-        if (last_check_only) {
-          // the (max_iter+1)-th column sweep: convergence test of f_max_iter
-          sweep_col(w.F, MA_F, w.G[ell > 0 ? 0 : p], ell > 0 ? w.Gt : w.G[1 - p], ell > 0 ? DOT_GT : DOT_G,
-                    ell > 0 ? MA_GT : MA_G, 0, nullptr, nullptr, W_NONE, G_NOT_DONE, F_CHECK | F_COUNT | F_GSEL, p);
-        } else if (ell > 0) {
-          sknr_iter(ell, launched == 0 && !resume);
-        } else {
-          sk_iter(p);
-          p = 1 - p;
+      if (ell == 0 && (k & 1) && k > 1) --k;
+      if (graphs && k >= 2 && p == 0) {
+        HIPCHK(hipGraphLaunch(chunk_graph(ell, k), s));
+      } else {
+        for (int t = 0; t < k; ++t) {
+          if (ell > 0) {
+            sknr_iter(ell, false);
+          } else {
+            sk_iter(p);
+            p = 1 - p;
+          }
         }
-        ++launched;
       }
+      launched += k;
       st = read_state();
       if (st.done) {
         done = true;
         break;
       }
-      if (check_every <= 0) chunk = std::min(chunk * 2, ell > 0 ? 16 : 64);
+      chunk = std::min(chunk * 2, chunk_max);
     }
-    if (!done) st = read_state();
+    if (!done) {
+      // the (max_iter+1)-th column sweep: convergence test of f_max_iter
+      sweep_col(w.F, MA_F, w.G[ell > 0 ? 0 : p], ell > 0 ? w.Gt : w.G[1 - p], ell > 0 ? DOT_GT : DOT_G,
+                ell > 0 ? MA_GT : MA_G, 0, nullptr, nullptr, W_NONE, G_NOT_DONE, F_CHECK | F_COUNT | F_GSEL, p);
+      st = read_state();
+    }
     *converged = st.done != 0;
     *tried = st.newton_tried;
     *accepted = st.newton_accepted;
@@ -589,6 +737,7 @@ struct Engine {
     z.maxabs[MA_G] = cur.maxabs[MA_G];
     z.dots[DOT_F] = cur.dots[DOT_F];
     z.dots[DOT_G] = cur.dots[DOT_G];
+    set_consts(z);
     std::memcpy(c->st_host, &z, sizeof(DevState));
     HIPCHK(hipMemcpyAsync(w.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -615,7 +764,7 @@ struct Engine {
     geo.cscale = P.cscale;
     int nrb, ncb;
     HIPCHK(launch_eval(geo, P.kind, f, g, pr->a, pr->b, eps, w.evrow, w.evcol, w.evscal, P.n0, P.m0, &nrb, &ncb, s));
-    HIPCHK(launch_eval_finish(w.evrow, w.evcol, w.evscal, pr->a, pr->b, P.n0, P.m0, nrb, ncb, w.evout, s));
+    HIPCHK(launch_eval_finish(w.evrow, w.evcol, w.evscal, pr->a, pr->b, P.n0, P.m0, nrb, ncb, w.evout, w.evblk, s));
     HIPCHK(launch_dot64(f, pr->a, P.n0, w.evout + 8, s));
     HIPCHK(launch_dot64(g, pr->b, P.m0, w.evout + 9, s));
     double h[16];
@@ -650,8 +799,8 @@ struct Engine {
     int kp = ell_pad(std::min(32, ell + std::max(0, oversample)));
     if (kp < ell_pad(ell)) kp = ell_pad(ell);
     const int n = P.n, m = P.m;
-    const int nbn = std::min(64, std::max(1, (n + 255) / 256));
-    const int nbm = std::min(64, std::max(1, (m + 255) / 256));
+    const int nbn = std::min(32, std::max(1, (n + 127) / 128));
+    const int nbm = std::min(32, std::max(1, (m + 127) / 128));
     if (w.have_Vw) HIPCHK(hipMemcpyAsync(w.Zw, w.Vw, sizeof(float) * (size_t)n * kp, hipMemcpyDeviceToDevice, s));
     else HIPCHK(launch_random_block(kp, w.Zw, n, 0, seed, s));
     std::vector<double> lp(kp, 0.0), lc(kp, 0.0);
@@ -783,6 +932,10 @@ int sknr_ctx_create(int device, uint64_t hbm_budget_bytes, void** out) {
     HIPCHK(hipMemGetInfo(&fr, &tot));
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * fr);
     HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault));
+    HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming));
+    const char* ng = getenv("SKNR_NO_GRAPHS");
+    c->use_graphs = !(ng && ng[0] == '1');
     *out = c;
     return SKNR_OK;
   });
@@ -794,8 +947,13 @@ int sknr_ctx_destroy(void* ctx) {
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
     HIPCHK(hipSetDevice(c->device));
     HIPCHK(hipDeviceSynchronize());
+    c->drop_graphs();
     if (c->arena.base) HIPCHK(hipFree(c->arena.base));
     if (c->st_host) HIPCHK(hipHostFree(c->st_host));
+    c->drain();
+    if (c->own) (void)hipStreamDestroy(c->own);
+    if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
     delete c;
     return SKNR_OK;
   });
@@ -812,7 +970,11 @@ int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts, doubl
     REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
     REQUIRE(opts->ell >= 0 && opts->ell <= SKNR_MAX_ELL, "ell out of range");
     auto t0 = std::chrono::steady_clock::now();
-    hipStream_t s = as_stream(opts->stream);
+    // run on the context's stream, after the work already queued on the caller's
+    hipStream_t cs = as_stream(opts->stream);
+    hipStream_t s = c->own;
+    HIPCHK(hipEventRecord(c->order_ev, cs));
+    HIPCHK(hipStreamWaitEvent(s, c->order_ev, 0));
     Prepared P = prepare(prob, s);
     REQUIRE(opts->ell < std::min(P.n0, P.m0), "ell must be < min(n, m)");
     if (opts->ell > 0) {
@@ -831,8 +993,8 @@ int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts, doubl
     WS w = make_ws(c, P, ellp, s);
     Engine E(c, P, w, s);
     const int eig_os = opts->eig_oversample > 0 ? opts->eig_oversample : 8;
-    const int eig_it = opts->eig_max_iter > 0 ? opts->eig_max_iter : 200;
-    const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 1e-9;
+    const int eig_it = opts->eig_max_iter > 0 ? opts->eig_max_iter : 100;
+    const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 1e-6;
     std::memset(res, 0, sizeof(*res));
     E.tol = opts->tol;
     int static_eig_iters = 0;
@@ -989,7 +1151,7 @@ int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps, const
     E.sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, 0, 0);
     HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
                               w.st, 0, s));
-    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, eps, w.coef32, w.coef64, w.Gout, w.gout,
+    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout,
                            w.st, 0, s));
     std::vector<double> hG((size_t)ell * ell), hg(ell);
     HIPCHK(hipMemcpyAsync(hG.data(), w.Gout, 8 * hG.size(), hipMemcpyDeviceToHost, s));
@@ -1073,6 +1235,39 @@ int sknr_coupling(void* ctx, const sknr_problem* prob, double eps, const double*
     geo.cscale = P.cscale;
     HIPCHK(launch_coupling(geo, P.kind, f, g, prob->a, prob->b, eps, P_out, P.n0, P.m0, s));
     HIPCHK(hipStreamSynchronize(s));
+    return SKNR_OK;
+  });
+}
+
+int sknr_profile(void* ctx, int32_t enable) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    HIPCHK(hipDeviceSynchronize());
+    c->drain();
+    c->profile = enable != 0;
+    c->prof.clear();
+    return SKNR_OK;
+  });
+}
+
+int sknr_profile_read(void* ctx, sknr_kprof* out, int32_t max_entries, int32_t* count) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    REQUIRE(count && (out || max_entries == 0), "count (and out) required");
+    HIPCHK(hipDeviceSynchronize());
+    c->drain();
+    int k = 0;
+    for (auto& e : c->prof) {
+      if (k < max_entries) {
+        std::memset(&out[k], 0, sizeof(sknr_kprof));
+        std::snprintf(out[k].name, sizeof(out[k].name), "%s", e.name.c_str());
+        out[k].launches = e.launches;
+        out[k].total_ms = e.total_ms;
+        out[k].units = e.units;
+      }
+      ++k;
+    }
+    *count = k;
     return SKNR_OK;
   });
 }

@@ -8,9 +8,10 @@ namespace sknr {
 
 // ----------------------------------------------------------------- state
 // Small device-resident control block of one solver instance.  Kernels of
-// one iteration read the gating flags at entry and the "last block" of a
-// sweep updates the scalars, so a whole chunk of iterations can be queued
-// (or captured in a graph) without host round trips.
+// one iteration read the gating flags at entry and a one-workgroup
+// finishing kernel after each sweep updates the scalars, so a whole chunk
+// of iterations can be queued (or captured in a graph) without host round
+// trips.
 enum DotSlot { DOT_F = 0, DOT_G = 1, DOT_GT = 2, DOT_FSK = 3, DOT_FP = 4, DOT_GP = 5, DOT_TMP = 6, NDOT = 8 };
 enum MaxSlot { MA_F = 0, MA_G = 1, MA_GT = 2, MA_FSK = 3, MA_FP = 4, MA_GP = 5, MA_G2 = 6, NMA = 8 };
 
@@ -27,8 +28,15 @@ struct DevState {
   double err_aux;       // sum |mdiff| of the last row sweep (row marginal of P~)
   double dots[NDOT];    // <U, w> of hat potentials (FP64 sums)
   float maxabs[NMA];    // max |U.hi| of hat potentials (for the Fast2Sum offset)
-  unsigned cnt[8];      // global "last block" counters, one per sweep kind
-  int pad[8];
+  // constants of the current eps, read by the kernels (so that a captured
+  // chunk of iterations serves every stage)
+  double eps;           // eps
+  double tol;           // L1 marginal tolerance
+  float K;              // log2(e)/eps
+  float inv_eps;        // 1/eps
+  float2 eps_df;        // eps as double-float
+  float2 eln2_df;       // eps*ln2 as double-float
+  int pad[6];
 };
 
 // gating bits: a kernel returns immediately unless all requested hold
@@ -74,22 +82,14 @@ struct SweepArgs {
   const float* Vred;     // n_red x ell, row-major
   float* Wout;           // n_out x ell
   int wmode;
-  // constants
-  float K;               // log2(e)/eps
-  float inv_eps;
-  float2 eps_df;         // eps as double-float
-  float2 eln2_df;        // eps*ln2 as double-float
-  double tol;
   // split-K bookkeeping
   int nsplit;
   int rows_per_split;
   float* part;           // [nsplit][3+ell][n_out]
-  unsigned* cnt_cb;      // per column block counters (zeroed, self-resetting)
   double* blk_err;       // per output-block partial scalars
   double* blk_dot;
   float* blk_max;
-  int nblk;              // number of output blocks
-  int cnt_id;            // which global counter
+  int nblk;              // number of output blocks (scalar partials)
   DevState* st;
   int gate;
   int flags;
@@ -115,7 +115,7 @@ hipError_t launch_copy_state_slot(DevState* st, int dst_dot, int src_dot, int ds
 hipError_t launch_nr_assemble(int ell, const float* V, const float* rdiff, const double* a, int n,
                               const float* W, const double* b, int m, double* part, int nrow_blk,
                               int ncol_blk, DevState* st, int gate, hipStream_t s);
-hipError_t launch_nr_solve(int ell, const double* part, int nblk, double eps, float* coef32,
+hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32,
                            double* coef64, double* Gout, double* gout, DevState* st, int gate,
                            hipStream_t s);
 hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a,
@@ -130,7 +130,7 @@ hipError_t launch_eval(const SweepArgs& geo, int cost_kind, const double* f, con
                        double* scal, int n, int m, int* nrb, int* ncb, hipStream_t s);
 hipError_t launch_eval_finish(const double* rowpart, const double* colpart, const double* scal,
                               const double* a, const double* b, int n, int m, int nrb, int ncb,
-                              double* out8, hipStream_t s);
+                              double* out8, double* blk, hipStream_t s);
 
 // spectral warm start: block subspace iteration helpers (k = kp <= 32)
 hipError_t launch_wgram(int kp, const float* Z, const double* w, int invert, int n, double* part, int nblk,

@@ -17,6 +17,7 @@
 
 #include <float.h>
 #include <math.h>
+#include <stdlib.h>
 
 namespace sknr {
 
@@ -132,9 +133,6 @@ __device__ __forceinline__ float block_max_f(float v, float* sbuf) {
   return r;
 }
 
-__device__ __forceinline__ unsigned atomic_ticket(unsigned* p) {
-  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // ----------------------------------------------------- LSE state merging
 // (sig, S, Sc): the partial sum  sum exp2((t - sig)*K) = S + Sc.
@@ -154,9 +152,23 @@ __device__ __forceinline__ void lse_merge(float& sig, float& S, float& Sc, float
 // Finalise one output of a sweep from its merged (sig, S, Sc) and write the
 // potential, the marginal-ratio term and the weighted average.
 // Returns |mdiff| (error contribution), accumulates dot and max.
+struct EpsConst {
+  float K, inv_eps;
+  float2 eps_df, eln2_df;
+};
+__device__ __forceinline__ EpsConst eps_const(const DevState* st) {
+  EpsConst c;
+  c.K = st->K;
+  c.inv_eps = st->inv_eps;
+  c.eps_df = st->eps_df;
+  c.eln2_df = st->eln2_df;
+  return c;
+}
+
 template <int ELL>
-__device__ __forceinline__ void finalize_output(const SweepArgs& A, int o, float L, float sig, float S, float Sc,
-                                                const float* acc, double& err, double& dot, float& mx) {
+__device__ __forceinline__ void finalize_output(const SweepArgs& A, const EpsConst& E, int o, float L, float sig,
+                                                float S, float Sc, const float* acc, double& err, double& dot,
+                                                float& mx) {
   // log2(S + Sc) = k + log2(mant) + Sc/(S ln 2), S = mant * 2^k, mant in [0.5, 1)
   int k;
   float mant = frexpf(S, &k);
@@ -164,8 +176,8 @@ __device__ __forceinline__ void finalize_output(const SweepArgs& A, int o, float
   float corr = (Sc / S) * 1.4426950408889634f;
   float2 l2 = fast_two_sum((float)k, lm);
   l2.y += corr;
-  float2 t = df_mul(A.eln2_df, l2);
-  float2 out = df_mul(A.eps_df, A.lw_out[o]);
+  float2 t = df_mul(E.eln2_df, l2);
+  float2 out = df_mul(E.eps_df, A.lw_out[o]);
   out = df_add_f(out, -sig);
   out = df_add_f(out, L);
   out = df_add(out, df_neg(t));
@@ -173,7 +185,7 @@ __device__ __forceinline__ void finalize_output(const SweepArgs& A, int o, float
   float ratio_m1 = 0.f;
   if (A.Uold) {
     float2 dlt = df_add(A.Uold[o], df_neg(out));
-    ratio_m1 = expm1f((dlt.x + dlt.y) * A.inv_eps);
+    ratio_m1 = expm1f((dlt.x + dlt.y) * E.inv_eps);
     float md = A.w_out[o] * ratio_m1;
     if (A.mdiff) A.mdiff[o] = md;
     err += fabs((double)md);
@@ -189,35 +201,35 @@ __device__ __forceinline__ void finalize_output(const SweepArgs& A, int o, float
   }
 }
 
-// Global "last block" reduction of the per-block scalars and the state
-// update.  Called by every block after its own outputs are written; (err,
-// dot, mx) are valid in thread 0.
-__device__ void finish_global(const SweepArgs& A, int bid, double err, double dot, float mx, double* sbd,
-                              float* sbf) {
-  __shared__ unsigned s_ticket;
+// Per-block scalar partials of a sweep (error, dot, max) for the scalar
+// finishing kernel.
+__device__ __forceinline__ void write_block_scalars(const SweepArgs& A, int bid, double err, double dot, float mx) {
   if (threadIdx.x == 0) {
     A.blk_err[bid] = err;
     A.blk_dot[bid] = dot;
     A.blk_max[bid] = mx;
-    __threadfence();
-    s_ticket = atomic_ticket(&A.st->cnt[A.cnt_id]);
   }
-  __syncthreads();
-  if (s_ticket != (unsigned)(A.nblk - 1)) return;
-  __threadfence();
+}
+
+// One workgroup: reduce the per-block scalars of a sweep in block order and
+// update the solver state (error, dots, max, convergence and acceptance
+// decisions).  Runs after the sweep, so its writes are visible.
+__global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
+  if (gate_closed(A.st, A.gate)) return;
+  __shared__ double sbd[16];
+  __shared__ float sbf[8];
   double e = 0, d = 0;
   float m = 0;
   for (int b = threadIdx.x; b < A.nblk; b += blockDim.x) {
-    e += __builtin_nontemporal_load(&A.blk_err[b]);
-    d += __builtin_nontemporal_load(&A.blk_dot[b]);
-    m = fmaxf(m, __builtin_nontemporal_load(&A.blk_max[b]));
+    e += A.blk_err[b];
+    d += A.blk_dot[b];
+    m = fmaxf(m, A.blk_max[b]);
   }
   e = block_sum_d(e, sbd);
   d = block_sum_d(d, sbd + 8);
   m = block_max_f(m, sbf);
   if (threadIdx.x == 0) {
     DevState* st = A.st;
-    st->cnt[A.cnt_id] = 0;
     if (A.Uold) {
       if (A.mdiff) st->err_aux = e; else st->err = e;
     }
@@ -225,7 +237,7 @@ __device__ void finish_global(const SweepArgs& A, int bid, double err, double do
     if (A.ma_out >= 0) st->maxabs[A.ma_out] = m;
     if (A.flags & F_COUNT) st->npass += 1;
     if (A.flags & F_CHECK) {
-      if (st->armed && e < A.tol) {
+      if (st->armed && e < st->tol) {
         st->done = 1;
         if (A.flags & F_GSEL) st->gsel = A.gsel_val;
       }
@@ -238,7 +250,6 @@ __device__ void finish_global(const SweepArgs& A, int bid, double err, double do
       st->accept = acc;
       st->newton_accepted += acc;
     }
-    __threadfence();
   }
 }
 
@@ -264,7 +275,8 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
   const int r0 = blockIdx.y * A.rows_per_split;
   const int nr = min(A.rows_per_split, A.n_red - r0);
   const int d = (COST == 1 && D > 0) ? D : A.d;
-  const float K = A.K;
+  const EpsConst EC = eps_const(A.st);
+  const float K = EC.K;
   const float L = 2.f * (A.cmax + A.st->maxabs[A.ma_in]);
 
   float2* sU = reinterpret_cast<float2*>(smem);
@@ -429,45 +441,88 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
     }
   }
 
-  // ---- last workgroup of this column block merges the splits
-  __threadfence();
-  __syncthreads();
-  __shared__ unsigned s_ticket;
-  if (threadIdx.x == 0) s_ticket = atomic_ticket(&A.cnt_cb[blockIdx.x]);
-  __syncthreads();
-  if (s_ticket != (unsigned)(A.nsplit - 1)) return;
-  __threadfence();
-  if (threadIdx.x == 0) A.cnt_cb[blockIdx.x] = 0;
+}
 
+// Merge the split-K partials of a streaming sweep: 4 lanes per output,
+// each merging a contiguous quarter of the splits in order, then a fixed
+// shuffle tree across the 4 lanes (deterministic), and finalise.
+template <int ELL>
+__global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) {
+  if (gate_closed(A.st, A.gate)) return;
+  constexpr int NQ = 3 + (ELL > 0 ? ELL : 0);
+  constexpr int EL = ELL > 0 ? ELL : 1;
+  const EpsConst EC = eps_const(A.st);
+  const float K = EC.K;
+  const float L = 2.f * (A.cmax + A.st->maxabs[A.ma_in]);
+  const int n_out = A.n_out;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = gid >> 2, part4 = gid & 3;
+  const int colc = min(col, n_out - 1);
+  const int ns = A.nsplit;
+  const int per = (ns + 3) >> 2;
+  const int s0 = part4 * per, s1 = min(ns, s0 + per);
+  const float* pp = A.part + colc;
+  const size_t stride = (size_t)n_out;
+  float sg = SIG0, Ss = 0.f, Sx = 0.f;
+  float ac[EL];
+#pragma unroll
+  for (int l = 0; l < EL; ++l) ac[l] = 0.f;
+  constexpr int BATCH = ELL > 16 ? 2 : (ELL > 0 ? 4 : 16);
+  for (int sp0 = s0; sp0 < s1; sp0 += BATCH) {
+    float bs[BATCH], bS[BATCH], bC[BATCH];
+    float ba[BATCH][EL];
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      const int sp = min(sp0 + q, ns - 1);
+      const float* q2 = pp + (size_t)sp * NQ * stride;
+      bs[q] = q2[0];
+      bS[q] = q2[stride];
+      bC[q] = q2[2 * stride];
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ba[q][l] = q2[(3 + l) * stride];
+    }
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) {
+      if (sp0 + q < s1) {
+        float f1, f2;
+        lse_merge(sg, Ss, Sx, bs[q], bS[q], bC[q], K, f1, f2);
+#pragma unroll
+        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = ac[l] * f1 + ba[q][l] * f2;
+      }
+    }
+  }
+  // lanes (0,1) and (2,3), then (01, 23): split order is preserved
+#pragma unroll
+  for (int off = 1; off <= 2; off <<= 1) {
+    float sg2 = __shfl_xor(sg, off, 64), S2 = __shfl_xor(Ss, off, 64), C2 = __shfl_xor(Sx, off, 64);
+    float a2[EL];
+#pragma unroll
+    for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) a2[l] = __shfl_xor(ac[l], off, 64);
+    const bool lower = (part4 & off) == 0;
+    float f1, f2;
+    if (lower) {
+      lse_merge(sg, Ss, Sx, sg2, S2, C2, K, f1, f2);
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = ac[l] * f1 + a2[l] * f2;
+    } else {
+      float t1 = sg2, t2 = S2, t3 = C2;
+      lse_merge(t1, t2, t3, sg, Ss, Sx, K, f1, f2);
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = a2[l] * f1 + ac[l] * f2;
+      sg = t1;
+      Ss = t2;
+      Sx = t3;
+    }
+  }
   double err = 0, dot = 0;
   float mxo = 0.f;
-  for (int t = threadIdx.x; t < NC; t += TPB) {
-    int col = blockIdx.x * NC + t;
-    if (col >= n_out) continue;
-    const float* pp = A.part + col;
-    const size_t stride = (size_t)n_out;
-    float sg = __builtin_nontemporal_load(pp), Ss = __builtin_nontemporal_load(pp + stride),
-          Sx = __builtin_nontemporal_load(pp + 2 * stride);
-    float ac[ELL > 0 ? ELL : 1];
-#pragma unroll
-    for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = __builtin_nontemporal_load(pp + (3 + l) * stride);
-    for (int sp = 1; sp < A.nsplit; ++sp) {
-      const float* q2 = pp + (size_t)sp * NQ * stride;
-      float f1, f2;
-      lse_merge(sg, Ss, Sx, __builtin_nontemporal_load(q2), __builtin_nontemporal_load(q2 + stride),
-                __builtin_nontemporal_load(q2 + 2 * stride), K, f1, f2);
-#pragma unroll
-      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l)
-        ac[l] = ac[l] * f1 + __builtin_nontemporal_load(q2 + (3 + l) * stride) * f2;
-    }
-    finalize_output<ELL>(A, col, L, sg, Ss, Sx, ac, err, dot, mxo);
-  }
+  if (col < n_out && part4 == 0) finalize_output<ELL>(A, EC, col, L, sg, Ss, Sx, ac, err, dot, mxo);
   __shared__ double sbd[16];
   __shared__ float sbf[8];
   err = block_sum_d(err, sbd);
   dot = block_sum_d(dot, sbd + 8);
   mxo = block_max_f(mxo, sbf);
-  finish_global(A, blockIdx.x, err, dot, mxo, sbd, sbf);
+  write_block_scalars(A, blockIdx.x, err, dot, mxo);
 }
 
 // ============================================================================
@@ -480,7 +535,8 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
 template <int RPW, int ELL, bool VEC4>
 __global__ __launch_bounds__(TPB) void k_sweep_rows(SweepArgs A) {
   if (gate_closed(A.st, A.gate)) return;
-  const float K = A.K;
+  const EpsConst EC = eps_const(A.st);
+  const float K = EC.K;
   const int o0 = blockIdx.x * RPW;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int EL = ELL > 0 ? ELL : 1;
@@ -613,14 +669,14 @@ __global__ __launch_bounds__(TPB) void k_sweep_rows(SweepArgs A) {
 #pragma unroll
       for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = ac[l] * f1 + cmb[w][rr][3 + l] * f2;
     }
-    finalize_output<ELL>(A, o0 + rr, 0.f, sg, Ss, Sx, ac, err, dot, mxo);
+    finalize_output<ELL>(A, EC, o0 + rr, 0.f, sg, Ss, Sx, ac, err, dot, mxo);
   }
   __shared__ double sbd[16];
   __shared__ float sbf[8];
   err = block_sum_d(err, sbd);
   dot = block_sum_d(dot, sbd + 8);
   mxo = block_max_f(mxo, sbf);
-  finish_global(A, blockIdx.x, err, dot, mxo, sbd, sbf);
+  write_block_scalars(A, blockIdx.x, err, dot, mxo);
 }
 
 // ----------------------------------------------------------- launch config
@@ -652,10 +708,14 @@ size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bo
   int cpt = stream_cpt(cost_kind, ell, vec);
   int nc = 64 * cpt;
   int ncb = (n_out + nc - 1) / nc;
-  int target = 2048;
+  // split-K geometry: about `target` workgroups, at least `rmin` reduce
+  // rows each (SKNR_SWEEP_TARGET_WG / SKNR_SWEEP_MIN_ROWS override)
+  static const int env_target = getenv("SKNR_SWEEP_TARGET_WG") ? atoi(getenv("SKNR_SWEEP_TARGET_WG")) : 0;
+  static const int env_rmin = getenv("SKNR_SWEEP_MIN_ROWS") ? atoi(getenv("SKNR_SWEEP_MIN_ROWS")) : 0;
+  int target = env_target > 0 ? env_target : 2048;
   int ns = (target + ncb - 1) / ncb;
   int r = (n_red + ns - 1) / ns;
-  int rmin = ell > 0 ? 128 : 64;
+  int rmin = env_rmin > 0 ? env_rmin : (ell > 0 ? 128 : 64);
   if (r < rmin) r = rmin;
   int rmx = rps_max(cost_kind, d);
   if (r > rmx) r = rmx;
@@ -663,7 +723,8 @@ size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bo
   ns = (n_red + r - 1) / r;
   *nsplit = ns;
   *rps = r;
-  *nblk = ncb;
+  *nblk = (n_out + 63) / 64;  // merge kernel blocks (4 lanes per output)
+  (void)ncb;
   int ellp = ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32));
   return (size_t)ns * (3 + ellp) * n_out;
 }
@@ -681,6 +742,8 @@ static hipError_t go_stream(const SweepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, true>), grid, dim3(TPB), sm, s, a);
   else
     hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, false>), grid, dim3(TPB), sm, s, a);
+  hipLaunchKernelGGL((k_sweep_merge<ELL>), dim3((a.n_out + 63) / 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sweep_finish, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -732,6 +795,7 @@ hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t s) {
       else hipLaunchKernelGGL((k_sweep_rows<1, 32, false>), grid, dim3(TPB), 0, s, a);
     }
   }
+  hipLaunchKernelGGL(k_sweep_finish, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -906,25 +970,36 @@ __global__ __launch_bounds__(256) void k_nr_assemble(const float* V, const float
   if ((int)threadIdx.x < ELL) out[NE + threadIdx.x] = gacc;
 }
 
+// sum over nblk (<= 32) partial blocks of entry e, loads issued together
+__device__ __forceinline__ double sum_partials(const double* part, int nblk, int stride, int e) {
+  double v[32];
+#pragma unroll
+  for (int b = 0; b < 32; ++b) v[b] = b < nblk ? part[(size_t)b * stride + e] : 0.0;
+  double s = 0;
+#pragma unroll
+  for (int b = 0; b < 32; ++b) s += v[b];
+  return s;
+}
+
 template <int ELL>
-__global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, int ell_real, double eps,
-                                                  float* coef32, double* coef64, double* Gout, double* gout,
-                                                  DevState* st, int gate) {
+__global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, int ell_real, float* coef32,
+                                                  double* coef64, double* Gout, double* gout, DevState* st,
+                                                  int gate) {
   if (gate_closed(st, gate)) return;
+  const double eps = st->eps;
   constexpr int NE = ELL * ELL;
   __shared__ double A[ELL][ELL + 1];
   __shared__ double g[ELL];
   __shared__ int ok;
-  for (int e = threadIdx.x; e < NE + ELL; e += 256) {
-    double s = 0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (NE + ELL) + e];
+  for (int e = threadIdx.x; e < NE + ELL; e += blockDim.x) {
+    double s = sum_partials(part, nblk, NE + ELL, e);
     if (e < NE) A[e / ELL][e % ELL] = s;
     else g[e - NE] = s;
   }
   if (threadIdx.x == 0) ok = 1;
   __syncthreads();
   // symmetrise
-  for (int e = threadIdx.x; e < NE; e += 256) {
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
     int i = e / ELL, j = e % ELL;
     if (i < j) {
       double v = 0.5 * (A[i][j] + A[j][i]);
@@ -934,16 +1009,16 @@ __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, 
   }
   __syncthreads();
   if (Gout) {
-    for (int e = threadIdx.x; e < ell_real * ell_real; e += 256) Gout[e] = A[e / ell_real][e % ell_real];
-    for (int e = threadIdx.x; e < ell_real; e += 256) gout[e] = g[e];
+    for (int e = threadIdx.x; e < ell_real * ell_real; e += blockDim.x) Gout[e] = A[e / ell_real][e % ell_real];
+    for (int e = threadIdx.x; e < ell_real; e += blockDim.x) gout[e] = g[e];
   }
   __syncthreads();
   // padded modes (columns of V beyond ell_real are zero): identity rows
-  for (int e = threadIdx.x; e < NE; e += 256) {
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
     int i = e / ELL, j = e % ELL;
     if (i >= ell_real || j >= ell_real) A[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  for (int e = threadIdx.x; e < ELL; e += 256)
+  for (int e = threadIdx.x; e < ELL; e += blockDim.x)
     if (e >= ell_real) g[e] = 0.0;
   __syncthreads();
   double dmax = 0;
@@ -959,27 +1034,32 @@ __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, 
     double dk = sqrt(piv);
     __syncthreads();
     if (threadIdx.x == 0) A[k][k] = dk;
-    for (int i = k + 1 + threadIdx.x; i < ELL; i += 256) A[i][k] /= dk;
+    for (int i = k + 1 + threadIdx.x; i < ELL; i += blockDim.x) A[i][k] /= dk;
     __syncthreads();
-    for (int e = threadIdx.x; e < NE; e += 256) {
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
       int i = e / ELL, j = e % ELL;
       if (j > k && i >= j) A[i][j] -= A[i][k] * A[j][k];
     }
   }
   __syncthreads();
-  // solve L y = g, L^T z = y (single wave, sequential over k)
+  // solve L y = g then L^T z = y: one row per step, the update of the
+  // remaining right-hand side in parallel
+  __shared__ double y[ELL];
+  if ((int)threadIdx.x < ELL) y[threadIdx.x] = g[threadIdx.x];
+  __syncthreads();
+  for (int i = 0; i < ELL; ++i) {
+    if (threadIdx.x == 0) y[i] /= A[i][i];
+    __syncthreads();
+    for (int r = i + 1 + threadIdx.x; r < ELL; r += blockDim.x) y[r] -= A[r][i] * y[i];
+    __syncthreads();
+  }
+  for (int i = ELL - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) y[i] /= A[i][i];
+    __syncthreads();
+    for (int r = threadIdx.x; r < i; r += blockDim.x) y[r] -= A[i][r] * y[i];
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    double y[ELL];
-    for (int i = 0; i < ELL; ++i) {
-      double s = g[i];
-      for (int j = 0; j < i; ++j) s -= A[i][j] * y[j];
-      y[i] = s / A[i][i];
-    }
-    for (int i = ELL - 1; i >= 0; --i) {
-      double s = y[i];
-      for (int j = i + 1; j < ELL; ++j) s -= A[j][i] * y[j];
-      y[i] = s / A[i][i];
-    }
     int good = ok;
     for (int i = 0; i < ELL; ++i) {
       double c = eps * y[i];
@@ -996,8 +1076,7 @@ __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, 
 template <int ELL>
 __global__ __launch_bounds__(256) void k_nr_apply(const float2* F, const float* V, const float* coef,
                                                   const double* a, float2* Fp, int n, double* blk, float* blkmax,
-                                                  DevState* st, int gate, int dot_slot, int ma_slot,
-                                                  unsigned* cnt) {
+                                                  DevState* st, int gate) {
   if (gate_closed(st, gate)) return;
   __shared__ float c[ELL];
   if (threadIdx.x < ELL) c[threadIdx.x] = coef[threadIdx.x];
@@ -1019,26 +1098,27 @@ __global__ __launch_bounds__(256) void k_nr_apply(const float2* F, const float* 
   __shared__ float sbf[8];
   dot = block_sum_d(dot, sbd);
   mx = block_max_f(mx, sbf);
-  __shared__ unsigned s_ticket;
   if (threadIdx.x == 0) {
     blk[blockIdx.x] = dot;
     blkmax[blockIdx.x] = mx;
-    __threadfence();
-    s_ticket = atomic_ticket(cnt);
   }
-  __syncthreads();
-  if (s_ticket != gridDim.x - 1) return;
-  __threadfence();
+}
+
+// one workgroup: st->dots[dot_slot] = sum of blk, st->maxabs[ma_slot] = max of blkmax
+__global__ __launch_bounds__(256) void k_scalars_finish(const double* blk, const float* blkmax, int nblk,
+                                                        DevState* st, int gate, int dot_slot, int ma_slot) {
+  if (gate_closed(st, gate)) return;
+  __shared__ double sbd[16];
+  __shared__ float sbf[8];
   double d = 0;
   float m = 0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-    d += __builtin_nontemporal_load(&blk[b]);
-    m = fmaxf(m, __builtin_nontemporal_load(&blkmax[b]));
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    d += blk[b];
+    m = fmaxf(m, blkmax[b]);
   }
   d = block_sum_d(d, sbd);
   m = block_max_f(m, sbf);
   if (threadIdx.x == 0) {
-    *cnt = 0;
     st->dots[dot_slot] = d;
     st->maxabs[ma_slot] = m;
   }
@@ -1063,24 +1143,24 @@ hipError_t launch_nr_assemble(int ell, const float* V, const float* mdiff, const
   return hipGetLastError();
 }
 template <int E>
-static void nr_solve_e(const double* part, int nblk, int ell, double eps, float* coef32, double* coef64,
-                       double* Gout, double* gout, DevState* st, int gate, hipStream_t s) {
-  hipLaunchKernelGGL((k_nr_solve<E>), dim3(1), dim3(256), 0, s, part, nblk, ell, eps, coef32, coef64, Gout, gout, st,
+static void nr_solve_e(const double* part, int nblk, int ell, float* coef32, double* coef64, double* Gout,
+                       double* gout, DevState* st, int gate, hipStream_t s) {
+  hipLaunchKernelGGL((k_nr_solve<E>), dim3(1), dim3(64), 0, s, part, nblk, ell, coef32, coef64, Gout, gout, st,
                      gate);
 }
-hipError_t launch_nr_solve(int ell, const double* part, int nblk, double eps, float* coef32, double* coef64,
-                           double* Gout, double* gout, DevState* st, int gate, hipStream_t s) {
-  if (ell <= 8) nr_solve_e<8>(part, nblk, ell, eps, coef32, coef64, Gout, gout, st, gate, s);
-  else if (ell <= 16) nr_solve_e<16>(part, nblk, ell, eps, coef32, coef64, Gout, gout, st, gate, s);
-  else nr_solve_e<32>(part, nblk, ell, eps, coef32, coef64, Gout, gout, st, gate, s);
+hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32, double* coef64, double* Gout,
+                           double* gout, DevState* st, int gate, hipStream_t s) {
+  if (ell <= 8) nr_solve_e<8>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, s);
+  else if (ell <= 16) nr_solve_e<16>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, s);
+  else nr_solve_e<32>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, s);
   return hipGetLastError();
 }
 template <int E>
 static void nr_apply_e(const float2* F, const float* V, const float* coef, const double* a, float2* Fp, int n,
                        double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot, hipStream_t s) {
   int nb = (n + 255) / 256;
-  hipLaunchKernelGGL((k_nr_apply<E>), dim3(nb), dim3(256), 0, s, F, V, coef, a, Fp, n, blk, blkmax, st, gate,
-                     dot_slot, ma_slot, &st->cnt[7]);
+  hipLaunchKernelGGL((k_nr_apply<E>), dim3(nb), dim3(256), 0, s, F, V, coef, a, Fp, n, blk, blkmax, st, gate);
+  hipLaunchKernelGGL(k_scalars_finish, dim3(1), dim3(256), 0, s, blk, blkmax, nb, st, gate, dot_slot, ma_slot);
 }
 hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a, float2* Fp,
                            int n, double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot,
@@ -1176,23 +1256,39 @@ hipError_t launch_eval(const SweepArgs& geo, int cost_kind, const double* f, con
   return hipGetLastError();
 }
 
-// out8 = {row_err, col_err, cost, mass, ent_sum, 0, 0, 0}
-__global__ __launch_bounds__(256) void k_eval_finish(const double* rowpart, const double* colpart,
-                                                     const double* scal, const double* a, const double* b, int n,
-                                                     int m, int nrb, int ncb, double* out8) {
+// first stage: per block of rows / columns, sum the tile partials of each
+// row (column) in order and accumulate |sum - weight|; block results in blk
+__global__ __launch_bounds__(256) void k_eval_marg(const double* rowpart, const double* colpart, const double* a,
+                                                   const double* b, int n, int m, int nrb, int ncb, double* blk) {
   __shared__ double sbd[16];
-  double re = 0, ce = 0, c1 = 0, c2 = 0, c3 = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0;
+  if (i < n) {
     double s = 0;
     for (int cb = 0; cb < ncb; ++cb) s += rowpart[(size_t)cb * n + i];
-    re += fabs(s - a[i]);
-  }
-  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    v = fabs(s - a[i]);
+  } else if (i < n + m) {
+    const int j = i - n;
     double s = 0;
     for (int rb = 0; rb < nrb; ++rb) s += colpart[(size_t)rb * m + j];
-    ce += fabs(s - b[j]);
+    v = fabs(s - b[j]);
   }
-  for (int q = threadIdx.x; q < nrb * ncb; q += blockDim.x) {
+  v = block_sum_d(v, sbd);
+  if (threadIdx.x == 0) blk[blockIdx.x] = v;
+}
+
+// out8 = {row_err, col_err, cost, mass, ent_sum, 0, 0, 0}; nrowblk blocks of
+// blk hold row terms only when n is a multiple of 256 -- rows and columns
+// are kept apart by the block boundary at n
+__global__ __launch_bounds__(256) void k_eval_finish(const double* blk, int nb_rows, int nb_all, const double* scal,
+                                                     int nscal, double* out8) {
+  __shared__ double sbd[16];
+  double re = 0, ce = 0, c1 = 0, c2 = 0, c3 = 0;
+  for (int q = threadIdx.x; q < nb_all; q += blockDim.x) {
+    if (q < nb_rows) re += blk[q];
+    else ce += blk[q];
+  }
+  for (int q = threadIdx.x; q < nscal; q += blockDim.x) {
     c1 += scal[(size_t)q * 3 + 0];
     c2 += scal[(size_t)q * 3 + 1];
     c3 += scal[(size_t)q * 3 + 2];
@@ -1211,8 +1307,13 @@ __global__ __launch_bounds__(256) void k_eval_finish(const double* rowpart, cons
   }
 }
 hipError_t launch_eval_finish(const double* rowpart, const double* colpart, const double* scal, const double* a,
-                              const double* b, int n, int m, int nrb, int ncb, double* out8, hipStream_t s) {
-  hipLaunchKernelGGL(k_eval_finish, dim3(1), dim3(256), 0, s, rowpart, colpart, scal, a, b, n, m, nrb, ncb, out8);
+                              const double* b, int n, int m, int nrb, int ncb, double* out8, double* blk,
+                              hipStream_t s) {
+  // rows and columns in separate block ranges so that each block holds one kind
+  const int nbr = (n + 255) / 256, nbc = (m + 255) / 256;
+  hipLaunchKernelGGL(k_eval_marg, dim3(nbr), dim3(256), 0, s, rowpart, colpart, a, b, n, 0, nrb, ncb, blk);
+  hipLaunchKernelGGL(k_eval_marg, dim3(nbc), dim3(256), 0, s, rowpart, colpart, a, b, 0, m, nrb, ncb, blk + nbr);
+  hipLaunchKernelGGL(k_eval_finish, dim3(1), dim3(256), 0, s, blk, nbr, nbr + nbc, scal, nrb * ncb, out8);
   return hipGetLastError();
 }
 

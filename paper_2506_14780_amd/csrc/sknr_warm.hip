@@ -14,6 +14,17 @@
 
 namespace sknr {
 
+// sum over nblk (<= 32) partial blocks of entry e, loads issued together
+__device__ __forceinline__ double sum_parts(const double* part, int nblk, int stride, int e) {
+  double v[32];
+#pragma unroll
+  for (int b = 0; b < 32; ++b) v[b] = b < nblk ? part[(size_t)b * stride + e] : 0.0;
+  double s = 0;
+#pragma unroll
+  for (int b = 0; b < 32; ++b) s += v[b];
+  return s;
+}
+
 // ----------------------------------------------------------------- Gram
 // part[blk] = ( sum_i w_i Z_i Z_i^T  (k x k),  sum_i w_i Z_i  (k) ),
 // w_i = wgt[i] or 1/wgt[i] (invert), over a contiguous block of rows.
@@ -74,59 +85,75 @@ __global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, doub
   __shared__ double B[KP][KP + 1];
   __shared__ double s[KP];
   __shared__ double Li[KP][KP + 1];
-  for (int e = threadIdx.x; e < NE + KP; e += 256) {
-    double v = 0;
-    for (int b = 0; b < nblk; ++b) v += part[(size_t)b * (NE + KP) + e];
+  for (int e = threadIdx.x; e < NE + KP; e += blockDim.x) {
+    double v = sum_parts(part, nblk, NE + KP, e);
     if (e < NE) B[e / KP][e % KP] = v;
     else s[e - NE] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < NE; e += 256) {
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
     int i = e / KP, j = e % KP;
     B[i][j] -= s[i] * s[j];
   }
   __syncthreads();
+  // symmetrise and regularise by a tiny multiple of the trace
+  __shared__ double tr_s;
+  __shared__ int ok_s;
   if (threadIdx.x == 0) {
-    // symmetrise, regularise by a tiny multiple of the trace, Cholesky
     double tr = 0;
     for (int i = 0; i < KP; ++i) tr += B[i][i];
-    int ok = tr > 0;
-    for (int i = 0; i < KP; ++i)
-      for (int j = 0; j < i; ++j) B[j][i] = B[i][j] = 0.5 * (B[i][j] + B[j][i]);
-    for (int i = 0; i < KP; ++i) B[i][i] += 1e-13 * tr / KP;
-    for (int k = 0; k < KP; ++k) {
-      double d = B[k][k];
-      for (int j = 0; j < k; ++j) d -= B[k][j] * B[k][j];
-      if (!(d > 1e-30 * tr)) {
-        ok = 0;
-        d = 1e-30 * tr + 1e-300;
-      }
-      double lk = sqrt(d);
-      B[k][k] = lk;
-      for (int i = k + 1; i < KP; ++i) {
-        double v = B[i][k];
-        for (int j = 0; j < k; ++j) v -= B[i][j] * B[k][j];
-        B[i][k] = v / lk;
-      }
-    }
-    // Li = L^-1 (lower)
-    for (int j = 0; j < KP; ++j) {
-      for (int i = 0; i < KP; ++i) Li[i][j] = 0;
-      Li[j][j] = 1.0 / B[j][j];
-      for (int i = j + 1; i < KP; ++i) {
-        double v = 0;
-        for (int t = j; t < i; ++t) v -= B[i][t] * Li[t][j];
-        Li[i][j] = v / B[i][i];
-      }
-    }
-    *ok_out = ok;
+    tr_s = tr;
+    ok_s = tr > 0;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < NE; e += 256) {
+  const double tr = tr_s;
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+    int i = e / KP, j = e % KP;
+    if (i > j) {
+      double v = 0.5 * (B[i][j] + B[j][i]);
+      B[i][j] = v;
+      B[j][i] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < KP) B[threadIdx.x][threadIdx.x] += 1e-13 * tr / KP;
+  // right-looking Cholesky (lower, in place), one column per step
+  for (int k = 0; k < KP; ++k) {
+    __syncthreads();
+    double d = B[k][k];
+    if (!(d > 1e-30 * tr)) {
+      d = 1e-30 * tr + 1e-300;
+      if (threadIdx.x == 0) ok_s = 0;
+    }
+    const double lk = sqrt(d);
+    __syncthreads();
+    if (threadIdx.x == 0) B[k][k] = lk;
+    for (int i = k + 1 + threadIdx.x; i < KP; i += blockDim.x) B[i][k] /= lk;
+    __syncthreads();
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+      int i = e / KP, j = e % KP;
+      if (j > k && i >= j) B[i][j] -= B[i][k] * B[j][k];
+    }
+  }
+  __syncthreads();
+  // Li = L^-1: column j by thread j (forward substitution)
+  if ((int)threadIdx.x < KP) {
+    const int j = threadIdx.x;
+    for (int i = 0; i < KP; ++i) Li[i][j] = 0;
+    Li[j][j] = 1.0 / B[j][j];
+    for (int i = j + 1; i < KP; ++i) {
+      double v = 0;
+      for (int t = j; t < i; ++t) v -= B[i][t] * Li[t][j];
+      Li[i][j] = v / B[i][i];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *ok_out = ok_s;
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
     int i = e / KP, j = e % KP;
     R[e] = Li[j][i];  // R = L^-T, row-major
   }
-  for (int e = threadIdx.x; e < KP; e += 256) s_out[e] = s[e];
+  for (int e = threadIdx.x; e < KP; e += blockDim.x) s_out[e] = s[e];
 }
 
 // ------------------------------------------------------ Rayleigh-Ritz
@@ -143,14 +170,13 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
   __shared__ double cs[NP][2];
   __shared__ int pr[NP][2];
   __shared__ double off_s;
-  for (int e = threadIdx.x; e < NE; e += 256) {
-    double v = 0;
-    for (int b = 0; b < nblk; ++b) v += part[(size_t)b * (NE + KP) + e];
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+    double v = sum_parts(part, nblk, NE + KP, e);
     A[e / KP][e % KP] = v;
     Q[e / KP][e % KP] = (e / KP == e % KP) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < NE; e += 256) {
+  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
     int i = e / KP, j = e % KP;
     if (i < j) {
       double v = 0.5 * (A[i][j] + A[j][i]);
@@ -159,15 +185,30 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
     }
   }
   __syncthreads();
+  __shared__ double red[2][4];
   for (int sw = 0; sw < sweeps; ++sw) {
+    double off = 0, dia = 0;
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+      double v = A[e / KP][e % KP];
+      if (e / KP == e % KP) dia += v * v;
+      else off += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = off;
+      red[1][threadIdx.x >> 6] = dia;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-      double off = 0, dia = 0;
-      for (int i = 0; i < KP; ++i) {
-        dia += A[i][i] * A[i][i];
-        for (int j = 0; j < KP; ++j)
-          if (i != j) off += A[i][j] * A[i][j];
+      double o2 = 0, d2 = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        o2 += red[0][w];
+        d2 += red[1][w];
       }
-      off_s = off <= 1e-30 * dia ? -1.0 : off;
+      off_s = o2 <= 1e-24 * d2 ? -1.0 : o2;
     }
     __syncthreads();
     if (off_s < 0) break;
@@ -192,7 +233,7 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
       }
       __syncthreads();
       // columns: A <- A J, Q <- Q J
-      for (int e = threadIdx.x; e < NP * KP; e += 256) {
+      for (int e = threadIdx.x; e < NP * KP; e += blockDim.x) {
         int r = e / KP, i = e % KP;
         int p = pr[r][0], q = pr[r][1];
         double c = cs[r][0], s = cs[r][1];
@@ -205,7 +246,7 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
       }
       __syncthreads();
       // rows: A <- J^T A
-      for (int e = threadIdx.x; e < NP * KP; e += 256) {
+      for (int e = threadIdx.x; e < NP * KP; e += blockDim.x) {
         int r = e / KP, j = e % KP;
         int p = pr[r][0], q = pr[r][1];
         double c = cs[r][0], s = cs[r][1];
@@ -236,11 +277,11 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
 
 // out_i = ((Z_i - s) R) * rowscale_i   (k x k transform per row, FP64 math)
 template <int KP>
-__global__ __launch_bounds__(256) void k_affine(const float* Z, const double* s, const double* R, const double* rs,
+__global__ __launch_bounds__(64) void k_affine(const float* Z, const double* s, const double* R, const double* rs,
                                                 int rs_invert, int n, float* out) {
   __shared__ double Rs[KP][KP];
   __shared__ double ss[KP];
-  for (int e = threadIdx.x; e < KP * KP; e += 256) Rs[e / KP][e % KP] = R[e];
+  for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) Rs[e / KP][e % KP] = R[e];
   if ((int)threadIdx.x < KP) ss[threadIdx.x] = s ? s[threadIdx.x] : 0.0;
   __syncthreads();
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -306,23 +347,23 @@ hipError_t launch_wgram(int kp, const float* Z, const double* w, int invert, int
   return hipGetLastError();
 }
 hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok, hipStream_t s) {
-  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
-  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
-  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
+  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok);
+  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok);
+  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok);
   return hipGetLastError();
 }
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, hipStream_t s) {
-  if (kp == 8) hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 30);
-  else if (kp == 16) hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 30);
-  else hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 30);
+  if (kp == 8) hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 12);
+  else if (kp == 16) hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 12);
+  else hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 12);
   return hipGetLastError();
 }
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
                          int n, float* out, hipStream_t s) {
-  int nb = (n + 255) / 256;
-  if (kp == 8) hipLaunchKernelGGL((k_affine<8>), dim3(nb), dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
-  else if (kp == 16) hipLaunchKernelGGL((k_affine<16>), dim3(nb), dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
-  else hipLaunchKernelGGL((k_affine<32>), dim3(nb), dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  int nb = (n + 63) / 64;
+  if (kp == 8) hipLaunchKernelGGL((k_affine<8>), dim3(nb), dim3(64), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  else if (kp == 16) hipLaunchKernelGGL((k_affine<16>), dim3(nb), dim3(64), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  else hipLaunchKernelGGL((k_affine<32>), dim3(nb), dim3(64), 0, s, Z, sv, R, rs, rs_invert, n, out);
   return hipGetLastError();
 }
 hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, hipStream_t s) {
