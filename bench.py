@@ -56,6 +56,39 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def stored_sweep_roofline(sk, ctx, side=128, reps=10):
+    """HBM roofline of the stored-cost sweeps on the 16384 x 16384 grid
+    histograms (C stored FP32, 1 GiB): average duration of the column sweep
+    (streaming, float4 along the output axis) and of the row sweep, each
+    reading C once; algorithmic bytes = 4 per cost element."""
+    import torch
+    import workloads as W
+    prob = W.grid_histograms(side=side, seed=2)
+    dev = torch.device("cuda:0")
+    gp = sk.Problem(a=torch.from_numpy(prob.a).to(dev), b=torch.from_numpy(prob.b).to(dev),
+                    C=torch.from_numpy(prob.C).to(dev))
+    del prob.C
+    f = torch.zeros(gp.a.shape[0], dtype=torch.float64, device=dev)
+    g = torch.zeros(gp.b.shape[0], dtype=torch.float64, device=dev)
+    ctx.profile(True)
+    for _ in range(reps):
+        sk.c_transform_col(ctx, gp, 5e-4, f)
+        sk.c_transform_row(ctx, gp, 5e-4, g)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    out = {}
+    n, m = gp.a.shape[0], gp.b.shape[0]
+    for e in prof:
+        avg_s = e["total_ms"] / e["launches"] / 1e3
+        gbs = 4.0 * n * m / avg_s / 1e9
+        out[e["name"]] = {"avg_launch_us": avg_s * 1e6, "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": gbs / PEAK_HBM_GBS, "bytes_per_launch": 4.0 * n * m}
+    del gp
+    torch.cuda.empty_cache()
+    return {"workload": f"grid_histograms {side}x{side} (n=m={side*side}), stored FP32 cost, eps 5e-4",
+            "kernels": out}
+
+
 def cpu_baseline(prob, ladder, tol, ell, iters_per_stage):
     """The FP64 oracle, untuned, timed on a bounded sample of the same
     workload on the host: two plain SK iterations, two SK-NR(l)
@@ -105,12 +138,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sk-steps", type=int, default=3, help="timed plain-SK solves for the comparison")
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--ell", type=int, default=30)
+    ap.add_argument("--ell", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sk", action="store_true")
+    ap.add_argument("--no-stored", action="store_true", help="skip the stored-cost HBM sweep measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               f"(how the path would shard is described in the design notes)", file=sys.stderr)
@@ -211,6 +255,8 @@ def main():
     out["kernel_profile"] = [{"name": e["name"], "launches": e["launches"],
                               "avg_us": 1e3 * e["total_ms"] / max(1, e["launches"]),
                               "total_ms": e["total_ms"]} for e in sorted(prof, key=lambda e: -e["total_ms"])]
+    if not args.no_stored:
+        out["roofline_stored_cost"] = stored_sweep_roofline(sk, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, ladder, args.tol, args.ell, iters_nr)
     ctx.close()

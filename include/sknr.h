@@ -105,7 +105,7 @@ typedef struct sknr_opts {
   double eps_prime;       /* STATIC: eps' of the warm-start solve */
   int32_t eig_oversample; /* extra subspace columns (0 -> 8) */
   int32_t eig_max_iter;   /* subspace iterations cap (0 -> 100) */
-  double eig_tol;         /* Ritz-value stagnation tolerance (0 -> 1e-6) */
+  double eig_tol;         /* Ritz-value stagnation tolerance (0 -> 1e-4) */
   int32_t check_every;    /* iterations per host convergence poll (0 -> auto) */
   int32_t first_stage_nr; /* 1: SK-NR also on stage 0 (WARM_USER or WARM_STATIC) */
   const double* f0;       /* [device] optional n FP64 initial f at eps[0] (NULL -> 0) */

@@ -175,6 +175,7 @@ struct WS {
   double *blk_err, *blk_dot;
   float* blk_max;
   double* nrpart;
+  double* nrsum;  // partials summed: one (k*k + k) block
   int nr_rows_blk, nr_cols_blk;
   float* coef32;
   double* coef64;
@@ -329,6 +330,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   add(sizeof(float) * nbmax);
   int nrb = 64, ncb = 64;
   add(sizeof(double) * (nrb + ncb) * (size_t)(std::max(ellw, 1) * std::max(ellw, 1) + std::max(ellw, 1)));
+  add(sizeof(double) * (size_t)(std::max(ellw, 1) * std::max(ellw, 1) + std::max(ellw, 1)));
   add(sizeof(float) * 32);
   add(sizeof(double) * 32);
   add(sizeof(DevState));
@@ -401,10 +403,11 @@ WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
   w.blk_max = (float*)A.take(sizeof(float) * nbmax);
   // at most 16 + 16 partial blocks: the one-wave solver sums them with
   // independent loads
-  w.nr_rows_blk = std::min(16, std::max(1, (n + 255) / 256));
-  w.nr_cols_blk = std::min(16, std::max(1, (m + 255) / 256));
+  w.nr_rows_blk = std::min(64, std::max(1, (n + 63) / 64));
+  w.nr_cols_blk = std::min(64, std::max(1, (m + 63) / 64));
   int e1 = std::max(ellw, 1);
   w.nrpart = (double*)A.take(sizeof(double) * (128) * (size_t)(e1 * e1 + e1));
+  w.nrsum = (double*)A.take(sizeof(double) * (size_t)(e1 * e1 + e1));
   w.coef32 = (float*)A.take(sizeof(float) * 32);
   w.coef64 = (double*)A.take(sizeof(double) * 32);
   w.st = (DevState*)A.take(sizeof(DevState));
@@ -603,8 +606,11 @@ struct Engine {
   void newton(int ell, int gate_base) {
     HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
                               w.st, gate_base, s));
-    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout,
-                           w.st, gate_base, s));
+    {
+      const int e = ell_pad(ell);
+      HIPCHK(launch_sum_partials(w.nrpart, w.nr_rows_blk + w.nr_cols_blk, e * e + e, w.nrsum, s));
+    }
+    HIPCHK(launch_nr_solve(ell, w.nrsum, 1, w.coef32, w.coef64, w.Gout, w.gout, w.st, gate_base, s));
     HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.blk_dot, w.blk_max, w.st,
                            gate_base | G_CHOL_OK, DOT_FP, MA_FP, s));
   }
@@ -799,8 +805,9 @@ struct Engine {
     int kp = ell_pad(std::min(32, ell + std::max(0, oversample)));
     if (kp < ell_pad(ell)) kp = ell_pad(ell);
     const int n = P.n, m = P.m;
-    const int nbn = std::min(32, std::max(1, (n + 127) / 128));
-    const int nbm = std::min(32, std::max(1, (m + 127) / 128));
+    const int nbn = std::min(128, std::max(1, (n + 63) / 64));
+    const int nbm = std::min(128, std::max(1, (m + 63) / 64));
+    const int plen = kp * kp + kp;
     if (w.have_Vw) HIPCHK(hipMemcpyAsync(w.Zw, w.Vw, sizeof(float) * (size_t)n * kp, hipMemcpyDeviceToDevice, s));
     else HIPCHK(launch_random_block(kp, w.Zw, n, 0, seed, s));
     std::vector<double> lp(kp, 0.0), lc(kp, 0.0);
@@ -808,18 +815,23 @@ struct Engine {
     for (it = 1; it <= max_it; ++it) {
       // V = orthonormalised (Z - 1 s^T) in L2(a)
       HIPCHK(launch_wgram(kp, w.Zw, P.wX, 0, n, w.nrpart, nbn, s));
-      HIPCHK(launch_orth(kp, w.nrpart, nbn, w.Rw, w.sw, w.okw, s));
+      HIPCHK(launch_sum_partials(w.nrpart, nbn, plen, w.nrsum, s));
+      HIPCHK(launch_orth(kp, w.nrsum, 1, w.Rw, w.sw, w.okw, s));
       HIPCHK(launch_affine(kp, w.Zw, w.sw, w.Rw, nullptr, 0, n, w.Vw, s));
       // U = P~^T V (and G~ = T_c(F))
       sweep_col(w.F, MA_F, nullptr, w.Gt, DOT_GT, MA_GT, kp, w.Vw, w.Uw, W_SCALE_WEIGHT, 0, 0);
       // Rayleigh-Ritz: T = U^T D_b^-1 U = V^T D_a M V
       HIPCHK(launch_wgram(kp, w.Uw, P.wY, 1, m, w.nrpart, nbm, s));
-      HIPCHK(launch_jacobi(kp, w.nrpart, nbm, w.Qw, w.lamw, s));
+      HIPCHK(launch_sum_partials(w.nrpart, nbm, plen, w.nrsum, s));
+      HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, w.lamw, w.okw + 1, s));
       HIPCHK(launch_affine(kp, w.Vw, nullptr, w.Qw, nullptr, 0, n, w.Zw, s));
       std::swap(w.Vw, w.Zw);  // V <- V Q (Ritz vectors)
       HIPCHK(launch_affine(kp, w.Uw, nullptr, w.Qw, P.wY, 1, m, w.Utw, s));  // D_b^-1 U Q
       HIPCHK(hipMemcpyAsync(lc.data(), w.lamw, sizeof(double) * kp, hipMemcpyDeviceToHost, s));
+      int jsw = 0;
+      HIPCHK(hipMemcpyAsync(&jsw, w.okw + 1, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      if (getenv("SKNR_DEBUG_EIG")) std::fprintf(stderr, "eig it %d jacobi sweeps %d lam0 %.6f lam%d %.6f\n", it, jsw, lc[0], ell - 1, lc[ell - 1]);
       double dmax = 0;
       for (int i = 0; i < ell; ++i) dmax = std::max(dmax, std::fabs(lc[i] - lp[i]));
       lp = lc;
@@ -994,7 +1006,7 @@ int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts, doubl
     Engine E(c, P, w, s);
     const int eig_os = opts->eig_oversample > 0 ? opts->eig_oversample : 8;
     const int eig_it = opts->eig_max_iter > 0 ? opts->eig_max_iter : 100;
-    const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 1e-6;
+    const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 1e-4;
     std::memset(res, 0, sizeof(*res));
     E.tol = opts->tol;
     int static_eig_iters = 0;
@@ -1151,8 +1163,8 @@ int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps, const
     E.sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, 0, 0);
     HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
                               w.st, 0, s));
-    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout,
-                           w.st, 0, s));
+    HIPCHK(launch_sum_partials(w.nrpart, w.nr_rows_blk + w.nr_cols_blk, ellp * ellp + ellp, w.nrsum, s));
+    HIPCHK(launch_nr_solve(ell, w.nrsum, 1, w.coef32, w.coef64, w.Gout, w.gout, w.st, 0, s));
     std::vector<double> hG((size_t)ell * ell), hg(ell);
     HIPCHK(hipMemcpyAsync(hG.data(), w.Gout, 8 * hG.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hg.data(), w.gout, 8 * hg.size(), hipMemcpyDeviceToHost, s));

@@ -981,93 +981,87 @@ __device__ __forceinline__ double sum_partials(const double* part, int nblk, int
   return s;
 }
 
+// One wavefront: lane i keeps row i of G in registers.  Padded modes
+// (columns of V beyond ell_real are zero) become identity rows.
 template <int ELL>
-__global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, int ell_real, float* coef32,
-                                                  double* coef64, double* Gout, double* gout, DevState* st,
-                                                  int gate) {
+__global__ __launch_bounds__(64) void k_nr_solve(const double* part, int nblk, int ell_real, float* coef32,
+                                                 double* coef64, double* Gout, double* gout, DevState* st,
+                                                 int gate) {
   if (gate_closed(st, gate)) return;
-  const double eps = st->eps;
   constexpr int NE = ELL * ELL;
+  const double eps = st->eps;
   __shared__ double A[ELL][ELL + 1];
   __shared__ double g[ELL];
-  __shared__ int ok;
   for (int e = threadIdx.x; e < NE + ELL; e += blockDim.x) {
-    double s = sum_partials(part, nblk, NE + ELL, e);
-    if (e < NE) A[e / ELL][e % ELL] = s;
-    else g[e - NE] = s;
-  }
-  if (threadIdx.x == 0) ok = 1;
-  __syncthreads();
-  // symmetrise
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-    int i = e / ELL, j = e % ELL;
-    if (i < j) {
-      double v = 0.5 * (A[i][j] + A[j][i]);
-      A[i][j] = v;
-      A[j][i] = v;
-    }
+    double v = sum_partials(part, nblk, NE + ELL, e);
+    if (e < NE) A[e / ELL][e % ELL] = v;
+    else g[e - NE] = v;
   }
   __syncthreads();
-  if (Gout) {
-    for (int e = threadIdx.x; e < ell_real * ell_real; e += blockDim.x) Gout[e] = A[e / ell_real][e % ell_real];
-    for (int e = threadIdx.x; e < ell_real; e += blockDim.x) gout[e] = g[e];
-  }
-  __syncthreads();
-  // padded modes (columns of V beyond ell_real are zero): identity rows
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-    int i = e / ELL, j = e % ELL;
-    if (i >= ell_real || j >= ell_real) A[i][j] = (i == j) ? 1.0 : 0.0;
-  }
-  for (int e = threadIdx.x; e < ELL; e += blockDim.x)
-    if (e >= ell_real) g[e] = 0.0;
-  __syncthreads();
+  const int lane = threadIdx.x;
+  const int i = lane < ELL ? lane : ELL - 1;
+  double a[ELL];
   double dmax = 0;
-  for (int i = 0; i < ELL; ++i) dmax = fmax(dmax, A[i][i]);
-  // right-looking Cholesky (lower), in place
+#pragma unroll
+  for (int j = 0; j < ELL; ++j) {
+    double v = 0.5 * (A[i][j] + A[j][i]);
+    if (i >= ell_real || j >= ell_real) v = (i == j) ? 1.0 : 0.0;
+    a[j] = v;
+    double djj = (j < ell_real) ? A[j][j] : 1.0;
+    dmax = fmax(dmax, djj);
+  }
+  const double bi = i < ell_real ? g[i] : 0.0;
+  if (Gout) {
+    for (int e = lane; e < ell_real * ell_real; e += blockDim.x) Gout[e] = 0.5 * (A[e / ell_real][e % ell_real] + A[e % ell_real][e / ell_real]);
+    for (int e = lane; e < ell_real; e += blockDim.x) gout[e] = g[e];
+  }
+  int ok = 1;
+#pragma unroll
   for (int k = 0; k < ELL; ++k) {
-    __syncthreads();
-    double piv = A[k][k];
-    if (!(piv > 1e-300 && piv > 1e-15 * dmax)) {
-      if (threadIdx.x == 0) ok = 0;
-      piv = 1.0;
+    double akk = __shfl(a[k], k, 64);
+    if (!(akk > 1e-300 && akk > 1e-15 * dmax)) {
+      ok = 0;
+      akk = 1.0;
     }
-    double dk = sqrt(piv);
-    __syncthreads();
-    if (threadIdx.x == 0) A[k][k] = dk;
-    for (int i = k + 1 + threadIdx.x; i < ELL; i += blockDim.x) A[i][k] /= dk;
-    __syncthreads();
-    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-      int i = e / ELL, j = e % ELL;
-      if (j > k && i >= j) A[i][j] -= A[i][k] * A[j][k];
+    const double lkk = sqrt(akk);
+    const double inv = 1.0 / lkk;
+    a[k] = (i > k) ? a[k] * inv : (i == k ? lkk : a[k]);
+#pragma unroll
+    for (int j = k + 1; j < ELL; ++j) {
+      const double ljk = __shfl(a[k], j, 64);
+      if (i >= j) a[j] -= a[k] * ljk;
     }
   }
-  __syncthreads();
-  // solve L y = g then L^T z = y: one row per step, the update of the
-  // remaining right-hand side in parallel
-  __shared__ double y[ELL];
-  if ((int)threadIdx.x < ELL) y[threadIdx.x] = g[threadIdx.x];
-  __syncthreads();
-  for (int i = 0; i < ELL; ++i) {
-    if (threadIdx.x == 0) y[i] /= A[i][i];
-    __syncthreads();
-    for (int r = i + 1 + threadIdx.x; r < ELL; r += blockDim.x) y[r] -= A[r][i] * y[i];
-    __syncthreads();
+  // L y = g: y[t] broadcast to all lanes
+  double y[ELL];
+#pragma unroll
+  for (int t = 0; t < ELL; ++t) {
+    double acc = bi;
+#pragma unroll
+    for (int r = 0; r < t; ++r) acc -= a[r] * y[r];
+    y[t] = __shfl(acc / a[t], t, 64);
   }
-  for (int i = ELL - 1; i >= 0; --i) {
-    if (threadIdx.x == 0) y[i] /= A[i][i];
-    __syncthreads();
-    for (int r = threadIdx.x; r < i; r += blockDim.x) y[r] -= A[i][r] * y[i];
-    __syncthreads();
+  // L^T z = y: z_t = (y_t - sum_{r>t} l_rt z_r) / l_tt, lane r holds l_rt = a[t]
+  double zi = 0;
+#pragma unroll
+  for (int t = ELL - 1; t >= 0; --t) {
+    double term = (i > t && lane < ELL) ? a[t] * zi : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) term += __shfl_xor(term, off, 64);
+    const double ltt = __shfl(a[t], t, 64);
+    const double zt = (y[t] - term) / ltt;
+    if (i == t) zi = zt;
   }
-  if (threadIdx.x == 0) {
-    int good = ok;
-    for (int i = 0; i < ELL; ++i) {
-      double c = eps * y[i];
-      if (!(fabs(c) < 1e30)) good = 0;
-      coef64[i] = c;
-    }
-    for (int i = 0; i < ELL; ++i) coef32[i] = good ? (float)coef64[i] : 0.f;
-    st->chol_ok = good;
+  const double c = eps * zi;
+  const int bad = (lane < ELL) && !(fabs(c) < 1e30);
+  const int anybad = __any(bad);
+  ok = ok && !anybad;
+  if (lane < ELL) {
+    coef64[lane] = c;
+    coef32[lane] = ok ? (float)c : 0.f;
+  }
+  if (lane == 0) {
+    st->chol_ok = ok;
     st->accept = 0;
     st->newton_tried += 1;
   }

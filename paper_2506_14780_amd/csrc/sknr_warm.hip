@@ -25,6 +25,22 @@ __device__ __forceinline__ double sum_parts(const double* part, int nblk, int st
   return s;
 }
 
+// out[e] = sum over blocks (in block order) of part[b * len + e]
+__global__ __launch_bounds__(256) void k_sum_partials(const double* part, int nblk, int len, double* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double s = 0;
+  for (int b0 = 0; b0 < nblk; b0 += 32) {
+    const int nb = min(32, nblk - b0);
+    s += sum_parts(part + (size_t)b0 * len, nb, len, e);
+  }
+  out[e] = s;
+}
+hipError_t launch_sum_partials(const double* part, int nblk, int len, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3((len + 255) / 256), dim3(256), 0, s, part, nblk, len, out);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------- Gram
 // part[blk] = ( sum_i w_i Z_i Z_i^T  (k x k),  sum_i w_i Z_i  (k) ),
 // w_i = wgt[i] or 1/wgt[i] (invert), over a contiguous block of rows.
@@ -79,81 +95,70 @@ __global__ __launch_bounds__(256) void k_wgram(const float* Z, const double* wgt
 // Projecting out the constant (Z - 1 s^T, since sum a = 1) gives
 // B' = B - s s^T; with B' = L L^T, V = (Z - 1 s^T) L^-T is orthonormal in
 // L2(a) and orthogonal to the constants.  Writes R = L^-T (k x k), s.
+// One wavefront, matrix in LDS: right-looking Cholesky with the trailing
+// update spread over the lanes, then column j of L^-1 by lane j with
+// broadcast LDS reads of L.
 template <int KP>
-__global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out) {
+__global__ __launch_bounds__(64) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out) {
   constexpr int NE = KP * KP;
   __shared__ double B[KP][KP + 1];
   __shared__ double s[KP];
-  __shared__ double Li[KP][KP + 1];
-  for (int e = threadIdx.x; e < NE + KP; e += blockDim.x) {
+  __shared__ int ok_s;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < NE + KP; e += 64) {
     double v = sum_parts(part, nblk, NE + KP, e);
     if (e < NE) B[e / KP][e % KP] = v;
     else s[e - NE] = v;
   }
+  if (lane == 0) ok_s = 1;
   __syncthreads();
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-    int i = e / KP, j = e % KP;
-    B[i][j] -= s[i] * s[j];
-  }
-  __syncthreads();
-  // symmetrise and regularise by a tiny multiple of the trace
-  __shared__ double tr_s;
-  __shared__ int ok_s;
-  if (threadIdx.x == 0) {
-    double tr = 0;
-    for (int i = 0; i < KP; ++i) tr += B[i][i];
-    tr_s = tr;
-    ok_s = tr > 0;
-  }
-  __syncthreads();
-  const double tr = tr_s;
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-    int i = e / KP, j = e % KP;
-    if (i > j) {
-      double v = 0.5 * (B[i][j] + B[j][i]);
+  double tr = 0;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) tr += B[k][k] - s[k] * s[k];
+  // B' = sym(B) - s s^T (+ tiny ridge), lower triangle suffices
+  for (int e = lane; e < NE; e += 64) {
+    const int i = e / KP, j = e % KP;
+    if (j <= i) {
+      double v = 0.5 * (B[i][j] + B[j][i]) - s[i] * s[j];
+      if (i == j) v += 1e-13 * tr / KP;
       B[i][j] = v;
-      B[j][i] = v;
     }
   }
   __syncthreads();
-  if ((int)threadIdx.x < KP) B[threadIdx.x][threadIdx.x] += 1e-13 * tr / KP;
-  // right-looking Cholesky (lower, in place), one column per step
   for (int k = 0; k < KP; ++k) {
-    __syncthreads();
     double d = B[k][k];
     if (!(d > 1e-30 * tr)) {
       d = 1e-30 * tr + 1e-300;
-      if (threadIdx.x == 0) ok_s = 0;
+      if (lane == 0) ok_s = 0;
     }
-    const double lk = sqrt(d);
+    const double lk = sqrt(d), inv = 1.0 / lk;
     __syncthreads();
-    if (threadIdx.x == 0) B[k][k] = lk;
-    for (int i = k + 1 + threadIdx.x; i < KP; i += blockDim.x) B[i][k] /= lk;
+    if (lane == 0) B[k][k] = lk;
+    for (int i = k + 1 + lane; i < KP; i += 64) B[i][k] *= inv;
     __syncthreads();
-    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-      int i = e / KP, j = e % KP;
-      if (j > k && i >= j) B[i][j] -= B[i][k] * B[j][k];
+    const int rem = KP - 1 - k;
+    for (int e = lane; e < rem * rem; e += 64) {
+      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+      if (j <= i) B[i][j] -= B[i][k] * B[j][k];
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // Li = L^-1: column j by thread j (forward substitution)
-  if ((int)threadIdx.x < KP) {
-    const int j = threadIdx.x;
-    for (int i = 0; i < KP; ++i) Li[i][j] = 0;
-    Li[j][j] = 1.0 / B[j][j];
-    for (int i = j + 1; i < KP; ++i) {
-      double v = 0;
-      for (int t = j; t < i; ++t) v -= B[i][t] * Li[t][j];
-      Li[i][j] = v / B[i][i];
+  // L^-1, column j by lane j: x_r = (delta_rj - sum_{t<r} L_rt x_t) / L_rr
+  if (lane < KP) {
+    const int j = lane;
+    double x[KP];
+#pragma unroll
+    for (int r = 0; r < KP; ++r) {
+      double acc = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int t = 0; t < r; ++t) acc -= B[r][t] * x[t];
+      x[r] = acc / B[r][r];
     }
+#pragma unroll
+    for (int t = 0; t < KP; ++t) R[j * KP + t] = x[t];  // R = L^-T
+    s_out[j] = s[j];
   }
-  __syncthreads();
-  if (threadIdx.x == 0) *ok_out = ok_s;
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-    int i = e / KP, j = e % KP;
-    R[e] = Li[j][i];  // R = L^-T, row-major
-  }
-  for (int e = threadIdx.x; e < KP; e += blockDim.x) s_out[e] = s[e];
+  if (lane == 0) *ok_out = ok_s;
 }
 
 // ------------------------------------------------------ Rayleigh-Ritz
@@ -162,7 +167,8 @@ __global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, doub
 // (k/2 disjoint rotations per step), then eigenpairs sorted descending:
 // Q (k x k, columns = eigenvectors, row-major), lam (k).
 template <int KP>
-__global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, double* Qout, double* lam, int sweeps) {
+__global__ __launch_bounds__(64) void k_jacobi(const double* part, int nblk, double* Qout, double* lam, int sweeps,
+                                               int* sweeps_out) {
   constexpr int NE = KP * KP;
   constexpr int NP = KP / 2;
   __shared__ double A[KP][KP + 1];
@@ -186,7 +192,8 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
   }
   __syncthreads();
   __shared__ double red[2][4];
-  for (int sw = 0; sw < sweeps; ++sw) {
+  int sw = 0;
+  for (sw = 0; sw < sweeps; ++sw) {
     double off = 0, dia = 0;
     for (int e = threadIdx.x; e < NE; e += blockDim.x) {
       double v = A[e / KP][e % KP];
@@ -208,7 +215,8 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
         o2 += red[0][w];
         d2 += red[1][w];
       }
-      off_s = o2 <= 1e-24 * d2 ? -1.0 : o2;
+      // the basis it rotates is FP32: stop at off-diagonal ~1e-7 relative
+      off_s = o2 <= 1e-14 * d2 ? -1.0 : o2;
     }
     __syncthreads();
     if (off_s < 0) break;
@@ -220,13 +228,17 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
         if (p > q) { int t = p; p = q; q = t; }
         pr[r][0] = p;
         pr[r][1] = q;
-        double apq = A[p][q];
+        // rotation angle in FP32 (rsq / rcp); (c, s) normalised in FP64
+        // so that the accumulated Q stays orthogonal to FP64 rounding
+        const double apq = A[p][q];
         double c = 1.0, s = 0.0;
         if (fabs(apq) > 1e-300) {
-          double th = (A[q][q] - A[p][p]) / (2.0 * apq);
-          double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
+          const float th = (float)((A[q][q] - A[p][p]) / (2.0 * apq));
+          const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(fmaf(th, th, 1.0f)));
+          const double td = (double)t;
+          const double rn = 1.0 / sqrt(1.0 + td * td);
+          c = rn;
+          s = td * rn;
         }
         cs[r][0] = c;
         cs[r][1] = s;
@@ -258,20 +270,24 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int idx[KP];
-    for (int i = 0; i < KP; ++i) idx[i] = i;
-    for (int i = 0; i < KP; ++i)
-      for (int j = i + 1; j < KP; ++j)
-        if (A[idx[j]][idx[j]] > A[idx[i]][idx[i]]) {
-          int t = idx[i];
-          idx[i] = idx[j];
-          idx[j] = t;
-        }
-    for (int i = 0; i < KP; ++i) {
-      lam[i] = A[idx[i]][idx[i]];
-      for (int r = 0; r < KP; ++r) Qout[r * KP + i] = Q[r][idx[i]];
+  if (threadIdx.x == 0 && sweeps_out) *sweeps_out = sw;
+  // descending order: rank of each eigenvalue (ties by index), in parallel
+  __shared__ int order[KP];
+  if ((int)threadIdx.x < KP) {
+    const int i = threadIdx.x;
+    const double li = A[i][i];
+    int rank = 0;
+    for (int j = 0; j < KP; ++j) {
+      const double lj = A[j][j];
+      rank += (lj > li) || (lj == li && j < i);
     }
+    order[rank] = i;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < KP) {
+    const int r = threadIdx.x;
+    lam[r] = A[order[r]][order[r]];
+    for (int i = 0; i < KP; ++i) Qout[r * KP + i] = Q[r][order[i]];
   }
 }
 
@@ -352,10 +368,11 @@ hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* 
   else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok);
   return hipGetLastError();
 }
-hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, hipStream_t s) {
-  if (kp == 8) hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 12);
-  else if (kp == 16) hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 12);
-  else hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 12);
+hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
+                         hipStream_t s) {
+  if (kp == 8) hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 10, sweeps_out);
+  else if (kp == 16) hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 10, sweeps_out);
+  else hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 10, sweeps_out);
   return hipGetLastError();
 }
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
