@@ -43,10 +43,32 @@ def algorithmic_work(kind: str):
     running max, exp2 (issued at half rate: 2 slots) and the accumulation:
     10 VALU slots; a weighted sweep adds one FMA per basis column.
     Stored-cost sweeps ("hbm"): 4 bytes of C read per element."""
+    kind = kind.split(":")[0]
     width = int(kind.rsplit("_l", 1)[1]) if "_l" in kind else 0
     if "stored" in kind:
         return "hbm", 4.0, "GB/s"
     return "alu", 10.0 + width, "TOP/s"
+
+
+# HBM bytes per launch of the main sweep kernels from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the counts of a
+# plain 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2.0, WRITE_SIZE 1 GiB
+# -> x1.0); see profiles/.  Valid only for the kernel source they were
+# taken with.
+TRAFFIC_KERNEL_SHA1 = "b75ca5e76b9c3f7a14c86b5033379db385aab648"
+TRAFFIC_BYTES = {
+    "sweep_stream_points_l0:main": (193.79 * 2.0 + 1836.06) * 1024,
+    "sweep_stream_stored_l0:main": (524897.39 * 2.0 + 6144.0) * 1024,
+    "sweep_rows_stored_l0:main": (525912.11 * 2.0 + 529.54) * 1024,
+}
+
+
+def kernel_traffic(name):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2506_14780_amd", "csrc", "sknr_kernels.hip")
+    if hashlib.sha1(open(src, "rb").read()).hexdigest() != TRAFFIC_KERNEL_SHA1:
+        return None
+    return TRAFFIC_BYTES.get(name)
 
 
 def percentile(xs, q):
@@ -79,10 +101,13 @@ def stored_sweep_roofline(sk, ctx, side=128, reps=10):
     out = {}
     n, m = gp.a.shape[0], gp.b.shape[0]
     for e in prof:
+        if not e["name"].endswith(":main"):
+            continue
         avg_s = e["total_ms"] / e["launches"] / 1e3
         gbs = 4.0 * n * m / avg_s / 1e9
         out[e["name"]] = {"avg_launch_us": avg_s * 1e6, "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                          "frac": gbs / PEAK_HBM_GBS, "bytes_per_launch": 4.0 * n * m}
+                          "frac": gbs / PEAK_HBM_GBS, "bytes_per_launch": 4.0 * n * m,
+                          "traffic": kernel_traffic(e["name"])}
     del gp
     torch.cuda.empty_cache()
     return {"workload": f"grid_histograms {side}x{side} (n=m={side*side}), stored FP32 cost, eps 5e-4",
@@ -238,7 +263,9 @@ def main():
     one(args.ell)
     prof = ctx.profile_read()
     ctx.profile(False)
-    dom = max(prof, key=lambda e: e["total_ms"])
+    mains = [e for e in prof if e["name"].endswith(":main")]
+    dom = max(mains, key=lambda e: e["total_ms"])
+    whole = next(e for e in prof if e["name"] == dom["name"].split(":")[0])
     bound, per_unit, unit = algorithmic_work(dom["name"])
     avg_s = dom["total_ms"] / dom["launches"] / 1e3
     per_launch = per_unit * dom["units"] / dom["launches"]
@@ -248,9 +275,13 @@ def main():
         achieved, peak = per_launch / avg_s / 1e12, PEAK_VALU_TOPS
     out["roofline"] = {
         "bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-        "traffic": None, "kernel": dom["name"], "avg_launch_us": avg_s * 1e6,
+        "traffic": kernel_traffic(dom["name"]), "kernel": dom["name"], "avg_launch_us": avg_s * 1e6,
         "launches_per_solve": dom["launches"], "elements_per_launch": dom["units"] / dom["launches"],
-        "share_of_sweep_time": dom["total_ms"] / sum(e["total_ms"] for e in prof),
+        "work_per_element": per_unit,
+        "with_merge_and_finish": {"avg_us": 1e3 * whole["total_ms"] / whole["launches"],
+                                  "frac": per_launch / (whole["total_ms"] / whole["launches"] / 1e3)
+                                  / (1e12 if bound != "hbm" else 1e9) / peak},
+        "share_of_sweep_time": dom["total_ms"] / sum(e["total_ms"] for e in prof if e["name"].endswith(":main")),
     }
     out["kernel_profile"] = [{"name": e["name"], "launches": e["launches"],
                               "avg_us": 1e3 * e["total_ms"] / max(1, e["launches"]),

@@ -132,14 +132,19 @@ struct Ctx {
   }
   // after a stream synchronisation: fold completed event pairs
   void drain() {
+    hipEvent_t last_e0 = nullptr;
     for (auto& p : pending) {
+      hipEvent_t e0 = p.e0 ? p.e0 : last_e0;  // a ":main" entry starts at its sweep's start
       float ms = 0;
-      if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+      if (e0 && hipEventElapsedTime(&ms, e0, p.e1) == hipSuccess) {
         prof[p.kind].launches += 1;
         prof[p.kind].total_ms += ms;
         prof[p.kind].units += p.units;
       }
-      evpool.push_back(p.e0);
+      if (p.e0) last_e0 = p.e0;
+    }
+    for (auto& p : pending) {
+      if (p.e0) evpool.push_back(p.e0);
       evpool.push_back(p.e1);
     }
     pending.clear();
@@ -489,21 +494,25 @@ struct Engine {
   }
 
   void launch_sweep(const SweepArgs& a, bool stream_kernel, bool vec, int ell) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t e0 = nullptr, em = nullptr, e1 = nullptr;
     if (c->profile) {
       e0 = c->get_event();
+      em = c->get_event();
       e1 = c->get_event();
       HIPCHK(hipEventRecord(e0, s));
     }
-    if (stream_kernel) HIPCHK(launch_sweep_stream(a, P.kind, vec, s));
-    else HIPCHK(launch_sweep_rows(a, s));
+    if (stream_kernel) HIPCHK(launch_sweep_stream(a, P.kind, vec, s, em));
+    else HIPCHK(launch_sweep_rows(a, s, em));
     if (c->profile) {
       HIPCHK(hipEventRecord(e1, s));
       char nm[96];
       std::snprintf(nm, sizeof nm, "%s_%s_l%d", stream_kernel ? "sweep_stream" : "sweep_rows",
                     P.kind == SKNR_COST_STORED ? "stored" : (P.d <= 8 ? "points" : "points_gen"),
                     ell <= 0 ? 0 : ell_pad(ell));
-      c->pending.push_back(Pending{c->kind_of(nm), e0, e1, (double)a.n_out * (double)a.n_red});
+      const double units = (double)a.n_out * (double)a.n_red;
+      // whole sweep (main kernel + merge/finish) and the main kernel alone
+      c->pending.push_back(Pending{c->kind_of(nm), e0, e1, units});
+      c->pending.push_back(Pending{c->kind_of(std::string(nm) + ":main"), nullptr, em, units});
     }
   }
 

@@ -99,8 +99,10 @@ struct SweepArgs {
 // ----------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
 // vec: the stored cost allows float4 access along the output axis
-hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t stream);
-hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t stream);
+// mid (optional): an event recorded right after the main sweep kernel
+hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t stream,
+                               hipEvent_t mid = nullptr);
+hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t stream, hipEvent_t mid = nullptr);
 size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bool vec, int* nsplit, int* rps,
                          int* nblk, bool stream_kernel);
 

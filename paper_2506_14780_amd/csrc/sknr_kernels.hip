@@ -730,7 +730,7 @@ size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bo
 }
 
 template <int CPT, int ELL, int COST, int D, int R>
-static hipError_t go_stream(const SweepArgs& a, hipStream_t s) {
+static hipError_t go_stream(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
   constexpr int NC = 64 * CPT;
   int ncb = (a.n_out + NC - 1) / NC;
   dim3 grid(ncb, a.nsplit);
@@ -742,41 +742,42 @@ static hipError_t go_stream(const SweepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, true>), grid, dim3(TPB), sm, s, a);
   else
     hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, false>), grid, dim3(TPB), sm, s, a);
+  if (mid) (void)hipEventRecord(mid, s);
   hipLaunchKernelGGL((k_sweep_merge<ELL>), dim3((a.n_out + 63) / 64), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_sweep_finish, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 template <int CPT, int ELL>
-static hipError_t go_stream_points(const SweepArgs& a, hipStream_t s) {
+static hipError_t go_stream_points(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
   switch (a.d) {
-    case 1: return go_stream<CPT, ELL, 1, 1, 4>(a, s);
-    case 2: return go_stream<CPT, ELL, 1, 2, 4>(a, s);
-    case 3: return go_stream<CPT, ELL, 1, 3, 4>(a, s);
-    case 4: return go_stream<CPT, ELL, 1, 4, 4>(a, s);
-    case 5: return go_stream<CPT, ELL, 1, 5, 2>(a, s);
-    case 6: return go_stream<CPT, ELL, 1, 6, 2>(a, s);
-    case 7: return go_stream<CPT, ELL, 1, 7, 2>(a, s);
-    case 8: return go_stream<CPT, ELL, 1, 8, 2>(a, s);
-    default: return go_stream<CPT, ELL, 1, 0, 2>(a, s);
+    case 1: return go_stream<CPT, ELL, 1, 1, 4>(a, s, mid);
+    case 2: return go_stream<CPT, ELL, 1, 2, 4>(a, s, mid);
+    case 3: return go_stream<CPT, ELL, 1, 3, 4>(a, s, mid);
+    case 4: return go_stream<CPT, ELL, 1, 4, 4>(a, s, mid);
+    case 5: return go_stream<CPT, ELL, 1, 5, 2>(a, s, mid);
+    case 6: return go_stream<CPT, ELL, 1, 6, 2>(a, s, mid);
+    case 7: return go_stream<CPT, ELL, 1, 7, 2>(a, s, mid);
+    case 8: return go_stream<CPT, ELL, 1, 8, 2>(a, s, mid);
+    default: return go_stream<CPT, ELL, 1, 0, 2>(a, s, mid);
   }
 }
 
-hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t s) {
+hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t s, hipEvent_t mid) {
   const int cpt = stream_cpt(cost_kind, a.ell, vec);
   if (cost_kind == 0) {
-    if (a.ell == 0) return cpt == 4 ? go_stream<4, 0, 0, 1, 8>(a, s) : go_stream<1, 0, 0, 1, 8>(a, s);
-    if (a.ell <= 8) return cpt == 4 ? go_stream<4, 8, 0, 1, 4>(a, s) : go_stream<1, 8, 0, 1, 4>(a, s);
-    if (a.ell <= 16) return cpt == 4 ? go_stream<4, 16, 0, 1, 4>(a, s) : go_stream<1, 16, 0, 1, 4>(a, s);
-    return go_stream<2, 32, 0, 1, 4>(a, s);
+    if (a.ell == 0) return cpt == 4 ? go_stream<4, 0, 0, 1, 8>(a, s, mid) : go_stream<1, 0, 0, 1, 8>(a, s, mid);
+    if (a.ell <= 8) return cpt == 4 ? go_stream<4, 8, 0, 1, 4>(a, s, mid) : go_stream<1, 8, 0, 1, 4>(a, s, mid);
+    if (a.ell <= 16) return cpt == 4 ? go_stream<4, 16, 0, 1, 4>(a, s, mid) : go_stream<1, 16, 0, 1, 4>(a, s, mid);
+    return go_stream<2, 32, 0, 1, 4>(a, s, mid);
   }
-  if (a.ell == 0) return go_stream_points<4, 0>(a, s);
-  if (a.ell <= 8) return go_stream_points<2, 8>(a, s);
-  if (a.ell <= 16) return go_stream_points<2, 16>(a, s);
-  return go_stream_points<2, 32>(a, s);
+  if (a.ell == 0) return go_stream_points<4, 0>(a, s, mid);
+  if (a.ell <= 8) return go_stream_points<2, 8>(a, s, mid);
+  if (a.ell <= 16) return go_stream_points<2, 16>(a, s, mid);
+  return go_stream_points<2, 32>(a, s, mid);
 }
 
-hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t s) {
+hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
   bool vec = (a.n_red % 4 == 0) && (a.ldc % 4 == 0) && ((uintptr_t)a.C % 16 == 0) && ((uintptr_t)a.Uin % 16 == 0);
   if (a.ell == 0) {
     dim3 grid((a.n_out + 3) / 4);
@@ -795,6 +796,7 @@ hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t s) {
       else hipLaunchKernelGGL((k_sweep_rows<1, 32, false>), grid, dim3(TPB), 0, s, a);
     }
   }
+  if (mid) (void)hipEventRecord(mid, s);
   hipLaunchKernelGGL(k_sweep_finish, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
