@@ -71,6 +71,16 @@ enum sknr_cost_kind {
  * term per coordinate (BF16) or a hi/lo bf16 split keeping hi*hi + hi*lo +
  * lo*hi (BF16X3).  AUTO picks FP32 for d < 16 and BF16X3 for d >= 16. */
 enum sknr_xterm { SKNR_XTERM_AUTO = 0, SKNR_XTERM_FP32 = 1, SKNR_XTERM_BF16 = 2, SKNR_XTERM_BF16X3 = 3 };
+/* Matrix-core cost in detail (BF16, BF16X3): the points are centred on mu,
+ * the FP64 mean of all n + m points rounded to bf16; v = fl32(x - mu) is
+ * rounded to bf16 hi = bf16(v) (and lo = bf16(v - hi) for BF16X3, x~ = hi
+ * + lo; for BF16 x~ = hi); per point n_i = fl32(cost_scale * ||x~_i||^2)
+ * with the norm summed in FP64; and
+ *   C~_ij = fma(-2 fl32(cost_scale), x~_i . y~_j, n_i + n_j)
+ * in FP32 with the dot product on matrix cores (FP32 accumulation, any
+ * order; |error| <= (dpad - 1) u sum_k |x~_ik y~_jk|, dpad = d rounded up
+ * to 32, u = 2^-24), omitting lo*lo for BF16X3.  C~ is symmetric in the
+ * roles of x and y, so both c-transforms use the same matrix. */
 
 typedef struct sknr_problem {
   int64_t n;            /* number of source points / size of a (n >= 1) */
@@ -137,6 +147,10 @@ typedef struct sknr_result {
   double dual_value;        /* Q_eps(f, g), eq. def_Q (FP64) */
   double primal_value;      /* <C,pi> + eps KL(pi || a(x)b) (FP64) */
   double mass;              /* sum_ij pi_ij */
+  double marginal_err_exact;   /* FP64 L1 marginal error vs the exact cost (SQEUCLID:
+                                  FP64 squared distances of the FP32 points; STORED:
+                                  equal to marginal_err) */
+  double transport_cost_exact; /* <C, pi> on that exact cost */
   double seconds;
 } sknr_result;
 
@@ -223,11 +237,16 @@ int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps,
 typedef struct sknr_eval {
   double row_err, col_err, marginal_err;   /* L1 marginal errors */
   double transport_cost, dual_value, primal_value, mass;
+  /* the same marginal errors and <C,pi> on the exact cost (SQEUCLID: FP64
+   * squared distances of the FP32 points; STORED: copies of the above) */
+  double row_err_exact, col_err_exact, marginal_err_exact, transport_cost_exact;
 } sknr_eval;
 
-/* FP64 evaluation of a pair (f, g) on the solver's cost: marginal errors,
- * <C,pi>, Q_eps (eq. def_Q) and the primal value <C,pi> + eps KL(pi||a(x)b)
- * (eq. primal_EOT).  f, g [device] FP64; out [host]. */
+/* FP64 evaluation of a pair (f, g) on the solver's cost C~ (the FP32 or
+ * matrix-core cost the sweeps use, per xterm): marginal errors, <C,pi>,
+ * Q_eps (eq. def_Q) and the primal value <C,pi> + eps KL(pi||a(x)b)
+ * (eq. primal_EOT); plus marginal errors and <C,pi> on the exact cost.
+ * f, g [device] FP64; out [host]. */
 int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps,
                   const double* f, const double* g, sknr_eval* out, void* stream);
 

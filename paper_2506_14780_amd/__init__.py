@@ -65,12 +65,14 @@ class _Result(ctypes.Structure):
     _fields_ = [("status", _i32), ("n_stages", _i32), ("total_iters", _i32), ("transposed", _i32),
                 ("stage", _Stage * MAX_STAGES), ("marginal_err", _d), ("row_err", _d),
                 ("col_err", _d), ("transport_cost", _d), ("dual_value", _d),
-                ("primal_value", _d), ("mass", _d), ("seconds", _d)]
+                ("primal_value", _d), ("mass", _d), ("marginal_err_exact", _d),
+                ("transport_cost_exact", _d), ("seconds", _d)]
 
 
 class _Eval(ctypes.Structure):
     _fields_ = [("row_err", _d), ("col_err", _d), ("marginal_err", _d), ("transport_cost", _d),
-                ("dual_value", _d), ("primal_value", _d), ("mass", _d)]
+                ("dual_value", _d), ("primal_value", _d), ("mass", _d), ("row_err_exact", _d),
+                ("col_err_exact", _d), ("marginal_err_exact", _d), ("transport_cost_exact", _d)]
 
 
 class _KProf(ctypes.Structure):
@@ -240,9 +242,7 @@ def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 1
     ps = prob.c_struct()
     st = lib.sknr_solve(ctx.handle, ctypes.byref(ps), ctypes.byref(o), _ptr(f), _ptr(g), ctypes.byref(r))
     _check(st, "sknr_solve")
-    res = {k: getattr(r, k) for k in ("status", "n_stages", "total_iters", "transposed", "marginal_err",
-                                       "row_err", "col_err", "transport_cost", "dual_value",
-                                       "primal_value", "mass", "seconds")}
+    res = {k: getattr(r, k) for k, _ in _Result._fields_ if k != "stage"}
     res["stages"] = [{k: getattr(r.stage[i], k) for k, _ in _Stage._fields_} for i in range(r.n_stages)]
     return f, g, res
 

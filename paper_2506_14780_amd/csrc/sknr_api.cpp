@@ -165,7 +165,12 @@ struct Prepared {
   const float* Y;  // points of side Y (m x d)
   int d;
   float cscale;
+  double cscale64;
   float cmax;
+  // cross term of a SQEUCLID cost: 1 FP32 direct, 2 bf16, 3 bf16 hi/lo split
+  int xmode = 0;
+  int dpad = 0;          // bf16 rows: d rounded up to a multiple of 32
+  std::vector<float> mu;  // centring point (bf16-rounded mean of all points)
   const double* wX;  // device FP64 weights
   const double* wY;
   std::vector<double> hX, hY;  // host copies
@@ -198,17 +203,34 @@ struct WS {
   double *Rw, *sw, *Qw, *lamw;
   int* okw;
   bool have_Vw;
+  // packed points of the matrix-core cost (engine orientation)
+  unsigned short *HX, *LX, *HY, *LY;
+  float *NX, *NY, *mu;
   // sweep geometry
   int ns_c, rps_c, nb_c, ns_r, rps_r, nb_r, ns_cw, rps_cw, nb_cw;
 };
 
 int ell_pad(int ell) { return ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32)); }
 
+// cost kind of the sweep kernels: 0 stored, 1 points FP32, 2 bf16, 3 bf16 split
+int sweep_kind(const Prepared& P) { return P.kind == SKNR_COST_STORED ? 0 : P.xmode; }
+
 bool col_is_stream(const Prepared& P) { return P.kind == SKNR_COST_SQEUCLID || !P.ctrans; }
 bool row_is_stream(const Prepared& P) { return P.kind == SKNR_COST_SQEUCLID || P.ctrans; }
 // float4 access along the output axis of a streaming sweep over a stored cost
 bool stream_vec(const Prepared& P, int n_out) {
   return P.kind == SKNR_COST_STORED && n_out % 4 == 0 && P.ldc % 4 == 0 && ((uintptr_t)P.C % 16) == 0;
+}
+
+// a value rounded to the nearest bf16 (round to nearest even), as FP32
+float bf16_round(double v) {
+  float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  u &= 0xFFFF0000u;
+  std::memcpy(&f, &u, 4);
+  return f;
 }
 
 // --------------------------------------------------------------- prepare
@@ -230,6 +252,7 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s) {
   P.ctrans = P.transposed;
   P.d = pr->d;
   P.cscale = 1.0f;
+  P.cscale64 = 1.0;
   if (pr->kind == SKNR_COST_STORED) {
     REQUIRE(pr->C, "stored cost C is NULL");
     REQUIRE(pr->ldc >= pr->m, "ldc < m");
@@ -240,6 +263,10 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s) {
     double sc = pr->cost_scale == 0.0 ? 1.0 : pr->cost_scale;
     REQUIRE(sc > 0 && std::isfinite(sc), "cost_scale must be positive");
     P.cscale = (float)sc;
+    P.cscale64 = sc;
+    REQUIRE(pr->xterm >= SKNR_XTERM_AUTO && pr->xterm <= SKNR_XTERM_BF16X3, "unknown xterm");
+    P.xmode = pr->xterm == SKNR_XTERM_AUTO ? (pr->d >= 16 ? SKNR_XTERM_BF16X3 : SKNR_XTERM_FP32) : pr->xterm;
+    if (P.xmode >= SKNR_XTERM_BF16) P.dpad = (pr->d + 31) & ~31;
     P.X = P.transposed ? pr->y : pr->x;
     P.Y = P.transposed ? pr->x : pr->y;
   }
@@ -282,20 +309,24 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(hy.data(), pr->y, hy.size() * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double bound = 0;
+    P.mu.assign(d, 0.f);
     for (int k = 0; k < d; ++k) {
-      double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY;
+      double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY, sum = 0;
       for (int i = 0; i < P.n0; ++i) {
         double v = hx[(size_t)i * d + k];
         REQUIRE(std::isfinite(v), "x has non-finite entries");
         xl = std::min(xl, v);
         xh = std::max(xh, v);
+        sum += v;
       }
       for (int j = 0; j < P.m0; ++j) {
         double v = hy[(size_t)j * d + k];
         REQUIRE(std::isfinite(v), "y has non-finite entries");
         yl = std::min(yl, v);
         yh = std::max(yh, v);
+        sum += v;
       }
+      P.mu[k] = bf16_round(sum / (double)(P.n0 + P.m0));
       double span = std::max(std::fabs(xh - yl), std::fabs(yh - xl));
       bound += span * span;
     }
@@ -315,10 +346,10 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   const int ellw = ellp > 0 ? 32 : 0;
   // T_c (output Y), with and without weights
   for (int e : {0, ellp, ellw}) {
-    size_t p = sweep_part_floats(m, n, e, P.kind, P.d, stream_vec(P, m), &ns, &rps, &nb, col_is_stream(P));
+    size_t p = sweep_part_floats(m, n, e, sweep_kind(P), P.d, stream_vec(P, m), &ns, &rps, &nb, col_is_stream(P));
     pmax = std::max(pmax, p);
     nbmax = std::max(nbmax, nb);
-    p = sweep_part_floats(n, m, e, P.kind, P.d, stream_vec(P, n), &ns, &rps, &nb, row_is_stream(P));
+    p = sweep_part_floats(n, m, e, sweep_kind(P), P.d, stream_vec(P, n), &ns, &rps, &nb, row_is_stream(P));
     pmax = std::max(pmax, p);
     nbmax = std::max(nbmax, nb);
   }
@@ -357,6 +388,14 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
     add(sizeof(float) * (size_t)m * 32 * 2);
     add(sizeof(double) * 32 * 32 * 2 + sizeof(double) * 64 + 64);
   }
+  if (P.xmode >= SKNR_XTERM_BF16) {
+    const int parts = P.xmode == SKNR_XTERM_BF16X3 ? 2 : 1;
+    add(sizeof(unsigned short) * (size_t)n * P.dpad * parts);
+    add(sizeof(unsigned short) * (size_t)m * P.dpad * parts);
+    add(sizeof(float) * n);
+    add(sizeof(float) * m);
+    add(sizeof(float) * P.d);
+  }
   if (geo) *geo = nbmax;
   return b + 4096;
 }
@@ -394,10 +433,10 @@ WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
   size_t pmax = 0;
   const int ellw = ellp > 0 ? 32 : 0;
   for (int e : {0, ellp, ellw}) {
-    pmax = std::max(pmax, sweep_part_floats(m, n, e, P.kind, P.d, stream_vec(P, m), &ns, &rps, &nb,
+    pmax = std::max(pmax, sweep_part_floats(m, n, e, sweep_kind(P), P.d, stream_vec(P, m), &ns, &rps, &nb,
                                             col_is_stream(P)));
     nbmax = std::max(nbmax, nb);
-    pmax = std::max(pmax, sweep_part_floats(n, m, e, P.kind, P.d, stream_vec(P, n), &ns, &rps, &nb,
+    pmax = std::max(pmax, sweep_part_floats(n, m, e, sweep_kind(P), P.d, stream_vec(P, n), &ns, &rps, &nb,
                                             row_is_stream(P)));
     nbmax = std::max(nbmax, nb);
   }
@@ -445,6 +484,23 @@ WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
     w.lamw = (double*)A.take(sizeof(double) * 32);
     w.okw = (int*)A.take(64);
   }
+  w.HX = w.LX = w.HY = w.LY = nullptr;
+  w.NX = w.NY = w.mu = nullptr;
+  if (P.xmode >= SKNR_XTERM_BF16) {
+    const bool x3 = P.xmode == SKNR_XTERM_BF16X3;
+    w.HX = (unsigned short*)A.take(sizeof(unsigned short) * (size_t)n * P.dpad);
+    w.HY = (unsigned short*)A.take(sizeof(unsigned short) * (size_t)m * P.dpad);
+    if (x3) {
+      w.LX = (unsigned short*)A.take(sizeof(unsigned short) * (size_t)n * P.dpad);
+      w.LY = (unsigned short*)A.take(sizeof(unsigned short) * (size_t)m * P.dpad);
+    }
+    w.NX = (float*)A.take(sizeof(float) * n);
+    w.NY = (float*)A.take(sizeof(float) * m);
+    w.mu = (float*)A.take(sizeof(float) * P.d);
+    HIPCHK(hipMemcpyAsync(w.mu, P.mu.data(), sizeof(float) * P.d, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_pack_points(P.X, n, P.d, w.mu, P.cscale64, P.dpad, x3, w.HX, w.LX, w.NX, s));
+    HIPCHK(launch_pack_points(P.Y, m, P.d, w.mu, P.cscale64, P.dpad, x3, w.HY, w.LY, w.NY, s));
+  }
   // weights and log-weights (host FP64 log, uploaded)
   std::vector<float> fx(n), fy(m);
   std::vector<double> lx(n), ly(m);
@@ -486,6 +542,8 @@ struct Engine {
     a.d = P.d;
     a.cscale = P.cscale;
     a.cmax = P.cmax;
+    a.dpad = P.dpad;
+    a.m2cs = -2.f * P.cscale;
     a.part = w.part;
     a.blk_err = w.blk_err;
     a.blk_dot = w.blk_dot;
@@ -501,13 +559,14 @@ struct Engine {
       e1 = c->get_event();
       HIPCHK(hipEventRecord(e0, s));
     }
-    if (stream_kernel) HIPCHK(launch_sweep_stream(a, P.kind, vec, s, em));
+    if (stream_kernel) HIPCHK(launch_sweep_stream(a, sweep_kind(P), vec, s, em));
     else HIPCHK(launch_sweep_rows(a, s, em));
     if (c->profile) {
       HIPCHK(hipEventRecord(e1, s));
       char nm[96];
-      std::snprintf(nm, sizeof nm, "%s_%s_l%d", stream_kernel ? "sweep_stream" : "sweep_rows",
-                    P.kind == SKNR_COST_STORED ? "stored" : (P.d <= 8 ? "points" : "points_gen"),
+      static const char* kinds[4] = {"stored", "points", "points_bf16", "points_bf16x3"};
+      std::snprintf(nm, sizeof nm, "%s_%s%s_l%d", stream_kernel ? "sweep_stream" : "sweep_rows",
+                    kinds[sweep_kind(P)], (sweep_kind(P) == 1 && P.d > 8) ? "_gen" : "",
                     ell <= 0 ? 0 : ell_pad(ell));
       const double units = (double)a.n_out * (double)a.n_red;
       // whole sweep (main kernel + merge/finish) and the main kernel alone
@@ -525,6 +584,12 @@ struct Engine {
     a.n_red = P.n;
     a.Pred = P.X;
     a.Pout = P.Y;
+    a.Hred = (const uint4*)w.HX;
+    a.Lred = (const uint4*)w.LX;
+    a.Nred = w.NX;
+    a.Hout = (const uint4*)w.HY;
+    a.Lout = (const uint4*)w.LY;
+    a.Nout = w.NY;
     a.Uin = Fin;
     a.ma_in = ma_in;
     a.lw_out = w.lYdf;
@@ -544,7 +609,7 @@ struct Engine {
     a.gsel_val = gsel_val;
     bool st = col_is_stream(P);
     bool vec = stream_vec(P, a.n_out);
-    sweep_part_floats(a.n_out, a.n_red, ell, P.kind, P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
+    sweep_part_floats(a.n_out, a.n_red, ell, sweep_kind(P), P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
     launch_sweep(a, st, vec, ell);
   }
 
@@ -557,6 +622,12 @@ struct Engine {
     a.n_red = P.m;
     a.Pred = P.Y;
     a.Pout = P.X;
+    a.Hred = (const uint4*)w.HY;
+    a.Lred = (const uint4*)w.LY;
+    a.Nred = w.NY;
+    a.Hout = (const uint4*)w.HX;
+    a.Lout = (const uint4*)w.LX;
+    a.Nout = w.NX;
     a.Uin = Gin;
     a.ma_in = ma_in;
     a.lw_out = w.lXdf;
@@ -575,7 +646,7 @@ struct Engine {
     a.flags = flags;
     bool st = row_is_stream(P);
     bool vec = stream_vec(P, a.n_out);
-    sweep_part_floats(a.n_out, a.n_red, ell, P.kind, P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
+    sweep_part_floats(a.n_out, a.n_red, ell, sweep_kind(P), P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
     launch_sweep(a, st, vec, ell);
   }
 
@@ -663,7 +734,7 @@ struct Engine {
     key.n = P.n;
     key.m = P.m;
     key.d = P.d;
-    key.kind = P.kind;
+    key.kind = sweep_kind(P);
     key.ell = ell;
     key.ellp = w.ellp;
     key.iters = k;
@@ -768,8 +839,8 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(go, w.gY64, 8 * (size_t)P.m, hipMemcpyDeviceToDevice, s));
   }
 
-  // FP64 evaluation in the caller's orientation
-  sknr_eval evaluate(const sknr_problem* pr, const double* f, const double* g) {
+  // cost description for kernels working in the caller's orientation
+  SweepArgs caller_geo(const sknr_problem* pr) const {
     SweepArgs geo{};
     geo.C = pr->C;
     geo.ldc = pr->ldc;
@@ -777,8 +848,30 @@ struct Engine {
     geo.Pout = pr->y;
     geo.d = pr->d;
     geo.cscale = P.cscale;
+    geo.cscale64 = P.cscale64;
+    geo.dpad = P.dpad;
+    geo.m2cs = -2.f * P.cscale;
+    const bool sw = P.transposed;  // engine side X holds the caller's y
+    geo.Hred = (const uint4*)(sw ? w.HY : w.HX);
+    geo.Lred = (const uint4*)(sw ? w.LY : w.LX);
+    geo.Nred = sw ? w.NY : w.NX;
+    geo.Hout = (const uint4*)(sw ? w.HX : w.HY);
+    geo.Lout = (const uint4*)(sw ? w.LX : w.LY);
+    geo.Nout = sw ? w.NX : w.NY;
+    return geo;
+  }
+
+  // FP64 evaluation in the caller's orientation, on the solver's cost or
+  // (exact) on the FP64 squared distance of the FP32 points
+  sknr_eval evaluate(const sknr_problem* pr, const double* f, const double* g, bool exact = false) {
+    SweepArgs geo = caller_geo(pr);
     int nrb, ncb;
-    HIPCHK(launch_eval(geo, P.kind, f, g, pr->a, pr->b, eps, w.evrow, w.evcol, w.evscal, P.n0, P.m0, &nrb, &ncb, s));
+    const int kind = (exact && P.kind == SKNR_COST_SQEUCLID) ? 4 : sweep_kind(P);
+    if (kind == 2 || kind == 3)
+      HIPCHK(launch_eval_mfma(geo, kind == 3, f, g, pr->a, pr->b, eps, w.evrow, w.evcol, w.evscal, P.n0, P.m0,
+                              &nrb, &ncb, s));
+    else
+      HIPCHK(launch_eval(geo, kind, f, g, pr->a, pr->b, eps, w.evrow, w.evcol, w.evscal, P.n0, P.m0, &nrb, &ncb, s));
     HIPCHK(launch_eval_finish(w.evrow, w.evcol, w.evscal, pr->a, pr->b, P.n0, P.m0, nrb, ncb, w.evout, w.evblk, s));
     HIPCHK(launch_dot64(f, pr->a, P.n0, w.evout + 8, s));
     HIPCHK(launch_dot64(g, pr->b, P.m0, w.evout + 9, s));
@@ -1095,6 +1188,14 @@ int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts, doubl
         res->dual_value = ev.dual_value;
         res->primal_value = ev.primal_value;
         res->mass = ev.mass;
+        if (P.kind == SKNR_COST_SQEUCLID) {
+          sknr_eval ex = E.evaluate(prob, f_out, g_out, true);
+          res->marginal_err_exact = ex.marginal_err;
+          res->transport_cost_exact = ex.transport_cost;
+        } else {
+          res->marginal_err_exact = ev.marginal_err;
+          res->transport_cost_exact = ev.transport_cost;
+        }
       }
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -1235,6 +1336,18 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps, const double*
     Engine E(c, P, w, s);
     E.eps = eps;
     *out = E.evaluate(prob, f, g);
+    if (P.kind == SKNR_COST_SQEUCLID) {
+      sknr_eval ex = E.evaluate(prob, f, g, true);
+      out->row_err_exact = ex.row_err;
+      out->col_err_exact = ex.col_err;
+      out->marginal_err_exact = ex.marginal_err;
+      out->transport_cost_exact = ex.transport_cost;
+    } else {
+      out->row_err_exact = out->row_err;
+      out->col_err_exact = out->col_err;
+      out->marginal_err_exact = out->marginal_err;
+      out->transport_cost_exact = out->transport_cost;
+    }
     return SKNR_OK;
   });
 }
@@ -1242,19 +1355,19 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps, const double*
 int sknr_coupling(void* ctx, const sknr_problem* prob, double eps, const double* f, const double* g, float* P_out,
                   void* stream) {
   return guarded([&]() -> int {
-    as_ctx(ctx);
+    Ctx* c = as_ctx(ctx);
     check_eps(eps);
     REQUIRE(f && g && P_out, "f, g, P_out are required");
     hipStream_t s = as_stream(stream);
     Prepared P = prepare_caller_orientation(prob, s);
-    SweepArgs geo{};
-    geo.C = prob->C;
-    geo.ldc = prob->ldc;
-    geo.Pred = prob->x;
-    geo.Pout = prob->y;
-    geo.d = prob->d;
-    geo.cscale = P.cscale;
-    HIPCHK(launch_coupling(geo, P.kind, f, g, prob->a, prob->b, eps, P_out, P.n0, P.m0, s));
+    WS w = make_ws(c, P, 0, s);
+    Engine E(c, P, w, s);
+    SweepArgs geo = E.caller_geo(prob);
+    const int kind = sweep_kind(P);
+    if (kind == 2 || kind == 3)
+      HIPCHK(launch_coupling_mfma(geo, kind == 3, f, g, prob->a, prob->b, eps, P_out, P.n0, P.m0, s));
+    else
+      HIPCHK(launch_coupling(geo, P.kind, f, g, prob->a, prob->b, eps, P_out, P.n0, P.m0, s));
     HIPCHK(hipStreamSynchronize(s));
     return SKNR_OK;
   });

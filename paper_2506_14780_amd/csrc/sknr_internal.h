@@ -65,6 +65,18 @@ struct SweepArgs {
   const float* Pout;
   int d;
   float cscale;
+  double cscale64;       // cost_scale as given (FP64 exact-cost evaluation)
+  // matrix-core cost (SQEUCLID with a bf16 cross term): centred points as
+  // bf16 rows of dpad entries (dpad a multiple of 32; hi, and lo for the
+  // split form, else null) and fl32(cost_scale * ||x~||^2) per point
+  const uint4* Hred;
+  const uint4* Lred;
+  const float* Nred;
+  const uint4* Hout;
+  const uint4* Lout;
+  const float* Nout;
+  int dpad;
+  float m2cs;            // -2 * cost_scale (FP32)
   float cmax;            // upper bound of |C| (Fast2Sum offset)
   // potentials
   const float2* Uin;     // reduce-side hat potential (n_red)
@@ -105,6 +117,19 @@ hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipS
 hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t stream, hipEvent_t mid = nullptr);
 size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bool vec, int* nsplit, int* rps,
                          int* nblk, bool stream_kernel);
+// split merge + scalar finishing kernels of a streaming sweep
+hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t stream);
+
+// matrix-core cost (cost kinds 2 = bf16 cross term, 3 = bf16 hi/lo split)
+hipError_t launch_sweep_mfma(const SweepArgs& a, bool x3, hipStream_t stream, hipEvent_t mid);
+size_t mfma_part_floats(int n_out, int n_red, int ell, int* nsplit, int* rps, int* nblk);
+hipError_t launch_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, bool x3,
+                              unsigned short* H, unsigned short* Lo, float* nrm, hipStream_t s);
+hipError_t launch_eval_mfma(const SweepArgs& geo, bool x3, const double* f, const double* g, const double* a,
+                            const double* b, double eps, double* rowpart, double* colpart, double* scal, int n,
+                            int m, int* nrb, int* ncb, hipStream_t s);
+hipError_t launch_coupling_mfma(const SweepArgs& geo, bool x3, const double* f, const double* g, const double* a,
+                                const double* b, double eps, float* P, int n, int m, hipStream_t s);
 
 // conversions between FP64 paper-convention potentials and hat double-floats
 hipError_t launch_to_hat(const double* f, const double* logw, double eps, float2* U, int n,

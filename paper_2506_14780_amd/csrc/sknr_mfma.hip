@@ -1,0 +1,519 @@
+// Matrix-core cost for squared-Euclidean problems with the cross term on
+// bf16 MFMA (gfx950 v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
+// The cost of a pair is built as
+//     C~_ij = fma(-2 s, xy_ij, n_i + n_j),   n_i = fl32(s * ||x~_i||^2),
+// where x~ are the centred points rounded to bf16 (BF16) or to a hi + lo
+// pair of bf16 (BF16X3), s is the cost scale and xy_ij = x~_i . y~_j comes
+// from matrix-core tiles.  For BF16X3 the product keeps hi*hi + hi*lo +
+// lo*hi: the two mixed chains run in separate accumulators and are added
+// in FP32 (a commutative add) before the hi*hi chain starts from their sum,
+// so C~ is the same matrix whichever side is the reduce side of a sweep:
+// a matrix-core tile is symmetric under swapping its two operands, and so
+// the row and column c-transforms see one and the same cost.
+//
+// The MFMA 16x16x32 lane layout (64 lanes, g = lane / 16, c = lane % 16):
+//   operand A (16 x 32): lane supplies row c, k = 8g .. 8g+7
+//   operand B (32 x 16): lane supplies column c, k = 8g .. 8g+7
+//   result    (16 x 16): lane holds rows 4g .. 4g+3 of column c
+// With A = reduce-side points and B = output-side points, a lane of the
+// result owns one output column and four reduce rows of each tile, so the
+// online log-sum-exp of the streaming sweep runs directly on MFMA results.
+#include "sknr_device.h"
+
+#include <stdlib.h>
+
+namespace sknr {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ bf16x8 as_bf8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// round-to-nearest-even FP32 -> bf16 (finite inputs)
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// Cross products of one 16 x 16 tile from operands already in registers
+// (ks K-steps of 32).  The accumulation order is fixed: mixed chains first
+// (ascending k), their FP32 sum, then the hi*hi chain (ascending k).
+template <bool X3, int KR>
+__device__ __forceinline__ f32x4 cross_regs(const bf16x8 (&ah)[KR], const bf16x8 (&al)[KR], const bf16x8 (&bh)[KR],
+                                            const bf16x8 (&bl)[KR]) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (X3) {
+    f32x4 t1 = acc, t2 = acc;
+#pragma unroll
+    for (int s = 0; s < KR; ++s) {
+      t1 = mfma_bf16(ah[s], bl[s], t1);
+      t2 = mfma_bf16(al[s], bh[s], t2);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = t1[i] + t2[i];
+  }
+#pragma unroll
+  for (int s = 0; s < KR; ++s) acc = mfma_bf16(ah[s], bh[s], acc);
+  return acc;
+}
+
+// The same tile with operands read from memory per K-step (any dpad).
+// pa / pb: uint4 rows of the lane's A / B point, offset by g.
+template <bool X3>
+__device__ __forceinline__ f32x4 cross_mem(const uint4* ha, const uint4* la, const uint4* hb, const uint4* lb,
+                                           int ks) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (X3) {
+    f32x4 t1 = acc, t2 = acc;
+    for (int s = 0; s < ks; ++s) {
+      t1 = mfma_bf16(as_bf8(ha[4 * s]), as_bf8(lb[4 * s]), t1);
+      t2 = mfma_bf16(as_bf8(la[4 * s]), as_bf8(hb[4 * s]), t2);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = t1[i] + t2[i];
+  }
+  for (int s = 0; s < ks; ++s) acc = mfma_bf16(as_bf8(ha[4 * s]), as_bf8(hb[4 * s]), acc);
+  return acc;
+}
+
+// ============================================================================
+// Streaming c-transform sweep with the matrix-core cost.  A workgroup owns
+// NC = 64*NT outputs (wave w: columns [16*NT*w, 16*NT*(w+1)) of the block,
+// NT tiles of 16) and one split of the reduce side, processed in tiles of 16
+// rows.  Lane (g, c) keeps an online (sig, S, Sc[, acc]) state per output
+// tile over the rows 4g..4g+3 of every row tile; the four states of a column
+// merge by a butterfly (xor 16, xor 32) with a fixed operand order, and the
+// partial is written in the layout of the generic streaming sweep
+// ([nsplit][3+ell][n_out]) so that the same split merge and finishing
+// kernels complete it.  KS > 0: K-steps known at compile time, the output
+// side operands stay in registers; KS == 0: any dpad, operands reloaded.
+// ============================================================================
+template <int ELL, int KS, bool X3, int NT>
+__global__ __launch_bounds__(TPB) void k_sweep_mfma(SweepArgs A) {
+  if (gate_closed(A.st, A.gate)) return;
+  extern __shared__ float4 smem4[];
+  constexpr int EL = ELL > 0 ? ELL : 1;
+  constexpr int NQ = 3 + (ELL > 0 ? ELL : 0);
+  constexpr int NCW = 16 * NT;
+  constexpr int NC = WAVES * NCW;
+  constexpr int KR = KS > 0 ? KS : 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, c16 = lane & 15;
+  const int r0 = blockIdx.y * A.rows_per_split;
+  const int nr = min(A.rows_per_split, A.n_red - r0);
+  const EpsConst EC = eps_const(A.st);
+  const float K = EC.K;
+  const float L = 2.f * (A.cmax + A.st->maxabs[A.ma_in]);
+  const int ks = KS > 0 ? KS : (A.dpad >> 5);
+  const int dq = A.dpad >> 3;  // uint4 per packed point
+  const float m2cs = A.m2cs;
+
+  // reduce-side rows of this split: offset hat potential U + L as a
+  // normalised double-float, and the scaled squared norm
+  float4* sR = smem4;
+  for (int t = threadIdx.x; t < nr; t += TPB) {
+    float2 u = A.Uin[r0 + t];
+    float2 s = two_sum(L, u.x);
+    s.y += u.y;
+    s = fast_two_sum(s.x, s.y);
+    sR[t] = make_float4(s.x, s.y, A.Nred[r0 + t], 0.f);
+  }
+  __syncthreads();
+
+  const int cb = blockIdx.x * NC + wave * NCW;
+  float hy[NT];
+  int colc[NT];
+  bf16x8 bh[NT][KR], bl[NT][KR];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    colc[t] = min(cb + 16 * t + c16, A.n_out - 1);
+    hy[t] = A.Nout[colc[t]];
+    if (KS > 0) {
+      const size_t base = (size_t)colc[t] * dq + g;
+#pragma unroll
+      for (int s = 0; s < KR; ++s) {
+        bh[t][s] = as_bf8(A.Hout[base + 4 * s]);
+        bl[t][s] = X3 ? as_bf8(A.Lout[base + 4 * s]) : bh[t][s];
+      }
+    }
+  }
+
+  float sig[NT], S[NT], Sc[NT], acc[NT][EL];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    sig[t] = SIG0;
+    S[t] = 0.f;
+    Sc[t] = 0.f;
+#pragma unroll
+    for (int l = 0; l < EL; ++l) acc[t][l] = 0.f;
+  }
+
+  for (int rt = 0; rt < nr; rt += 16) {
+    // matrix-core cross terms of this row tile for the NT output tiles
+    const size_t ra = (size_t)(r0 + min(rt + c16, nr - 1)) * dq + g;
+    f32x4 xy[NT];
+    if (KS > 0) {
+      bf16x8 ah[KR], al[KR];
+#pragma unroll
+      for (int s = 0; s < KR; ++s) {
+        ah[s] = as_bf8(A.Hred[ra + 4 * s]);
+        al[s] = X3 ? as_bf8(A.Lred[ra + 4 * s]) : ah[s];
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) xy[t] = cross_regs<X3, KR>(ah, al, bh[t], bl[t]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const size_t rb = (size_t)colc[t] * dq + g;
+        xy[t] = cross_mem<X3>(A.Hred + ra, A.Lred + ra, A.Hout + rb, A.Lout + rb, ks);
+      }
+    }
+    // this lane's four reduce rows
+    float4 rw[4];
+    bool ok[4];
+    int rowc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rl = rt + 4 * g + i;
+      ok[i] = rl < nr;
+      rowc[i] = ok[i] ? rl : nr - 1;
+      rw[i] = sR[rowc[i]];
+    }
+    float p[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float s[4], e[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float cv = fmaf(m2cs, xy[t][i], rw[i].z + hy[t]);
+        // Fast2Sum: U + L dominates |C~| (L >= 2 max|C~|)
+        const float sv = rw[i].x - cv;
+        const float ev = ((rw[i].x - sv) - cv) + rw[i].y;
+        s[i] = ok[i] ? sv : SIG0;
+        e[i] = ok[i] ? ev : 0.f;
+      }
+      const float mx = fmaxf(fmaxf(s[0], s[1]), fmaxf(s[2], s[3]));
+      if (mx > sig[t]) {
+        const float sc = ex2((sig[t] - mx) * K);
+        S[t] *= sc;
+        Sc[t] *= sc;
+#pragma unroll
+        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[t][l] *= sc;
+        sig[t] = mx;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) p[t][i] = ex2(((s[i] - sig[t]) + e[i]) * K);
+      const float2 ts = two_sum(S[t], (p[t][0] + p[t][1]) + (p[t][2] + p[t][3]));
+      S[t] = ts.x;
+      Sc[t] += ts.y;
+    }
+    if (ELL > 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float4* vr = reinterpret_cast<const float4*>(A.Vred + (size_t)(r0 + rowc[i]) * EL);
+#pragma unroll
+        for (int l4 = 0; l4 < EL / 4; ++l4) {
+          const float4 v = vr[l4];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            acc[t][4 * l4 + 0] = fmaf(p[t][i], v.x, acc[t][4 * l4 + 0]);
+            acc[t][4 * l4 + 1] = fmaf(p[t][i], v.y, acc[t][4 * l4 + 1]);
+            acc[t][4 * l4 + 2] = fmaf(p[t][i], v.z, acc[t][4 * l4 + 2]);
+            acc[t][4 * l4 + 3] = fmaf(p[t][i], v.w, acc[t][4 * l4 + 3]);
+          }
+        }
+      }
+    }
+  }
+
+  // butterfly over the four row groups of a column: both partners merge
+  // (lower, upper) in that order, so they hold identical results
+#pragma unroll
+  for (int off = 16; off <= 32; off <<= 1) {
+    const bool lower = (lane & off) == 0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const float sg2 = __shfl_xor(sig[t], off, 64), S2 = __shfl_xor(S[t], off, 64),
+                  C2 = __shfl_xor(Sc[t], off, 64);
+      float a2[EL];
+#pragma unroll
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) a2[l] = __shfl_xor(acc[t][l], off, 64);
+      float f1, f2;
+      if (lower) {
+        lse_merge(sig[t], S[t], Sc[t], sg2, S2, C2, K, f1, f2);
+#pragma unroll
+        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[t][l] = acc[t][l] * f1 + a2[l] * f2;
+      } else {
+        float t1 = sg2, t2 = S2, t3 = C2;
+        lse_merge(t1, t2, t3, sig[t], S[t], Sc[t], K, f1, f2);
+#pragma unroll
+        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[t][l] = a2[l] * f1 + acc[t][l] * f2;
+        sig[t] = t1;
+        S[t] = t2;
+        Sc[t] = t3;
+      }
+    }
+  }
+
+  // partial of this split: lane (g, c) writes the quantities q = g (mod 4)
+  const int n_out = A.n_out;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = cb + 16 * t + c16;
+    if (col < n_out) {
+      float* base = A.part + (size_t)blockIdx.y * NQ * n_out + col;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if ((q & 3) == g) {
+          const float v = q == 0 ? sig[t] : (q == 1 ? S[t] : (q == 2 ? Sc[t] : acc[t][q >= 3 ? q - 3 : 0]));
+          base[(size_t)q * n_out] = v;
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------- geometry
+static int mfma_nt(int ell) { return ell > 16 ? 2 : 4; }
+
+size_t mfma_part_floats(int n_out, int n_red, int ell, int* nsplit, int* rps, int* nblk) {
+  const int nc = 64 * mfma_nt(ell);
+  const int ncb = (n_out + nc - 1) / nc;
+  static const int env_target = getenv("SKNR_SWEEP_TARGET_WG") ? atoi(getenv("SKNR_SWEEP_TARGET_WG")) : 0;
+  const int target = env_target > 0 ? env_target : 2048;
+  int ns = (target + ncb - 1) / ncb;
+  int r = (n_red + ns - 1) / ns;
+  r = (r + 15) & ~15;
+  if (r < 64) r = 64;
+  if (r > 2048) r = 2048;
+  const int rmax = (n_red + 15) & ~15;
+  if (r > rmax) r = rmax;
+  ns = (n_red + r - 1) / r;
+  *nsplit = ns;
+  *rps = r;
+  *nblk = (n_out + 63) / 64;
+  const int ellp = ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32));
+  return (size_t)ns * (3 + ellp) * n_out;
+}
+
+template <int ELL, bool X3>
+static void go_mfma(const SweepArgs& a, hipStream_t s) {
+  constexpr int NT = ELL > 16 ? 2 : 4;
+  const int nc = 64 * NT;
+  dim3 grid((a.n_out + nc - 1) / nc, a.nsplit);
+  const size_t sm = (size_t)a.rows_per_split * sizeof(float4);
+  const int ks = a.dpad >> 5;
+  if (ks == 1) hipLaunchKernelGGL((k_sweep_mfma<ELL, 1, X3, NT>), grid, dim3(TPB), sm, s, a);
+  else if (ks == 2) hipLaunchKernelGGL((k_sweep_mfma<ELL, 2, X3, NT>), grid, dim3(TPB), sm, s, a);
+  else hipLaunchKernelGGL((k_sweep_mfma<ELL, 0, X3, NT>), grid, dim3(TPB), sm, s, a);
+}
+
+hipError_t launch_sweep_mfma(const SweepArgs& a, bool x3, hipStream_t s, hipEvent_t mid) {
+  if (a.dpad <= 0 || (a.dpad & 31) || a.rows_per_split > 2048) return hipErrorInvalidValue;
+  const int e = a.ell;
+  if (x3) {
+    if (e == 0) go_mfma<0, true>(a, s);
+    else if (e <= 8) go_mfma<8, true>(a, s);
+    else if (e <= 16) go_mfma<16, true>(a, s);
+    else go_mfma<32, true>(a, s);
+  } else {
+    if (e == 0) go_mfma<0, false>(a, s);
+    else if (e <= 8) go_mfma<8, false>(a, s);
+    else if (e <= 16) go_mfma<16, false>(a, s);
+    else go_mfma<32, false>(a, s);
+  }
+  if (mid) (void)hipEventRecord(mid, s);
+  return launch_sweep_tail(a, s);
+}
+
+// ============================================================================
+// Packing: centred points rounded to bf16 (hi, and lo = bf16(v - hi) for
+// BF16X3), rows zero-padded to dpad, and n = fl32(scale * ||x~||^2) with
+// x~ = hi (+ lo) summed in FP64.  One thread per point.
+// ============================================================================
+__global__ void k_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, int x3,
+                              unsigned short* H, unsigned short* Lo, float* nrm) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double s2 = 0.0;
+  for (int k = 0; k < dpad; ++k) {
+    unsigned short h = 0, l = 0;
+    if (k < d) {
+      const float v = x[(size_t)p * d + k] - mu[k];
+      h = bf16_rne(v);
+      const float hv = bf16_val(h);
+      float xt = hv;
+      if (x3) {
+        l = bf16_rne(v - hv);
+        xt = hv + bf16_val(l);
+      }
+      s2 += (double)xt * (double)xt;
+    }
+    H[(size_t)p * dpad + k] = h;
+    if (x3) Lo[(size_t)p * dpad + k] = l;
+  }
+  nrm[p] = (float)(scale * s2);
+}
+
+hipError_t launch_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, bool x3,
+                              unsigned short* H, unsigned short* Lo, float* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_points, dim3((np + 255) / 256), dim3(256), 0, s, x, np, d, mu, scale, dpad, x3 ? 1 : 0,
+                     H, Lo, nrm);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// FP64 evaluation on the matrix-core cost: the same tiles of 64 rows x 256
+// columns as the generic evaluation; each 16-row slice of C~ is built by
+// the four waves (64 columns each) into LDS, then every thread runs the
+// FP64 terms of its column.
+// ============================================================================
+template <bool X3, int KS>
+__global__ __launch_bounds__(256) void k_eval_mfma(SweepArgs G, const double* f, const double* g,
+                                                   const double* a, const double* b, double eps, double* rowpart,
+                                                   double* colpart, double* scal, int n, int m) {
+  constexpr int KR = KS > 0 ? KS : 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g4 = lane >> 4, c16 = lane & 15;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int i0 = blockIdx.y * 64;
+  const int jc = min(j, m - 1);
+  const int dq = G.dpad >> 3;
+  const int ks = KS > 0 ? KS : (G.dpad >> 5);
+  const double inv = 1.0 / eps;
+  const double gj = g[jc], bj = b[jc];
+  __shared__ float sC[16][257];
+  __shared__ double srow[WAVES][64];
+  double cs = 0, cost = 0, mass = 0, ent = 0;
+  for (int rt = 0; rt < 64; rt += 16) {
+    const size_t ra = (size_t)min(i0 + rt + c16, n - 1) * dq + g4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int cl = wave * 64 + 16 * t + c16;
+      const int jt = min((int)blockIdx.x * 256 + cl, m - 1);
+      const size_t rb = (size_t)jt * dq + g4;
+      f32x4 xy;
+      if (KS > 0) {
+        bf16x8 ah[KR], al[KR], bh[KR], bl[KR];
+#pragma unroll
+        for (int s = 0; s < KR; ++s) {
+          ah[s] = as_bf8(G.Hred[ra + 4 * s]);
+          bh[s] = as_bf8(G.Hout[rb + 4 * s]);
+          al[s] = X3 ? as_bf8(G.Lred[ra + 4 * s]) : ah[s];
+          bl[s] = X3 ? as_bf8(G.Lout[rb + 4 * s]) : bh[s];
+        }
+        xy = cross_regs<X3, KR>(ah, al, bh, bl);
+      } else {
+        xy = cross_mem<X3>(G.Hred + ra, G.Lred + ra, G.Hout + rb, G.Lout + rb, ks);
+      }
+      const float ny = G.Nout[jt];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float nx = G.Nred[min(i0 + rt + 4 * g4 + i, n - 1)];
+        sC[4 * g4 + i][cl] = fmaf(G.m2cs, xy[i], nx + ny);
+      }
+    }
+    __syncthreads();
+    for (int r = 0; r < 16; ++r) {
+      const int i = i0 + rt + r;
+      double p = 0;
+      if (i < n && j < m) {
+        const double cij = (double)sC[r][threadIdx.x];
+        const double t = (f[i] + gj - cij) * inv;
+        p = a[i] * bj * exp(t);
+        cs += p;
+        cost += p * cij;
+        mass += p;
+        ent += p * t;
+      }
+      const double rs = wave_sum(p);
+      if (lane == 0) srow[wave][rt + r] = rs;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 64) {
+    const int i = i0 + threadIdx.x;
+    if (i < n) rowpart[(size_t)blockIdx.x * n + i] = srow[0][threadIdx.x] + srow[1][threadIdx.x] +
+                                                     srow[2][threadIdx.x] + srow[3][threadIdx.x];
+  }
+  if (j < m) colpart[(size_t)blockIdx.y * m + j] = cs;
+  __shared__ double sbd[16];
+  const double c1 = block_sum_d(cost, sbd);
+  const double c2 = block_sum_d(mass, sbd);
+  const double c3 = block_sum_d(ent, sbd);
+  if (threadIdx.x == 0) {
+    const size_t bid = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    scal[bid * 3 + 0] = c1;
+    scal[bid * 3 + 1] = c2;
+    scal[bid * 3 + 2] = c3;
+  }
+}
+
+hipError_t launch_eval_mfma(const SweepArgs& geo, bool x3, const double* f, const double* g, const double* a,
+                            const double* b, double eps, double* rowpart, double* colpart, double* scal, int n,
+                            int m, int* nrb, int* ncb, hipStream_t s) {
+  if (geo.dpad <= 0 || (geo.dpad & 31)) return hipErrorInvalidValue;
+  dim3 grid((m + 255) / 256, (n + 63) / 64);
+  *ncb = grid.x;
+  *nrb = grid.y;
+  const int ks = geo.dpad >> 5;
+#define SKNR_EVAL_MFMA(X, KK) \
+  hipLaunchKernelGGL((k_eval_mfma<X, KK>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m)
+  if (x3) {
+    if (ks == 1) SKNR_EVAL_MFMA(true, 1);
+    else if (ks == 2) SKNR_EVAL_MFMA(true, 2);
+    else SKNR_EVAL_MFMA(true, 0);
+  } else {
+    if (ks == 1) SKNR_EVAL_MFMA(false, 1);
+    else if (ks == 2) SKNR_EVAL_MFMA(false, 2);
+    else SKNR_EVAL_MFMA(false, 0);
+  }
+#undef SKNR_EVAL_MFMA
+  return hipGetLastError();
+}
+
+// coupling on the matrix-core cost: 16 rows x 256 columns per workgroup
+template <bool X3>
+__global__ __launch_bounds__(256) void k_coupling_mfma(SweepArgs G, const double* f, const double* g,
+                                                       const double* a, const double* b, double eps, float* P,
+                                                       int n, int m) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g4 = lane >> 4, c16 = lane & 15;
+  const int dq = G.dpad >> 3, ks = G.dpad >> 5;
+  const int i0 = blockIdx.y * 16;
+  const size_t ra = (size_t)min(i0 + c16, n - 1) * dq + g4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = (int)blockIdx.x * 256 + wave * 64 + 16 * t + c16;
+    const int jc = min(j, m - 1);
+    const size_t rb = (size_t)jc * dq + g4;
+    const f32x4 xy = cross_mem<X3>(G.Hred + ra, G.Lred + ra, G.Hout + rb, G.Lout + rb, ks);
+    const float ny = G.Nout[jc];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ii = i0 + 4 * g4 + i;
+      if (ii < n && j < m) {
+        const float cf = fmaf(G.m2cs, xy[i], G.Nred[ii] + ny);
+        P[(size_t)ii * m + j] = (float)(a[ii] * b[j] * exp((f[ii] + g[j] - (double)cf) / eps));
+      }
+    }
+  }
+}
+
+hipError_t launch_coupling_mfma(const SweepArgs& geo, bool x3, const double* f, const double* g, const double* a,
+                                const double* b, double eps, float* P, int n, int m, hipStream_t s) {
+  if (geo.dpad <= 0 || (geo.dpad & 31)) return hipErrorInvalidValue;
+  dim3 grid((m + 255) / 256, (n + 15) / 16);
+  if (x3) hipLaunchKernelGGL((k_coupling_mfma<true>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
+  else hipLaunchKernelGGL((k_coupling_mfma<false>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
+  return hipGetLastError();
+}
+
+}  // namespace sknr

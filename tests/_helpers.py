@@ -49,3 +49,50 @@ def gpu_problem(prob, stored=False, C32=None):
         return sk.Problem(a=a, b=b, C=to_dev(np.asarray(C, np.float32)))
     return sk.Problem(a=a, b=b, x=to_dev(prob.x.astype(np.float32)), y=to_dev(prob.y.astype(np.float32)),
                       cost_scale=prob.cost_scale)
+
+
+def bf16_rne(v):
+    """float32 -> the nearest bf16 value (round to nearest even), as float32."""
+    u = np.ascontiguousarray(v, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def bf16_cost_model(x, y, scale=1.0, x3=True):
+    """The matrix-core cost as the library defines it, in FP64, with a
+    rigorous per-element bound on the GPU's deviation from it.
+
+    Centre mu = bf16(mean of all points); v = fl32(x - mu); hi = bf16(v),
+    lo = bf16(v - hi) (x3) or 0; x~ = hi + lo; n_i = fl32(scale ||x~_i||^2);
+    model C_ij = n_i + n_j - 2 fl32(scale) (x~_i . y~_j) with lo*lo omitted.
+    The GPU forms the dot product on matrix cores (FP32 accumulation, any
+    order: error <= (N - 1) u sum|terms| over N products), adds the norms in
+    FP32 and applies one fma: bound = 2 s N u T_ij + 2 u (n_i + n_j) + u |C_ij|
+    (the second term also covers a last-bit difference of the FP64 norm)."""
+    x = np.asarray(x, np.float32)
+    y = np.asarray(y, np.float32)
+    d = x.shape[1]
+    dpad = (d + 31) // 32 * 32
+    mu = bf16_rne(np.float32(np.concatenate([x, y]).astype(np.float64).mean(axis=0)))
+
+    def split(p):
+        v = (p - mu).astype(np.float32)
+        hi = bf16_rne(v)
+        lo = bf16_rne((v - hi).astype(np.float32)) if x3 else np.zeros_like(hi)
+        return hi.astype(np.float64), lo.astype(np.float64)
+
+    xh, xl = split(x)
+    yh, yl = split(y)
+    s32 = float(np.float32(scale))
+    nx = np.float32(scale * ((xh + xl) ** 2).sum(1)).astype(np.float64)
+    ny = np.float32(scale * ((yh + yl) ** 2).sum(1)).astype(np.float64)
+    E = xh @ yh.T
+    T = np.abs(xh) @ np.abs(yh).T
+    nprod = dpad
+    if x3:
+        E = E + xh @ yl.T + xl @ yh.T
+        T = T + np.abs(xh) @ np.abs(yl).T + np.abs(xl) @ np.abs(yh).T
+        nprod = 3 * dpad
+    C = nx[:, None] + ny[None, :] - 2.0 * s32 * E
+    bound = 2.0 * s32 * nprod * U32 * T + 2 * U32 * (nx[:, None] + ny[None, :]) + U32 * np.abs(C)
+    return C, bound
