@@ -23,6 +23,8 @@
 
 #include <stdlib.h>
 
+#include <type_traits>
+
 namespace sknr {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
@@ -95,7 +97,7 @@ __device__ __forceinline__ f32x4 cross_mem(const uint4* ha, const uint4* la, con
 // side operands stay in registers; KS == 0: any dpad, operands reloaded.
 // ============================================================================
 template <int ELL, int KS, bool X3, int NT>
-__global__ __launch_bounds__(TPB) void k_sweep_mfma(SweepArgs A) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_mfma(SweepArgs A) {
   if (gate_closed(A.st, A.gate)) return;
   extern __shared__ float4 smem4[];
   constexpr int EL = ELL > 0 ? ELL : 1;
@@ -145,44 +147,64 @@ __global__ __launch_bounds__(TPB) void k_sweep_mfma(SweepArgs A) {
     }
   }
 
-  float sig[NT], S[NT], Sc[NT], acc[NT][EL];
+  // (sig, S + Sc) per output as in the generic sweep; T collects the
+  // chunk sums of two row tiles in plain FP32 (at most 8 terms <= 1 each)
+  // before one TwoSum adds it into (S, Sc)
+  float sig[NT], S[NT], Sc[NT], T[NT], acc[NT][EL];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     sig[t] = SIG0;
     S[t] = 0.f;
     Sc[t] = 0.f;
+    T[t] = 0.f;
 #pragma unroll
     for (int l = 0; l < EL; ++l) acc[t][l] = 0.f;
   }
 
-  for (int rt = 0; rt < nr; rt += 16) {
-    // matrix-core cross terms of this row tile for the NT output tiles
-    const size_t ra = (size_t)(r0 + min(rt + c16, nr - 1)) * dq + g;
-    f32x4 xy[NT];
+  // (the lambdas below capture these locals, not the argument struct, so
+  // that the struct stays in kernel-argument registers)
+  const uint4* const Hred = A.Hred;
+  const uint4* const Lred = A.Lred;
+  const uint4* const Hout = A.Hout;
+  const uint4* const Lout = A.Lout;
+  const float* const Vred = A.Vred;
+  // Software pipeline over row tiles: while the log-sum-exp of tile k runs
+  // on the VALU, the matrix cores work on tile k+1 (its operands loaded one
+  // iteration earlier) and the loads of tile k+2 are in flight.
+  bf16x8 ah[KR], al[KR];
+  auto load_a = [&](int rt) __attribute__((always_inline)) {
     if (KS > 0) {
-      bf16x8 ah[KR], al[KR];
+      const size_t ra = (size_t)(r0 + min(rt + c16, nr - 1)) * dq + g;
 #pragma unroll
       for (int s = 0; s < KR; ++s) {
-        ah[s] = as_bf8(A.Hred[ra + 4 * s]);
-        al[s] = X3 ? as_bf8(A.Lred[ra + 4 * s]) : ah[s];
+        ah[s] = as_bf8(Hred[ra + 4 * s]);
+        al[s] = X3 ? as_bf8(Lred[ra + 4 * s]) : ah[s];
       }
+    }
+  };
+  auto cross = [&](int rt, f32x4 (&xy)[NT]) __attribute__((always_inline)) {
+    if (KS > 0) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) xy[t] = cross_regs<X3, KR>(ah, al, bh[t], bl[t]);
     } else {
+      const size_t ra = (size_t)(r0 + min(rt + c16, nr - 1)) * dq + g;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const size_t rb = (size_t)colc[t] * dq + g;
-        xy[t] = cross_mem<X3>(A.Hred + ra, A.Lred + ra, A.Hout + rb, A.Lout + rb, ks);
+        xy[t] = cross_mem<X3>(Hred + ra, Lred + ra, Hout + rb, Lout + rb, ks);
       }
     }
-    // this lane's four reduce rows
+  };
+  // online log-sum-exp update of one row tile (MASK: rows past nr present)
+  auto lse_tile = [&](auto maskc, int rt, const f32x4 (&xy)[NT]) __attribute__((always_inline)) {
+    constexpr bool MASK = decltype(maskc)::value;
     float4 rw[4];
     bool ok[4];
     int rowc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int rl = rt + 4 * g + i;
-      ok[i] = rl < nr;
+      ok[i] = MASK ? rl < nr : true;
       rowc[i] = ok[i] ? rl : nr - 1;
       rw[i] = sR[rowc[i]];
     }
@@ -196,28 +218,27 @@ __global__ __launch_bounds__(TPB) void k_sweep_mfma(SweepArgs A) {
         // Fast2Sum: U + L dominates |C~| (L >= 2 max|C~|)
         const float sv = rw[i].x - cv;
         const float ev = ((rw[i].x - sv) - cv) + rw[i].y;
-        s[i] = ok[i] ? sv : SIG0;
-        e[i] = ok[i] ? ev : 0.f;
+        s[i] = (!MASK || ok[i]) ? sv : SIG0;
+        e[i] = (!MASK || ok[i]) ? ev : 0.f;
       }
       const float mx = fmaxf(fmaxf(s[0], s[1]), fmaxf(s[2], s[3]));
       if (mx > sig[t]) {
         const float sc = ex2((sig[t] - mx) * K);
         S[t] *= sc;
         Sc[t] *= sc;
+        T[t] *= sc;
 #pragma unroll
         for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[t][l] *= sc;
         sig[t] = mx;
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) p[t][i] = ex2(((s[i] - sig[t]) + e[i]) * K);
-      const float2 ts = two_sum(S[t], (p[t][0] + p[t][1]) + (p[t][2] + p[t][3]));
-      S[t] = ts.x;
-      Sc[t] += ts.y;
+      T[t] += (p[t][0] + p[t][1]) + (p[t][2] + p[t][3]);
     }
     if (ELL > 0) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float4* vr = reinterpret_cast<const float4*>(A.Vred + (size_t)(r0 + rowc[i]) * EL);
+        const float4* vr = reinterpret_cast<const float4*>(Vred + (size_t)(r0 + rowc[i]) * EL);
 #pragma unroll
         for (int l4 = 0; l4 < EL / 4; ++l4) {
           const float4 v = vr[l4];
@@ -231,6 +252,41 @@ __global__ __launch_bounds__(TPB) void k_sweep_mfma(SweepArgs A) {
         }
       }
     }
+  };
+
+  auto flush = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const float2 ts = two_sum(S[t], T[t]);
+      S[t] = ts.x;
+      Sc[t] += ts.y;
+      T[t] = 0.f;
+    }
+  };
+  auto lse_any = [&](int rt, const f32x4 (&xy)[NT]) __attribute__((always_inline)) {
+    if (rt + 16 <= nr) lse_tile(std::integral_constant<bool, false>{}, rt, xy);
+    else lse_tile(std::integral_constant<bool, true>{}, rt, xy);
+  };
+
+  // two row tiles per iteration; the xy buffers alternate roles
+  f32x4 xy0[NT], xy1[NT];
+  load_a(0);
+  cross(0, xy0);
+  if (16 < nr) load_a(16);
+  for (int rt = 0; rt < nr; rt += 32) {
+    if (rt + 16 < nr) {
+      cross(rt + 16, xy1);
+      if (rt + 32 < nr) load_a(rt + 32);
+    }
+    lse_any(rt, xy0);
+    if (rt + 16 < nr) {
+      if (rt + 32 < nr) {
+        cross(rt + 32, xy0);
+        if (rt + 48 < nr) load_a(rt + 48);
+      }
+      lse_any(rt + 16, xy1);
+    }
+    flush();
   }
 
   // butterfly over the four row groups of a column: both partners merge
@@ -269,19 +325,24 @@ __global__ __launch_bounds__(TPB) void k_sweep_mfma(SweepArgs A) {
     const int col = cb + 16 * t + c16;
     if (col < n_out) {
       float* base = A.part + (size_t)blockIdx.y * NQ * n_out + col;
+      if (g == 0) base[0] = sig[t];
+      else if (g == 1) base[(size_t)n_out] = S[t];
+      else if (g == 2) base[(size_t)2 * n_out] = Sc[t];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        if ((q & 3) == g) {
-          const float v = q == 0 ? sig[t] : (q == 1 ? S[t] : (q == 2 ? Sc[t] : acc[t][q >= 3 ? q - 3 : 0]));
-          base[(size_t)q * n_out] = v;
-        }
-      }
+      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l)
+        if (((3 + l) & 3) == g) base[(size_t)(3 + l) * n_out] = acc[t][l];
     }
   }
 }
 
 // ----------------------------------------------------------- geometry
-static int mfma_nt(int ell) { return ell > 16 ? 2 : 4; }
+// output tiles of 16 per wave: 4 for plain sweeps (SKNR_MFMA_NT=2 overrides),
+// 2 for weighted sweeps (register budget of the l-wide accumulators)
+static int mfma_nt(int ell) {
+  static const int env_nt = getenv("SKNR_MFMA_NT") ? atoi(getenv("SKNR_MFMA_NT")) : 0;
+  if (ell > 0) return 2;
+  return env_nt == 2 ? 2 : 4;
+}
 
 size_t mfma_part_floats(int n_out, int n_red, int ell, int* nsplit, int* rps, int* nblk) {
   const int nc = 64 * mfma_nt(ell);
@@ -303,9 +364,8 @@ size_t mfma_part_floats(int n_out, int n_red, int ell, int* nsplit, int* rps, in
   return (size_t)ns * (3 + ellp) * n_out;
 }
 
-template <int ELL, bool X3>
+template <int ELL, bool X3, int NT>
 static void go_mfma(const SweepArgs& a, hipStream_t s) {
-  constexpr int NT = ELL > 16 ? 2 : 4;
   const int nc = 64 * NT;
   dim3 grid((a.n_out + nc - 1) / nc, a.nsplit);
   const size_t sm = (size_t)a.rows_per_split * sizeof(float4);
@@ -318,16 +378,17 @@ static void go_mfma(const SweepArgs& a, hipStream_t s) {
 hipError_t launch_sweep_mfma(const SweepArgs& a, bool x3, hipStream_t s, hipEvent_t mid) {
   if (a.dpad <= 0 || (a.dpad & 31) || a.rows_per_split > 2048) return hipErrorInvalidValue;
   const int e = a.ell;
+  const bool nt2 = mfma_nt(e) == 2;
   if (x3) {
-    if (e == 0) go_mfma<0, true>(a, s);
-    else if (e <= 8) go_mfma<8, true>(a, s);
-    else if (e <= 16) go_mfma<16, true>(a, s);
-    else go_mfma<32, true>(a, s);
+    if (e == 0) nt2 ? go_mfma<0, true, 2>(a, s) : go_mfma<0, true, 4>(a, s);
+    else if (e <= 8) go_mfma<8, true, 2>(a, s);
+    else if (e <= 16) go_mfma<16, true, 2>(a, s);
+    else go_mfma<32, true, 2>(a, s);
   } else {
-    if (e == 0) go_mfma<0, false>(a, s);
-    else if (e <= 8) go_mfma<8, false>(a, s);
-    else if (e <= 16) go_mfma<16, false>(a, s);
-    else go_mfma<32, false>(a, s);
+    if (e == 0) nt2 ? go_mfma<0, false, 2>(a, s) : go_mfma<0, false, 4>(a, s);
+    else if (e <= 8) go_mfma<8, false, 2>(a, s);
+    else if (e <= 16) go_mfma<16, false, 2>(a, s);
+    else go_mfma<32, false, 2>(a, s);
   }
   if (mid) (void)hipEventRecord(mid, s);
   return launch_sweep_tail(a, s);
