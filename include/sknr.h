@@ -151,7 +151,9 @@ typedef struct sknr_result {
                                   FP64 squared distances of the FP32 points; STORED:
                                   equal to marginal_err) */
   double transport_cost_exact; /* <C, pi> on that exact cost */
-  double seconds;
+  double seconds;           /* wall time of the solve itself */
+  double queue_seconds;     /* serving: submit -> start of the solve (0 for sknr_solve) */
+  double latency_seconds;   /* serving: submit -> completion (0 for sknr_solve) */
 } sknr_result;
 
 /* --------------------------------------------------------------- context */
@@ -254,6 +256,61 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps,
  * row-major.  Diagnostic; O(nm) memory. */
 int sknr_coupling(void* ctx, const sknr_problem* prob, double eps,
                   const double* f, const double* g, float* P_out, void* stream);
+
+/* -------------------------------------------------------------- serving */
+/* Continuous batching of independent solves (mixed n, m, d, cost kind and
+ * eps schedule) on one device.  The context runs `max_active` worker lanes,
+ * each with its own HIP stream; device memory for requests comes from one
+ * pool allocated at the first submit.  A queued request is admitted, in
+ * arrival order with bounded backfilling, as soon as a lane is idle and its
+ * footprint (inputs, workspace and outputs) fits in the pool; admitted
+ * requests run concurrently, their kernels overlapping on the device, and
+ * each runs exactly the schedule sknr_solve would (Sec. 5 sequential or
+ * static warm start, Algorithm 4.1 per stage), so its result does not
+ * depend on the other requests.  The serving calls below are thread-safe
+ * with respect to each other. */
+
+/* Configure serving before the first submit on ctx: max_active lanes (1 ..
+ * 64, 0 -> env SKNR_SERVE_LANES or 8) and the pool size in bytes (0 ->
+ * min(budget, 8 GiB)).  Errors: EBUSY once serving has started, EINVAL. */
+int sknr_serve_config(void* ctx, int32_t max_active, uint64_t pool_bytes);
+
+/* Queue one solve.  prob and opts as for sknr_solve (opts.f0, opts.V0 and
+ * WARM_USER are not accepted; opts.stream orders the copy of the inputs).
+ * The inputs are validated and deep-copied before the call returns, so
+ * the caller may free them at once.  *ticket identifies the request.
+ * Errors: EINVAL, ENOMEM (footprint larger than the pool), EDEVICE. */
+int sknr_submit(void* ctx, const sknr_problem* prob, const sknr_opts* opts, uint64_t* ticket);
+
+/* *done = 1 when the request has finished (converged, not converged,
+ * failed or cancelled), else 0.  Errors: EINVAL (unknown ticket). */
+int sknr_poll(void* ctx, uint64_t ticket, int32_t* done);
+
+/* Block until the request finishes, copy its potentials into f_out [device]
+ * n FP64 and g_out [device] m FP64 (either may be NULL) and its statistics
+ * into res [host] (may be NULL), release the request and return its status
+ * (OK, NOT_CONVERGED, ECANCELED or the error it failed with).  The ticket
+ * is invalid afterwards. */
+int sknr_wait(void* ctx, uint64_t ticket, double* f_out, double* g_out, sknr_result* res);
+
+/* Cancel a request: a queued request is dropped, a running one stops at
+ * its next convergence poll.  sknr_wait still has to collect it (status
+ * ECANCELED unless it had already finished). */
+int sknr_cancel(void* ctx, uint64_t ticket);
+
+typedef struct sknr_serve_info {
+  int32_t lanes;        /* worker lanes */
+  int32_t queued;       /* requests waiting for admission */
+  int32_t running;      /* requests on the device */
+  int32_t reserved0;
+  int64_t completed;    /* requests finished since serving started */
+  uint64_t pool_bytes;  /* size of the device pool */
+  uint64_t pool_used;   /* bytes reserved now */
+  uint64_t pool_peak;   /* largest reservation so far */
+} sknr_serve_info;
+
+/* Snapshot of the serving runtime (all zero before the first submit). */
+int sknr_serve_stats(void* ctx, sknr_serve_info* out);
 
 /* ------------------------------------------------------------ profiling */
 typedef struct sknr_kprof {

@@ -17,7 +17,8 @@ __all__ = [
     "projected_system", "newton_step", "spectral_basis", "evaluate", "coupling",
     "SknrError", "COST_STORED", "COST_SQEUCLID", "XTERM_AUTO", "XTERM_FP32",
     "XTERM_BF16", "XTERM_BF16X3", "WARM_SEQUENTIAL", "WARM_STATIC", "WARM_USER",
-    "LIB_PATH", "MAX_STAGES", "MAX_ELL",
+    "LIB_PATH", "MAX_STAGES", "MAX_ELL", "serve_config", "submit", "poll", "wait", "cancel",
+    "serve_stats", "OK", "NOT_CONVERGED", "EINVAL", "ENOMEM", "EDEVICE", "EBUSY", "ECANCELED", "EINTERNAL",
 ]
 
 # torch ships its own HIP runtime; importing it first makes libsknr bind to
@@ -35,6 +36,7 @@ COST_STORED, COST_SQEUCLID = 0, 1
 XTERM_AUTO, XTERM_FP32, XTERM_BF16, XTERM_BF16X3 = 0, 1, 2, 3
 WARM_SEQUENTIAL, WARM_STATIC, WARM_USER = 0, 1, 2
 OK, NOT_CONVERGED = 0, 1
+EINVAL, ENOMEM, EDEVICE, EBUSY, ECANCELED, EINTERNAL = -1, -2, -3, -4, -5, -6
 
 _p = ctypes.c_void_p
 _d = ctypes.c_double
@@ -66,13 +68,20 @@ class _Result(ctypes.Structure):
                 ("stage", _Stage * MAX_STAGES), ("marginal_err", _d), ("row_err", _d),
                 ("col_err", _d), ("transport_cost", _d), ("dual_value", _d),
                 ("primal_value", _d), ("mass", _d), ("marginal_err_exact", _d),
-                ("transport_cost_exact", _d), ("seconds", _d)]
+                ("transport_cost_exact", _d), ("seconds", _d), ("queue_seconds", _d),
+                ("latency_seconds", _d)]
 
 
 class _Eval(ctypes.Structure):
     _fields_ = [("row_err", _d), ("col_err", _d), ("marginal_err", _d), ("transport_cost", _d),
                 ("dual_value", _d), ("primal_value", _d), ("mass", _d), ("row_err_exact", _d),
                 ("col_err_exact", _d), ("marginal_err_exact", _d), ("transport_cost_exact", _d)]
+
+
+class _ServeInfo(ctypes.Structure):
+    _fields_ = [("lanes", _i32), ("queued", _i32), ("running", _i32), ("reserved0", _i32),
+                ("completed", _i64), ("pool_bytes", ctypes.c_uint64), ("pool_used", ctypes.c_uint64),
+                ("pool_peak", ctypes.c_uint64)]
 
 
 class _KProf(ctypes.Structure):
@@ -103,6 +112,12 @@ _sig("sknr_spectral_basis", [_p, _P(_Problem), _d, _p, _i32, _i32, _i32, _d, cty
 _sig("sknr_evaluate", [_p, _P(_Problem), _d, _p, _p, _P(_Eval), _p])
 _sig("sknr_coupling", [_p, _P(_Problem), _d, _p, _p, _p, _p])
 _sig("sknr_profile", [_p, _i32])
+_sig("sknr_serve_config", [_p, _i32, ctypes.c_uint64])
+_sig("sknr_submit", [_p, _P(_Problem), _P(_Opts), _P(ctypes.c_uint64)])
+_sig("sknr_poll", [_p, ctypes.c_uint64, _P(_i32)])
+_sig("sknr_wait", [_p, ctypes.c_uint64, _p, _p, _P(_Result)])
+_sig("sknr_cancel", [_p, ctypes.c_uint64])
+_sig("sknr_serve_stats", [_p, _P(_ServeInfo)])
 _sig("sknr_profile_read", [_p, _P(_KProf), _i32, _P(_i32)])
 
 
@@ -208,18 +223,8 @@ class Problem:
         return p
 
 
-def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,
-          warm_mode: int = WARM_USER, V0=None, f0=None, eps_prime: float = 0.0, check_every: int = 0,
-          first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
-          eig_tol: float = 0.0, seed: int = 0, stream=None, f_out=None, g_out=None):
-    """sknr_solve.  Returns (f, g, result dict); f, g are float64 device
-    tensors in the caller's orientation."""
-    import torch
-    eps = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
-    dev = prob.a.device
-    n, m = int(prob.a.shape[0]), int(prob.b.shape[0])
-    f = f_out if f_out is not None else torch.empty(n, dtype=torch.float64, device=dev)
-    g = g_out if g_out is not None else torch.empty(m, dtype=torch.float64, device=dev)
+def _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr, eig_oversample,
+          eig_max_iter, eig_tol, seed, stream):
     earr = (_d * len(eps))(*eps)
     o = _Opts()
     o.eps = ctypes.cast(earr, _P(_d))
@@ -238,13 +243,87 @@ def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 1
     o.V0 = _ptr(V0)
     o.seed = seed
     o.stream = _stream(stream)
+    return o, earr  # earr must outlive the call
+
+
+def _result_dict(r):
+    res = {k: getattr(r, k) for k, _ in _Result._fields_ if k != "stage"}
+    res["stages"] = [{k: getattr(r.stage[i], k) for k, _ in _Stage._fields_} for i in range(r.n_stages)]
+    return res
+
+
+def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,
+          warm_mode: int = WARM_USER, V0=None, f0=None, eps_prime: float = 0.0, check_every: int = 0,
+          first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
+          eig_tol: float = 0.0, seed: int = 0, stream=None, f_out=None, g_out=None):
+    """sknr_solve.  Returns (f, g, result dict); f, g are float64 device
+    tensors in the caller's orientation."""
+    import torch
+    eps = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
+    dev = prob.a.device
+    n, m = int(prob.a.shape[0]), int(prob.b.shape[0])
+    f = f_out if f_out is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    g = g_out if g_out is not None else torch.empty(m, dtype=torch.float64, device=dev)
+    o, earr = _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr,
+                    eig_oversample, eig_max_iter, eig_tol, seed, stream)
     r = _Result()
     ps = prob.c_struct()
     st = lib.sknr_solve(ctx.handle, ctypes.byref(ps), ctypes.byref(o), _ptr(f), _ptr(g), ctypes.byref(r))
     _check(st, "sknr_solve")
-    res = {k: getattr(r, k) for k, _ in _Result._fields_ if k != "stage"}
-    res["stages"] = [{k: getattr(r.stage[i], k) for k, _ in _Stage._fields_} for i in range(r.n_stages)]
+    return f, g, _result_dict(r)
+
+
+# ------------------------------------------------------------------ serving
+def serve_config(ctx: Context, max_active: int = 0, pool_bytes: int = 0):
+    """sknr_serve_config: lanes and pool size, before the first submit."""
+    _check(lib.sknr_serve_config(ctx.handle, max_active, pool_bytes), "sknr_serve_config")
+
+
+def submit(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,
+           warm_mode: int = WARM_SEQUENTIAL, eps_prime: float = 0.0, check_every: int = 0,
+           first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
+           eig_tol: float = 0.0, seed: int = 0, stream=None) -> int:
+    """sknr_submit: queue a solve (inputs are copied before returning);
+    returns the ticket."""
+    eps = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
+    o, earr = _opts(eps, tol, max_iter, ell, warm_mode, None, None, eps_prime, check_every, first_stage_nr,
+                    eig_oversample, eig_max_iter, eig_tol, seed, stream)
+    ps = prob.c_struct()
+    t = ctypes.c_uint64()
+    _check(lib.sknr_submit(ctx.handle, ctypes.byref(ps), ctypes.byref(o), ctypes.byref(t)), "sknr_submit")
+    return t.value
+
+
+def poll(ctx: Context, ticket: int) -> bool:
+    d = _i32()
+    _check(lib.sknr_poll(ctx.handle, ticket, ctypes.byref(d)), "sknr_poll")
+    return bool(d.value)
+
+
+def wait(ctx: Context, ticket: int, n: int, m: int, device=None, raise_on_error: bool = True):
+    """sknr_wait: (f, g, result dict); result["status"] carries
+    NOT_CONVERGED / ECANCELED when raise_on_error is False."""
+    import torch
+    dev = device if device is not None else torch.device("cuda", ctx.device)
+    f = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty(m, dtype=torch.float64, device=dev)
+    r = _Result()
+    st = lib.sknr_wait(ctx.handle, ticket, _ptr(f), _ptr(g), ctypes.byref(r))
+    if raise_on_error:
+        _check(st, "sknr_wait")
+    res = _result_dict(r)
+    res["status"] = st
     return f, g, res
+
+
+def cancel(ctx: Context, ticket: int):
+    _check(lib.sknr_cancel(ctx.handle, ticket), "sknr_cancel")
+
+
+def serve_stats(ctx: Context) -> dict:
+    i = _ServeInfo()
+    _check(lib.sknr_serve_stats(ctx.handle, ctypes.byref(i)), "sknr_serve_stats")
+    return {k: getattr(i, k) for k, _ in _ServeInfo._fields_ if k != "reserved0"}
 
 
 def c_transform_row(ctx, prob: Problem, eps: float, g, stream=None):

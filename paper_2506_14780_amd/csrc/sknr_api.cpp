@@ -18,163 +18,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sknr.h"
-#include "sknr_internal.h"
+#include "sknr_host.h"
 
 using namespace sknr;
 
-namespace {
+namespace sknr_host {
 
 thread_local std::string g_last_error;
-
-struct Err {
-  int code;
-  std::string msg;
-};
-
-#define HIPCHK(expr)                                                                        \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess) throw Err{SKNR_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
-  } while (0)
-#define REQUIRE(cond, msg)                                   \
-  do {                                                       \
-    if (!(cond)) throw Err{SKNR_EINVAL, std::string(msg)};   \
-  } while (0)
-
-float2 split_df(double v) {
-  float hi = (float)v;
-  float lo = (float)(v - (double)hi);
-  return make_float2(hi, lo);
-}
-
-// ------------------------------------------------------------------ arena
-// One device allocation carved into aligned buffers; grown (reallocated)
-// when a larger problem arrives.  Counters inside are zeroed at growth.
-struct Arena {
-  char* base = nullptr;
-  size_t cap = 0;
-  size_t off = 0;
-  void reset() { off = 0; }
-  void* take(size_t bytes) {
-    size_t a = (off + 255) & ~size_t(255);
-    if (a + bytes > cap) throw Err{SKNR_EINTERNAL, "arena overflow"};
-    off = a + bytes;
-    return base + a;
-  }
-};
-
-// Per-kernel-kind timing with HIP events recorded on the launch stream
-// around each sweep (enabled by sknr_profile).
-struct ProfEntry {
-  std::string name;
-  long long launches = 0;
-  double total_ms = 0;
-  double units = 0;  // algorithmic elements (n_out * n_red) processed
-};
-struct Pending {
-  int kind;
-  hipEvent_t e0, e1;
-  double units;
-};
-// A captured chunk of solver iterations.  Every pointer and constant baked
-// into its kernel arguments is part of the key; eps-dependent values live
-// in the device state, so one graph serves all stages of a schedule.
-struct GraphKey {
-  const void* ws;
-  const void* C;
-  const void* X;
-  const void* Y;
-  const void* wX;
-  const void* wY;
-  long long ldc;
-  int n, m, d, kind, ell, ellp, iters, ctrans;
-  float cscale, cmax;
-  void* stream;
-  bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
-};
-struct CachedGraph {
-  GraphKey key;
-  hipGraphExec_t exec;
-};
-struct Ctx {
-  int device = 0;
-  uint64_t budget = 0;
-  Arena arena;
-  hipStream_t own = nullptr;     // solver stream (default priority); graphs are captured on it
-  hipEvent_t order_ev = nullptr;  // orders the solver stream after the caller's stream
-  bool use_graphs = true;
-  std::vector<CachedGraph> graphs;
-  void drop_graphs() {
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
-    graphs.clear();
-  }
-  DevState* st_host = nullptr;  // pinned mirror of the state
-  bool profile = false;
-  std::vector<ProfEntry> prof;
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> evpool;
-  hipEvent_t get_event() {
-    if (!evpool.empty()) {
-      hipEvent_t e = evpool.back();
-      evpool.pop_back();
-      return e;
-    }
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) throw Err{SKNR_EDEVICE, "hipEventCreate failed"};
-    return e;
-  }
-  int kind_of(const std::string& name) {
-    for (size_t i = 0; i < prof.size(); ++i)
-      if (prof[i].name == name) return (int)i;
-    prof.push_back(ProfEntry{name});
-    return (int)prof.size() - 1;
-  }
-  // after a stream synchronisation: fold completed event pairs
-  void drain() {
-    hipEvent_t last_e0 = nullptr;
-    for (auto& p : pending) {
-      hipEvent_t e0 = p.e0 ? p.e0 : last_e0;  // a ":main" entry starts at its sweep's start
-      float ms = 0;
-      if (e0 && hipEventElapsedTime(&ms, e0, p.e1) == hipSuccess) {
-        prof[p.kind].launches += 1;
-        prof[p.kind].total_ms += ms;
-        prof[p.kind].units += p.units;
-      }
-      if (p.e0) last_e0 = p.e0;
-    }
-    for (auto& p : pending) {
-      if (p.e0) evpool.push_back(p.e0);
-      evpool.push_back(p.e1);
-    }
-    pending.clear();
-  }
-};
-
-struct Prepared {
-  // caller orientation
-  int n0, m0;
-  // engine orientation
-  int n, m;
-  bool transposed;
-  int kind;
-  const float* C;
-  long long ldc;
-  bool ctrans;  // engine element (i, j) is C[j*ldc + i]
-  const float* X;  // points of side X (n x d)
-  const float* Y;  // points of side Y (m x d)
-  int d;
-  float cscale;
-  double cscale64;
-  float cmax;
-  // cross term of a SQEUCLID cost: 1 FP32 direct, 2 bf16, 3 bf16 hi/lo split
-  int xmode = 0;
-  int dpad = 0;          // bf16 rows: d rounded up to a multiple of 32
-  std::vector<float> mu;  // centring point (bf16-rounded mean of all points)
-  const double* wX;  // device FP64 weights
-  const double* wY;
-  std::vector<double> hX, hY;  // host copies
-};
 
 struct WS {
   float2 *F, *Fsk, *Fp, *G[2], *Gt, *Gp;
@@ -400,9 +250,10 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   return b + 4096;
 }
 
-WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
+WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
   size_t need = ws_bytes(P, ellp, nullptr);
   if (need > c->arena.cap) {
+    if (c->arena_external) throw Err{SKNR_EINTERNAL, "workspace exceeds the reserved block"};
     HIPCHK(hipStreamSynchronize(s));
     c->drop_graphs();  // captured kernels point into the old arena
     if (c->arena.base) HIPCHK(hipFree(c->arena.base));
@@ -527,14 +378,14 @@ WS make_ws(Ctx* c, const Prepared& P, int ellp, hipStream_t s) {
 
 // ------------------------------------------------------------------ engine
 struct Engine {
-  Ctx* c;
-  Prepared& P;
+  Lane* c;
+  const Prepared& P;
   WS& w;
   hipStream_t s;
   double eps = 1.0;
   double tol = 1e-6;
 
-  Engine(Ctx* c_, Prepared& P_, WS& w_, hipStream_t s_) : c(c_), P(P_), w(w_), s(s_) {}
+  Engine(Lane* c_, const Prepared& P_, WS& w_, hipStream_t s_) : c(c_), P(P_), w(w_), s(s_) {}
 
   void fill_common(SweepArgs& a) const {
     a.C = P.C;
@@ -665,6 +516,9 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(w.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
   }
+  void check_cancel() const {
+    if (c->cancel && c->cancel->load(std::memory_order_relaxed)) throw Err{SKNR_ECANCELED, "request cancelled"};
+  }
   DevState read_state() {
     HIPCHK(hipMemcpyAsync(c->st_host, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -794,6 +648,7 @@ struct Engine {
       }
       launched += k;
       st = read_state();
+      check_cancel();
       if (st.done) {
         done = true;
         break;
@@ -933,6 +788,7 @@ struct Engine {
       int jsw = 0;
       HIPCHK(hipMemcpyAsync(&jsw, w.okw + 1, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      check_cancel();
       if (getenv("SKNR_DEBUG_EIG")) std::fprintf(stderr, "eig it %d jacobi sweeps %d lam0 %.6f lam%d %.6f\n", it, jsw, lc[0], ell - 1, lc[ell - 1]);
       double dmax = 0;
       for (int i = 0; i < ell; ++i) dmax = std::max(dmax, std::fabs(lc[i] - lp[i]));
@@ -984,34 +840,174 @@ Prepared prepare_caller_orientation(const sknr_problem* prob, hipStream_t s) {
   return P;
 }
 
-hipStream_t as_stream(void* p) { return reinterpret_cast<hipStream_t>(p); }
 
-template <typename Fn>
-int guarded(Fn fn) {
-  try {
-    return fn();
-  } catch (const Err& e) {
-    g_last_error = e.msg;
-    return e.code;
-  } catch (const std::exception& e) {
-    g_last_error = e.what();
-    return SKNR_EINTERNAL;
-  } catch (...) {
-    g_last_error = "unknown error";
-    return SKNR_EINTERNAL;
+// The eps schedule of sknr_solve on one lane (see the header for the
+// stage protocol): optional static warm start, per stage the spectral warm
+// start (sequential), the rebase of the potentials to the new eps, the SK /
+// SK-NR iterations and the FP64 check; the gauge and reported values after
+// the last stage.
+int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sknr_opts* opts, double* f_out,
+                  double* g_out, sknr_result* res) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = L->own;
+  int ellp = ell_pad(opts->ell);
+  WS w = make_ws(L, P, ellp, s);
+  Engine E(L, P, w, s);
+  const int eig_os = opts->eig_oversample > 0 ? opts->eig_oversample : 8;
+  const int eig_it = opts->eig_max_iter > 0 ? opts->eig_max_iter : 100;
+  const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 1e-4;
+  std::memset(res, 0, sizeof(*res));
+  E.tol = opts->tol;
+  int static_eig_iters = 0;
+  if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) {
+    // plain SK at eps' from the initial potential, then V_l once
+    E.eps = opts->eps_prime;
+    E.init_state();
+    E.load_f(opts->f0);
+    E.load_g(nullptr, w.G[0], MA_G, DOT_G);
+    bool cv;
+    int tr, ac;
+    E.run_stage(0, opts->max_iter, opts->check_every, false, &cv, &tr, &ac);
+    static_eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed, nullptr);
+    E.use_warm_V(opts->ell, eig_os);
   }
+  E.eps = opts->eps[0];
+  E.init_state();
+  E.load_f(opts->f0);
+  E.load_g(nullptr, w.G[0], MA_G, DOT_G);
+  if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_USER) E.load_V(opts->V0, opts->ell);
+  res->n_stages = opts->n_eps;
+  res->transposed = P.transposed ? 1 : 0;
+  int status = SKNR_OK;
+  for (int st = 0; st < opts->n_eps; ++st) {
+    auto ts = std::chrono::steady_clock::now();
+    double eps = opts->eps[st];
+    int eig_iters = 0;
+    if (st > 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_SEQUENTIAL) {
+      // V_l from the optimum of the previous stage (its eps), Sec. 4
+      eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed + st, nullptr);
+      E.use_warm_V(opts->ell, eig_os);
+    }
+    if (st == 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) eig_iters = static_eig_iters;
+    if (st > 0) {
+      double de = eps - E.eps;
+      E.init_state();
+      HIPCHK(launch_rebase(w.F, w.lXdf, split_df(de), P.n, w.st, MA_F, s));
+      HIPCHK(launch_rebase(w.G[0], w.lYdf, split_df(de), P.m, w.st, MA_G, s));
+      E.eps = eps;
+    }
+    bool use_nr = opts->ell > 0 && (st > 0 || opts->first_stage_nr);
+    bool conv = false;
+    int tried = 0, acc = 0, it = 0;
+    sknr_eval ev{};
+    // The sweeps estimate the error in FP32 (column marginal via the next
+    // c-transform); the FP64 check decides.  If it disagrees, continue
+    // the stage with a tighter FP32 threshold.
+    E.tol = opts->tol;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+      int tr = 0, ac = 0;
+      bool cv = false;
+      it += E.run_stage(use_nr ? opts->ell : 0, opts->max_iter - it, opts->check_every, attempt > 0, &cv, &tr, &ac);
+      tried += tr;
+      acc += ac;
+      E.export_fg(f_out, g_out);
+      ev = E.evaluate(prob, f_out, g_out);
+      conv = cv && ev.marginal_err < opts->tol;
+      if (conv || !cv || it >= opts->max_iter) break;
+      E.tol = E.tol * std::min(0.9, opts->tol / ev.marginal_err);
+    }
+    if (!conv) status = SKNR_NOT_CONVERGED;
+    sknr_stage_stats& ss = res->stage[st];
+    ss.eps = eps;
+    ss.iters = it;
+    ss.newton_tried = tried;
+    ss.newton_accepted = acc;
+    ss.eig_iters = eig_iters;
+    ss.marginal_err = ev.marginal_err;
+    ss.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+    res->total_iters += it;
+    if (st == opts->n_eps - 1) {
+      E.gauge(prob, f_out, g_out);
+      res->marginal_err = ev.marginal_err;
+      res->row_err = ev.row_err;
+      res->col_err = ev.col_err;
+      res->transport_cost = ev.transport_cost;
+      res->dual_value = ev.dual_value;
+      res->primal_value = ev.primal_value;
+      res->mass = ev.mass;
+      if (P.kind == SKNR_COST_SQEUCLID) {
+        sknr_eval ex = E.evaluate(prob, f_out, g_out, true);
+        res->marginal_err_exact = ex.marginal_err;
+        res->transport_cost_exact = ex.transport_cost;
+      } else {
+        res->marginal_err_exact = ev.marginal_err;
+        res->transport_cost_exact = ev.transport_cost;
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  res->status = status;
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return status;
 }
 
-Ctx* as_ctx(void* p) {
-  if (!p) throw Err{SKNR_EINVAL, "context is NULL"};
-  Ctx* c = reinterpret_cast<Ctx*>(p);
-  HIPCHK(hipSetDevice(c->device));
-  return c;
+void check_opts(const sknr_opts* opts, const Prepared& P) {
+  REQUIRE(opts->n_eps >= 1 && opts->n_eps <= SKNR_MAX_STAGES && opts->eps, "eps schedule length out of range");
+  for (int s = 0; s < opts->n_eps; ++s) check_eps(opts->eps[s]);
+  REQUIRE(opts->tol > 0 && std::isfinite(opts->tol), "tol must be positive");
+  REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
+  REQUIRE(opts->ell >= 0 && opts->ell <= SKNR_MAX_ELL, "ell out of range");
+  REQUIRE(opts->ell < std::min(P.n0, P.m0), "ell must be < min(n, m)");
+  if (opts->ell > 0) {
+    REQUIRE(opts->warm_mode == SKNR_WARM_USER || opts->warm_mode == SKNR_WARM_SEQUENTIAL ||
+                opts->warm_mode == SKNR_WARM_STATIC, "unknown warm_mode");
+    if (opts->warm_mode == SKNR_WARM_USER) {
+      REQUIRE(opts->V0, "WARM_USER needs V0");
+      REQUIRE(!P.transposed, "WARM_USER needs n <= m");
+    }
+    if (opts->warm_mode == SKNR_WARM_STATIC) check_eps(opts->eps_prime);
+    REQUIRE(!opts->first_stage_nr || opts->warm_mode != SKNR_WARM_SEQUENTIAL,
+            "first_stage_nr needs WARM_USER or WARM_STATIC");
+  }
+  if (opts->f0) REQUIRE(!P.transposed, "f0 needs n <= m");
+}
+
+void rebind(Prepared& P, const sknr_problem* pr) {
+  P.C = pr->C;
+  P.X = P.transposed ? pr->y : pr->x;
+  P.Y = P.transposed ? pr->x : pr->y;
+  P.wX = P.transposed ? pr->b : pr->a;
+  P.wY = P.transposed ? pr->a : pr->b;
+}
+
+void lane_init(Lane* L, int device) {
+  L->device = device;
+  HIPCHK(hipHostMalloc((void**)&L->st_host, sizeof(DevState), hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking));
+  const char* ng = getenv("SKNR_NO_GRAPHS");
+  L->use_graphs = !(ng && ng[0] == '1');
+}
+
+void lane_release(Lane* L) {
+  if (L->own) (void)hipStreamSynchronize(L->own);
+  L->drop_graphs();
+  if (L->arena.base && !L->arena_external) (void)hipFree(L->arena.base);
+  L->arena.base = nullptr;
+  L->arena.cap = 0;
+  if (L->st_host) (void)hipHostFree(L->st_host);
+  L->st_host = nullptr;
+  L->drain();
+  if (L->own) (void)hipStreamDestroy(L->own);
+  L->own = nullptr;
+  for (auto e : L->evpool) (void)hipEventDestroy(e);
+  L->evpool.clear();
 }
 
 void check_eps(double eps) { REQUIRE(eps > 0 && std::isfinite(eps), "eps must be positive and finite"); }
 
-}  // namespace
+}  // namespace sknr_host
+
+using namespace sknr_host;
 
 // ============================================================================
 extern "C" {
@@ -1045,11 +1041,8 @@ int sknr_ctx_create(int device, uint64_t hbm_budget_bytes, void** out) {
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * fr);
-    HIPCHK(hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault));
-    HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+    lane_init(&c->lane, device);
     HIPCHK(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming));
-    const char* ng = getenv("SKNR_NO_GRAPHS");
-    c->use_graphs = !(ng && ng[0] == '1');
     *out = c;
     return SKNR_OK;
   });
@@ -1060,14 +1053,10 @@ int sknr_ctx_destroy(void* ctx) {
     if (!ctx) return SKNR_OK;
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
     HIPCHK(hipSetDevice(c->device));
+    server_destroy(c);
     HIPCHK(hipDeviceSynchronize());
-    c->drop_graphs();
-    if (c->arena.base) HIPCHK(hipFree(c->arena.base));
-    if (c->st_host) HIPCHK(hipHostFree(c->st_host));
-    c->drain();
-    if (c->own) (void)hipStreamDestroy(c->own);
+    lane_release(&c->lane);
     if (c->order_ev) (void)hipEventDestroy(c->order_ev);
-    for (auto e : c->evpool) (void)hipEventDestroy(e);
     delete c;
     return SKNR_OK;
   });
@@ -1078,130 +1067,14 @@ int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts, doubl
   return guarded([&]() -> int {
     Ctx* c = as_ctx(ctx);
     REQUIRE(opts && res && f_out && g_out, "opts, res, f_out, g_out are required");
-    REQUIRE(opts->n_eps >= 1 && opts->n_eps <= SKNR_MAX_STAGES && opts->eps, "eps schedule length out of range");
-    for (int s = 0; s < opts->n_eps; ++s) check_eps(opts->eps[s]);
-    REQUIRE(opts->tol > 0 && std::isfinite(opts->tol), "tol must be positive");
-    REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
-    REQUIRE(opts->ell >= 0 && opts->ell <= SKNR_MAX_ELL, "ell out of range");
-    auto t0 = std::chrono::steady_clock::now();
     // run on the context's stream, after the work already queued on the caller's
     hipStream_t cs = as_stream(opts->stream);
-    hipStream_t s = c->own;
+    hipStream_t s = c->lane.own;
     HIPCHK(hipEventRecord(c->order_ev, cs));
     HIPCHK(hipStreamWaitEvent(s, c->order_ev, 0));
     Prepared P = prepare(prob, s);
-    REQUIRE(opts->ell < std::min(P.n0, P.m0), "ell must be < min(n, m)");
-    if (opts->ell > 0) {
-      REQUIRE(opts->warm_mode == SKNR_WARM_USER || opts->warm_mode == SKNR_WARM_SEQUENTIAL ||
-                  opts->warm_mode == SKNR_WARM_STATIC, "unknown warm_mode");
-      if (opts->warm_mode == SKNR_WARM_USER) {
-        REQUIRE(opts->V0, "WARM_USER needs V0");
-        REQUIRE(!P.transposed, "WARM_USER needs n <= m");
-      }
-      if (opts->warm_mode == SKNR_WARM_STATIC) check_eps(opts->eps_prime);
-      REQUIRE(!opts->first_stage_nr || opts->warm_mode != SKNR_WARM_SEQUENTIAL,
-              "first_stage_nr needs WARM_USER or WARM_STATIC");
-    }
-    if (opts->f0) REQUIRE(!P.transposed, "f0 needs n <= m");
-    int ellp = ell_pad(opts->ell);
-    WS w = make_ws(c, P, ellp, s);
-    Engine E(c, P, w, s);
-    const int eig_os = opts->eig_oversample > 0 ? opts->eig_oversample : 8;
-    const int eig_it = opts->eig_max_iter > 0 ? opts->eig_max_iter : 100;
-    const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 1e-4;
-    std::memset(res, 0, sizeof(*res));
-    E.tol = opts->tol;
-    int static_eig_iters = 0;
-    if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) {
-      // plain SK at eps' from the initial potential, then V_l once
-      E.eps = opts->eps_prime;
-      E.init_state();
-      E.load_f(opts->f0);
-      E.load_g(nullptr, w.G[0], MA_G, DOT_G);
-      bool cv;
-      int tr, ac;
-      E.run_stage(0, opts->max_iter, opts->check_every, false, &cv, &tr, &ac);
-      static_eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed, nullptr);
-      E.use_warm_V(opts->ell, eig_os);
-    }
-    E.eps = opts->eps[0];
-    E.init_state();
-    E.load_f(opts->f0);
-    E.load_g(nullptr, w.G[0], MA_G, DOT_G);
-    if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_USER) E.load_V(opts->V0, opts->ell);
-    res->n_stages = opts->n_eps;
-    res->transposed = P.transposed ? 1 : 0;
-    int status = SKNR_OK;
-    for (int st = 0; st < opts->n_eps; ++st) {
-      auto ts = std::chrono::steady_clock::now();
-      double eps = opts->eps[st];
-      int eig_iters = 0;
-      if (st > 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_SEQUENTIAL) {
-        // V_l from the optimum of the previous stage (its eps), Sec. 4
-        eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed + st, nullptr);
-        E.use_warm_V(opts->ell, eig_os);
-      }
-      if (st == 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) eig_iters = static_eig_iters;
-      if (st > 0) {
-        double de = eps - E.eps;
-        E.init_state();
-        HIPCHK(launch_rebase(w.F, w.lXdf, split_df(de), P.n, w.st, MA_F, s));
-        HIPCHK(launch_rebase(w.G[0], w.lYdf, split_df(de), P.m, w.st, MA_G, s));
-        E.eps = eps;
-      }
-      bool use_nr = opts->ell > 0 && (st > 0 || opts->first_stage_nr);
-      bool conv = false;
-      int tried = 0, acc = 0, it = 0;
-      sknr_eval ev{};
-      // The sweeps estimate the error in FP32 (column marginal via the next
-      // c-transform); the FP64 check decides.  If it disagrees, continue
-      // the stage with a tighter FP32 threshold.
-      E.tol = opts->tol;
-      for (int attempt = 0; attempt < 8; ++attempt) {
-        int tr = 0, ac = 0;
-        bool cv = false;
-        it += E.run_stage(use_nr ? opts->ell : 0, opts->max_iter - it, opts->check_every, attempt > 0, &cv, &tr, &ac);
-        tried += tr;
-        acc += ac;
-        E.export_fg(f_out, g_out);
-        ev = E.evaluate(prob, f_out, g_out);
-        conv = cv && ev.marginal_err < opts->tol;
-        if (conv || !cv || it >= opts->max_iter) break;
-        E.tol = E.tol * std::min(0.9, opts->tol / ev.marginal_err);
-      }
-      if (!conv) status = SKNR_NOT_CONVERGED;
-      sknr_stage_stats& ss = res->stage[st];
-      ss.eps = eps;
-      ss.iters = it;
-      ss.newton_tried = tried;
-      ss.newton_accepted = acc;
-      ss.eig_iters = eig_iters;
-      ss.marginal_err = ev.marginal_err;
-      ss.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
-      res->total_iters += it;
-      if (st == opts->n_eps - 1) {
-        E.gauge(prob, f_out, g_out);
-        res->marginal_err = ev.marginal_err;
-        res->row_err = ev.row_err;
-        res->col_err = ev.col_err;
-        res->transport_cost = ev.transport_cost;
-        res->dual_value = ev.dual_value;
-        res->primal_value = ev.primal_value;
-        res->mass = ev.mass;
-        if (P.kind == SKNR_COST_SQEUCLID) {
-          sknr_eval ex = E.evaluate(prob, f_out, g_out, true);
-          res->marginal_err_exact = ex.marginal_err;
-          res->transport_cost_exact = ex.transport_cost;
-        } else {
-          res->marginal_err_exact = ev.marginal_err;
-          res->transport_cost_exact = ev.transport_cost;
-        }
-      }
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    res->status = status;
-    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return status;
+    check_opts(opts, P);
+    return solve_on_lane(&c->lane, prob, P, opts, f_out, g_out, res);
   });
 }
 
@@ -1213,8 +1086,8 @@ int sknr_c_transform_col(void* ctx, const sknr_problem* prob, double eps, const 
     REQUIRE(f && g_out, "f and g_out are required");
     hipStream_t s = as_stream(stream);
     Prepared P = prepare_caller_orientation(prob, s);
-    WS w = make_ws(c, P, 0, s);
-    Engine E(c, P, w, s);
+    WS w = make_ws(&c->lane, P, 0, s);
+    Engine E(&c->lane, P, w, s);
     E.eps = eps;
     E.init_state();
     E.load_f(f);
@@ -1242,8 +1115,8 @@ int sknr_c_transform_row(void* ctx, const sknr_problem* prob, double eps, const 
     REQUIRE(g && f_out, "g and f_out are required");
     hipStream_t s = as_stream(stream);
     Prepared P = prepare_caller_orientation(prob, s);
-    WS w = make_ws(c, P, 0, s);
-    Engine E(c, P, w, s);
+    WS w = make_ws(&c->lane, P, 0, s);
+    Engine E(&c->lane, P, w, s);
     E.eps = eps;
     E.init_state();
     E.load_g(g, w.G[0], MA_G, DOT_G);
@@ -1263,8 +1136,8 @@ int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps, const
     hipStream_t s = as_stream(stream);
     Prepared P = prepare_caller_orientation(prob, s);
     int ellp = ell_pad(ell);
-    WS w = make_ws(c, P, ellp, s);
-    Engine E(c, P, w, s);
+    WS w = make_ws(&c->lane, P, ellp, s);
+    Engine E(&c->lane, P, w, s);
     E.eps = eps;
     E.init_state();
     E.load_f(f);
@@ -1301,8 +1174,8 @@ int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps, double* f_
     hipStream_t s = as_stream(stream);
     Prepared P = prepare_caller_orientation(prob, s);
     int ellp = ell_pad(ell);
-    WS w = make_ws(c, P, ellp, s);
-    Engine E(c, P, w, s);
+    WS w = make_ws(&c->lane, P, ellp, s);
+    Engine E(&c->lane, P, w, s);
     E.eps = eps;
     E.init_state();
     E.load_f(f_inout);
@@ -1332,8 +1205,8 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps, const double*
     REQUIRE(f && g && out, "f, g, out are required");
     hipStream_t s = as_stream(stream);
     Prepared P = prepare_caller_orientation(prob, s);
-    WS w = make_ws(c, P, 0, s);
-    Engine E(c, P, w, s);
+    WS w = make_ws(&c->lane, P, 0, s);
+    Engine E(&c->lane, P, w, s);
     E.eps = eps;
     *out = E.evaluate(prob, f, g);
     if (P.kind == SKNR_COST_SQEUCLID) {
@@ -1360,8 +1233,8 @@ int sknr_coupling(void* ctx, const sknr_problem* prob, double eps, const double*
     REQUIRE(f && g && P_out, "f, g, P_out are required");
     hipStream_t s = as_stream(stream);
     Prepared P = prepare_caller_orientation(prob, s);
-    WS w = make_ws(c, P, 0, s);
-    Engine E(c, P, w, s);
+    WS w = make_ws(&c->lane, P, 0, s);
+    Engine E(&c->lane, P, w, s);
     SweepArgs geo = E.caller_geo(prob);
     const int kind = sweep_kind(P);
     if (kind == 2 || kind == 3)
@@ -1377,9 +1250,9 @@ int sknr_profile(void* ctx, int32_t enable) {
   return guarded([&]() -> int {
     Ctx* c = as_ctx(ctx);
     HIPCHK(hipDeviceSynchronize());
-    c->drain();
-    c->profile = enable != 0;
-    c->prof.clear();
+    c->lane.drain();
+    c->lane.profile = enable != 0;
+    c->lane.prof.clear();
     return SKNR_OK;
   });
 }
@@ -1389,9 +1262,9 @@ int sknr_profile_read(void* ctx, sknr_kprof* out, int32_t max_entries, int32_t* 
     Ctx* c = as_ctx(ctx);
     REQUIRE(count && (out || max_entries == 0), "count (and out) required");
     HIPCHK(hipDeviceSynchronize());
-    c->drain();
+    c->lane.drain();
     int k = 0;
-    for (auto& e : c->prof) {
+    for (auto& e : c->lane.prof) {
       if (k < max_entries) {
         std::memset(&out[k], 0, sizeof(sknr_kprof));
         std::snprintf(out[k].name, sizeof(out[k].name), "%s", e.name.c_str());
@@ -1418,8 +1291,8 @@ int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps, const d
     hipStream_t s = as_stream(stream);
     Prepared P = prepare_caller_orientation(prob, s);
     REQUIRE(ell < std::min(P.n, P.m), "ell must be < min(n, m)");
-    WS w = make_ws(c, P, ell_pad(ell), s);
-    Engine E(c, P, w, s);
+    WS w = make_ws(&c->lane, P, ell_pad(ell), s);
+    Engine E(&c->lane, P, w, s);
     E.eps = eps;
     E.init_state();
     E.load_f(f);

@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
     for required in ("sknr_ctx_create", "sknr_ctx_destroy", "sknr_solve", "sknr_c_transform_row",
                      "sknr_c_transform_col", "sknr_projected_system", "sknr_newton_step",
                      "sknr_spectral_basis", "sknr_evaluate", "sknr_coupling", "sknr_status_str",
-                     "sknr_last_error"):
+                     "sknr_last_error", "sknr_submit", "sknr_poll", "sknr_wait", "sknr_cancel",
+                     "sknr_serve_config", "sknr_serve_stats"):
         assert required in names
 
 
@@ -47,3 +48,11 @@ def test_status_strings_and_null_context():
     assert st == -1
     assert lib.sknr_last_error()
     assert lib.sknr_ctx_destroy(None) == 0
+    # serving calls too
+    t = ctypes.c_uint64()
+    assert lib.sknr_submit(None, None, None, ctypes.byref(t)) == -1
+    d = ctypes.c_int32()
+    assert lib.sknr_poll(None, ctypes.c_uint64(1), ctypes.byref(d)) == -1
+    assert lib.sknr_wait(None, ctypes.c_uint64(1), None, None, None) == -1
+    assert lib.sknr_cancel(None, ctypes.c_uint64(1)) == -1
+    assert lib.sknr_serve_config(None, 1, ctypes.c_uint64(0)) == -1

@@ -210,3 +210,15 @@ def serving_trace(n_requests: int = 2048, rate: float = 100.0, seed: int = 4,
                            problem=Problem(a=a, b=b, x=x, y=y, cost_scale=1.0 / d,
                                            name=f"req{r}_{n}x{m}_d{d}")))
     return out
+
+
+def request_ladder(target: float, eps0: float = 1.0) -> list[float]:
+    """eps schedule of a serving request: halving from eps0 while above the
+    target, then the target itself (Sec. 5 anneals eps from 1 by halving)."""
+    out = [eps0]
+    while out[-1] * 0.5 > target * (1 + 1e-12):
+        out.append(out[-1] * 0.5)
+    if out[-1] > target:
+        out.append(target)
+    return out
+
