@@ -47,6 +47,12 @@ def algorithmic_work(kind: str):
     width = int(kind.rsplit("_l", 1)[1]) if "_l" in kind else 0
     if "stored" in kind:
         return "hbm", 4.0, "GB/s"
+    if "bf16" in kind:
+        # matrix-core cost: the cross term is MFMA work; on the VALU the
+        # cost is finished by one add and one fma (plus one add joining the
+        # two mixed-product chains of the hi/lo split), then the same
+        # exponent, max, exp and accumulation as above
+        return "alu", (9.0 if "bf16x3" in kind else 8.0) + width, "TOP/s"
     return "alu", 10.0 + width, "TOP/s"
 
 
@@ -69,6 +75,99 @@ def kernel_traffic(name):
     if hashlib.sha1(open(src, "rb").read()).hexdigest() != TRAFFIC_KERNEL_SHA1:
         return None
     return TRAFFIC_BYTES.get(name)
+
+
+PEAK_MFMA_BF16_TFLOPS = 2500.0  # dense bf16 matrix-core peak
+
+
+def mfma_sweep_roofline(sk, W, torch, reps=4):
+    """The d = 64 point-cloud sweep (20000 x 30000, cost cross term on
+    bf16 matrix cores with the hi/lo split): per-kernel HIP event timing of
+    column and row c-transforms, VALU fraction against the algorithmic
+    slots per element and matrix-core fraction against the bf16 peak."""
+    prob = W.gaussian_clouds()
+    dev = torch.device("cuda:0")
+    x, y = torch.from_numpy(prob.x).to(dev), torch.from_numpy(prob.y).to(dev)
+    a, b = torch.from_numpy(prob.a).to(dev), torch.from_numpy(prob.b).to(dev)
+    out = {"workload": f"gaussian_clouds {prob.n}x{prob.m} d={prob.d}, one column + one row c-transform per rep"}
+    ctx = sk.Context(0)
+    f = torch.zeros(prob.n, dtype=torch.float64, device=dev)
+    for name, xt in (("bf16x3", sk.XTERM_BF16X3), ("bf16", sk.XTERM_BF16)):
+        gp = sk.Problem(a=a, b=b, x=x, y=y, xterm=xt)
+        g, _, _ = sk.c_transform_col(ctx, gp, 0.1, f)  # warm-up
+        ctx.profile(True)
+        for _ in range(reps):
+            g, _, _ = sk.c_transform_col(ctx, gp, 0.1, f)
+            sk.c_transform_row(ctx, gp, 0.1, g)
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        main = [e for e in prof if e["name"].endswith(":main")][0]
+        avg_s = main["total_ms"] / main["launches"] / 1e3
+        elems = main["units"] / main["launches"]
+        _, slots, _ = algorithmic_work(main["name"])
+        dpad = (prob.d + 31) // 32 * 32
+        flops = 2.0 * dpad * (3 if name == "bf16x3" else 1) * elems
+        out[name] = {"kernel": main["name"], "avg_launch_us": avg_s * 1e6, "elements_per_launch": elems,
+                     "bound": "alu", "achieved": slots * elems / avg_s / 1e12, "peak": PEAK_VALU_TOPS,
+                     "unit": "TOP/s", "frac": slots * elems / avg_s / 1e12 / PEAK_VALU_TOPS,
+                     "work_per_element": slots, "mfma_tflops": flops / avg_s / 1e12,
+                     "mfma_frac": flops / avg_s / 1e12 / PEAK_MFMA_BF16_TFLOPS}
+    ctx.close()
+    return out
+
+
+def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4):
+    """Mixed-request serving: Poisson arrivals, n, m log-uniform on
+    [64, 8192], d in {2, 3, 64}, target eps in {1e-1, 1e-2, 1e-3} reached by
+    halving from 1, l = min(30, min(n, m) - 1).  A closed-loop run (all
+    requests submitted at once) calibrates the arrival rate to 0.8 x the
+    SK-NR capacity; the same arrival trace then runs with SK-NR and with
+    plain SK.  Latency = completion - scheduled arrival."""
+    trace = W.serving_trace(n_requests=n_req, rate=1.0, seed=seed)
+    dev = torch.device("cuda:0")
+    probs = [sk.Problem(a=torch.from_numpy(q.problem.a).to(dev), b=torch.from_numpy(q.problem.b).to(dev),
+                        x=torch.from_numpy(q.problem.x).to(dev), y=torch.from_numpy(q.problem.y).to(dev),
+                        cost_scale=q.problem.cost_scale) for q in trace]
+    torch.cuda.synchronize()
+    base = np.array([q.arrival for q in trace])
+    base = base - base[0]
+
+    def run(nr, rate):
+        ctx = sk.Context(0)
+        sk.serve_config(ctx, max_active=lanes, pool_bytes=8 << 30)
+        arr = base / rate if rate else np.zeros(n_req)
+        t0 = time.monotonic()
+        sub = []
+        for q, gp, ta in zip(trace, probs, arr):
+            wait_s = ta - (time.monotonic() - t0)
+            if wait_s > 0:
+                time.sleep(wait_s)
+            n, m = q.problem.n, q.problem.m
+            tk = sk.submit(ctx, gp, W.request_ladder(q.eps), tol=tol, max_iter=20000,
+                           ell=min(30, min(n, m) - 1) if nr else 0, warm_mode=sk.WARM_SEQUENTIAL, seed=q.rid)
+            sub.append((tk, ta, time.monotonic() - t0))
+        lat, ends, status, iters = [], [], [], []
+        for q, (tk, ta, tret) in zip(trace, sub):
+            _, _, r = sk.wait(ctx, tk, q.problem.n, q.problem.m, raise_on_error=False)
+            l = r["latency_seconds"] + (tret - ta)
+            lat.append(l)
+            ends.append(ta + l)
+            status.append(r["status"])
+            iters.append(r["total_iters"])
+        ctx.close()
+        makespan = max(ends) - arr[0]
+        return {"solves_per_s": n_req / makespan, "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+                "makespan_s": makespan, "converged": int(sum(1 for v in status if v == 0)),
+                "not_converged": int(sum(1 for v in status if v == 1)),
+                "failed": int(sum(1 for v in status if v < 0)), "mean_iters": float(np.mean(iters))}
+
+    closed = run(True, 0.0)
+    rate = 0.8 * closed["solves_per_s"]
+    return {"workload": f"serving_trace {n_req} requests, n,m log-uniform [64,8192], d in {{2,3,64}}, "
+                        f"eps in {{1e-1,1e-2,1e-3}} by halving from 1, tol {tol:g}, l=min(30,min(n,m)-1)",
+            "lanes": lanes, "closed_loop_sknr": closed, "arrival_rate_per_s": rate,
+            "sknr": run(True, rate), "sk": run(False, rate)}
 
 
 def percentile(xs, q):
@@ -169,6 +268,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sk", action="store_true")
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-cost HBM sweep measurement")
+    ap.add_argument("--no-mfma", action="store_true", help="skip the d = 64 matrix-core sweep measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the mixed-request serving run")
+    ap.add_argument("--serve-requests", type=int, default=2048)
+    ap.add_argument("--serve-lanes", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -288,6 +391,10 @@ def main():
                               "total_ms": e["total_ms"]} for e in sorted(prof, key=lambda e: -e["total_ms"])]
     if not args.no_stored:
         out["roofline_stored_cost"] = stored_sweep_roofline(sk, ctx)
+    if not args.no_mfma:
+        out["roofline_mfma_cost"] = mfma_sweep_roofline(sk, W, torch)
+    if not args.no_serve:
+        out["serving"] = serving_bench(sk, W, torch, args.serve_requests, args.serve_lanes, args.tol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, ladder, args.tol, args.ell, iters_nr)
     ctx.close()
