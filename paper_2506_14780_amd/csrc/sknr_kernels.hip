@@ -70,9 +70,9 @@ __global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
 // waves take interleaved reduce rows; per row the reduce-side data
 // (offset potential, point) is a wave-uniform LDS broadcast.  For a stored
 // cost the outputs are columns of the row-major C, so each wave reads
-// 64*CPT*4 contiguous bytes per row.  Per-wave states merge through LDS, the
-// workgroup writes its (sig, S, Sc, acc) partial, and the last workgroup of
-// each column block merges the splits in split order (deterministic).
+// 64*CPT*4 contiguous bytes per row.  Per-wave states merge through LDS and
+// the workgroup writes its (sig, S, Sc, acc) partial; the merge kernel then
+// combines the splits of each output in split order (deterministic).
 // ============================================================================
 template <int CPT, int ELL, int COST, int D, int R, bool SCALE>
 __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {

@@ -163,40 +163,44 @@ __global__ __launch_bounds__(64) void k_orth(const double* part, int nblk, doubl
 
 // ------------------------------------------------------ Rayleigh-Ritz
 // T = U^T diag(b)^-1 U from Gram partials (U = P^T V, V orthonormal in
-// L2(a), so T = V^T D_a M V).  Cyclic Jacobi with a round-robin pairing
-// (k/2 disjoint rotations per step), then eigenpairs sorted descending:
-// Q (k x k, columns = eigenvectors, row-major), lam (k).
+// L2(a), so T = V^T D_a M V).  Cyclic Jacobi with a round-robin pairing:
+// each step rotates k/2 disjoint index pairs at once.  With the pairs of a
+// step, A <- J^T A J splits into independent 2x2 blocks (row pair r,
+// column pair t), so one thread updates one block (and one row pair of the
+// accumulated Q) per step: two barriers per step.  Then eigenpairs sorted
+// descending: Q (k x k, columns = eigenvectors, row-major), lam (k).
 template <int KP>
-__global__ __launch_bounds__(64) void k_jacobi(const double* part, int nblk, double* Qout, double* lam, int sweeps,
-                                               int* sweeps_out) {
+__global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, double* Qout, double* lam, int sweeps,
+                                                int* sweeps_out) {
   constexpr int NE = KP * KP;
   constexpr int NP = KP / 2;
+  constexpr int NT = 256;
   __shared__ double A[KP][KP + 1];
   __shared__ double Q[KP][KP + 1];
   __shared__ double cs[NP][2];
   __shared__ int pr[NP][2];
-  __shared__ double off_s;
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-    double v = sum_parts(part, nblk, NE + KP, e);
-    A[e / KP][e % KP] = v;
+  __shared__ double red[2][NT / 64];
+  __shared__ int stop_s;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NE; e += NT) {
+    A[e / KP][e % KP] = sum_parts(part, nblk, NE + KP, e);
     Q[e / KP][e % KP] = (e / KP == e % KP) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-    int i = e / KP, j = e % KP;
+  for (int e = tid; e < NE; e += NT) {
+    const int i = e / KP, j = e % KP;
     if (i < j) {
-      double v = 0.5 * (A[i][j] + A[j][i]);
+      const double v = 0.5 * (A[i][j] + A[j][i]);
       A[i][j] = v;
       A[j][i] = v;
     }
   }
   __syncthreads();
-  __shared__ double red[2][4];
   int sw = 0;
   for (sw = 0; sw < sweeps; ++sw) {
     double off = 0, dia = 0;
-    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
-      double v = A[e / KP][e % KP];
+    for (int e = tid; e < NE; e += NT) {
+      const double v = A[e / KP][e % KP];
       if (e / KP == e % KP) dia += v * v;
       else off += v * v;
     }
@@ -204,77 +208,85 @@ __global__ __launch_bounds__(64) void k_jacobi(const double* part, int nblk, dou
       off += __shfl_xor(off, o, 64);
       dia += __shfl_xor(dia, o, 64);
     }
-    if ((threadIdx.x & 63) == 0) {
-      red[0][threadIdx.x >> 6] = off;
-      red[1][threadIdx.x >> 6] = dia;
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = off;
+      red[1][tid >> 6] = dia;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       double o2 = 0, d2 = 0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      for (int w = 0; w < NT / 64; ++w) {
         o2 += red[0][w];
         d2 += red[1][w];
       }
       // the basis it rotates is FP32: stop at off-diagonal ~1e-7 relative
-      off_s = o2 <= 1e-14 * d2 ? -1.0 : o2;
+      stop_s = o2 <= 1e-14 * d2 ? 1 : 0;
     }
     __syncthreads();
-    if (off_s < 0) break;
+    if (stop_s) break;
     for (int step = 0; step < KP - 1; ++step) {
-      if ((int)threadIdx.x < NP) {
-        int r = threadIdx.x;
+      if (tid < NP) {
+        const int r = tid;
         auto pos = [&](int i) { return i == 0 ? 0 : 1 + (i - 1 + step) % (KP - 1); };
         int p = pos(r), q = pos(KP - 1 - r);
-        if (p > q) { int t = p; p = q; q = t; }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
         pr[r][0] = p;
         pr[r][1] = q;
-        // rotation angle in FP32 (rsq / rcp); (c, s) normalised in FP64
-        // so that the accumulated Q stays orthogonal to FP64 rounding
-        const double apq = A[p][q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > 1e-300) {
-          const float th = (float)((A[q][q] - A[p][p]) / (2.0 * apq));
+        // rotation angle in FP32; (c, s) normalised to FP64 accuracy (one
+        // Newton step on the FP32 reciprocal square root) so that the
+        // accumulated Q stays orthogonal to FP64 rounding
+        const double apq = A[p][q], dqp = A[q][q] - A[p][p];
+        double c = 1.0, sn = 0.0;
+        if (fabs(apq) > 1e-30 * (fabs(A[p][p]) + fabs(A[q][q])) && fabs(apq) > 1e-300) {
+          const float th = (float)(dqp / (2.0 * apq));
           const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(fmaf(th, th, 1.0f)));
           const double td = (double)t;
-          const double rn = 1.0 / sqrt(1.0 + td * td);
+          const double x = fma(td, td, 1.0);
+          double rn = (double)__frsqrt_rn((float)x);
+          rn = rn * fma(-0.5 * x, rn * rn, 1.5);
           c = rn;
-          s = td * rn;
+          sn = td * rn;
         }
         cs[r][0] = c;
-        cs[r][1] = s;
+        cs[r][1] = sn;
       }
       __syncthreads();
-      // columns: A <- A J, Q <- Q J
-      for (int e = threadIdx.x; e < NP * KP; e += blockDim.x) {
-        int r = e / KP, i = e % KP;
-        int p = pr[r][0], q = pr[r][1];
-        double c = cs[r][0], s = cs[r][1];
-        double aip = A[i][p], aiq = A[i][q];
-        A[i][p] = c * aip - s * aiq;
-        A[i][q] = s * aip + c * aiq;
-        double qip = Q[i][p], qiq = Q[i][q];
-        Q[i][p] = c * qip - s * qiq;
-        Q[i][q] = s * qip + c * qiq;
+      // A <- J^T A J by 2x2 blocks; J acts on columns (p, q) as
+      // (p, q) -> (c p - s q, s p + c q) and the same on rows
+      for (int b = tid; b < NP * NP; b += NT) {
+        const int r = b / NP, t = b % NP;
+        const int p = pr[r][0], q = pr[r][1], u = pr[t][0], v = pr[t][1];
+        const double cr = cs[r][0], sr = cs[r][1], ct = cs[t][0], st = cs[t][1];
+        const double b00 = A[p][u], b01 = A[p][v], b10 = A[q][u], b11 = A[q][v];
+        const double c00 = ct * b00 - st * b01, c01 = st * b00 + ct * b01;
+        const double c10 = ct * b10 - st * b11, c11 = st * b10 + ct * b11;
+        A[p][u] = cr * c00 - sr * c10;
+        A[p][v] = cr * c01 - sr * c11;
+        A[q][u] = sr * c00 + cr * c10;
+        A[q][v] = sr * c01 + cr * c11;
       }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int e = threadIdx.x; e < NP * KP; e += blockDim.x) {
-        int r = e / KP, j = e % KP;
-        int p = pr[r][0], q = pr[r][1];
-        double c = cs[r][0], s = cs[r][1];
-        double apj = A[p][j], aqj = A[q][j];
-        A[p][j] = c * apj - s * aqj;
-        A[q][j] = s * apj + c * aqj;
+      // Q <- Q J: row i, column pair t
+      for (int e = tid; e < KP * NP; e += NT) {
+        const int i = e / NP, t = e % NP;
+        const int u = pr[t][0], v = pr[t][1];
+        const double ct = cs[t][0], st = cs[t][1];
+        const double qiu = Q[i][u], qiv = Q[i][v];
+        Q[i][u] = ct * qiu - st * qiv;
+        Q[i][v] = st * qiu + ct * qiv;
       }
       __syncthreads();
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && sweeps_out) *sweeps_out = sw;
+  if (tid == 0 && sweeps_out) *sweeps_out = sw;
   // descending order: rank of each eigenvalue (ties by index), in parallel
   __shared__ int order[KP];
-  if ((int)threadIdx.x < KP) {
-    const int i = threadIdx.x;
+  if (tid < KP) {
+    const int i = tid;
     const double li = A[i][i];
     int rank = 0;
     for (int j = 0; j < KP; ++j) {
@@ -284,10 +296,10 @@ __global__ __launch_bounds__(64) void k_jacobi(const double* part, int nblk, dou
     order[rank] = i;
   }
   __syncthreads();
-  if ((int)threadIdx.x < KP) {
-    const int r = threadIdx.x;
-    lam[r] = A[order[r]][order[r]];
-    for (int i = 0; i < KP; ++i) Qout[r * KP + i] = Q[r][order[i]];
+  if (tid < KP) lam[tid] = A[order[tid]][order[tid]];
+  for (int e = tid; e < NE; e += NT) {
+    const int r = e / KP, i = e % KP;
+    Qout[r * KP + i] = Q[r][order[i]];
   }
 }
 
@@ -370,9 +382,9 @@ hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* 
 }
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
                          hipStream_t s) {
-  if (kp == 8) hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 10, sweeps_out);
-  else if (kp == 16) hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 10, sweeps_out);
-  else hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, 10, sweeps_out);
+  if (kp == 8) hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out);
+  else if (kp == 16) hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out);
+  else hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out);
   return hipGetLastError();
 }
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
