@@ -59,20 +59,24 @@ def algorithmic_work(kind: str):
 # HBM bytes per launch of the main sweep kernels from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the counts of a
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2.0, WRITE_SIZE 1 GiB
-# -> x1.0); see profiles/.  Valid only for the kernel source they were
-# taken with.
-TRAFFIC_KERNEL_SHA1 = "b75ca5e76b9c3f7a14c86b5033379db385aab648"
+# -> x1.0); see profiles/.  Valid only for the kernel sources they were
+# taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip).
+TRAFFIC_KERNEL_SHA1 = "13e54225dd2c30907e77981ea69078b661342eee"
 TRAFFIC_BYTES = {
-    "sweep_stream_points_l0:main": (193.79 * 2.0 + 1836.06) * 1024,
-    "sweep_stream_stored_l0:main": (524897.39 * 2.0 + 6144.0) * 1024,
-    "sweep_rows_stored_l0:main": (525912.11 * 2.0 + 529.54) * 1024,
+    "sweep_stream_points_l0:main": (196.22 * 1.9999 + 1857.49) * 1024,
+    "sweep_stream_stored_l0:main": (524899.89 * 1.9999 + 6144.00) * 1024,
+    "sweep_rows_stored_l0:main": (525907.24 * 1.9999 + 530.76) * 1024,
+    "sweep_stream_points_bf16x3_l0:main": (91282.29 * 1.9999 + 6224.01) * 1024,
+    "sweep_stream_points_bf16_l0:main": (25511.56 * 1.9999 + 6223.96) * 1024,
 }
 
 
 def kernel_traffic(name):
     import hashlib
-    src = os.path.join(ROOT, "paper_2506_14780_amd", "csrc", "sknr_kernels.hip")
-    if hashlib.sha1(open(src, "rb").read()).hexdigest() != TRAFFIC_KERNEL_SHA1:
+    h = hashlib.sha1()
+    for f in ("sknr_device.h", "sknr_kernels.hip", "sknr_mfma.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2506_14780_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != TRAFFIC_KERNEL_SHA1:
         return None
     return TRAFFIC_BYTES.get(name)
 
@@ -111,7 +115,8 @@ def mfma_sweep_roofline(sk, W, torch, reps=4):
         out[name] = {"kernel": main["name"], "avg_launch_us": avg_s * 1e6, "elements_per_launch": elems,
                      "bound": "alu", "achieved": slots * elems / avg_s / 1e12, "peak": PEAK_VALU_TOPS,
                      "unit": "TOP/s", "frac": slots * elems / avg_s / 1e12 / PEAK_VALU_TOPS,
-                     "work_per_element": slots, "mfma_tflops": flops / avg_s / 1e12,
+                     "work_per_element": slots, "traffic": kernel_traffic(main["name"]),
+                     "mfma_tflops": flops / avg_s / 1e12,
                      "mfma_frac": flops / avg_s / 1e12 / PEAK_MFMA_BF16_TFLOPS}
     ctx.close()
     return out
