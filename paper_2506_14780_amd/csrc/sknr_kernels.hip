@@ -85,7 +85,11 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r0 = blockIdx.y * A.rows_per_split;
   const int nr = min(A.rows_per_split, A.n_red - r0);
-  const int d = (COST == 1 && D > 0) ? D : A.d;
+  // points: dg coordinates in memory; d = the compile-time width D >= dg
+  // (rows zero-padded in LDS and registers, which leaves the FP32 cost
+  // unchanged: the padded terms are fma(0, 0, acc)), or dg when D == 0
+  const int dg = A.d;
+  const int d = (COST == 1 && D > 0) ? D : dg;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
   const float L = 2.f * (A.cmax + A.st->maxabs[A.ma_in]);
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
     s.y += u.y;
     sU[t] = fast_two_sum(s.x, s.y);
     if (COST == 1) {
-      for (int k = 0; k < d; ++k) sX[t * d + k] = A.Pred[(size_t)(r0 + t) * d + k];
+      for (int k = 0; k < d; ++k) sX[t * d + k] = k < dg ? A.Pred[(size_t)(r0 + t) * dg + k] : 0.f;
     }
   }
   __syncthreads();
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
       int col = min(colbase + c, A.n_out - 1);
       if (D > 0) {
 #pragma unroll
-        for (int k = 0; k < DD; ++k) q[c][k] = A.Pout[(size_t)col * DD + k];
+        for (int k = 0; k < DD; ++k) q[c][k] = k < dg ? A.Pout[(size_t)col * dg + k] : 0.f;
       }
       ccol[c] = col;
     }
@@ -491,19 +495,30 @@ __global__ __launch_bounds__(TPB) void k_sweep_rows(SweepArgs A) {
 }
 
 // ----------------------------------------------------------- launch config
+// LDS / register width of the points of a streaming sweep: d itself up to
+// 8 (one kernel per d), else padded to 16, 32 or 64, else d (generic loop)
+static int point_width(int d) {
+  if (d <= 8) return d;
+  if (d <= 16) return 16;
+  if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  return d;
+}
+
 static int rps_max(int cost_kind, int d) {
   if (cost_kind == 0) return 4096;                   // 8 B per row of LDS
-  int per = 8 + 4 * d;
+  int per = 8 + 4 * point_width(d);
   int cap = (40 * 1024) / per;
   return cap < 16 ? 16 : cap;
 }
 
 // outputs per thread of the streaming sweep (shared by sizing and launch)
-static int stream_cpt(int cost_kind, int ell, bool vec) {
+static int stream_cpt(int cost_kind, int ell, bool vec, int d) {
   if (cost_kind == 0) {
     if (ell > 16) return 2;
     return vec ? 4 : 1;
   }
+  if (d > 8 && d <= 64) return 1;  // padded widths: the points of one output fill the registers
   return ell > 0 ? 2 : 4;
 }
 
@@ -517,7 +532,7 @@ size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bo
     *nblk = (n_out + rpw - 1) / rpw;
     return 0;
   }
-  int cpt = stream_cpt(cost_kind, ell, vec);
+  int cpt = stream_cpt(cost_kind, ell, vec, d);
   int nc = 64 * cpt;
   int ncb = (n_out + nc - 1) / nc;
   // split-K geometry: about `target` workgroups, at least `rmin` reduce
@@ -546,7 +561,7 @@ static hipError_t go_stream(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
   constexpr int NC = 64 * CPT;
   int ncb = (a.n_out + NC - 1) / NC;
   dim3 grid(ncb, a.nsplit);
-  size_t rows_bytes = (size_t)a.rows_per_split * (8 + (COST == 1 ? 4 * a.d : 0));
+  size_t rows_bytes = (size_t)a.rows_per_split * (8 + (COST == 1 ? 4 * (D > 0 ? D : a.d) : 0));
   size_t cmb_bytes = (size_t)(3 + ELL) * NC * 4;
   size_t sm = rows_bytes > cmb_bytes ? rows_bytes : cmb_bytes;
   bool scale = (COST == 1) && a.cscale != 1.0f;
@@ -571,7 +586,11 @@ static hipError_t go_stream_points(const SweepArgs& a, hipStream_t s, hipEvent_t
     case 6: return go_stream<CPT, ELL, 1, 6, 2>(a, s, mid);
     case 7: return go_stream<CPT, ELL, 1, 7, 2>(a, s, mid);
     case 8: return go_stream<CPT, ELL, 1, 8, 2>(a, s, mid);
-    default: return go_stream<CPT, ELL, 1, 0, 2>(a, s, mid);
+    default:
+      if (a.d <= 16) return go_stream<1, ELL, 1, 16, 2>(a, s, mid);
+      if (a.d <= 32) return go_stream<1, ELL, 1, 32, 2>(a, s, mid);
+      if (a.d <= 64) return go_stream<1, ELL, 1, 64, 2>(a, s, mid);
+      return go_stream<CPT, ELL, 1, 0, 2>(a, s, mid);
   }
 }
 
@@ -587,7 +606,7 @@ hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t s) {
 
 hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t s, hipEvent_t mid) {
   if (cost_kind >= 2) return launch_sweep_mfma(a, cost_kind == 3, s, mid);
-  const int cpt = stream_cpt(cost_kind, a.ell, vec);
+  const int cpt = stream_cpt(cost_kind, a.ell, vec, a.d);
   if (cost_kind == 0) {
     if (a.ell == 0) return cpt == 4 ? go_stream<4, 0, 0, 1, 8>(a, s, mid) : go_stream<1, 0, 0, 1, 8>(a, s, mid);
     if (a.ell <= 8) return cpt == 4 ? go_stream<4, 8, 0, 1, 4>(a, s, mid) : go_stream<1, 8, 0, 1, 4>(a, s, mid);

@@ -76,7 +76,8 @@ def test_c_transforms_stored_cost(sk, ctx, n, m, eps):
     assert df.max() <= tol
 
 
-@pytest.mark.parametrize("n,m,d", [(1000, 1500, 2), (777, 513, 3), (300, 2100, 5), (257, 300, 12)])
+@pytest.mark.parametrize("n,m,d", [(1000, 1500, 2), (777, 513, 3), (300, 2100, 5), (257, 300, 12), (300, 700, 40),
+                                   (200, 333, 70)])
 @pytest.mark.parametrize("eps", [1e-1, 1e-3])
 def test_c_transforms_points(sk, ctx, n, m, d, eps):
     rng = np.random.default_rng(d * 100 + n)
@@ -88,6 +89,7 @@ def test_c_transforms_points(sk, ctx, n, m, d, eps):
     Ct = fp32_sqeuclid(x, y, prob.cost_scale).astype(np.float64)   # the GPU's FP32 cost
     C = O.sqeuclid_cost(x, y, prob.cost_scale)                      # exact cost
     gp = gpu_problem(prob)
+    gp.xterm = sk.XTERM_FP32  # the FP32 cost modelled above (AUTO would pick bf16 for d >= 16)
     f = 0.2 * rng.standard_normal(n)
     print(f"case points n={n} m={m} d={d} eps={eps}", flush=True)
     g_gpu, _, _ = sk.c_transform_col(ctx, gp, eps, to_dev(f))
