@@ -58,7 +58,7 @@ def bf16_rne(v):
     return u.astype(np.uint32).view(np.float32)
 
 
-def bf16_cost_model(x, y, scale=1.0, x3=True):
+def bf16_cost_model(x, y, scale=1.0, x3=True, mu_points=None):
     """The matrix-core cost as the library defines it, in FP64, with a
     rigorous per-element bound on the GPU's deviation from it.
 
@@ -68,12 +68,16 @@ def bf16_cost_model(x, y, scale=1.0, x3=True):
     The GPU forms the dot product on matrix cores (FP32 accumulation, any
     order: error <= (N - 1) u sum|terms| over N products), adds the norms in
     FP32 and applies one fma: bound = 2 s N u T_ij + 2 u (n_i + n_j) + u |C_ij|
-    (the second term also covers a last-bit difference of the FP64 norm)."""
+    (the second term also covers a last-bit difference of the FP64 norm).
+    mu_points: the full point sets (x, y) when x or y is only a subset of
+    the rows of the problem (the centre is taken over all points)."""
     x = np.asarray(x, np.float32)
     y = np.asarray(y, np.float32)
     d = x.shape[1]
     dpad = (d + 31) // 32 * 32
-    mu = bf16_rne(np.float32(np.concatenate([x, y]).astype(np.float64).mean(axis=0)))
+    px, py = mu_points if mu_points is not None else (x, y)
+    mu = bf16_rne(np.float32(np.concatenate([np.asarray(px, np.float32), np.asarray(py, np.float32)])
+                             .astype(np.float64).mean(axis=0)))
 
     def split(p):
         v = (p - mu).astype(np.float32)
