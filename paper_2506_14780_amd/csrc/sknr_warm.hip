@@ -99,24 +99,31 @@ __global__ __launch_bounds__(256) void k_wgram(const float* Z, const double* wgt
 // update spread over the lanes, then column j of L^-1 by lane j with
 // broadcast LDS reads of L.
 template <int KP>
-__global__ __launch_bounds__(64) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out) {
+__global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out) {
   constexpr int NE = KP * KP;
+  constexpr int NT = 256;
   __shared__ double B[KP][KP + 1];
   __shared__ double s[KP];
+  __shared__ double lcol[KP];
+  __shared__ double tr_s;
   __shared__ int ok_s;
-  const int lane = threadIdx.x;
-  for (int e = lane; e < NE + KP; e += 64) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NE + KP; e += NT) {
     double v = sum_parts(part, nblk, NE + KP, e);
     if (e < NE) B[e / KP][e % KP] = v;
     else s[e - NE] = v;
   }
-  if (lane == 0) ok_s = 1;
+  if (tid == 0) ok_s = 1;
   __syncthreads();
-  double tr = 0;
-#pragma unroll
-  for (int k = 0; k < KP; ++k) tr += B[k][k] - s[k] * s[k];
+  if (tid == 0) {
+    double tr = 0;
+    for (int k = 0; k < KP; ++k) tr += B[k][k] - s[k] * s[k];
+    tr_s = tr;
+  }
+  __syncthreads();
+  const double tr = tr_s;
   // B' = sym(B) - s s^T (+ tiny ridge), lower triangle suffices
-  for (int e = lane; e < NE; e += 64) {
+  for (int e = tid; e < NE; e += NT) {
     const int i = e / KP, j = e % KP;
     if (j <= i) {
       double v = 0.5 * (B[i][j] + B[j][i]) - s[i] * s[j];
@@ -125,27 +132,30 @@ __global__ __launch_bounds__(64) void k_orth(const double* part, int nblk, doubl
     }
   }
   __syncthreads();
+  // right-looking Cholesky: column k of L from the current B, then the
+  // trailing update; two barriers per column
   for (int k = 0; k < KP; ++k) {
-    double d = B[k][k];
-    if (!(d > 1e-30 * tr)) {
-      d = 1e-30 * tr + 1e-300;
-      if (lane == 0) ok_s = 0;
+    if (tid >= k && tid < KP) {
+      double d = B[k][k];
+      if (!(d > 1e-30 * tr)) {
+        d = 1e-30 * tr + 1e-300;
+        if (tid == k) ok_s = 0;
+      }
+      const double lk = sqrt(d);
+      lcol[tid] = tid == k ? lk : B[tid][k] / lk;
     }
-    const double lk = sqrt(d), inv = 1.0 / lk;
-    __syncthreads();
-    if (lane == 0) B[k][k] = lk;
-    for (int i = k + 1 + lane; i < KP; i += 64) B[i][k] *= inv;
     __syncthreads();
     const int rem = KP - 1 - k;
-    for (int e = lane; e < rem * rem; e += 64) {
+    for (int e = tid; e < rem * rem; e += NT) {
       const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j <= i) B[i][j] -= B[i][k] * B[j][k];
+      if (j <= i) B[i][j] -= lcol[i] * lcol[j];
     }
+    if (tid >= k && tid < KP) B[tid][k] = lcol[tid];
     __syncthreads();
   }
-  // L^-1, column j by lane j: x_r = (delta_rj - sum_{t<r} L_rt x_t) / L_rr
-  if (lane < KP) {
-    const int j = lane;
+  // L^-1, column j by thread j: x_r = (delta_rj - sum_{t<r} L_rt x_t) / L_rr
+  if (tid < KP) {
+    const int j = tid;
     double x[KP];
 #pragma unroll
     for (int r = 0; r < KP; ++r) {
@@ -158,7 +168,7 @@ __global__ __launch_bounds__(64) void k_orth(const double* part, int nblk, doubl
     for (int t = 0; t < KP; ++t) R[j * KP + t] = x[t];  // R = L^-T
     s_out[j] = s[j];
   }
-  if (lane == 0) *ok_out = ok_s;
+  if (tid == 0) *ok_out = ok_s;
 }
 
 // ------------------------------------------------------ Rayleigh-Ritz
@@ -375,9 +385,9 @@ hipError_t launch_wgram(int kp, const float* Z, const double* w, int invert, int
   return hipGetLastError();
 }
 hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok, hipStream_t s) {
-  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok);
-  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok);
-  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok);
+  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
+  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
+  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
   return hipGetLastError();
 }
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
