@@ -1,0 +1,64 @@
+"""Precision of the cross-term modes on the d = 64 point-cloud workload
+(20000 x 30000, x ~ N(0, I), y ~ N(0.5 e1, I), raw squared distance), per
+eps, against the FP64 oracle on the exact cost.
+
+For a fixed f, the GPU column c-transform g = T_c(f) is compared on sampled
+columns with the oracle's T_c on the exact FP64 cost of the FP32 points.  A
+c-transform is 1-Lipschitz in the sup norm of the cost, so |dg_j| is bounded
+by max_i |C~_ij - C_ij|, which the test bounds per mode:
+  FP32 (sequential fma order): d u sum_k t_k^2 (+ rounding of the LSE),
+  BF16 / BF16X3: the matrix-core model bound plus |C_model - C| (the
+  representation error of the bf16 split), computed exactly per element.
+The relative error of the coupling weights is then |exp(dg/eps) - 1|,
+which grows as eps falls: the table printed here is the precision study
+(cost error stated per eps and mode).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests._helpers import U32, bf16_cost_model, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2506_14780_amd as sk
+    return sk
+
+
+def test_cost_precision_study_d64(sk):
+    prob = W.gaussian_clouds()
+    x, y = prob.x, prob.y
+    cols = np.sort(np.random.default_rng(5).choice(prob.m, size=24, replace=False))
+    Cx = O.sqeuclid_cost(x.astype(np.float64), y[cols].astype(np.float64))  # exact, n x 24
+    rng = np.random.default_rng(8)
+    f = 0.05 * rng.standard_normal(prob.n)
+    ctx = sk.Context(0)
+    modes = {"FP32": sk.XTERM_FP32, "BF16X3": sk.XTERM_BF16X3, "BF16": sk.XTERM_BF16}
+    bounds = {}
+    for name in ("BF16X3", "BF16"):
+        Cm, bnd = bf16_cost_model(x, y[cols], 1.0, name == "BF16X3", mu_points=(x, y))
+        bounds[name] = (bnd + np.abs(Cm - Cx)).max()
+    # FP32 sequential sum of d squares: |fl - exact| <= (d - 1) u sum t_k^2 (+ rounding of each t_k)
+    bounds["FP32"] = (x.shape[1] + 2) * U32 * Cx.max()
+    rows = []
+    for eps in (1e-1, 1e-2, 2e-3):
+        g_ref = O.c_transform_col(f, Cx, prob.a, eps)
+        for name, xt in modes.items():
+            gp = sk.Problem(a=to_dev(prob.a), b=to_dev(prob.b), x=to_dev(x), y=to_dev(y), xterm=xt)
+            g = sk.c_transform_col(ctx, gp, eps, to_dev(f))[0].cpu().numpy()[cols]
+            dg = np.abs(g - g_ref).max()
+            rel_w = np.expm1(dg / eps)
+            rows.append((eps, name, dg, rel_w, bounds[name]))
+            print(f"eps={eps:<7g} {name:7s} max|dg|={dg:.3e}  coupling weight error ~{rel_w:.2e}  "
+                  f"bound on max|C~-C| {bounds[name]:.3e}", flush=True)
+            assert dg <= bounds[name] + 64 * U32 * eps + 1e-12 * np.abs(g_ref).max()
+    ctx.close()
+    # the matrix-core split stays within an order of magnitude of FP32 and
+    # far below plain bf16 at every eps
+    for eps in (1e-1, 1e-2, 2e-3):
+        e = {r[1]: r[2] for r in rows if r[0] == eps}
+        assert e["BF16X3"] < e["BF16"] / 30
