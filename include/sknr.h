@@ -70,17 +70,26 @@ enum sknr_cost_kind {
  * x.y products on bf16 matrix cores with FP32 accumulation, from one bf16
  * term per coordinate (BF16) or a hi/lo bf16 split keeping hi*hi + hi*lo +
  * lo*hi (BF16X3).  AUTO picks FP32 for d < 16 and BF16X3 for d >= 16. */
-enum sknr_xterm { SKNR_XTERM_AUTO = 0, SKNR_XTERM_FP32 = 1, SKNR_XTERM_BF16 = 2, SKNR_XTERM_BF16X3 = 3 };
-/* Matrix-core cost in detail (BF16, BF16X3): the points are centred on mu,
- * the FP64 mean of all n + m points rounded to bf16; v = fl32(x - mu) is
- * rounded to bf16 hi = bf16(v) (and lo = bf16(v - hi) for BF16X3, x~ = hi
- * + lo; for BF16 x~ = hi); per point n_i = fl32(cost_scale * ||x~_i||^2)
- * with the norm summed in FP64; and
+enum sknr_xterm {
+  SKNR_XTERM_AUTO = 0,
+  SKNR_XTERM_FP32 = 1,
+  SKNR_XTERM_BF16 = 2,
+  SKNR_XTERM_BF16X3 = 3,
+  SKNR_XTERM_BF16X6 = 4  /* hi + mid + lo bf16 split: hi*hi + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid */
+};
+/* Matrix-core cost in detail (BF16, BF16X3, BF16X6): the points are
+ * centred on mu, the FP64 mean of all n + m points rounded to bf16;
+ * v = fl32(x - mu) is rounded to bf16 hi = bf16(v) (x~ = hi for BF16);
+ * BF16X3 adds lo = bf16(v - hi) (x~ = hi + lo); BF16X6 adds mid =
+ * bf16(v - hi) and lo = bf16(v - hi - mid) (x~ = hi + mid + lo); per point
+ * n_i = fl32(cost_scale * ||x~_i||^2) with the norm summed in FP64; and
  *   C~_ij = fma(-2 fl32(cost_scale), x~_i . y~_j, n_i + n_j)
  * in FP32 with the dot product on matrix cores (FP32 accumulation, any
- * order; |error| <= (dpad - 1) u sum_k |x~_ik y~_jk|, dpad = d rounded up
- * to 32, u = 2^-24), omitting lo*lo for BF16X3.  C~ is symmetric in the
- * roles of x and y, so both c-transforms use the same matrix. */
+ * order; |error| <= (N - 1) u sum |products| over the N kept products,
+ * dpad = d rounded up to 32, u = 2^-24), keeping hi*hi + hi*lo + lo*hi
+ * (BF16X3) or hi*hi + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid (BF16X6).
+ * C~ is symmetric in the roles of x and y, so both c-transforms use the
+ * same matrix. */
 
 typedef struct sknr_problem {
   int64_t n;            /* number of source points / size of a (n >= 1) */

@@ -16,7 +16,7 @@ __all__ = [
     "lib", "Context", "Problem", "solve", "c_transform_row", "c_transform_col",
     "projected_system", "newton_step", "spectral_basis", "evaluate", "coupling",
     "SknrError", "COST_STORED", "COST_SQEUCLID", "XTERM_AUTO", "XTERM_FP32",
-    "XTERM_BF16", "XTERM_BF16X3", "WARM_SEQUENTIAL", "WARM_STATIC", "WARM_USER",
+    "XTERM_BF16", "XTERM_BF16X3", "XTERM_BF16X6", "WARM_SEQUENTIAL", "WARM_STATIC", "WARM_USER",
     "LIB_PATH", "MAX_STAGES", "MAX_ELL", "serve_config", "submit", "poll", "wait", "cancel",
     "serve_stats", "OK", "NOT_CONVERGED", "EINVAL", "ENOMEM", "EDEVICE", "EBUSY", "ECANCELED", "EINTERNAL",
 ]
@@ -33,7 +33,7 @@ lib = ctypes.CDLL(LIB_PATH)
 MAX_STAGES = 32
 MAX_ELL = 32
 COST_STORED, COST_SQEUCLID = 0, 1
-XTERM_AUTO, XTERM_FP32, XTERM_BF16, XTERM_BF16X3 = 0, 1, 2, 3
+XTERM_AUTO, XTERM_FP32, XTERM_BF16, XTERM_BF16X3, XTERM_BF16X6 = 0, 1, 2, 3, 4
 WARM_SEQUENTIAL, WARM_STATIC, WARM_USER = 0, 1, 2
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EDEVICE, EBUSY, ECANCELED, EINTERNAL = -1, -2, -3, -4, -5, -6

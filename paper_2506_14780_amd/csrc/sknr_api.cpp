@@ -54,7 +54,7 @@ struct WS {
   int* okw;
   bool have_Vw;
   // packed points of the matrix-core cost (engine orientation)
-  unsigned short *HX, *LX, *HY, *LY;
+  unsigned short *HX, *MX, *LX, *HY, *MY, *LY;
   float *NX, *NY, *mu;
   // sweep geometry
   int ns_c, rps_c, nb_c, ns_r, rps_r, nb_r, ns_cw, rps_cw, nb_cw;
@@ -62,7 +62,8 @@ struct WS {
 
 int ell_pad(int ell) { return ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32)); }
 
-// cost kind of the sweep kernels: 0 stored, 1 points FP32, 2 bf16, 3 bf16 split
+// cost kind of the sweep kernels: 0 stored, 1 points FP32, 2 bf16, 3 bf16
+// hi/lo split, 4 bf16 hi/mid/lo split (bf16 parts = kind - 1)
 int sweep_kind(const Prepared& P) { return P.kind == SKNR_COST_STORED ? 0 : P.xmode; }
 
 bool col_is_stream(const Prepared& P) { return P.kind == SKNR_COST_SQEUCLID || !P.ctrans; }
@@ -114,7 +115,7 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s) {
     REQUIRE(sc > 0 && std::isfinite(sc), "cost_scale must be positive");
     P.cscale = (float)sc;
     P.cscale64 = sc;
-    REQUIRE(pr->xterm >= SKNR_XTERM_AUTO && pr->xterm <= SKNR_XTERM_BF16X3, "unknown xterm");
+    REQUIRE(pr->xterm >= SKNR_XTERM_AUTO && pr->xterm <= SKNR_XTERM_BF16X6, "unknown xterm");
     P.xmode = pr->xterm == SKNR_XTERM_AUTO ? (pr->d >= 16 ? SKNR_XTERM_BF16X3 : SKNR_XTERM_FP32) : pr->xterm;
     if (P.xmode >= SKNR_XTERM_BF16) P.dpad = (pr->d + 31) & ~31;
     P.X = P.transposed ? pr->y : pr->x;
@@ -239,7 +240,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
     add(sizeof(double) * 32 * 32 * 2 + sizeof(double) * 64 + 64);
   }
   if (P.xmode >= SKNR_XTERM_BF16) {
-    const int parts = P.xmode == SKNR_XTERM_BF16X3 ? 2 : 1;
+    const int parts = P.xmode - 1;
     add(sizeof(unsigned short) * (size_t)n * P.dpad * parts);
     add(sizeof(unsigned short) * (size_t)m * P.dpad * parts);
     add(sizeof(float) * n);
@@ -335,22 +336,27 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
     w.lamw = (double*)A.take(sizeof(double) * 32);
     w.okw = (int*)A.take(64);
   }
-  w.HX = w.LX = w.HY = w.LY = nullptr;
+  w.HX = w.MX = w.LX = w.HY = w.MY = w.LY = nullptr;
   w.NX = w.NY = w.mu = nullptr;
   if (P.xmode >= SKNR_XTERM_BF16) {
-    const bool x3 = P.xmode == SKNR_XTERM_BF16X3;
-    w.HX = (unsigned short*)A.take(sizeof(unsigned short) * (size_t)n * P.dpad);
-    w.HY = (unsigned short*)A.take(sizeof(unsigned short) * (size_t)m * P.dpad);
-    if (x3) {
-      w.LX = (unsigned short*)A.take(sizeof(unsigned short) * (size_t)n * P.dpad);
-      w.LY = (unsigned short*)A.take(sizeof(unsigned short) * (size_t)m * P.dpad);
+    const int parts = P.xmode - 1;
+    auto pk = [&](int np) { return (unsigned short*)A.take(sizeof(unsigned short) * (size_t)np * P.dpad); };
+    w.HX = pk(n);
+    w.HY = pk(m);
+    if (parts == 3) {
+      w.MX = pk(n);
+      w.MY = pk(m);
+    }
+    if (parts >= 2) {
+      w.LX = pk(n);
+      w.LY = pk(m);
     }
     w.NX = (float*)A.take(sizeof(float) * n);
     w.NY = (float*)A.take(sizeof(float) * m);
     w.mu = (float*)A.take(sizeof(float) * P.d);
     HIPCHK(hipMemcpyAsync(w.mu, P.mu.data(), sizeof(float) * P.d, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_pack_points(P.X, n, P.d, w.mu, P.cscale64, P.dpad, x3, w.HX, w.LX, w.NX, s));
-    HIPCHK(launch_pack_points(P.Y, m, P.d, w.mu, P.cscale64, P.dpad, x3, w.HY, w.LY, w.NY, s));
+    HIPCHK(launch_pack_points(P.X, n, P.d, w.mu, P.cscale64, P.dpad, parts, w.HX, w.MX, w.LX, w.NX, s));
+    HIPCHK(launch_pack_points(P.Y, m, P.d, w.mu, P.cscale64, P.dpad, parts, w.HY, w.MY, w.LY, w.NY, s));
   }
   // weights and log-weights (host FP64 log, uploaded)
   std::vector<float> fx(n), fy(m);
@@ -415,7 +421,7 @@ struct Engine {
     if (c->profile) {
       HIPCHK(hipEventRecord(e1, s));
       char nm[96];
-      static const char* kinds[4] = {"stored", "points", "points_bf16", "points_bf16x3"};
+      static const char* kinds[5] = {"stored", "points", "points_bf16", "points_bf16x3", "points_bf16x6"};
       std::snprintf(nm, sizeof nm, "%s_%s%s_l%d", stream_kernel ? "sweep_stream" : "sweep_rows",
                     kinds[sweep_kind(P)], (sweep_kind(P) == 1 && P.d > 8) ? "_gen" : "",
                     ell <= 0 ? 0 : ell_pad(ell));
@@ -436,9 +442,11 @@ struct Engine {
     a.Pred = P.X;
     a.Pout = P.Y;
     a.Hred = (const uint4*)w.HX;
+    a.Mred = (const uint4*)w.MX;
     a.Lred = (const uint4*)w.LX;
     a.Nred = w.NX;
     a.Hout = (const uint4*)w.HY;
+    a.Mout = (const uint4*)w.MY;
     a.Lout = (const uint4*)w.LY;
     a.Nout = w.NY;
     a.Uin = Fin;
@@ -474,9 +482,11 @@ struct Engine {
     a.Pred = P.Y;
     a.Pout = P.X;
     a.Hred = (const uint4*)w.HY;
+    a.Mred = (const uint4*)w.MY;
     a.Lred = (const uint4*)w.LY;
     a.Nred = w.NY;
     a.Hout = (const uint4*)w.HX;
+    a.Mout = (const uint4*)w.MX;
     a.Lout = (const uint4*)w.LX;
     a.Nout = w.NX;
     a.Uin = Gin;
@@ -708,9 +718,11 @@ struct Engine {
     geo.m2cs = -2.f * P.cscale;
     const bool sw = P.transposed;  // engine side X holds the caller's y
     geo.Hred = (const uint4*)(sw ? w.HY : w.HX);
+    geo.Mred = (const uint4*)(sw ? w.MY : w.MX);
     geo.Lred = (const uint4*)(sw ? w.LY : w.LX);
     geo.Nred = sw ? w.NY : w.NX;
     geo.Hout = (const uint4*)(sw ? w.HX : w.HY);
+    geo.Mout = (const uint4*)(sw ? w.MX : w.MY);
     geo.Lout = (const uint4*)(sw ? w.LX : w.LY);
     geo.Nout = sw ? w.NX : w.NY;
     return geo;
@@ -721,9 +733,9 @@ struct Engine {
   sknr_eval evaluate(const sknr_problem* pr, const double* f, const double* g, bool exact = false) {
     SweepArgs geo = caller_geo(pr);
     int nrb, ncb;
-    const int kind = (exact && P.kind == SKNR_COST_SQEUCLID) ? 4 : sweep_kind(P);
-    if (kind == 2 || kind == 3)
-      HIPCHK(launch_eval_mfma(geo, kind == 3, f, g, pr->a, pr->b, eps, w.evrow, w.evcol, w.evscal, P.n0, P.m0,
+    const int kind = (exact && P.kind == SKNR_COST_SQEUCLID) ? kEvalExact : sweep_kind(P);
+    if (kind >= 2 && kind <= 4)
+      HIPCHK(launch_eval_mfma(geo, kind - 1, f, g, pr->a, pr->b, eps, w.evrow, w.evcol, w.evscal, P.n0, P.m0,
                               &nrb, &ncb, s));
     else
       HIPCHK(launch_eval(geo, kind, f, g, pr->a, pr->b, eps, w.evrow, w.evcol, w.evscal, P.n0, P.m0, &nrb, &ncb, s));
@@ -1237,8 +1249,8 @@ int sknr_coupling(void* ctx, const sknr_problem* prob, double eps, const double*
     Engine E(&c->lane, P, w, s);
     SweepArgs geo = E.caller_geo(prob);
     const int kind = sweep_kind(P);
-    if (kind == 2 || kind == 3)
-      HIPCHK(launch_coupling_mfma(geo, kind == 3, f, g, prob->a, prob->b, eps, P_out, P.n0, P.m0, s));
+    if (kind >= 2 && kind <= 4)
+      HIPCHK(launch_coupling_mfma(geo, kind - 1, f, g, prob->a, prob->b, eps, P_out, P.n0, P.m0, s));
     else
       HIPCHK(launch_coupling(geo, P.kind, f, g, prob->a, prob->b, eps, P_out, P.n0, P.m0, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -161,7 +161,8 @@ struct Prepared {
   float cscale;
   double cscale64;
   float cmax;
-  // cross term of a SQEUCLID cost: 1 FP32 direct, 2 bf16, 3 bf16 hi/lo split
+  // cross term of a SQEUCLID cost: 1 FP32 direct, 2 bf16, 3 bf16 hi/lo split,
+  // 4 bf16 hi/mid/lo split
   int xmode = 0;
   int dpad = 0;          // bf16 rows: d rounded up to a multiple of 32
   std::vector<float> mu;  // centring point (bf16-rounded mean of all points)

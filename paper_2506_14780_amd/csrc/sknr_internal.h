@@ -70,9 +70,11 @@ struct SweepArgs {
   // bf16 rows of dpad entries (dpad a multiple of 32; hi, and lo for the
   // split form, else null) and fl32(cost_scale * ||x~||^2) per point
   const uint4* Hred;
+  const uint4* Mred;     // mid part (three-part split only)
   const uint4* Lred;
   const float* Nred;
   const uint4* Hout;
+  const uint4* Mout;
   const uint4* Lout;
   const float* Nout;
   int dpad;
@@ -120,15 +122,16 @@ size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bo
 // split merge + scalar finishing kernels of a streaming sweep
 hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t stream);
 
-// matrix-core cost (cost kinds 2 = bf16 cross term, 3 = bf16 hi/lo split)
-hipError_t launch_sweep_mfma(const SweepArgs& a, bool x3, hipStream_t stream, hipEvent_t mid);
-size_t mfma_part_floats(int n_out, int n_red, int ell, int* nsplit, int* rps, int* nblk);
-hipError_t launch_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, bool x3,
-                              unsigned short* H, unsigned short* Lo, float* nrm, hipStream_t s);
-hipError_t launch_eval_mfma(const SweepArgs& geo, bool x3, const double* f, const double* g, const double* a,
+// matrix-core cost (cost kinds 2, 3, 4 = bf16 cross term with 1, 2, 3 bf16
+// parts per coordinate; `parts` below)
+hipError_t launch_sweep_mfma(const SweepArgs& a, int parts, hipStream_t stream, hipEvent_t mid);
+size_t mfma_part_floats(int n_out, int n_red, int ell, int parts, int* nsplit, int* rps, int* nblk);
+hipError_t launch_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, int parts,
+                              unsigned short* H, unsigned short* M, unsigned short* Lo, float* nrm, hipStream_t s);
+hipError_t launch_eval_mfma(const SweepArgs& geo, int parts, const double* f, const double* g, const double* a,
                             const double* b, double eps, double* rowpart, double* colpart, double* scal, int n,
                             int m, int* nrb, int* ncb, hipStream_t s);
-hipError_t launch_coupling_mfma(const SweepArgs& geo, bool x3, const double* f, const double* g, const double* a,
+hipError_t launch_coupling_mfma(const SweepArgs& geo, int parts, const double* f, const double* g, const double* a,
                                 const double* b, double eps, float* P, int n, int m, hipStream_t s);
 
 // conversions between FP64 paper-convention potentials and hat double-floats
@@ -151,7 +154,9 @@ hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float
 hipError_t launch_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp,
                          const float2* Gt, float2* G, int m, DevState* st, int gate, hipStream_t s);
 
-// FP64 evaluation (final check)
+// FP64 evaluation (final check).  cost_kind: a sweep kind (0 stored, 1 FP32
+// points) or kEvalExact, the FP64 squared distance of the FP32 points.
+constexpr int kEvalExact = 5;
 hipError_t launch_eval(const SweepArgs& geo, int cost_kind, const double* f, const double* g,
                        const double* a, const double* b, double eps, double* rowpart, double* colpart,
                        double* scal, int n, int m, int* nrb, int* ncb, hipStream_t s);

@@ -524,7 +524,7 @@ static int stream_cpt(int cost_kind, int ell, bool vec, int d) {
 
 size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bool vec, int* nsplit, int* rps,
                          int* nblk, bool stream_kernel) {
-  if (cost_kind >= 2) return mfma_part_floats(n_out, n_red, ell, nsplit, rps, nblk);
+  if (cost_kind >= 2) return mfma_part_floats(n_out, n_red, ell, cost_kind - 1, nsplit, rps, nblk);
   if (!stream_kernel) {
     int rpw = ell > 0 ? 1 : 4;
     *nsplit = 1;
@@ -605,7 +605,7 @@ hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t s, hipEvent_t mid) {
-  if (cost_kind >= 2) return launch_sweep_mfma(a, cost_kind == 3, s, mid);
+  if (cost_kind >= 2) return launch_sweep_mfma(a, cost_kind - 1, s, mid);
   const int cpt = stream_cpt(cost_kind, a.ell, vec, a.d);
   if (cost_kind == 0) {
     if (a.ell == 0) return cpt == 4 ? go_stream<4, 0, 0, 1, 8>(a, s, mid) : go_stream<1, 0, 0, 1, 8>(a, s, mid);
@@ -1033,7 +1033,7 @@ __global__ __launch_bounds__(256) void k_eval(SweepArgs G, const double* f, cons
     int i = i0 + r;
     double p = 0, cij = 0;
     if (i < n && j < m) {
-      if (COST == 4) {
+      if (COST == kEvalExact) {
         // the exact cost of the FP32 points, in FP64
         const float* xp = G.Pred + (size_t)i * G.d;
         const float* yp = G.Pout + (size_t)jc * G.d;
@@ -1090,8 +1090,8 @@ hipError_t launch_eval(const SweepArgs& geo, int cost_kind, const double* f, con
   *nrb = grid.y;
   if (cost_kind == 0) {
     hipLaunchKernelGGL((k_eval<0, 1>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m);
-  } else if (cost_kind == 4) {
-    hipLaunchKernelGGL((k_eval<4, 0>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m);
+  } else if (cost_kind == kEvalExact) {
+    hipLaunchKernelGGL((k_eval<kEvalExact, 0>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m);
   } else {
     switch (geo.d) {
       case 1: hipLaunchKernelGGL((k_eval<1, 1>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m); break;

@@ -3,14 +3,16 @@
 //
 // The cost of a pair is built as
 //     C~_ij = fma(-2 s, xy_ij, n_i + n_j),   n_i = fl32(s * ||x~_i||^2),
-// where x~ are the centred points rounded to bf16 (BF16) or to a hi + lo
-// pair of bf16 (BF16X3), s is the cost scale and xy_ij = x~_i . y~_j comes
-// from matrix-core tiles.  For BF16X3 the product keeps hi*hi + hi*lo +
-// lo*hi: the two mixed chains run in separate accumulators and are added
-// in FP32 (a commutative add) before the hi*hi chain starts from their sum,
-// so C~ is the same matrix whichever side is the reduce side of a sweep:
-// a matrix-core tile is symmetric under swapping its two operands, and so
-// the row and column c-transforms see one and the same cost.
+// where x~ are the centred points rounded to bf16 (BF16), to a hi + lo
+// pair of bf16 (BF16X3) or to hi + mid + lo (BF16X6), s is the cost scale
+// and xy_ij = x~_i . y~_j comes from matrix-core tiles.  BF16X3 keeps
+// hi*hi + hi*lo + lo*hi; BF16X6 keeps hi*hi + hi*mid + mid*hi + hi*lo +
+// lo*hi + mid*mid.  Each mirrored pair (a*b, b*a) runs as two chains in
+// separate accumulators joined by an FP32 add (commutative), and every
+// other chain is a single operand pair used in both orders, so C~ is the
+// same matrix whichever side is the reduce side of a sweep: a matrix-core
+// tile is symmetric under swapping its two operands, and so the row and
+// column c-transforms see one and the same cost.
 //
 // The MFMA 16x16x32 lane layout (64 lanes, g = lane / 16, c = lane % 16):
 //   operand A (16 x 32): lane supplies row c, k = 8g .. 8g+7
@@ -43,44 +45,71 @@ __device__ __forceinline__ unsigned short bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-// Cross products of one 16 x 16 tile from operands already in registers
-// (ks K-steps of 32).  The accumulation order is fixed: mixed chains first
-// (ascending k), their FP32 sum, then the hi*hi chain (ascending k).
-template <bool X3, int KR>
-__device__ __forceinline__ f32x4 cross_regs(const bf16x8 (&ah)[KR], const bf16x8 (&al)[KR], const bf16x8 (&bh)[KR],
-                                            const bf16x8 (&bl)[KR]) {
+// Cross products of one 16 x 16 tile (ks K-steps of 32).  XP = number of
+// bf16 parts per coordinate (1: hi; 2: hi, lo; 3: hi, mid, lo).  The order
+// is fixed: the smallest mirrored pair first (separate accumulators, FP32
+// add), then for XP = 3 the mid*mid chain from that sum and the hi*mid
+// pair added to it, then the hi*hi chain starting from the total.  Operand
+// p[q][s] is part q (0 = hi, 1 = lo for XP = 2; 0 = hi, 1 = mid, 2 = lo for
+// XP = 3) of K-step s.
+template <int XP, int KR>
+__device__ __forceinline__ f32x4 cross_regs(const bf16x8 (&a)[3][KR], const bf16x8 (&b)[3][KR]) {
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  if (X3) {
+  if (XP >= 2) {
+    constexpr int LO = XP - 1;  // index of the lo part
     f32x4 t1 = acc, t2 = acc;
 #pragma unroll
     for (int s = 0; s < KR; ++s) {
-      t1 = mfma_bf16(ah[s], bl[s], t1);
-      t2 = mfma_bf16(al[s], bh[s], t2);
+      t1 = mfma_bf16(a[0][s], b[LO][s], t1);
+      t2 = mfma_bf16(a[LO][s], b[0][s], t2);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = t1[i] + t2[i];
   }
+  if (XP == 3) {
 #pragma unroll
-  for (int s = 0; s < KR; ++s) acc = mfma_bf16(ah[s], bh[s], acc);
+    for (int s = 0; s < KR; ++s) acc = mfma_bf16(a[1][s], b[1][s], acc);
+    f32x4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1;
+#pragma unroll
+    for (int s = 0; s < KR; ++s) {
+      t1 = mfma_bf16(a[0][s], b[1][s], t1);
+      t2 = mfma_bf16(a[1][s], b[0][s], t2);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = acc[i] + (t1[i] + t2[i]);
+  }
+#pragma unroll
+  for (int s = 0; s < KR; ++s) acc = mfma_bf16(a[0][s], b[0][s], acc);
   return acc;
 }
 
-// The same tile with operands read from memory per K-step (any dpad).
-// pa / pb: uint4 rows of the lane's A / B point, offset by g.
-template <bool X3>
-__device__ __forceinline__ f32x4 cross_mem(const uint4* ha, const uint4* la, const uint4* hb, const uint4* lb,
-                                           int ks) {
+// The same tile with operands read from memory per K-step (any dpad):
+// pa[q] / pb[q] = uint4 rows of part q of the lane's A / B point, offset
+// by the lane's k-slice.
+template <int XP>
+__device__ __forceinline__ f32x4 cross_mem(const uint4* const (&pa)[3], const uint4* const (&pb)[3], int ks) {
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  if (X3) {
+  if (XP >= 2) {
+    constexpr int LO = XP - 1;
     f32x4 t1 = acc, t2 = acc;
     for (int s = 0; s < ks; ++s) {
-      t1 = mfma_bf16(as_bf8(ha[4 * s]), as_bf8(lb[4 * s]), t1);
-      t2 = mfma_bf16(as_bf8(la[4 * s]), as_bf8(hb[4 * s]), t2);
+      t1 = mfma_bf16(as_bf8(pa[0][4 * s]), as_bf8(pb[LO][4 * s]), t1);
+      t2 = mfma_bf16(as_bf8(pa[LO][4 * s]), as_bf8(pb[0][4 * s]), t2);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = t1[i] + t2[i];
   }
-  for (int s = 0; s < ks; ++s) acc = mfma_bf16(as_bf8(ha[4 * s]), as_bf8(hb[4 * s]), acc);
+  if (XP == 3) {
+    for (int s = 0; s < ks; ++s) acc = mfma_bf16(as_bf8(pa[1][4 * s]), as_bf8(pb[1][4 * s]), acc);
+    f32x4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1;
+    for (int s = 0; s < ks; ++s) {
+      t1 = mfma_bf16(as_bf8(pa[0][4 * s]), as_bf8(pb[1][4 * s]), t1);
+      t2 = mfma_bf16(as_bf8(pa[1][4 * s]), as_bf8(pb[0][4 * s]), t2);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = acc[i] + (t1[i] + t2[i]);
+  }
+  for (int s = 0; s < ks; ++s) acc = mfma_bf16(as_bf8(pa[0][4 * s]), as_bf8(pb[0][4 * s]), acc);
   return acc;
 }
 
@@ -96,7 +125,7 @@ __device__ __forceinline__ f32x4 cross_mem(const uint4* ha, const uint4* la, con
 // kernels complete it.  KS > 0: K-steps known at compile time, the output
 // side operands stay in registers; KS == 0: any dpad, operands reloaded.
 // ============================================================================
-template <int ELL, int KS, bool X3, int NT>
+template <int ELL, int KS, int XP, int NT>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_mfma(SweepArgs A) {
   if (gate_closed(A.st, A.gate)) return;
   extern __shared__ float4 smem4[];
@@ -132,7 +161,10 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int cb = blockIdx.x * NC + wave * NCW;
   float hy[NT];
   int colc[NT];
-  bf16x8 bh[NT][KR], bl[NT][KR];
+  // parts of the output-side points: [0] hi, then lo (XP = 2) or mid, lo
+  const uint4* const pout[3] = {A.Hout, XP == 3 ? A.Mout : A.Lout, A.Lout};
+  const uint4* const pred[3] = {A.Hred, XP == 3 ? A.Mred : A.Lred, A.Lred};
+  bf16x8 bo[NT][3][KR];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     colc[t] = min(cb + 16 * t + c16, A.n_out - 1);
@@ -140,10 +172,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (KS > 0) {
       const size_t base = (size_t)colc[t] * dq + g;
 #pragma unroll
-      for (int s = 0; s < KR; ++s) {
-        bh[t][s] = as_bf8(A.Hout[base + 4 * s]);
-        bl[t][s] = X3 ? as_bf8(A.Lout[base + 4 * s]) : bh[t][s];
-      }
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int s = 0; s < KR; ++s) bo[t][q][s] = q < XP ? as_bf8(pout[q][base + 4 * s]) : bo[t][0][s];
     }
   }
 
@@ -163,35 +194,32 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
 
   // (the lambdas below capture these locals, not the argument struct, so
   // that the struct stays in kernel-argument registers)
-  const uint4* const Hred = A.Hred;
-  const uint4* const Lred = A.Lred;
-  const uint4* const Hout = A.Hout;
-  const uint4* const Lout = A.Lout;
   const float* const Vred = A.Vred;
   // Software pipeline over row tiles: while the log-sum-exp of tile k runs
   // on the VALU, the matrix cores work on tile k+1 (its operands loaded one
   // iteration earlier) and the loads of tile k+2 are in flight.
-  bf16x8 ah[KR], al[KR];
+  bf16x8 ai[3][KR];
   auto load_a = [&](int rt) __attribute__((always_inline)) {
     if (KS > 0) {
       const size_t ra = (size_t)(r0 + min(rt + c16, nr - 1)) * dq + g;
 #pragma unroll
-      for (int s = 0; s < KR; ++s) {
-        ah[s] = as_bf8(Hred[ra + 4 * s]);
-        al[s] = X3 ? as_bf8(Lred[ra + 4 * s]) : ah[s];
-      }
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int s = 0; s < KR; ++s) ai[q][s] = q < XP ? as_bf8(pred[q][ra + 4 * s]) : ai[0][s];
     }
   };
   auto cross = [&](int rt, f32x4 (&xy)[NT]) __attribute__((always_inline)) {
     if (KS > 0) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) xy[t] = cross_regs<X3, KR>(ah, al, bh[t], bl[t]);
+      for (int t = 0; t < NT; ++t) xy[t] = cross_regs<XP, KR>(ai, bo[t]);
     } else {
       const size_t ra = (size_t)(r0 + min(rt + c16, nr - 1)) * dq + g;
+      const uint4* const pa[3] = {pred[0] + ra, pred[1] + ra, pred[2] + ra};
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const size_t rb = (size_t)colc[t] * dq + g;
-        xy[t] = cross_mem<X3>(Hred + ra, Lred + ra, Hout + rb, Lout + rb, ks);
+        const uint4* const pb[3] = {pout[0] + rb, pout[1] + rb, pout[2] + rb};
+        xy[t] = cross_mem<XP>(pa, pb, ks);
       }
     }
   };
@@ -336,16 +364,19 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // ----------------------------------------------------------- geometry
-// output tiles of 16 per wave: 4 for plain sweeps (SKNR_MFMA_NT=2 overrides),
-// 2 for weighted sweeps (register budget of the l-wide accumulators)
-static int mfma_nt(int ell) {
+// output tiles of 16 per wave: 4 for plain sweeps with one or two parts
+// (SKNR_MFMA_NT=2 overrides), 2 for weighted sweeps (register budget of the
+// l-wide accumulators) and for three parts (their output-side operands),
+// 1 for 32-wide weighted sweeps with three parts
+static int mfma_nt(int ell, int parts) {
   static const int env_nt = getenv("SKNR_MFMA_NT") ? atoi(getenv("SKNR_MFMA_NT")) : 0;
-  if (ell > 0) return 2;
+  if (ell > 16 && parts >= 3) return 1;
+  if (ell > 0 || parts >= 3) return 2;
   return env_nt == 2 ? 2 : 4;
 }
 
-size_t mfma_part_floats(int n_out, int n_red, int ell, int* nsplit, int* rps, int* nblk) {
-  const int nc = 64 * mfma_nt(ell);
+size_t mfma_part_floats(int n_out, int n_red, int ell, int parts, int* nsplit, int* rps, int* nblk) {
+  const int nc = 64 * mfma_nt(ell, parts);
   const int ncb = (n_out + nc - 1) / nc;
   static const int env_target = getenv("SKNR_SWEEP_TARGET_WG") ? atoi(getenv("SKNR_SWEEP_TARGET_WG")) : 0;
   const int target = env_target > 0 ? env_target : 2048;
@@ -364,69 +395,78 @@ size_t mfma_part_floats(int n_out, int n_red, int ell, int* nsplit, int* rps, in
   return (size_t)ns * (3 + ellp) * n_out;
 }
 
-template <int ELL, bool X3, int NT>
+template <int ELL, int XP, int NT>
 static void go_mfma(const SweepArgs& a, hipStream_t s) {
   const int nc = 64 * NT;
   dim3 grid((a.n_out + nc - 1) / nc, a.nsplit);
   const size_t sm = (size_t)a.rows_per_split * sizeof(float4);
   const int ks = a.dpad >> 5;
-  if (ks == 1) hipLaunchKernelGGL((k_sweep_mfma<ELL, 1, X3, NT>), grid, dim3(TPB), sm, s, a);
-  else if (ks == 2) hipLaunchKernelGGL((k_sweep_mfma<ELL, 2, X3, NT>), grid, dim3(TPB), sm, s, a);
-  else hipLaunchKernelGGL((k_sweep_mfma<ELL, 0, X3, NT>), grid, dim3(TPB), sm, s, a);
+  if (ks == 1) hipLaunchKernelGGL((k_sweep_mfma<ELL, 1, XP, NT>), grid, dim3(TPB), sm, s, a);
+  else if (ks == 2) hipLaunchKernelGGL((k_sweep_mfma<ELL, 2, XP, NT>), grid, dim3(TPB), sm, s, a);
+  else hipLaunchKernelGGL((k_sweep_mfma<ELL, 0, XP, NT>), grid, dim3(TPB), sm, s, a);
 }
 
-hipError_t launch_sweep_mfma(const SweepArgs& a, bool x3, hipStream_t s, hipEvent_t mid) {
-  if (a.dpad <= 0 || (a.dpad & 31) || a.rows_per_split > 2048) return hipErrorInvalidValue;
+template <int XP>
+static void go_mfma_ell(const SweepArgs& a, hipStream_t s) {
   const int e = a.ell;
-  const bool nt2 = mfma_nt(e) == 2;
-  if (x3) {
-    if (e == 0) nt2 ? go_mfma<0, true, 2>(a, s) : go_mfma<0, true, 4>(a, s);
-    else if (e <= 8) go_mfma<8, true, 2>(a, s);
-    else if (e <= 16) go_mfma<16, true, 2>(a, s);
-    else go_mfma<32, true, 2>(a, s);
-  } else {
-    if (e == 0) nt2 ? go_mfma<0, false, 2>(a, s) : go_mfma<0, false, 4>(a, s);
-    else if (e <= 8) go_mfma<8, false, 2>(a, s);
-    else if (e <= 16) go_mfma<16, false, 2>(a, s);
-    else go_mfma<32, false, 2>(a, s);
-  }
+  if (e == 0) {
+    if (mfma_nt(0, XP) == 2) go_mfma<0, XP, 2>(a, s);
+    else go_mfma<0, XP, (XP >= 3 ? 2 : 4)>(a, s);
+  } else if (e <= 8) go_mfma<8, XP, 2>(a, s);
+  else if (e <= 16) go_mfma<16, XP, 2>(a, s);
+  else go_mfma<32, XP, (XP >= 3 ? 1 : 2)>(a, s);
+}
+
+hipError_t launch_sweep_mfma(const SweepArgs& a, int parts, hipStream_t s, hipEvent_t mid) {
+  if (a.dpad <= 0 || (a.dpad & 31) || a.rows_per_split > 2048 || parts < 1 || parts > 3) return hipErrorInvalidValue;
+  if (parts == 1) go_mfma_ell<1>(a, s);
+  else if (parts == 2) go_mfma_ell<2>(a, s);
+  else go_mfma_ell<3>(a, s);
   if (mid) (void)hipEventRecord(mid, s);
   return launch_sweep_tail(a, s);
 }
 
 // ============================================================================
-// Packing: centred points rounded to bf16 (hi, and lo = bf16(v - hi) for
-// BF16X3), rows zero-padded to dpad, and n = fl32(scale * ||x~||^2) with
-// x~ = hi (+ lo) summed in FP64.  One thread per point.
+// Packing: centred points v = fl32(x - mu) rounded to `parts` bf16 pieces
+// (hi = bf16(v); lo = bf16(v - hi) for two parts; mid = bf16(v - hi),
+// lo = bf16(v - hi - mid) for three), rows zero-padded to dpad, and
+// n = fl32(scale * ||x~||^2) with x~ = the sum of the pieces, in FP64.
+// One thread per point.
 // ============================================================================
-__global__ void k_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, int x3,
-                              unsigned short* H, unsigned short* Lo, float* nrm) {
+__global__ void k_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, int parts,
+                              unsigned short* H, unsigned short* M, unsigned short* Lo, float* nrm) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
   double s2 = 0.0;
   for (int k = 0; k < dpad; ++k) {
-    unsigned short h = 0, l = 0;
+    unsigned short h = 0, m = 0, l = 0;
     if (k < d) {
       const float v = x[(size_t)p * d + k] - mu[k];
       h = bf16_rne(v);
-      const float hv = bf16_val(h);
-      float xt = hv;
-      if (x3) {
-        l = bf16_rne(v - hv);
-        xt = hv + bf16_val(l);
+      const float r1 = v - bf16_val(h);  // exact
+      double xt = (double)bf16_val(h);
+      if (parts == 2) {
+        l = bf16_rne(r1);
+        xt += (double)bf16_val(l);
+      } else if (parts == 3) {
+        m = bf16_rne(r1);
+        const float r2 = r1 - bf16_val(m);  // exact
+        l = bf16_rne(r2);
+        xt += (double)bf16_val(m) + (double)bf16_val(l);
       }
-      s2 += (double)xt * (double)xt;
+      s2 += xt * xt;
     }
     H[(size_t)p * dpad + k] = h;
-    if (x3) Lo[(size_t)p * dpad + k] = l;
+    if (parts == 3) M[(size_t)p * dpad + k] = m;
+    if (parts >= 2) Lo[(size_t)p * dpad + k] = l;
   }
   nrm[p] = (float)(scale * s2);
 }
 
-hipError_t launch_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, bool x3,
-                              unsigned short* H, unsigned short* Lo, float* nrm, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_points, dim3((np + 255) / 256), dim3(256), 0, s, x, np, d, mu, scale, dpad, x3 ? 1 : 0,
-                     H, Lo, nrm);
+hipError_t launch_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, int parts,
+                              unsigned short* H, unsigned short* M, unsigned short* Lo, float* nrm, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_points, dim3((np + 255) / 256), dim3(256), 0, s, x, np, d, mu, scale, dpad, parts, H, M,
+                     Lo, nrm);
   return hipGetLastError();
 }
 
@@ -436,44 +476,34 @@ hipError_t launch_pack_points(const float* x, int np, int d, const float* mu, do
 // the four waves (64 columns each) into LDS, then every thread runs the
 // FP64 terms of its column.
 // ============================================================================
-template <bool X3, int KS>
+template <int XP>
 __global__ __launch_bounds__(256) void k_eval_mfma(SweepArgs G, const double* f, const double* g,
                                                    const double* a, const double* b, double eps, double* rowpart,
                                                    double* colpart, double* scal, int n, int m) {
-  constexpr int KR = KS > 0 ? KS : 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g4 = lane >> 4, c16 = lane & 15;
   const int j = blockIdx.x * 256 + threadIdx.x;
   const int i0 = blockIdx.y * 64;
   const int jc = min(j, m - 1);
   const int dq = G.dpad >> 3;
-  const int ks = KS > 0 ? KS : (G.dpad >> 5);
+  const int ks = G.dpad >> 5;
   const double inv = 1.0 / eps;
   const double gj = g[jc], bj = b[jc];
+  const uint4* const pred[3] = {G.Hred, XP == 3 ? G.Mred : G.Lred, G.Lred};
+  const uint4* const pout[3] = {G.Hout, XP == 3 ? G.Mout : G.Lout, G.Lout};
   __shared__ float sC[16][257];
   __shared__ double srow[WAVES][64];
   double cs = 0, cost = 0, mass = 0, ent = 0;
   for (int rt = 0; rt < 64; rt += 16) {
     const size_t ra = (size_t)min(i0 + rt + c16, n - 1) * dq + g4;
+    const uint4* const pa[3] = {pred[0] + ra, pred[1] + ra, pred[2] + ra};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int cl = wave * 64 + 16 * t + c16;
       const int jt = min((int)blockIdx.x * 256 + cl, m - 1);
       const size_t rb = (size_t)jt * dq + g4;
-      f32x4 xy;
-      if (KS > 0) {
-        bf16x8 ah[KR], al[KR], bh[KR], bl[KR];
-#pragma unroll
-        for (int s = 0; s < KR; ++s) {
-          ah[s] = as_bf8(G.Hred[ra + 4 * s]);
-          bh[s] = as_bf8(G.Hout[rb + 4 * s]);
-          al[s] = X3 ? as_bf8(G.Lred[ra + 4 * s]) : ah[s];
-          bl[s] = X3 ? as_bf8(G.Lout[rb + 4 * s]) : bh[s];
-        }
-        xy = cross_regs<X3, KR>(ah, al, bh, bl);
-      } else {
-        xy = cross_mem<X3>(G.Hred + ra, G.Lred + ra, G.Hout + rb, G.Lout + rb, ks);
-      }
+      const uint4* const pb[3] = {pout[0] + rb, pout[1] + rb, pout[2] + rb};
+      const f32x4 xy = cross_mem<XP>(pa, pb, ks);
       const float ny = G.Nout[jt];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -517,31 +547,24 @@ __global__ __launch_bounds__(256) void k_eval_mfma(SweepArgs G, const double* f,
   }
 }
 
-hipError_t launch_eval_mfma(const SweepArgs& geo, bool x3, const double* f, const double* g, const double* a,
+hipError_t launch_eval_mfma(const SweepArgs& geo, int parts, const double* f, const double* g, const double* a,
                             const double* b, double eps, double* rowpart, double* colpart, double* scal, int n,
                             int m, int* nrb, int* ncb, hipStream_t s) {
-  if (geo.dpad <= 0 || (geo.dpad & 31)) return hipErrorInvalidValue;
+  if (geo.dpad <= 0 || (geo.dpad & 31) || parts < 1 || parts > 3) return hipErrorInvalidValue;
   dim3 grid((m + 255) / 256, (n + 63) / 64);
   *ncb = grid.x;
   *nrb = grid.y;
-  const int ks = geo.dpad >> 5;
-#define SKNR_EVAL_MFMA(X, KK) \
-  hipLaunchKernelGGL((k_eval_mfma<X, KK>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m)
-  if (x3) {
-    if (ks == 1) SKNR_EVAL_MFMA(true, 1);
-    else if (ks == 2) SKNR_EVAL_MFMA(true, 2);
-    else SKNR_EVAL_MFMA(true, 0);
-  } else {
-    if (ks == 1) SKNR_EVAL_MFMA(false, 1);
-    else if (ks == 2) SKNR_EVAL_MFMA(false, 2);
-    else SKNR_EVAL_MFMA(false, 0);
-  }
-#undef SKNR_EVAL_MFMA
+  if (parts == 1)
+    hipLaunchKernelGGL((k_eval_mfma<1>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m);
+  else if (parts == 2)
+    hipLaunchKernelGGL((k_eval_mfma<2>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m);
+  else
+    hipLaunchKernelGGL((k_eval_mfma<3>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, rowpart, colpart, scal, n, m);
   return hipGetLastError();
 }
 
 // coupling on the matrix-core cost: 16 rows x 256 columns per workgroup
-template <bool X3>
+template <int XP>
 __global__ __launch_bounds__(256) void k_coupling_mfma(SweepArgs G, const double* f, const double* g,
                                                        const double* a, const double* b, double eps, float* P,
                                                        int n, int m) {
@@ -550,12 +573,14 @@ __global__ __launch_bounds__(256) void k_coupling_mfma(SweepArgs G, const double
   const int dq = G.dpad >> 3, ks = G.dpad >> 5;
   const int i0 = blockIdx.y * 16;
   const size_t ra = (size_t)min(i0 + c16, n - 1) * dq + g4;
+  const uint4* const pa[3] = {G.Hred + ra, (XP == 3 ? G.Mred : G.Lred) + ra, G.Lred + ra};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int j = (int)blockIdx.x * 256 + wave * 64 + 16 * t + c16;
     const int jc = min(j, m - 1);
     const size_t rb = (size_t)jc * dq + g4;
-    const f32x4 xy = cross_mem<X3>(G.Hred + ra, G.Lred + ra, G.Hout + rb, G.Lout + rb, ks);
+    const uint4* const pb[3] = {G.Hout + rb, (XP == 3 ? G.Mout : G.Lout) + rb, G.Lout + rb};
+    const f32x4 xy = cross_mem<XP>(pa, pb, ks);
     const float ny = G.Nout[jc];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -568,12 +593,13 @@ __global__ __launch_bounds__(256) void k_coupling_mfma(SweepArgs G, const double
   }
 }
 
-hipError_t launch_coupling_mfma(const SweepArgs& geo, bool x3, const double* f, const double* g, const double* a,
+hipError_t launch_coupling_mfma(const SweepArgs& geo, int parts, const double* f, const double* g, const double* a,
                                 const double* b, double eps, float* P, int n, int m, hipStream_t s) {
-  if (geo.dpad <= 0 || (geo.dpad & 31)) return hipErrorInvalidValue;
+  if (geo.dpad <= 0 || (geo.dpad & 31) || parts < 1 || parts > 3) return hipErrorInvalidValue;
   dim3 grid((m + 255) / 256, (n + 15) / 16);
-  if (x3) hipLaunchKernelGGL((k_coupling_mfma<true>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
-  else hipLaunchKernelGGL((k_coupling_mfma<false>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
+  if (parts == 1) hipLaunchKernelGGL((k_coupling_mfma<1>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
+  else if (parts == 2) hipLaunchKernelGGL((k_coupling_mfma<2>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
+  else hipLaunchKernelGGL((k_coupling_mfma<3>), grid, dim3(256), 0, s, geo, f, g, a, b, eps, P, n, m);
   return hipGetLastError();
 }
 

@@ -58,19 +58,23 @@ def bf16_rne(v):
     return u.astype(np.uint32).view(np.float32)
 
 
-def bf16_cost_model(x, y, scale=1.0, x3=True, mu_points=None):
+def bf16_cost_model(x, y, scale=1.0, x3=True, mu_points=None, parts=None):
     """The matrix-core cost as the library defines it, in FP64, with a
     rigorous per-element bound on the GPU's deviation from it.
 
-    Centre mu = bf16(mean of all points); v = fl32(x - mu); hi = bf16(v),
-    lo = bf16(v - hi) (x3) or 0; x~ = hi + lo; n_i = fl32(scale ||x~_i||^2);
-    model C_ij = n_i + n_j - 2 fl32(scale) (x~_i . y~_j) with lo*lo omitted.
-    The GPU forms the dot product on matrix cores (FP32 accumulation, any
-    order: error <= (N - 1) u sum|terms| over N products), adds the norms in
-    FP32 and applies one fma: bound = 2 s N u T_ij + 2 u (n_i + n_j) + u |C_ij|
-    (the second term also covers a last-bit difference of the FP64 norm).
-    mu_points: the full point sets (x, y) when x or y is only a subset of
-    the rows of the problem (the centre is taken over all points)."""
+    Centre mu = bf16(mean of all points); v = fl32(x - mu) split into bf16
+    parts: hi = bf16(v) (1 part), lo = bf16(v - hi) (2 parts), or mid =
+    bf16(v - hi), lo = bf16(v - hi - mid) (3 parts); x~ = the sum of the
+    parts; n_i = fl32(scale ||x~_i||^2); model C_ij = n_i + n_j -
+    2 fl32(scale) (x~_i . y~_j) over the kept products (hi*hi; + hi*lo +
+    lo*hi; or + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid).  The GPU forms
+    the dot product on matrix cores (FP32 accumulation, any order: error <=
+    (N - 1) u sum|terms| over N products), adds the norms in FP32 and applies
+    one fma: bound = 2 s N u T_ij + 2 u (n_i + n_j) + u |C_ij| (the second
+    term also covers a last-bit difference of the FP64 norm).
+    parts defaults to 2 if x3 else 1.  mu_points: the full point sets (x, y)
+    when x or y is only a subset of the rows of the problem."""
+    parts = parts if parts is not None else (2 if x3 else 1)
     x = np.asarray(x, np.float32)
     y = np.asarray(y, np.float32)
     d = x.shape[1]
@@ -82,21 +86,25 @@ def bf16_cost_model(x, y, scale=1.0, x3=True, mu_points=None):
     def split(p):
         v = (p - mu).astype(np.float32)
         hi = bf16_rne(v)
-        lo = bf16_rne((v - hi).astype(np.float32)) if x3 else np.zeros_like(hi)
-        return hi.astype(np.float64), lo.astype(np.float64)
+        r1 = (v - hi).astype(np.float32)
+        if parts == 1:
+            out = [hi]
+        elif parts == 2:
+            out = [hi, bf16_rne(r1)]
+        else:
+            mid = bf16_rne(r1)
+            out = [hi, mid, bf16_rne((r1 - mid).astype(np.float32))]
+        return [o.astype(np.float64) for o in out]
 
-    xh, xl = split(x)
-    yh, yl = split(y)
+    X, Y = split(x), split(y)
     s32 = float(np.float32(scale))
-    nx = np.float32(scale * ((xh + xl) ** 2).sum(1)).astype(np.float64)
-    ny = np.float32(scale * ((yh + yl) ** 2).sum(1)).astype(np.float64)
-    E = xh @ yh.T
-    T = np.abs(xh) @ np.abs(yh).T
-    nprod = dpad
-    if x3:
-        E = E + xh @ yl.T + xl @ yh.T
-        T = T + np.abs(xh) @ np.abs(yl).T + np.abs(xl) @ np.abs(yh).T
-        nprod = 3 * dpad
+    nx = np.float32(scale * (sum(X) ** 2).sum(1)).astype(np.float64)
+    ny = np.float32(scale * (sum(Y) ** 2).sum(1)).astype(np.float64)
+    pairs = {1: [(0, 0)], 2: [(0, 0), (0, 1), (1, 0)],
+             3: [(0, 0), (0, 1), (1, 0), (0, 2), (2, 0), (1, 1)]}[parts]
+    E = sum(X[i] @ Y[j].T for i, j in pairs)
+    T = sum(np.abs(X[i]) @ np.abs(Y[j]).T for i, j in pairs)
+    nprod = len(pairs) * dpad
     C = nx[:, None] + ny[None, :] - 2.0 * s32 * E
     bound = 2.0 * s32 * nprod * U32 * T + 2 * U32 * (nx[:, None] + ny[None, :]) + U32 * np.abs(C)
     return C, bound

@@ -58,15 +58,15 @@ CASES = [(700, 1300, 64, 1.0 / 64), (333, 1299, 16, 1.0), (1500, 257, 40, 1.0 / 
 
 @pytest.mark.parametrize("n,m,d,scale", CASES)
 @pytest.mark.parametrize("eps", [1e-1, 1e-2])
-@pytest.mark.parametrize("x3", [True, False])
-def test_c_transforms_mfma(sk, ctx, n, m, d, scale, eps, x3):
+@pytest.mark.parametrize("parts", [2, 1, 3])
+def test_c_transforms_mfma(sk, ctx, n, m, d, scale, eps, parts):
     x, y, a, b = _clouds(n, m, d, seed=n + d)
-    Cm, bound = bf16_cost_model(x, y, scale, x3)
-    xterm = sk.XTERM_BF16X3 if x3 else sk.XTERM_BF16
+    Cm, bound = bf16_cost_model(x, y, scale, parts=parts)
+    xterm = {1: sk.XTERM_BF16, 2: sk.XTERM_BF16X3, 3: sk.XTERM_BF16X6}[parts]
     gp = _gp(sk, x, y, a, b, scale, xterm)
     rng = np.random.default_rng(7)
     f = 0.2 * rng.standard_normal(n)
-    print(f"case mfma n={n} m={m} d={d} s={scale:.4g} eps={eps} x3={x3} bound={bound.max():.3e}", flush=True)
+    print(f"case mfma n={n} m={m} d={d} s={scale:.4g} eps={eps} parts={parts} bound={bound.max():.3e}", flush=True)
     g_gpu = sk.c_transform_col(ctx, gp, eps, to_dev(f))[0].cpu().numpy()
     g_ref = O.c_transform_col(f, Cm, a, eps)
     tol = bound.max() + 64 * U32 * eps + 1e-12 * np.abs(g_ref).max()
@@ -135,13 +135,13 @@ def test_mfma_projected_system(sk, ctx):
     assert abs(q - O.semidual_value(r.f, Cm, a, b, eps)) <= 64 * U32 * eps + bound.max()
 
 
-@pytest.mark.parametrize("x3", [True, False])
-def test_mfma_solve_against_exact_oracle(sk, ctx, x3):
+@pytest.mark.parametrize("parts", [2, 1, 3])
+def test_mfma_solve_against_exact_oracle(sk, ctx, parts):
     """A point-cloud problem of the d = 64 workload's shape (standard normal
     clouds, y shifted by 0.5 e1, uniform weights, raw squared distance) on a
     three-stage eps ladder with SK-NR (sequential warm start), against the
-    oracle on the exact FP64 cost.  BF16X3 meets the FP32-mode targets;
-    BF16 is reported and held to its own cost-error bound."""
+    oracle on the exact FP64 cost.  BF16X3 and BF16X6 meet the FP32-mode
+    targets; BF16 is reported and held to its own cost-error bound."""
     n, m, d = 320, 480, 64
     rng = np.random.default_rng(40)
     x = rng.standard_normal((n, d)).astype(np.float32)
@@ -153,22 +153,25 @@ def test_mfma_solve_against_exact_oracle(sk, ctx, x3):
     Cx = O.sqeuclid_cost(x.astype(np.float64), y.astype(np.float64))
     fo, go, _ = O.solve_schedule(Cx, a, b, ladder, 1e-10, 200000)
     fo, go = O.normalize_gauge(fo, go, a, b)
-    xterm = sk.XTERM_BF16X3 if x3 else sk.XTERM_BF16
+    xterm = {1: sk.XTERM_BF16, 2: sk.XTERM_BF16X3, 3: sk.XTERM_BF16X6}[parts]
     gp = _gp(sk, x, y, a, b, 1.0, xterm)
     f, g, res = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=50000, ell=10, warm_mode=sk.WARM_SEQUENTIAL)
     ep = e_pot(f.cpu().numpy(), g.cpu().numpy(), fo, go, Cx)
     tc = O.transport_cost(fo, go, Cx, a, b, ladder[-1])
     dc = abs(res["transport_cost_exact"] - tc) / tc
-    Cm, bound = bf16_cost_model(x, y, 1.0, x3)
+    Cm, bound = bf16_cost_model(x, y, 1.0, parts=parts)
     cerr = np.abs(Cm - Cx).max() + bound.max()
-    print(f"x3={x3} iters={[s['iters'] for s in res['stages']]} marg={res['marginal_err']:.2e} "
+    print(f"parts={parts} iters={[s['iters'] for s in res['stages']]} marg={res['marginal_err']:.2e} "
           f"marg_exact={res['marginal_err_exact']:.2e} e_pot={ep:.2e} cost_rel={dc:.2e} "
           f"max|C~-C|<={cerr:.2e}", flush=True)
     assert res["status"] == 0
     assert res["marginal_err"] < 1e-6
-    if x3:
+    if parts >= 2:
         assert ep <= 1e-5
         assert dc <= 1e-6
-    else:
+    if parts == 3:
+        # three parts: the cost is FP32-accurate, so is the marginal on the exact cost
+        assert res["marginal_err_exact"] < 1e-4
+    if parts == 1:
         # potentials move by at most max|C~ - C| (1-Lipschitz fixed point)
         assert ep * (Cx.max() - Cx.min()) <= 2 * cerr + 1e-6

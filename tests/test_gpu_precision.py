@@ -7,8 +7,8 @@ columns with the oracle's T_c on the exact FP64 cost of the FP32 points.  A
 c-transform is 1-Lipschitz in the sup norm of the cost, so |dg_j| is bounded
 by max_i |C~_ij - C_ij|, which the test bounds per mode:
   FP32 (sequential fma order): d u sum_k t_k^2 (+ rounding of the LSE),
-  BF16 / BF16X3: the matrix-core model bound plus |C_model - C| (the
-  representation error of the bf16 split), computed exactly per element.
+  BF16 / BF16X3 / BF16X6: the matrix-core model bound plus |C_model - C|
+  (the representation error of the bf16 split), computed exactly per element.
 The relative error of the coupling weights is then |exp(dg/eps) - 1|,
 which grows as eps falls: the table printed here is the precision study
 (cost error stated per eps and mode).
@@ -37,10 +37,10 @@ def test_cost_precision_study_d64(sk):
     rng = np.random.default_rng(8)
     f = 0.05 * rng.standard_normal(prob.n)
     ctx = sk.Context(0)
-    modes = {"FP32": sk.XTERM_FP32, "BF16X3": sk.XTERM_BF16X3, "BF16": sk.XTERM_BF16}
+    modes = {"FP32": sk.XTERM_FP32, "BF16X6": sk.XTERM_BF16X6, "BF16X3": sk.XTERM_BF16X3, "BF16": sk.XTERM_BF16}
     bounds = {}
-    for name in ("BF16X3", "BF16"):
-        Cm, bnd = bf16_cost_model(x, y[cols], 1.0, name == "BF16X3", mu_points=(x, y))
+    for name, parts in (("BF16X6", 3), ("BF16X3", 2), ("BF16", 1)):
+        Cm, bnd = bf16_cost_model(x, y[cols], 1.0, parts=parts, mu_points=(x, y))
         bounds[name] = (bnd + np.abs(Cm - Cx)).max()
     # FP32 sequential sum of d squares: |fl - exact| <= (d - 1) u sum t_k^2 (+ rounding of each t_k)
     bounds["FP32"] = (x.shape[1] + 2) * U32 * Cx.max()
@@ -62,3 +62,4 @@ def test_cost_precision_study_d64(sk):
     for eps in (1e-1, 1e-2, 2e-3):
         e = {r[1]: r[2] for r in rows if r[0] == eps}
         assert e["BF16X3"] < e["BF16"] / 30
+        assert e["BF16X6"] < e["BF16X3"] / 4
