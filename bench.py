@@ -49,10 +49,11 @@ def algorithmic_work(kind: str):
         return "hbm", 4.0, "GB/s"
     if "bf16" in kind:
         # matrix-core cost: the cross term is MFMA work; on the VALU the
-        # cost is finished by one add and one fma (plus one add joining the
-        # two mixed-product chains of the hi/lo split), then the same
-        # exponent, max, exp and accumulation as above
-        return "alu", (9.0 if "bf16x3" in kind else 8.0) + width, "TOP/s"
+        # cost is finished by one add and one fma, then the same exponent,
+        # max, exp and accumulation as above; the adds joining the product
+        # chains come on top (hi/lo split: 1, hi/mid/lo split: 3)
+        join = 3.0 if "bf16x6" in kind else 1.0 if "bf16x3" in kind else 0.0
+        return "alu", 8.0 + join + width, "TOP/s"
     return "alu", 10.0 + width, "TOP/s"
 
 
@@ -86,9 +87,10 @@ PEAK_MFMA_BF16_TFLOPS = 2500.0  # dense bf16 matrix-core peak
 
 def mfma_sweep_roofline(sk, W, torch, reps=4):
     """The d = 64 point-cloud sweep (20000 x 30000, cost cross term on
-    bf16 matrix cores with the hi/lo split): per-kernel HIP event timing of
-    column and row c-transforms, VALU fraction against the algorithmic
-    slots per element and matrix-core fraction against the bf16 peak."""
+    bf16 matrix cores: one, two or three bf16 parts per point coordinate):
+    per-kernel HIP event timing of column and row c-transforms, VALU
+    fraction against the algorithmic slots per element and matrix-core
+    fraction against the bf16 peak."""
     prob = W.gaussian_clouds()
     dev = torch.device("cuda:0")
     x, y = torch.from_numpy(prob.x).to(dev), torch.from_numpy(prob.y).to(dev)
@@ -96,7 +98,7 @@ def mfma_sweep_roofline(sk, W, torch, reps=4):
     out = {"workload": f"gaussian_clouds {prob.n}x{prob.m} d={prob.d}, one column + one row c-transform per rep"}
     ctx = sk.Context(0)
     f = torch.zeros(prob.n, dtype=torch.float64, device=dev)
-    for name, xt in (("bf16x3", sk.XTERM_BF16X3), ("bf16", sk.XTERM_BF16)):
+    for name, xt in (("bf16x3", sk.XTERM_BF16X3), ("bf16x6", sk.XTERM_BF16X6), ("bf16", sk.XTERM_BF16)):
         gp = sk.Problem(a=a, b=b, x=x, y=y, xterm=xt)
         g, _, _ = sk.c_transform_col(ctx, gp, 0.1, f)  # warm-up
         ctx.profile(True)
@@ -111,7 +113,7 @@ def mfma_sweep_roofline(sk, W, torch, reps=4):
         elems = main["units"] / main["launches"]
         _, slots, _ = algorithmic_work(main["name"])
         dpad = (prob.d + 31) // 32 * 32
-        flops = 2.0 * dpad * (3 if name == "bf16x3" else 1) * elems
+        flops = 2.0 * dpad * {"bf16": 1, "bf16x3": 3, "bf16x6": 6}[name] * elems
         out[name] = {"kernel": main["name"], "avg_launch_us": avg_s * 1e6, "elements_per_launch": elems,
                      "bound": "alu", "achieved": slots * elems / avg_s / 1e12, "peak": PEAK_VALU_TOPS,
                      "unit": "TOP/s", "frac": slots * elems / avg_s / 1e12 / PEAK_VALU_TOPS,

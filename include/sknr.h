@@ -69,7 +69,7 @@ enum sknr_cost_kind {
  * order k = 0..d-1; BF16 / BF16X3 form ||x||^2 + ||y||^2 - 2 x.y with the
  * x.y products on bf16 matrix cores with FP32 accumulation, from one bf16
  * term per coordinate (BF16) or a hi/lo bf16 split keeping hi*hi + hi*lo +
- * lo*hi (BF16X3).  AUTO picks FP32 for d < 16 and BF16X3 for d >= 16. */
+ * lo*hi (BF16X3).  AUTO picks FP32 for d < 16 and BF16X6 for d >= 16. */
 enum sknr_xterm {
   SKNR_XTERM_AUTO = 0,
   SKNR_XTERM_FP32 = 1,

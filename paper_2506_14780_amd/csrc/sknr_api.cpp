@@ -116,7 +116,7 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s) {
     P.cscale = (float)sc;
     P.cscale64 = sc;
     REQUIRE(pr->xterm >= SKNR_XTERM_AUTO && pr->xterm <= SKNR_XTERM_BF16X6, "unknown xterm");
-    P.xmode = pr->xterm == SKNR_XTERM_AUTO ? (pr->d >= 16 ? SKNR_XTERM_BF16X3 : SKNR_XTERM_FP32) : pr->xterm;
+    P.xmode = pr->xterm == SKNR_XTERM_AUTO ? (pr->d >= 16 ? SKNR_XTERM_BF16X6 : SKNR_XTERM_FP32) : pr->xterm;
     if (P.xmode >= SKNR_XTERM_BF16) P.dpad = (pr->d + 31) & ~31;
     P.X = P.transposed ? pr->y : pr->x;
     P.Y = P.transposed ? pr->x : pr->y;

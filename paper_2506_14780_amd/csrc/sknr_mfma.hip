@@ -364,14 +364,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // ----------------------------------------------------------- geometry
-// output tiles of 16 per wave: 4 for plain sweeps with one or two parts
-// (SKNR_MFMA_NT=2 overrides), 2 for weighted sweeps (register budget of the
-// l-wide accumulators) and for three parts (their output-side operands),
-// 1 for 32-wide weighted sweeps with three parts
+// output tiles of 16 per wave: 4 for plain sweeps (SKNR_MFMA_NT=2
+// overrides), 2 for weighted sweeps (register budget of the l-wide
+// accumulators), 1 for 32-wide weighted sweeps with three parts (their
+// output-side operands on top)
 static int mfma_nt(int ell, int parts) {
   static const int env_nt = getenv("SKNR_MFMA_NT") ? atoi(getenv("SKNR_MFMA_NT")) : 0;
   if (ell > 16 && parts >= 3) return 1;
-  if (ell > 0 || parts >= 3) return 2;
+  if (ell > 0) return 2;
   return env_nt == 2 ? 2 : 4;
 }
 
@@ -411,7 +411,7 @@ static void go_mfma_ell(const SweepArgs& a, hipStream_t s) {
   const int e = a.ell;
   if (e == 0) {
     if (mfma_nt(0, XP) == 2) go_mfma<0, XP, 2>(a, s);
-    else go_mfma<0, XP, (XP >= 3 ? 2 : 4)>(a, s);
+    else go_mfma<0, XP, 4>(a, s);
   } else if (e <= 8) go_mfma<8, XP, 2>(a, s);
   else if (e <= 16) go_mfma<16, XP, 2>(a, s);
   else go_mfma<32, XP, (XP >= 3 ? 1 : 2)>(a, s);

@@ -82,10 +82,11 @@ def test_fullsize_stored_cost(sk, ctx):
     assert df <= 64 * U32 * ladder[-1] + 1e-12 * np.abs(f).max()
 
 
-def test_fullsize_clouds_matrix_core_cost(sk, ctx):
+@pytest.mark.parametrize("parts", [2, 3])
+def test_fullsize_clouds_matrix_core_cost(sk, ctx, parts):
     prob = W.gaussian_clouds()
     gp = sk.Problem(a=to_dev(prob.a), b=to_dev(prob.b), x=to_dev(prob.x), y=to_dev(prob.y),
-                    xterm=sk.XTERM_BF16X3)
+                    xterm=sk.XTERM_BF16X3 if parts == 2 else sk.XTERM_BF16X6)
     ladder = [1e-1, 1e-2, 2e-3]
     f, g, res = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=150, ell=16, warm_mode=sk.WARM_SEQUENTIAL)
     f, g = f.cpu().numpy(), g.cpu().numpy()
@@ -93,7 +94,7 @@ def test_fullsize_clouds_matrix_core_cost(sk, ctx):
           "vs exact", res["marginal_err_exact"], flush=True)
     assert res["status"] in (0, 1) and np.all(np.isfinite(f)) and np.all(np.isfinite(g))
     rows = _rows(prob.n)
-    Cm, bound = bf16_cost_model(prob.x[rows], prob.y, 1.0, True, mu_points=(prob.x, prob.y))
+    Cm, bound = bf16_cost_model(prob.x[rows], prob.y, 1.0, parts=parts, mu_points=(prob.x, prob.y))
     fr = O.c_transform_row(g, Cm, prob.b, ladder[-1])
     df = np.abs(f[rows] - fr).max()
     print(f"rows: max|f - T_r(g)| = {df:.3e}  (cost bound {bound.max():.3e})", flush=True)

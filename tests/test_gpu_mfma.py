@@ -1,7 +1,7 @@
 """GPU parity of the matrix-core (bf16 cross term) cost against the FP64
 oracle.
 
-The library's cost for xterm BF16 / BF16X3 is C~_ij = fma(-2 s, x~_i .
+The library's cost for xterm BF16 / BF16X3 / BF16X6 is C~_ij = fma(-2 s, x~_i .
 y~_j, n_i + n_j) with the dot product on matrix cores.  Its exact
 definition apart from the order of the FP32 accumulation inside the matrix
 cores is modelled on the CPU (tests._helpers.bf16_cost_model), which also
@@ -10,7 +10,8 @@ gives a rigorous per-element bound on |C~ - C_model|.  A c-transform is
 match the oracle's on C_model within max(bound) + the FP32 log-sum-exp
 tolerance 64 u eps.  End-to-end solves are compared with the oracle on the
 exact cost with the stated targets (potentials 1e-5 relative to the cost
-range, transport cost 1e-6 relative) for BF16X3; plain BF16 is reported.
+range, transport cost 1e-6 relative) for BF16X3 and BF16X6; plain BF16 is
+reported.
 """
 import numpy as np
 import pytest
@@ -82,23 +83,24 @@ def test_c_transforms_mfma(sk, ctx, n, m, d, scale, eps, parts):
 
 
 def test_mfma_auto_selects_split_for_large_d(sk, ctx):
-    """xterm AUTO uses the bf16 hi/lo split for d >= 16 (bit-identical)."""
+    """xterm AUTO uses the three-part bf16 split for d >= 16 (bit-identical)."""
     x, y, a, b = _clouds(300, 400, 32, seed=3)
     f = to_dev(0.1 * np.random.default_rng(0).standard_normal(300))
     g1 = sk.c_transform_col(ctx, _gp(sk, x, y, a, b, 1.0, sk.XTERM_AUTO), 0.05, f)[0].cpu().numpy()
-    g2 = sk.c_transform_col(ctx, _gp(sk, x, y, a, b, 1.0, sk.XTERM_BF16X3), 0.05, f)[0].cpu().numpy()
+    g2 = sk.c_transform_col(ctx, _gp(sk, x, y, a, b, 1.0, sk.XTERM_BF16X6), 0.05, f)[0].cpu().numpy()
     assert np.array_equal(g1, g2)
 
 
-def test_mfma_evaluate_and_coupling(sk, ctx):
+@pytest.mark.parametrize("parts", [2, 3])
+def test_mfma_evaluate_and_coupling(sk, ctx, parts):
     """FP64 evaluation on C~ (vs the oracle on C_model, relative slack
     exp(max bound / eps) - 1) and on the exact cost (FP64 distances)."""
     n, m, d, scale, eps = 260, 530, 64, 1.0 / 64, 0.05
     x, y, a, b = _clouds(n, m, d, seed=11)
-    Cm, bound = bf16_cost_model(x, y, scale, True)
+    Cm, bound = bf16_cost_model(x, y, scale, parts=parts)
     Cx = O.sqeuclid_cost(x.astype(np.float64), y.astype(np.float64), scale)
     r = O.sinkhorn(Cm, a, b, eps, tol=1e-8, max_iter=20000)
-    gp = _gp(sk, x, y, a, b, scale, sk.XTERM_BF16X3)
+    gp = _gp(sk, x, y, a, b, scale, sk.XTERM_BF16X3 if parts == 2 else sk.XTERM_BF16X6)
     ev = sk.evaluate(ctx, gp, eps, to_dev(r.f), to_dev(r.g))
     rel = np.expm1(bound.max() / eps)
     rows, cols = O.marginals(r.f, r.g, Cm, a, b, eps)
@@ -115,15 +117,17 @@ def test_mfma_evaluate_and_coupling(sk, ctx):
     assert np.all(np.abs(P - Pm) <= (rel + 1e-6) * Pm + 1e-45)
 
 
-def test_mfma_projected_system(sk, ctx):
-    """Weighted sweep (W = P~^T V) and the projected Newton system on C~."""
+@pytest.mark.parametrize("parts,ell", [(2, 5), (3, 5), (3, 24)])
+def test_mfma_projected_system(sk, ctx, parts, ell):
+    """Weighted sweep (W = P~^T V) and the projected Newton system on C~;
+    l = 24 takes the widest basis-width instance."""
     n, m, d, scale, eps = 400, 650, 64, 1.0 / 64, 0.05
     x, y, a, b = _clouds(n, m, d, seed=12)
-    Cm, bound = bf16_cost_model(x, y, scale, True)
+    Cm, bound = bf16_cost_model(x, y, scale, parts=parts)
     rng = np.random.default_rng(3)
     r = O.sinkhorn(Cm, a, b, eps, tol=1e-4, max_iter=5000)
-    V = np.linalg.qr(rng.standard_normal((n, 5)))[0]
-    gp = _gp(sk, x, y, a, b, scale, sk.XTERM_BF16X3)
+    V = np.linalg.qr(rng.standard_normal((n, ell)))[0]
+    gp = _gp(sk, x, y, a, b, scale, sk.XTERM_BF16X3 if parts == 2 else sk.XTERM_BF16X6)
     G, grad, q = sk.projected_system(ctx, gp, eps, to_dev(r.f), to_dev(V))
     step = O.projected_newton(r.f, Cm, a, b, eps, V)
     G_ref = -eps * step["hess"]
