@@ -124,6 +124,10 @@ hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t stream);
 
 // matrix-core cost (cost kinds 2, 3, 4 = bf16 cross term with 1, 2, 3 bf16
 // parts per coordinate; `parts` below)
+// weighted sweeps of FP32 point costs, 2 <= d <= 3: the matrix-core lane
+// layout with the cost on the VALU and W = P^T V on FP32 matrix cores
+bool sweep_pw_eligible(int ell, int d);
+hipError_t launch_sweep_pw(const SweepArgs& a, hipStream_t s, hipEvent_t mid);
 hipError_t launch_sweep_mfma(const SweepArgs& a, int parts, hipStream_t stream, hipEvent_t mid);
 size_t mfma_part_floats(int n_out, int n_red, int ell, int parts, int* nsplit, int* rps, int* nblk);
 hipError_t launch_pack_points(const float* x, int np, int d, const float* mu, double scale, int dpad, int parts,

@@ -525,6 +525,8 @@ static int stream_cpt(int cost_kind, int ell, bool vec, int d) {
 size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bool vec, int* nsplit, int* rps,
                          int* nblk, bool stream_kernel) {
   if (cost_kind >= 2) return mfma_part_floats(n_out, n_red, ell, cost_kind - 1, nsplit, rps, nblk);
+  if (cost_kind == 1 && stream_kernel && sweep_pw_eligible(ell, d))
+    return mfma_part_floats(n_out, n_red, ell, 0, nsplit, rps, nblk);
   if (!stream_kernel) {
     int rpw = ell > 0 ? 1 : 4;
     *nsplit = 1;
@@ -606,6 +608,7 @@ hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t s) {
 
 hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t s, hipEvent_t mid) {
   if (cost_kind >= 2) return launch_sweep_mfma(a, cost_kind - 1, s, mid);
+  if (cost_kind == 1 && sweep_pw_eligible(a.ell, a.d)) return launch_sweep_pw(a, s, mid);
   const int cpt = stream_cpt(cost_kind, a.ell, vec, a.d);
   if (cost_kind == 0) {
     if (a.ell == 0) return cpt == 4 ? go_stream<4, 0, 0, 1, 8>(a, s, mid) : go_stream<1, 0, 0, 1, 8>(a, s, mid);

@@ -114,26 +114,54 @@ __device__ __forceinline__ f32x4 cross_mem(const uint4* const (&pa)[3], const ui
 }
 
 // ============================================================================
-// Streaming c-transform sweep with the matrix-core cost.  A workgroup owns
-// NC = 64*NT outputs (wave w: columns [16*NT*w, 16*NT*(w+1)) of the block,
-// NT tiles of 16) and one split of the reduce side, processed in tiles of 16
-// rows.  Lane (g, c) keeps an online (sig, S, Sc[, acc]) state per output
-// tile over the rows 4g..4g+3 of every row tile; the four states of a column
-// merge by a butterfly (xor 16, xor 32) with a fixed operand order, and the
-// partial is written in the layout of the generic streaming sweep
+// Streaming c-transform sweep in the matrix-core lane layout.  A workgroup
+// owns NC = 64*NT outputs (wave w: columns [16*NT*w, 16*NT*(w+1)) of the
+// block, NT tiles of 16) and one split of the reduce side, processed in
+// tiles of 16 rows.  Lane (g, c) keeps an online (sig, S, Sc) state per
+// output tile over the rows 4g..4g+3 of every row tile; the four states of a
+// column merge by a butterfly (xor 16, xor 32) with a fixed operand order,
+// and the partial is written in the layout of the generic streaming sweep
 // ([nsplit][3+ell][n_out]) so that the same split merge and finishing
-// kernels complete it.  KS > 0: K-steps known at compile time, the output
-// side operands stay in registers; KS == 0: any dpad, operands reloaded.
+// kernels complete it.
+//
+// Cost: XP >= 1 bf16 parts, cross term on matrix cores (KS > 0: K-steps
+// known at compile time, the output-side operands stay in registers;
+// KS == 0: any dpad, operands reloaded); XP == 0: FP32 squared distance of
+// DV-dimensional points on the VALU, in the order of the generic sweep
+// (t_k = x_k - y_k, t_0^2 then fma(t_k, t_k, .)), times the cost scale when
+// SC.
+//
+// Weighted sweeps (ELL > 0): W = sum_r p_r V_r is a contraction over the
+// reduce rows, run on FP32 matrix cores (16x16x4 f32: A = V^T with M = basis
+// index, K = rows; B = p with K = rows, N = columns; lane (g, c) supplies
+// V[row 4g+i][basis c] and p[row 4g+i][column c] for MFMA i of a row tile
+// and holds W[basis 4g..4g+3][column c]).  The four row groups of a column
+// share one shift sig, so every lane rescales only its own column of the
+// accumulators.  The shift only has to keep the terms finite: it is
+// re-synchronised (cross-lane max) only when some row exceeds it by more
+// than 32 / K, a wave-uniform test, so terms stay below 2^32 and the
+// relative precision of FP32 is unchanged.  With the VALU cost the V rows of
+// the split are staged in LDS, transposed (one 16-byte read gives a lane
+// its four rows of a basis column).
 // ============================================================================
-template <int ELL, int KS, int XP, int NT>
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int ELL, int KS, int XP, int NT, int DV = 0, bool SC = false>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_mfma(SweepArgs A) {
   if (gate_closed(A.st, A.gate)) return;
   extern __shared__ float4 smem4[];
   constexpr int EL = ELL > 0 ? ELL : 1;
   constexpr int NQ = 3 + (ELL > 0 ? ELL : 0);
+  constexpr int NB = ELL > 0 ? (ELL + 15) / 16 : 1;  // 16-wide basis blocks of W
   constexpr int NCW = 16 * NT;
   constexpr int NC = WAVES * NCW;
   constexpr int KR = KS > 0 ? KS : 1;
+  constexpr int DQ = XP == 0 ? (DV > 0 ? DV : 1) : 1;  // output-side point width (VALU cost)
+  constexpr int DX = XP == 0 && DV > 2 ? DV - 2 : 0;   // reduce-side coordinates beyond sR.zw
+  constexpr bool VLDS = XP == 0 && ELL > 0;             // V of the split in LDS
+  static_assert(XP > 0 || (DV >= 1 && DV <= 8), "VALU cost: 1 <= d <= 8");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, c16 = lane & 15;
@@ -145,16 +173,36 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int ks = KS > 0 ? KS : (A.dpad >> 5);
   const int dq = A.dpad >> 3;  // uint4 per packed point
   const float m2cs = A.m2cs;
+  const float cscale = A.cscale;
+  const float thr = 32.f / K;  // slack of the lazy shift (cost units)
 
   // reduce-side rows of this split: offset hat potential U + L as a
-  // normalised double-float, and the scaled squared norm
+  // normalised double-float, then the scaled squared norm (matrix-core
+  // cost) or the first two coordinates (VALU cost; sX holds the rest)
   float4* sR = smem4;
+  float* sX = reinterpret_cast<float*>(smem4 + A.rows_per_split);
+  // transposed V: sV[l * vrs + row], vrs = rows_per_split + 4 (16-byte rows)
+  const int vrs = A.rows_per_split + 4;
+  float* sV = sX + (size_t)A.rows_per_split * DX;
   for (int t = threadIdx.x; t < nr; t += TPB) {
     float2 u = A.Uin[r0 + t];
     float2 s = two_sum(L, u.x);
     s.y += u.y;
     s = fast_two_sum(s.x, s.y);
-    sR[t] = make_float4(s.x, s.y, A.Nred[r0 + t], 0.f);
+    if (XP > 0) {
+      sR[t] = make_float4(s.x, s.y, A.Nred[r0 + t], 0.f);
+    } else {
+      const float* xp = A.Pred + (size_t)(r0 + t) * DQ;
+      sR[t] = make_float4(s.x, s.y, xp[0], DQ > 1 ? xp[DQ > 1 ? 1 : 0] : 0.f);
+#pragma unroll
+      for (int k = 0; k < DX; ++k) sX[t * (DX > 0 ? DX : 1) + k] = xp[2 + k];
+    }
+  }
+  if (VLDS) {
+    for (int idx = threadIdx.x; idx < nr * EL; idx += TPB) {
+      const int r = idx / EL, l = idx - r * EL;
+      sV[l * vrs + r] = A.Vred[(size_t)(r0 + r) * EL + l];
+    }
   }
   __syncthreads();
 
@@ -165,23 +213,31 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   const uint4* const pout[3] = {A.Hout, XP == 3 ? A.Mout : A.Lout, A.Lout};
   const uint4* const pred[3] = {A.Hred, XP == 3 ? A.Mred : A.Lred, A.Lred};
   bf16x8 bo[NT][3][KR];
+  float qy[NT][DQ];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     colc[t] = min(cb + 16 * t + c16, A.n_out - 1);
-    hy[t] = A.Nout[colc[t]];
-    if (KS > 0) {
-      const size_t base = (size_t)colc[t] * dq + g;
+    if (XP > 0) {
+      hy[t] = A.Nout[colc[t]];
+      if (KS > 0) {
+        const size_t base = (size_t)colc[t] * dq + g;
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int s = 0; s < KR; ++s) bo[t][q][s] = q < XP ? as_bf8(pout[q][base + 4 * s]) : bo[t][0][s];
+          for (int s = 0; s < KR; ++s) bo[t][q][s] = q < XP ? as_bf8(pout[q][base + 4 * s]) : bo[t][0][s];
+      }
+    } else {
+      hy[t] = 0.f;
+#pragma unroll
+      for (int k = 0; k < DQ; ++k) qy[t][k] = A.Pout[(size_t)colc[t] * DQ + k];
     }
   }
 
   // (sig, S + Sc) per output as in the generic sweep; T collects the
   // chunk sums of two row tiles in plain FP32 (at most 8 terms <= 1 each)
   // before one TwoSum adds it into (S, Sc)
-  float sig[NT], S[NT], Sc[NT], T[NT], acc[NT][EL];
+  float sig[NT], S[NT], Sc[NT], T[NT];
+  f32x4 W[NT][NB];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     sig[t] = SIG0;
@@ -189,7 +245,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     Sc[t] = 0.f;
     T[t] = 0.f;
 #pragma unroll
-    for (int l = 0; l < EL; ++l) acc[t][l] = 0.f;
+    for (int b = 0; b < NB; ++b) W[t][b] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
 
   // (the lambdas below capture these locals, not the argument struct, so
@@ -200,7 +256,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   // iteration earlier) and the loads of tile k+2 are in flight.
   bf16x8 ai[3][KR];
   auto load_a = [&](int rt) __attribute__((always_inline)) {
-    if (KS > 0) {
+    if (XP > 0 && KS > 0) {
       const size_t ra = (size_t)(r0 + min(rt + c16, nr - 1)) * dq + g;
 #pragma unroll
       for (int q = 0; q < 3; ++q)
@@ -209,6 +265,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
   };
   auto cross = [&](int rt, f32x4 (&xy)[NT]) __attribute__((always_inline)) {
+    if (XP == 0) return;
     if (KS > 0) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) xy[t] = cross_regs<XP, KR>(ai, bo[t]);
@@ -236,27 +293,66 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
       rowc[i] = ok[i] ? rl : nr - 1;
       rw[i] = sR[rowc[i]];
     }
+    float xr[4][DX > 0 ? DX : 1];
+    if (DX > 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < DX; ++k) xr[i][k] = sX[rowc[i] * (DX > 0 ? DX : 1) + k];
+    }
     float p[NT][4];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       float s[4], e[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float cv = fmaf(m2cs, xy[t][i], rw[i].z + hy[t]);
+        float cv;
+        if (XP > 0) {
+          cv = fmaf(m2cs, xy[t][i], rw[i].z + hy[t]);
+        } else {
+          float dt = rw[i].z - qy[t][0];
+          float c2 = dt * dt;
+          if (DQ > 1) {
+            dt = rw[i].w - qy[t][DQ > 1 ? 1 : 0];
+            c2 = fmaf(dt, dt, c2);
+          }
+#pragma unroll
+          for (int k = 0; k < DX; ++k) {
+            dt = xr[i][k] - qy[t][2 + k < DQ ? 2 + k : 0];
+            c2 = fmaf(dt, dt, c2);
+          }
+          cv = SC ? c2 * cscale : c2;
+        }
         // Fast2Sum: U + L dominates |C~| (L >= 2 max|C~|)
         const float sv = rw[i].x - cv;
         const float ev = ((rw[i].x - sv) - cv) + rw[i].y;
         s[i] = (!MASK || ok[i]) ? sv : SIG0;
         e[i] = (!MASK || ok[i]) ? ev : 0.f;
       }
-      const float mx = fmaxf(fmaxf(s[0], s[1]), fmaxf(s[2], s[3]));
-      if (mx > sig[t]) {
+      float mx = fmaxf(fmaxf(s[0], s[1]), fmaxf(s[2], s[3]));
+      if (ELL > 0) {
+        // one shift per column across its four row groups (W sums over
+        // them), raised lazily: the test is wave-uniform
+        if (__any(mx > sig[t] + thr)) {
+          mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+          mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+          if (mx > sig[t]) {
+            const float sc = ex2((sig[t] - mx) * K);
+            S[t] *= sc;
+            Sc[t] *= sc;
+            T[t] *= sc;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) W[t][b][i] *= sc;
+            sig[t] = mx;
+          }
+        }
+      } else if (mx > sig[t]) {
         const float sc = ex2((sig[t] - mx) * K);
         S[t] *= sc;
         Sc[t] *= sc;
         T[t] *= sc;
-#pragma unroll
-        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[t][l] *= sc;
         sig[t] = mx;
       }
 #pragma unroll
@@ -265,19 +361,27 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     if (ELL > 0) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float4* vr = reinterpret_cast<const float4*>(Vred + (size_t)(r0 + rowc[i]) * EL);
+      for (int b = 0; b < NB; ++b) {
+        const int l = 16 * b + c16;
+        float va[4];
+        if (VLDS) {
+          // rows rt+4g .. rt+4g+3 lie inside the staged block (rt + 16 <=
+          // rows_per_split); rows past nr are unset and replaced by 0
+          const float4 v4 = *reinterpret_cast<const float4*>(&sV[(l < EL ? l : 0) * vrs + rt + 4 * g]);
+          va[0] = v4.x;
+          va[1] = v4.y;
+          va[2] = v4.z;
+          va[3] = v4.w;
 #pragma unroll
-        for (int l4 = 0; l4 < EL / 4; ++l4) {
-          const float4 v = vr[l4];
+          for (int i = 0; i < 4; ++i) va[i] = (l < EL && (!MASK || ok[i])) ? va[i] : 0.f;
+        } else {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            acc[t][4 * l4 + 0] = fmaf(p[t][i], v.x, acc[t][4 * l4 + 0]);
-            acc[t][4 * l4 + 1] = fmaf(p[t][i], v.y, acc[t][4 * l4 + 1]);
-            acc[t][4 * l4 + 2] = fmaf(p[t][i], v.z, acc[t][4 * l4 + 2]);
-            acc[t][4 * l4 + 3] = fmaf(p[t][i], v.w, acc[t][4 * l4 + 3]);
-          }
+          for (int i = 0; i < 4; ++i) va[i] = l < EL ? Vred[(size_t)(r0 + rowc[i]) * EL + (l < EL ? l : 0)] : 0.f;
         }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) W[t][b] = mfma_f32(va[i], p[t][i], W[t][b]);
       }
     }
   };
@@ -326,19 +430,12 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int t = 0; t < NT; ++t) {
       const float sg2 = __shfl_xor(sig[t], off, 64), S2 = __shfl_xor(S[t], off, 64),
                   C2 = __shfl_xor(Sc[t], off, 64);
-      float a2[EL];
-#pragma unroll
-      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) a2[l] = __shfl_xor(acc[t][l], off, 64);
       float f1, f2;
       if (lower) {
         lse_merge(sig[t], S[t], Sc[t], sg2, S2, C2, K, f1, f2);
-#pragma unroll
-        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[t][l] = acc[t][l] * f1 + a2[l] * f2;
       } else {
         float t1 = sg2, t2 = S2, t3 = C2;
         lse_merge(t1, t2, t3, sig[t], S[t], Sc[t], K, f1, f2);
-#pragma unroll
-        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) acc[t][l] = a2[l] * f1 + acc[t][l] * f2;
         sig[t] = t1;
         S[t] = t2;
         Sc[t] = t3;
@@ -346,7 +443,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
   }
 
-  // partial of this split: lane (g, c) writes the quantities q = g (mod 4)
+  // partial of this split: lanes g = 0, 1, 2 write sig, S, Sc; lane (g, c)
+  // writes W[basis 16b + 4g + i][column c]
   const int n_out = A.n_out;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -357,19 +455,36 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
       else if (g == 1) base[(size_t)n_out] = S[t];
       else if (g == 2) base[(size_t)2 * n_out] = Sc[t];
 #pragma unroll
-      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l)
-        if (((3 + l) & 3) == g) base[(size_t)(3 + l) * n_out] = acc[t][l];
+      for (int b = 0; b < (ELL > 0 ? NB : 0); ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int l = 16 * b + 4 * g + i;
+          if (l < EL) base[(size_t)(3 + l) * n_out] = W[t][b][i];
+        }
     }
   }
 }
 
 // ----------------------------------------------------------- geometry
-// output tiles of 16 per wave: 4 for plain sweeps (SKNR_MFMA_NT=2
-// overrides), 2 for weighted sweeps (register budget of the l-wide
-// accumulators), 1 for 32-wide weighted sweeps with three parts (their
-// output-side operands on top)
+// output tiles of 16 per wave (matrix-core cost): 4 for plain sweeps
+// (SKNR_MFMA_NT=2 overrides), 2 for weighted sweeps, 1 for 32-wide weighted
+// sweeps with three parts (register budget of the output-side operands, the
+// W accumulators and the V operands)
+//
+// VALU-cost weighted sweeps: one output tile per wave and at least 256
+// reduce rows per split (SKNR_PW_RMIN overrides).  Measured on the 4096^2
+// d = 2 solve: more splits (fewer rows each) cost more in partials written
+// and merged (3 + l floats per output per split) than they gain in
+// parallelism, and more output tiles per wave halve the workgroup count.
+constexpr int kPwNT = 1;
+static int pw_rmin() {
+  static const int env = getenv("SKNR_PW_RMIN") ? atoi(getenv("SKNR_PW_RMIN")) : 0;
+  return env >= 16 ? (env & ~15) : 256;
+}
+
 static int mfma_nt(int ell, int parts) {
   static const int env_nt = getenv("SKNR_MFMA_NT") ? atoi(getenv("SKNR_MFMA_NT")) : 0;
+  if (parts == 0) return kPwNT;
   if (ell > 16 && parts >= 3) return 1;
   if (ell > 0) return 2;
   return env_nt == 2 ? 2 : 4;
@@ -383,8 +498,13 @@ size_t mfma_part_floats(int n_out, int n_red, int ell, int parts, int* nsplit, i
   int ns = (target + ncb - 1) / ncb;
   int r = (n_red + ns - 1) / ns;
   r = (r + 15) & ~15;
-  if (r < 64) r = 64;
-  if (r > 2048) r = 2048;
+  const int rmin = (parts == 0 && ell > 0) ? pw_rmin() : 64;
+  if (r < rmin) r = rmin;
+  // VALU-cost weighted sweeps stage V in LDS: 16 + 4 + 4 ell bytes per row
+  // (+ 4 padding rows) within 48 KiB
+  const int ellp0 = ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32));
+  const int rcap = (parts == 0 && ell > 0) ? (((49152 - 16 * ellp0) / (20 + 4 * ellp0)) & ~15) : 2048;
+  if (r > rcap) r = rcap;
   const int rmax = (n_red + 15) & ~15;
   if (r > rmax) r = rmax;
   ns = (n_red + r - 1) / r;
@@ -415,6 +535,40 @@ static void go_mfma_ell(const SweepArgs& a, hipStream_t s) {
   } else if (e <= 8) go_mfma<8, XP, 2>(a, s);
   else if (e <= 16) go_mfma<16, XP, 2>(a, s);
   else go_mfma<32, XP, (XP >= 3 ? 1 : 2)>(a, s);
+}
+
+// weighted sweeps of FP32 point costs with 2 <= d <= 3 (the VALU cost in
+// the matrix-core layout, W on FP32 matrix cores)
+bool sweep_pw_eligible(int ell, int d) {
+  static const int env_pw = getenv("SKNR_PW") ? atoi(getenv("SKNR_PW")) : 1;
+  return env_pw != 0 && ell > 0 && (d == 2 || d == 3);
+}
+
+template <int ELL, int DV, int NT>
+static hipError_t go_pw(const SweepArgs& a, hipStream_t s) {
+  dim3 grid((a.n_out + 64 * NT - 1) / (64 * NT), a.nsplit);
+  const size_t sm = (size_t)a.rows_per_split * (sizeof(float4) + (DV > 2 ? (DV - 2) * sizeof(float) : 0)) +
+                    (size_t)ELL * (a.rows_per_split + 4) * sizeof(float);
+  if (sm > 49152 || (a.rows_per_split & 15)) return hipErrorInvalidValue;
+  if (a.cscale != 1.0f) hipLaunchKernelGGL((k_sweep_mfma<ELL, 1, 0, NT, DV, true>), grid, dim3(TPB), sm, s, a);
+  else hipLaunchKernelGGL((k_sweep_mfma<ELL, 1, 0, NT, DV, false>), grid, dim3(TPB), sm, s, a);
+  return hipSuccess;
+}
+
+template <int DV, int NT>
+static hipError_t go_pw_ell(const SweepArgs& a, hipStream_t s) {
+  if (a.ell <= 8) return go_pw<8, DV, NT>(a, s);
+  if (a.ell <= 16) return go_pw<16, DV, NT>(a, s);
+  return go_pw<32, DV, NT>(a, s);
+}
+
+
+hipError_t launch_sweep_pw(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
+  if (!sweep_pw_eligible(a.ell, a.d) || a.ell > 32) return hipErrorInvalidValue;
+  const hipError_t e = a.d == 2 ? go_pw_ell<2, kPwNT>(a, s) : go_pw_ell<3, kPwNT>(a, s);
+  if (e != hipSuccess) return e;
+  if (mid) (void)hipEventRecord(mid, s);
+  return launch_sweep_tail(a, s);
 }
 
 hipError_t launch_sweep_mfma(const SweepArgs& a, int parts, hipStream_t s, hipEvent_t mid) {

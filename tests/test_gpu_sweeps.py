@@ -150,6 +150,34 @@ def test_projected_system_matches_oracle(sk, ctx):
     assert abs(q - O.semidual_value(f, C, prob.a, prob.b, eps)) <= 64 * U32 * eps
 
 
+@pytest.mark.parametrize("n,m,d,ell,scale", [(400, 650, 2, 5, 1.0), (1100, 900, 2, 16, 1.0),
+                                             (700, 1333, 3, 32, 0.37), (1300, 517, 3, 12, 1.0)])
+def test_projected_system_points(sk, ctx, n, m, d, ell, scale):
+    """The projected system on a cost built from points (the weighted sweep
+    accumulates W = P~^T V on FP32 matrix cores, in splits of several
+    hundred rows with a ragged last split) against the oracle on the FP32
+    cost model of the same points."""
+    rng = np.random.default_rng(n + m + d)
+    x = rng.random((n, d)).astype(np.float32)
+    y = rng.random((m, d)).astype(np.float32)
+    a = rng.dirichlet(np.full(n, 4.0))
+    b = rng.dirichlet(np.full(m, 4.0))
+    C = fp32_sqeuclid(x, y, scale).astype(np.float64)
+    eps = 0.02
+    r = O.sinkhorn(C, a, b, eps, tol=1e-4, max_iter=4000)
+    V = np.linalg.qr(rng.standard_normal((n, ell)))[0]
+    gp = sk.Problem(a=to_dev(a), b=to_dev(b), x=to_dev(x), y=to_dev(y), cost_scale=scale)
+    print(f"case n={n} m={m} d={d} ell={ell} scale={scale}", flush=True)
+    G, grad, q = sk.projected_system(ctx, gp, eps, to_dev(r.f), to_dev(V))
+    step = O.projected_newton(r.f, C, a, b, eps, V)
+    G_ref = -eps * step["hess"]
+    print("G rel err", np.abs(G - G_ref).max() / np.abs(G_ref).max(), "grad", np.abs(grad - step["grad"]).max(),
+          flush=True)
+    assert np.allclose(G, G_ref, rtol=0, atol=1e-5 * np.abs(G_ref).max())
+    assert np.allclose(grad, step["grad"], rtol=0, atol=1e-6 * np.abs(a).max() + 1e-4 * np.abs(step["grad"]).max())
+    assert abs(q - O.semidual_value(r.f, C, a, b, eps)) <= 64 * U32 * eps
+
+
 def test_newton_step_matches_oracle(sk, ctx):
     prob = _stored_problem(300, 420, seed=7)
     C = prob.C.astype(np.float64)
@@ -194,6 +222,31 @@ def test_spectral_basis_matches_oracle(sk, ctx, ell):
     assert rho[0] == 1.0
     assert np.allclose(rho[1:], rho_r[1:ell + 1], atol=1e-6)
     # orthonormal in L2(a), orthogonal to the constants
+    assert np.allclose(V.T @ (prob.a[:, None] * V), np.eye(ell), atol=1e-5)
+    assert np.abs(prob.a @ V).max() < 1e-5
+    gap = rho_r[ell] - rho_r[ell + 1]
+    if gap > 1e-3:
+        cos = _principal_cosines(V, Vr[:, :ell], prob.a)
+        print("min cos", cos.min(), flush=True)
+        assert cos.min() > 1 - 1e-4
+
+
+def test_spectral_basis_points(sk, ctx):
+    """The warm-start basis on a cost built from points (its products run
+    the 32-wide weighted sweeps in both orientations) against the oracle's
+    dense eigh on the FP32 cost model."""
+    prob = W.uniform_square(900, 700, seed=22)
+    ell = 12
+    C = fp32_sqeuclid(prob.x, prob.y, prob.cost_scale).astype(np.float64)
+    eps = 0.05
+    ref = O.sinkhorn(C, prob.a, prob.b, eps, tol=1e-11, max_iter=100000)
+    Vr, rho_r = O.spectral_basis(ref.f, ref.g, C, prob.a, prob.b, eps, ell + 1, method="dense")
+    V, rho, it = sk.spectral_basis(ctx, gpu_problem(prob), eps, to_dev(ref.f), ell, oversample=8, max_iter=300,
+                                   tol=1e-10)
+    V = V.cpu().numpy()
+    print("rho gpu", rho[:6], "oracle", rho_r[:6], "iters", it, flush=True)
+    assert rho[0] == 1.0
+    assert np.allclose(rho[1:], rho_r[1:ell + 1], atol=1e-6)
     assert np.allclose(V.T @ (prob.a[:, None] * V), np.eye(ell), atol=1e-5)
     assert np.abs(prob.a @ V).max() < 1e-5
     gap = rho_r[ell] - rho_r[ell + 1]
