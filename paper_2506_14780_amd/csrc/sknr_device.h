@@ -49,6 +49,16 @@ __device__ __forceinline__ float2 df_mul(float2 a, float2 b) {
 __device__ __forceinline__ float2 df_neg(float2 a) { return make_float2(-a.x, -a.y); }
 
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Offset L of the streaming sweeps.  The reduce side enters as U + L (a
+// normalised double-float (h, l), |U| <= maxabs) and the running max sig of
+// a column is one of the values fl(h - C) with |C| <= cmax, so h lies in
+// [L - maxabs, L + maxabs] and sig in [L - maxabs - cmax, L + maxabs].
+// With L = 3 (cmax + maxabs), h / sig stays within [1/2, 2] (with a margin
+// of cmax on both sides), so h - sig is exact (Sterbenz) and the exponent
+// argument ((h - sig) - C + l) K is rounded only relative to its own size:
+// it is formed as fma((h - sig) - C, K, l K) with l K staged per row.
+__device__ __forceinline__ float sweep_offset(float cmax, float maxabs) { return 3.f * (cmax + maxabs); }
 __device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
 
 __device__ __forceinline__ bool gate_closed(const DevState* st, int gate) {
@@ -158,9 +168,16 @@ template <int ELL>
 __device__ __forceinline__ void finalize_output(const SweepArgs& A, const EpsConst& E, int o, float L, float sig,
                                                 float S, float Sc, const float* acc, double& err, double& dot,
                                                 float& mx) {
-  // log2(S + Sc) = k + log2(mant) + Sc/(S ln 2), S = mant * 2^k, mant in [0.5, 1)
+  // log2(S + Sc) = k + log2(mant) + Sc/(S ln 2), S = mant * 2^k with mant
+  // in [sqrt(1/2), sqrt(2)): a sum just above a power of two then gets a
+  // small log of the mantissa (accurate relative to itself) instead of
+  // log2(~0.5) ~ -1 whose last-bit error survives the cancellation with k
   int k;
   float mant = frexpf(S, &k);
+  if (mant < 0.70710678f) {
+    mant *= 2.f;
+    k -= 1;
+  }
   float lm = lg2(mant);
   float corr = (Sc / S) * 1.4426950408889634f;
   float2 l2 = fast_two_sum((float)k, lm);

@@ -7,9 +7,10 @@
 // and runs an online max-shifted log-sum-exp in FP32.  Precision (the FP32
 // exponent (U_r - C_ro)/eps cancels O(|C|) terms down to O(eps)) is kept by:
 //   * double-float potentials (hi, lo FP32 pairs);
-//   * an exact subtraction U_r - C_ro: Fast2Sum after offsetting U by a
-//     constant L >= |C| (streaming sweep) or TwoSum (row sweep of a stored
-//     cost), the error term joining the small argument;
+//   * an argument formed without cancellation error: after offsetting U by
+//     L = 3 (max|C| + max|U|) the difference of (U + L) and the running max
+//     is exact (Sterbenz), and C is subtracted from that small difference
+//     (streaming sweeps); TwoSum in the row sweep of a stored cost;
 //   * compensated accumulation of the exponentials and of the split merges;
 //   * log of the sum split into exponent + log2 of the mantissa.
 // Everything else (cross-block merges, epilogues) works on O(n + m) data.
@@ -19,6 +20,8 @@
 #include <float.h>
 #include <math.h>
 #include <stdlib.h>
+
+#include <type_traits>
 
 namespace sknr {
 
@@ -92,15 +95,17 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
   const int d = (COST == 1 && D > 0) ? D : dg;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = 2.f * (A.cmax + A.st->maxabs[A.ma_in]);
+  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
 
+  // sU[r] = (h, l K) of the offset potential U_r + L = h + l
   float2* sU = reinterpret_cast<float2*>(smem);
   float* sX = reinterpret_cast<float*>(smem + (size_t)A.rows_per_split * sizeof(float2));
   for (int t = threadIdx.x; t < nr; t += TPB) {
     float2 u = A.Uin[r0 + t];
     float2 s = two_sum(L, u.x);
     s.y += u.y;
-    sU[t] = fast_two_sum(s.x, s.y);
+    s = fast_two_sum(s.x, s.y);
+    sU[t] = make_float2(s.x, s.y * K);
     if (COST == 1) {
       for (int k = 0; k < d; ++k) sX[t * d + k] = k < dg ? A.Pred[(size_t)(r0 + t) * dg + k] : 0.f;
     }
@@ -139,16 +144,22 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
     for (int l = 0; l < (ELL > 0 ? ELL : 1); ++l) acc[c][l] = 0.f;
   }
 
-  for (int rb = wave; rb < nr; rb += WAVES * R) {
-    float s[R][CPT], e[R][CPT];
+  // one chunk of R rows per wave (MASK: rows past nr present)
+  auto chunk = [&](auto maskc, int rb) __attribute__((always_inline)) {
+    constexpr bool MASK = decltype(maskc)::value;
+    float s[R][CPT], cvr[R][CPT], ux[R], uk[R];
+    bool okr[R];
     int rowl[R];
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       int rl = rb + rr * WAVES;
-      bool ok = rl < nr;
+      bool ok = MASK ? rl < nr : true;
       int rlc = ok ? rl : (nr - 1);
       rowl[rr] = rlc;
+      okr[rr] = ok;
       float2 u = sU[rlc];
+      ux[rr] = u.x;
+      uk[rr] = u.y;
       float cv[CPT];
       if (COST == 0) {
         const float* crow = crow0 + (size_t)(r0 + rlc) * A.ldc;
@@ -171,11 +182,8 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
       }
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
-        // Fast2Sum: |u.x| >= |C| because u carries the offset L >= 2 max|C|
-        float sv = u.x - cv[c];
-        float ev = ((u.x - sv) - cv[c]) + u.y;
-        s[rr][c] = ok ? sv : SIG0;
-        e[rr][c] = ok ? ev : 0.f;
+        cvr[rr][c] = cv[c];
+        s[rr][c] = ok ? u.x - cv[c] : SIG0;
       }
     }
 #pragma unroll
@@ -193,7 +201,10 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
       }
       float p[R];
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) p[rr] = ex2(((s[rr][c] - sig[c]) + e[rr][c]) * K);
+      for (int rr = 0; rr < R; ++rr) {
+        const float pv = ex2(fmaf((ux[rr] - sig[c]) - cvr[rr][c], K, uk[rr]));
+        p[rr] = (!MASK || okr[rr]) ? pv : 0.f;
+      }
       // pairwise sum of the chunk, then a compensated add
       float t[R];
 #pragma unroll
@@ -215,7 +226,11 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
         }
       }
     }
-  }
+  };
+  // full chunks, then at most one chunk with rows past nr
+  int rb = wave;
+  for (; rb + (R - 1) * WAVES < nr; rb += WAVES * R) chunk(std::integral_constant<bool, false>{}, rb);
+  if (rb < nr) chunk(std::integral_constant<bool, true>{}, rb);
 
   // ---- merge the 4 waves through LDS, in wave order (deterministic)
   __syncthreads();
@@ -268,7 +283,7 @@ __global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) {
   constexpr int EL = ELL > 0 ? ELL : 1;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = 2.f * (A.cmax + A.st->maxabs[A.ma_in]);
+  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
   const int n_out = A.n_out;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int col = gid >> 2, part4 = gid & 3;

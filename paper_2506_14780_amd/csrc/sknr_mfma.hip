@@ -169,16 +169,16 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int nr = min(A.rows_per_split, A.n_red - r0);
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = 2.f * (A.cmax + A.st->maxabs[A.ma_in]);
+  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
   const int ks = KS > 0 ? KS : (A.dpad >> 5);
   const int dq = A.dpad >> 3;  // uint4 per packed point
   const float m2cs = A.m2cs;
   const float cscale = A.cscale;
   const float thr = 32.f / K;  // slack of the lazy shift (cost units)
 
-  // reduce-side rows of this split: offset hat potential U + L as a
-  // normalised double-float, then the scaled squared norm (matrix-core
-  // cost) or the first two coordinates (VALU cost; sX holds the rest)
+  // reduce-side rows of this split: offset hat potential U + L = h + l as
+  // (h, l K), then the scaled squared norm (matrix-core cost) or the first
+  // two coordinates (VALU cost; sX holds the rest)
   float4* sR = smem4;
   float* sX = reinterpret_cast<float*>(smem4 + A.rows_per_split);
   // transposed V: sV[l * vrs + row], vrs = rows_per_split + 4 (16-byte rows)
@@ -190,10 +190,10 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     s.y += u.y;
     s = fast_two_sum(s.x, s.y);
     if (XP > 0) {
-      sR[t] = make_float4(s.x, s.y, A.Nred[r0 + t], 0.f);
+      sR[t] = make_float4(s.x, s.y * K, A.Nred[r0 + t], 0.f);
     } else {
       const float* xp = A.Pred + (size_t)(r0 + t) * DQ;
-      sR[t] = make_float4(s.x, s.y, xp[0], DQ > 1 ? xp[DQ > 1 ? 1 : 0] : 0.f);
+      sR[t] = make_float4(s.x, s.y * K, xp[0], DQ > 1 ? xp[DQ > 1 ? 1 : 0] : 0.f);
 #pragma unroll
       for (int k = 0; k < DX; ++k) sX[t * (DX > 0 ? DX : 1) + k] = xp[2 + k];
     }
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
     float p[NT][4];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      float s[4], e[4];
+      float s[4], cvk[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float cv;
@@ -323,11 +323,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
           }
           cv = SC ? c2 * cscale : c2;
         }
-        // Fast2Sum: U + L dominates |C~| (L >= 2 max|C~|)
-        const float sv = rw[i].x - cv;
-        const float ev = ((rw[i].x - sv) - cv) + rw[i].y;
-        s[i] = (!MASK || ok[i]) ? sv : SIG0;
-        e[i] = (!MASK || ok[i]) ? ev : 0.f;
+        cvk[i] = cv;
+        s[i] = (!MASK || ok[i]) ? rw[i].x - cv : SIG0;
       }
       float mx = fmaxf(fmaxf(s[0], s[1]), fmaxf(s[2], s[3]));
       if (ELL > 0) {
@@ -356,7 +353,11 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
         sig[t] = mx;
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) p[t][i] = ex2(((s[i] - sig[t]) + e[i]) * K);
+      for (int i = 0; i < 4; ++i) {
+        // (h - sig) exact, see sweep_offset
+        const float pv = ex2(fmaf((rw[i].x - sig[t]) - cvk[i], K, rw[i].y));
+        p[t][i] = (!MASK || ok[i]) ? pv : 0.f;
+      }
       T[t] += (p[t][0] + p[t][1]) + (p[t][2] + p[t][3]);
     }
     if (ELL > 0) {

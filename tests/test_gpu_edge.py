@@ -41,8 +41,14 @@ def test_degenerate_shapes_match_oracle(sk, ctx, n, m):
     gp = sk.Problem(a=to_dev(a), b=to_dev(b), x=to_dev(x), y=to_dev(y))
     ladder = [2e-1, 1e-1, 5e-2]
     print(f"case n={n} m={m}", flush=True)
-    f, g, res = sk.solve(ctx, gp, ladder, tol=1e-7, max_iter=20000)
-    assert res["status"] == 0 and res["marginal_err"] < 1e-7
+    # With one or two points on a side a single term dominates each FP32
+    # log-sum-exp; its sum S ~ 1 is rounded once (relative 2^-24) on each
+    # side, so the attainable L1 marginal error is about 2 * 2^-24 = 1.2e-7.
+    # The tolerance sits above that floor.
+    tol = 3e-7
+    f, g, res = sk.solve(ctx, gp, ladder, tol=tol, max_iter=20000)
+    print("status", res["status"], "marginal", res["marginal_err"], flush=True)
+    assert res["status"] == 0 and res["marginal_err"] < tol
     C = fp32_sqeuclid(x, y).astype(np.float64)
     fo, go, _ = O.solve_schedule(C, a, b, ladder, 1e-11, 200000)
     fo, go = O.normalize_gauge(fo, go, a, b)
