@@ -843,89 +843,84 @@ __device__ __forceinline__ double sum_partials(const double* part, int nblk, int
   return s;
 }
 
-// One wavefront: lane i keeps row i of G in registers.  Padded modes
-// (columns of V beyond ell_real are zero) become identity rows.
+// One workgroup: the l x l Newton system (Algorithm 4.1, NR update) from the
+// block partials of k_nr_assemble.  The partials are summed per entry in
+// block order (chunks of 32 blocks); G is symmetrised and modes beyond
+// ell_real (zero columns of V) become identity rows.  [G | grad] is then
+// reduced by Gauss-Jordan elimination without pivoting, one barrier per
+// column: step k updates the entries (i, j), i != k, j > k, and reads only
+// column k and row k, which it does not write.  Its pivots are those of
+// G = L D L^T, so the positive-definiteness test (every pivot > 1e-15 of
+// the largest diagonal entry) is the one of a Cholesky factorisation.
 template <int ELL>
-__global__ __launch_bounds__(64) void k_nr_solve(const double* part, int nblk, int ell_real, float* coef32,
-                                                 double* coef64, double* Gout, double* gout, DevState* st,
-                                                 int gate) {
+__global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, int ell_real, float* coef32,
+                                                  double* coef64, double* Gout, double* gout, DevState* st,
+                                                  int gate) {
   if (gate_closed(st, gate)) return;
   constexpr int NE = ELL * ELL;
+  constexpr int NA = ELL + 1;  // augmented width
+  const int tid = threadIdx.x;
   const double eps = st->eps;
-  __shared__ double A[ELL][ELL + 1];
-  __shared__ double g[ELL];
-  for (int e = threadIdx.x; e < NE + ELL; e += blockDim.x) {
-    double v = sum_partials(part, nblk, NE + ELL, e);
-    if (e < NE) A[e / ELL][e % ELL] = v;
-    else g[e - NE] = v;
+  __shared__ double R[NE + ELL];   // raw sums: G row-major, then grad
+  __shared__ double A[ELL][NA + 1];
+  for (int e = tid; e < NE + ELL; e += 256) {
+    double v = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 32)
+      v += sum_partials(part + (size_t)b0 * (NE + ELL), min(32, nblk - b0), NE + ELL, e);
+    R[e] = v;
   }
   __syncthreads();
-  const int lane = threadIdx.x;
-  const int i = lane < ELL ? lane : ELL - 1;
-  double a[ELL];
   double dmax = 0;
-#pragma unroll
-  for (int j = 0; j < ELL; ++j) {
-    double v = 0.5 * (A[i][j] + A[j][i]);
-    if (i >= ell_real || j >= ell_real) v = (i == j) ? 1.0 : 0.0;
-    a[j] = v;
-    double djj = (j < ell_real) ? A[j][j] : 1.0;
-    dmax = fmax(dmax, djj);
+  for (int j = 0; j < ell_real; ++j) dmax = fmax(dmax, R[j * ELL + j]);
+  for (int e = tid; e < ELL * NA; e += 256) {
+    const int i = e / NA, j = e - i * NA;
+    double v;
+    if (j == ELL) v = i < ell_real ? R[NE + i] : 0.0;
+    else if (i >= ell_real || j >= ell_real) v = (i == j) ? 1.0 : 0.0;
+    else v = 0.5 * (R[i * ELL + j] + R[j * ELL + i]);
+    A[i][j] = v;
   }
-  const double bi = i < ell_real ? g[i] : 0.0;
   if (Gout) {
-    for (int e = lane; e < ell_real * ell_real; e += blockDim.x) Gout[e] = 0.5 * (A[e / ell_real][e % ell_real] + A[e % ell_real][e / ell_real]);
-    for (int e = lane; e < ell_real; e += blockDim.x) gout[e] = g[e];
+    for (int e = tid; e < ell_real * ell_real; e += 256) {
+      const int i = e / ell_real, j = e - i * ell_real;
+      Gout[e] = 0.5 * (R[i * ELL + j] + R[j * ELL + i]);
+    }
+    for (int e = tid; e < ell_real; e += 256) gout[e] = R[NE + e];
   }
+  __syncthreads();
   int ok = 1;
-#pragma unroll
   for (int k = 0; k < ELL; ++k) {
-    double akk = __shfl(a[k], k, 64);
-    if (!(akk > 1e-300 && akk > 1e-15 * dmax)) {
+    double piv = A[k][k];
+    if (!(piv > 1e-300 && piv > 1e-15 * dmax)) {
       ok = 0;
-      akk = 1.0;
+      piv = 1.0;
     }
-    const double lkk = sqrt(akk);
-    const double inv = 1.0 / lkk;
-    a[k] = (i > k) ? a[k] * inv : (i == k ? lkk : a[k]);
-#pragma unroll
-    for (int j = k + 1; j < ELL; ++j) {
-      const double ljk = __shfl(a[k], j, 64);
-      if (i >= j) a[j] -= a[k] * ljk;
+    const double inv = 1.0 / piv;
+    const int w = NA - (k + 1);  // columns k+1 .. ELL (the last is grad)
+    for (int e = tid; e < ELL * w; e += 256) {
+      const int i = e / w, j = k + 1 + (e - i * w);
+      if (i != k) A[i][j] -= A[i][k] * (A[k][j] * inv);
     }
+    __syncthreads();
   }
-  // L y = g: y[t] broadcast to all lanes
-  double y[ELL];
-#pragma unroll
-  for (int t = 0; t < ELL; ++t) {
-    double acc = bi;
-#pragma unroll
-    for (int r = 0; r < t; ++r) acc -= a[r] * y[r];
-    y[t] = __shfl(acc / a[t], t, 64);
-  }
-  // L^T z = y: z_t = (y_t - sum_{r>t} l_rt z_r) / l_tt, lane r holds l_rt = a[t]
-  double zi = 0;
-#pragma unroll
-  for (int t = ELL - 1; t >= 0; --t) {
-    double term = (i > t && lane < ELL) ? a[t] * zi : 0.0;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) term += __shfl_xor(term, off, 64);
-    const double ltt = __shfl(a[t], t, 64);
-    const double zt = (y[t] - term) / ltt;
-    if (i == t) zi = zt;
-  }
-  const double c = eps * zi;
-  const int bad = (lane < ELL) && !(fabs(c) < 1e30);
-  const int anybad = __any(bad);
-  ok = ok && !anybad;
-  if (lane < ELL) {
-    coef64[lane] = c;
-    coef32[lane] = ok ? (float)c : 0.f;
-  }
-  if (lane == 0) {
-    st->chol_ok = ok;
-    st->accept = 0;
-    st->newton_tried += 1;
+  // the system is now diagonal: z_i = A[i][ELL] / A[i][i]
+  if (tid < 64) {
+    const int i = tid < ELL ? tid : ELL - 1;
+    double di = A[i][i];
+    if (!(di > 1e-300 && di > 1e-15 * dmax)) di = 1.0;
+    const double c = eps * (A[i][ELL] / di);
+    const int bad = (tid < ELL) && !(fabs(c) < 1e30);
+    const int anybad = __any(bad);
+    ok = ok && !anybad;
+    if (tid < ELL) {
+      coef64[tid] = c;
+      coef32[tid] = ok ? (float)c : 0.f;
+    }
+    if (tid == 0) {
+      st->chol_ok = ok;
+      st->accept = 0;
+      st->newton_tried += 1;
+    }
   }
 }
 
@@ -1001,7 +996,7 @@ hipError_t launch_nr_assemble(int ell, const float* V, const float* mdiff, const
 template <int E>
 static void nr_solve_e(const double* part, int nblk, int ell, float* coef32, double* coef64, double* Gout,
                        double* gout, DevState* st, int gate, hipStream_t s) {
-  hipLaunchKernelGGL((k_nr_solve<E>), dim3(1), dim3(64), 0, s, part, nblk, ell, coef32, coef64, Gout, gout, st,
+  hipLaunchKernelGGL((k_nr_solve<E>), dim3(1), dim3(256), 0, s, part, nblk, ell, coef32, coef64, Gout, gout, st,
                      gate);
 }
 hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32, double* coef64, double* Gout,
