@@ -62,13 +62,14 @@ def algorithmic_work(kind: str):
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2.0, WRITE_SIZE 1 GiB
 # -> x1.0); see profiles/.  Valid only for the kernel sources they were
 # taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip).
-TRAFFIC_KERNEL_SHA1 = "aa839824d9103439410a239f9ca7542a60314190"
+TRAFFIC_KERNEL_SHA1 = "8ab8666a4a385f5580abf60a2076fd1b0ab66dd1"
 TRAFFIC_BYTES = {
-    "sweep_stream_points_l0:main": (198.04 * 1.9999 + 1857.49 * 1.0000) * 1024,
-    "sweep_stream_stored_l0:main": (524898.60 * 1.9999 + 6144.00 * 1.0000) * 1024,
-    "sweep_rows_stored_l0:main": (525903.19 * 1.9999 + 530.48 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x3_l0:main": (91197.44 * 1.9999 + 6224.05 * 1.0000) * 1024,
-    "sweep_stream_points_bf16_l0:main": (25480.29 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_l0:main": (222.19 * 1.9999 + 2072.50 * 1.0000) * 1024,
+    "sweep_stream_stored_l0:main": (524980.33 * 1.9999 + 6144.00 * 1.0000) * 1024,
+    "sweep_rows_stored_l0:main": (525907.89 * 1.9999 + 531.21 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x3_l0:main": (91561.05 * 1.9999 + 6224.04 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x6_l0:main": (140509.32 * 1.9999 + 6225.81 * 1.0000) * 1024,
+    "sweep_stream_points_bf16_l0:main": (25468.08 * 1.9999 + 6223.96 * 1.0000) * 1024,
 }
 
 

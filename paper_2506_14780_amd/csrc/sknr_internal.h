@@ -27,7 +27,7 @@ struct DevState {
   double err;           // last L1 marginal error estimate (output side)
   double err_aux;       // sum |mdiff| of the last row sweep (row marginal of P~)
   double dots[NDOT];    // <U, w> of hat potentials (FP64 sums)
-  float maxabs[NMA];    // max |U.hi| of hat potentials (for the Fast2Sum offset)
+  float maxabs[NMA];    // max |U.hi| of hat potentials (for the sweep offset L)
   // constants of the current eps, read by the kernels (so that a captured
   // chunk of iterations serves every stage)
   double eps;           // eps
@@ -79,7 +79,7 @@ struct SweepArgs {
   const float* Nout;
   int dpad;
   float m2cs;            // -2 * cost_scale (FP32)
-  float cmax;            // upper bound of |C| (Fast2Sum offset)
+  float cmax;            // upper bound of |C| (sweep offset L)
   // potentials
   const float2* Uin;     // reduce-side hat potential (n_red)
   int ma_in;             // maxabs slot of Uin
