@@ -34,6 +34,8 @@ struct WS {
   float* part;
   double *blk_err, *blk_dot;
   float* blk_max;
+  double* ap_dot;  // per-block partials of the Newton update F' (its consumer reduces them)
+  float* ap_max;
   double* nrpart;
   double* nrsum;  // partials summed: one (k*k + k) block
   int nr_rows_blk, nr_cols_blk;
@@ -213,6 +215,8 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   add(sizeof(float) * (size_t)n * std::max(ellp, 1));
   add(sizeof(float) * (size_t)m * std::max(ellp, 1));
   add(sizeof(float) * pmax + 16);
+  add(sizeof(double) * ((n + 255) / 256));
+  add(sizeof(float) * ((n + 255) / 256));
   add(sizeof(double) * nbmax * 2);
   add(sizeof(float) * nbmax);
   int nrb = 64, ncb = 64;
@@ -297,8 +301,9 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
   w.blk_err = (double*)A.take(sizeof(double) * nbmax);
   w.blk_dot = (double*)A.take(sizeof(double) * nbmax);
   w.blk_max = (float*)A.take(sizeof(float) * nbmax);
-  // at most 16 + 16 partial blocks: the one-wave solver sums them with
-  // independent loads
+  w.ap_dot = (double*)A.take(sizeof(double) * ((n + 255) / 256));
+  w.ap_max = (float*)A.take(sizeof(float) * ((n + 255) / 256));
+  // Newton partial blocks: at most 64 row + 64 column blocks
   w.nr_rows_blk = std::min(64, std::max(1, (n + 63) / 64));
   w.nr_cols_blk = std::min(64, std::max(1, (m + 63) / 64));
   int e1 = std::max(ellw, 1);
@@ -451,6 +456,14 @@ struct Engine {
     a.Nout = w.NY;
     a.Uin = Fin;
     a.ma_in = ma_in;
+    if (Fin == w.Fp) {
+      // F' comes straight from the Newton update, whose scalars are left
+      // as block partials
+      a.in_blkmax = w.ap_max;
+      a.in_blkdot = w.ap_dot;
+      a.in_nblk = (P.n + 255) / 256;
+      a.in_dot_slot = DOT_FP;
+    }
     a.lw_out = w.lYdf;
     a.w_out = w.wY32;
     a.w_out64 = P.wY;
@@ -552,8 +565,8 @@ struct Engine {
                               w.st, gate_base, s));
     HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout, w.st,
                            gate_base, s));
-    HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.blk_dot, w.blk_max, w.st,
-                           gate_base | G_CHOL_OK, DOT_FP, MA_FP, s));
+    HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.ap_dot, w.ap_max, w.st,
+                           gate_base | G_CHOL_OK, DOT_FP, MA_FP, s, /*with_finish=*/false));
   }
 
   // One SK iteration (ping-pong on G[p]).

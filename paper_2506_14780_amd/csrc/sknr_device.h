@@ -59,6 +59,15 @@ __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x)
 // argument ((h - sig) - C + l) K is rounded only relative to its own size:
 // it is formed as fma((h - sig) - C, K, l K) with l K staged per row.
 __device__ __forceinline__ float sweep_offset(float cmax, float maxabs) { return 3.f * (cmax + maxabs); }
+
+// max |Uin.hi| of a sweep's reduce-side input: from the producer's
+// per-block partials when given, else from the solver state
+__device__ __forceinline__ float sweep_in_maxabs(const SweepArgs& A) {
+  if (!A.in_blkmax) return A.st->maxabs[A.ma_in];
+  float m = 0.f;
+  for (int b = 0; b < A.in_nblk; ++b) m = fmaxf(m, A.in_blkmax[b]);
+  return m;
+}
 __device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
 
 __device__ __forceinline__ bool gate_closed(const DevState* st, int gate) {

@@ -83,6 +83,15 @@ struct SweepArgs {
   // potentials
   const float2* Uin;     // reduce-side hat potential (n_red)
   int ma_in;             // maxabs slot of Uin
+  // optional: Uin's scalars as per-block partials of the kernel that wrote
+  // it (the Newton update): max|Uin.hi| = max of in_blkmax (used for the
+  // offset instead of st->maxabs[ma_in]); the finish kernel stores that
+  // max in st->maxabs[ma_in] and the block-order sum of in_blkdot in
+  // st->dots[in_dot_slot] before its decisions
+  const float* in_blkmax;
+  const double* in_blkdot;
+  int in_nblk;
+  int in_dot_slot;
   const float2* lw_out;  // output-side log weights (double-float)
   const float* w_out;    // output-side weights FP32
   const double* w_out64; // output-side weights FP64 (dots)
@@ -152,9 +161,11 @@ hipError_t launch_nr_assemble(int ell, const float* V, const float* rdiff, const
 hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32,
                            double* coef64, double* Gout, double* gout, DevState* st, int gate,
                            hipStream_t s);
+// with_finish == false leaves the per-block partials (blk, blkmax) to the
+// consumer of Fp (SweepArgs.in_blkmax / in_blkdot)
 hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a,
                            float2* Fp, int n, double* blk, float* blkmax, DevState* st, int gate,
-                           int dot_slot, int ma_slot, hipStream_t s);
+                           int dot_slot, int ma_slot, hipStream_t s, bool with_finish = true);
 hipError_t launch_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp,
                          const float2* Gt, float2* G, int m, DevState* st, int gate, hipStream_t s);
 

@@ -42,8 +42,26 @@ __global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
   e = block_sum_d(e, sbd);
   d = block_sum_d(d, sbd + 8);
   m = block_max_f(m, sbf);
+  // the input's scalars from its producer's block partials (same order as
+  // the one-workgroup scalar reduction they replace)
+  double din = 0;
+  float mxin = 0.f;
+  if (A.in_blkdot) {
+    __shared__ double sbd2[8];
+    __shared__ float sbf2[8];
+    for (int b = threadIdx.x; b < A.in_nblk; b += blockDim.x) {
+      din += A.in_blkdot[b];
+      mxin = fmaxf(mxin, A.in_blkmax[b]);
+    }
+    din = block_sum_d(din, sbd2);
+    mxin = block_max_f(mxin, sbf2);
+  }
   if (threadIdx.x == 0) {
     DevState* st = A.st;
+    if (A.in_blkdot) {
+      st->dots[A.in_dot_slot] = din;
+      st->maxabs[A.ma_in] = mxin;
+    }
     if (A.Uold) {
       if (A.mdiff) st->err_aux = e; else st->err = e;
     }
@@ -95,7 +113,7 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
   const int d = (COST == 1 && D > 0) ? D : dg;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
+  const float L = sweep_offset(A.cmax, sweep_in_maxabs(A));
 
   // sU[r] = (h, l K) of the offset potential U_r + L = h + l
   float2* sU = reinterpret_cast<float2*>(smem);
@@ -283,7 +301,7 @@ __global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) {
   constexpr int EL = ELL > 0 ? ELL : 1;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
+  const float L = sweep_offset(A.cmax, sweep_in_maxabs(A));
   const int n_out = A.n_out;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int col = gid >> 2, part4 = gid & 3;
@@ -1008,17 +1026,19 @@ hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32,
 }
 template <int E>
 static void nr_apply_e(const float2* F, const float* V, const float* coef, const double* a, float2* Fp, int n,
-                       double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot, hipStream_t s) {
+                       double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot, hipStream_t s,
+                       bool with_finish) {
   int nb = (n + 255) / 256;
   hipLaunchKernelGGL((k_nr_apply<E>), dim3(nb), dim3(256), 0, s, F, V, coef, a, Fp, n, blk, blkmax, st, gate);
-  hipLaunchKernelGGL(k_scalars_finish, dim3(1), dim3(256), 0, s, blk, blkmax, nb, st, gate, dot_slot, ma_slot);
+  if (with_finish)
+    hipLaunchKernelGGL(k_scalars_finish, dim3(1), dim3(256), 0, s, blk, blkmax, nb, st, gate, dot_slot, ma_slot);
 }
 hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a, float2* Fp,
                            int n, double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot,
-                           hipStream_t s) {
-  if (ell <= 8) nr_apply_e<8>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s);
-  else if (ell <= 16) nr_apply_e<16>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s);
-  else nr_apply_e<32>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s);
+                           hipStream_t s, bool with_finish) {
+  if (ell <= 8) nr_apply_e<8>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s, with_finish);
+  else if (ell <= 16) nr_apply_e<16>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s, with_finish);
+  else nr_apply_e<32>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s, with_finish);
   return hipGetLastError();
 }
 
