@@ -34,8 +34,10 @@ struct WS {
   float* part;
   double *blk_err, *blk_dot;
   float* blk_max;
-  double* ap_dot;  // per-block partials of the Newton update F' (its consumer reduces them)
+  double* ap_dot;   // per-block partials of the Newton update F' (the candidate's finish reduces them)
   float* ap_max;
+  double* ap_ddot;  // per-block <F' - F, a>
+  float* E1;        // n x 8: expm1((F' - F)/eps) in column 0, the candidate sweep's basis
   double* nrpart;
   double* nrsum;  // partials summed: one (k*k + k) block
   int nr_rows_blk, nr_cols_blk;
@@ -198,7 +200,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   // weighted sweeps run l-wide (Newton) or up to 32-wide (warm start)
   const int ellw = ellp > 0 ? 32 : 0;
   // T_c (output Y), with and without weights
-  for (int e : {0, ellp, ellw}) {
+  for (int e : {0, ellp > 0 ? 8 : 0, ellp, ellw}) {
     size_t p = sweep_part_floats(m, n, e, sweep_kind(P), P.d, stream_vec(P, m), &ns, &rps, &nb, col_is_stream(P));
     pmax = std::max(pmax, p);
     nbmax = std::max(nbmax, nb);
@@ -217,6 +219,8 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   add(sizeof(float) * pmax + 16);
   add(sizeof(double) * ((n + 255) / 256));
   add(sizeof(float) * ((n + 255) / 256));
+  add(sizeof(double) * ((n + 255) / 256));
+  add(sizeof(float) * 8 * (size_t)n);
   add(sizeof(double) * nbmax * 2);
   add(sizeof(float) * nbmax);
   int nrb = 64, ncb = 64;
@@ -288,7 +292,7 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
   int ns, rps, nb, nbmax = 0;
   size_t pmax = 0;
   const int ellw = ellp > 0 ? 32 : 0;
-  for (int e : {0, ellp, ellw}) {
+  for (int e : {0, ellp > 0 ? 8 : 0, ellp, ellw}) {
     pmax = std::max(pmax, sweep_part_floats(m, n, e, sweep_kind(P), P.d, stream_vec(P, m), &ns, &rps, &nb,
                                             col_is_stream(P)));
     nbmax = std::max(nbmax, nb);
@@ -303,6 +307,8 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
   w.blk_max = (float*)A.take(sizeof(float) * nbmax);
   w.ap_dot = (double*)A.take(sizeof(double) * ((n + 255) / 256));
   w.ap_max = (float*)A.take(sizeof(float) * ((n + 255) / 256));
+  w.ap_ddot = (double*)A.take(sizeof(double) * ((n + 255) / 256));
+  w.E1 = (float*)A.take(sizeof(float) * 8 * (size_t)n);
   // Newton partial blocks: at most 64 row + 64 column blocks
   w.nr_rows_blk = std::min(64, std::max(1, (n + 63) / 64));
   w.nr_cols_blk = std::min(64, std::max(1, (m + 63) / 64));
@@ -456,13 +462,15 @@ struct Engine {
     a.Nout = w.NY;
     a.Uin = Fin;
     a.ma_in = ma_in;
-    if (Fin == w.Fp) {
-      // F' comes straight from the Newton update, whose scalars are left
-      // as block partials
-      a.in_blkmax = w.ap_max;
-      a.in_blkdot = w.ap_dot;
-      a.in_nblk = (P.n + 255) / 256;
-      a.in_dot_slot = DOT_FP;
+    if (wmode == W_CAND) {
+      // the candidate of a Newton step: the update's scalars arrive as its
+      // block partials
+      a.aux_blkmax = w.ap_max;
+      a.aux_blkdot = w.ap_dot;
+      a.aux_blkddot = w.ap_ddot;
+      a.aux_nblk = (P.n + 255) / 256;
+      a.aux_dot_slot = DOT_FP;
+      a.aux_ma_slot = MA_FP;
     }
     a.lw_out = w.lYdf;
     a.w_out = w.wY32;
@@ -565,8 +573,15 @@ struct Engine {
                               w.st, gate_base, s));
     HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout, w.st,
                            gate_base, s));
-    HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.ap_dot, w.ap_max, w.st,
-                           gate_base | G_CHOL_OK, DOT_FP, MA_FP, s, /*with_finish=*/false));
+    HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.ap_dot, w.ap_max, w.ap_ddot, w.E1, w.st,
+                           gate_base | G_CHOL_OK, s));
+  }
+
+  // T_c(F') and the acceptance test of the Newton step: a sweep on F whose
+  // basis is the single column expm1((F' - F)/eps), giving T_c(F') =
+  // T_c(F) - eps log1p(w) and Q(F') - Q(F) without cancellation
+  void candidate(int gate) {
+    sweep_col(w.F, MA_F, nullptr, w.Gp, DOT_GP, MA_GP, 8, w.E1, nullptr, W_CAND, gate, F_ACCEPT_DQ);
   }
 
   // One SK iteration (ping-pong on G[p]).
@@ -584,8 +599,7 @@ struct Engine {
     sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, G_NOT_DONE, 0);
     if (!first) {
       newton(ell, G_NOT_DONE);
-      sweep_col(w.Fp, MA_FP, nullptr, w.Gp, DOT_GP, MA_GP, 0, nullptr, nullptr, W_NONE, G_NOT_DONE | G_CHOL_OK,
-                F_ACCEPT_TEST);
+      candidate(G_NOT_DONE | G_CHOL_OK);
     }
     HIPCHK(launch_select(w.Fp, w.Fsk, w.F, P.n, w.Gp, w.Gt, w.G[0], P.m, w.st, G_NOT_DONE, s));
     if (!first)
@@ -1205,7 +1219,7 @@ int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps, double* f_
     E.sweep_col(w.F, MA_F, nullptr, w.Gt, DOT_GT, MA_GT, ellp, w.V, w.W, W_SCALE_WEIGHT, 0, 0);
     E.sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, 0, 0);
     E.newton(ell, 0);
-    E.sweep_col(w.Fp, MA_FP, nullptr, w.Gp, DOT_GP, MA_GP, 0, nullptr, nullptr, W_NONE, G_CHOL_OK, F_ACCEPT_TEST);
+    E.candidate(G_CHOL_OK);
     DevState st = E.read_state();
     double ca = 0, cb = 0;
     for (int i = 0; i < P.n; ++i) ca += P.hX[i] * std::log(P.hX[i]);

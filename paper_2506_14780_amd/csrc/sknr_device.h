@@ -60,14 +60,7 @@ __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x)
 // it is formed as fma((h - sig) - C, K, l K) with l K staged per row.
 __device__ __forceinline__ float sweep_offset(float cmax, float maxabs) { return 3.f * (cmax + maxabs); }
 
-// max |Uin.hi| of a sweep's reduce-side input: from the producer's
-// per-block partials when given, else from the solver state
-__device__ __forceinline__ float sweep_in_maxabs(const SweepArgs& A) {
-  if (!A.in_blkmax) return A.st->maxabs[A.ma_in];
-  float m = 0.f;
-  for (int b = 0; b < A.in_nblk; ++b) m = fmaxf(m, A.in_blkmax[b]);
-  return m;
-}
+
 __device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
 
 __device__ __forceinline__ bool gate_closed(const DevState* st, int gate) {
@@ -196,6 +189,16 @@ __device__ __forceinline__ void finalize_output(const SweepArgs& A, const EpsCon
   out = df_add_f(out, -sig);
   out = df_add_f(out, L);
   out = df_add(out, df_neg(t));
+  if (ELL > 0 && A.wmode == W_CAND) {
+    // candidate of the Newton step: T_c(f')_o = T_c(f)_o - eps log1p(w_o),
+    // w_o = the softmax(f)-weighted average of expm1((f' - f)/eps); the
+    // error slot collects sum_o w_out_o eps log1p(w_o) for Q(f') - Q(f)
+    const double w = (double)acc[0] / ((double)S + (double)Sc);
+    const double tt = ((double)E.eps_df.x + (double)E.eps_df.y) * log1p(w);
+    const float th = (float)tt;
+    out = df_add(out, make_float2(-th, -(float)(tt - (double)th)));
+    err += A.w_out64[o] * tt;
+  }
   A.Uout[o] = out;
   float ratio_m1 = 0.f;
   if (A.Uold) {
@@ -207,7 +210,7 @@ __device__ __forceinline__ void finalize_output(const SweepArgs& A, const EpsCon
   }
   dot += A.w_out64[o] * ((double)out.x + (double)out.y);
   mx = fmaxf(mx, fabsf(out.x));
-  if (ELL > 0) {
+  if (ELL > 0 && A.wmode != W_CAND) {
     float inv = 1.f / (S + Sc);
     float scale = A.wmode == W_SCALE_WEIGHT ? A.w_out[o] : (A.wmode == W_SCALE_RATIO ? 1.f + ratio_m1 : 1.f);
     scale *= inv;

@@ -46,9 +46,12 @@ enum SweepFlag {
   F_CHECK = 1,       // compare the L1 error with tol and set done (col sweeps)
   F_COUNT = 2,       // count this sweep in npass
   F_GSEL = 4,        // record gsel_val into state->gsel when setting done
-  F_ACCEPT_TEST = 8  // after this sweep decide the Newton acceptance test
+  F_ACCEPT_DQ = 16    // after this sweep decide the Newton acceptance test from Q(f') - Q(f)
+                      // formed without cancellation (W_CAND sweep)
 };
-enum WMode { W_NONE = 0, W_SCALE_WEIGHT = 1, W_SCALE_RATIO = 2 };
+// W_CAND: the sweep runs on f with the single basis column expm1((f' - f)/eps)
+// and writes the candidate T_c(f') = T_c(f) - eps log1p(w) instead of W
+enum WMode { W_NONE = 0, W_SCALE_WEIGHT = 1, W_SCALE_RATIO = 2, W_CAND = 3 };
 
 // ---------------------------------------------------------- sweep arguments
 // One c-transform sweep: out_o = eps*lw_o - eps*log sum_r exp((Uin_r - C_ro)/eps)
@@ -83,15 +86,17 @@ struct SweepArgs {
   // potentials
   const float2* Uin;     // reduce-side hat potential (n_red)
   int ma_in;             // maxabs slot of Uin
-  // optional: Uin's scalars as per-block partials of the kernel that wrote
-  // it (the Newton update): max|Uin.hi| = max of in_blkmax (used for the
-  // offset instead of st->maxabs[ma_in]); the finish kernel stores that
-  // max in st->maxabs[ma_in] and the block-order sum of in_blkdot in
-  // st->dots[in_dot_slot] before its decisions
-  const float* in_blkmax;
-  const double* in_blkdot;
-  int in_nblk;
-  int in_dot_slot;
+  // optional scalars of the Newton update f' = f + V c, left as per-block
+  // partials by its kernel; the finish kernel stores, before its decisions,
+  // dots[aux_dot_slot] = sum of aux_blkdot (<f', a>), maxabs[aux_ma_slot] =
+  // max of aux_blkmax, and uses sum of aux_blkddot (<f' - f, a>) in the
+  // acceptance test F_ACCEPT_DQ (sums in block order)
+  const float* aux_blkmax;
+  const double* aux_blkdot;
+  const double* aux_blkddot;
+  int aux_nblk;
+  int aux_dot_slot;
+  int aux_ma_slot;
   const float2* lw_out;  // output-side log weights (double-float)
   const float* w_out;    // output-side weights FP32
   const double* w_out64; // output-side weights FP64 (dots)
@@ -161,11 +166,12 @@ hipError_t launch_nr_assemble(int ell, const float* V, const float* rdiff, const
 hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32,
                            double* coef64, double* Gout, double* gout, DevState* st, int gate,
                            hipStream_t s);
-// with_finish == false leaves the per-block partials (blk, blkmax) to the
-// consumer of Fp (SweepArgs.in_blkmax / in_blkdot)
+// Newton update f' = f + V c (hat form), per-block partials blk = <f', a>,
+// blkmax = max|f'.hi|, blkd = <f' - f, a>, and E1[i * 8] = expm1((f' - f)_i /
+// eps) (columns 1..7 zero: the single basis column of the W_CAND sweep)
 hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a,
-                           float2* Fp, int n, double* blk, float* blkmax, DevState* st, int gate,
-                           int dot_slot, int ma_slot, hipStream_t s, bool with_finish = true);
+                           float2* Fp, int n, double* blk, float* blkmax, double* blkd, float* E1, DevState* st,
+                           int gate, hipStream_t s);
 hipError_t launch_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp,
                          const float2* Gt, float2* G, int m, DevState* st, int gate, hipStream_t s);
 

@@ -42,25 +42,27 @@ __global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
   e = block_sum_d(e, sbd);
   d = block_sum_d(d, sbd + 8);
   m = block_max_f(m, sbf);
-  // the input's scalars from its producer's block partials (same order as
-  // the one-workgroup scalar reduction they replace)
-  double din = 0;
-  float mxin = 0.f;
-  if (A.in_blkdot) {
-    __shared__ double sbd2[8];
+  // the Newton update's scalars from its block partials (same order as a
+  // one-workgroup reduction of them)
+  double dax = 0, ddx = 0;
+  float mxa = 0.f;
+  if (A.aux_blkdot) {
+    __shared__ double sbd2[16];
     __shared__ float sbf2[8];
-    for (int b = threadIdx.x; b < A.in_nblk; b += blockDim.x) {
-      din += A.in_blkdot[b];
-      mxin = fmaxf(mxin, A.in_blkmax[b]);
+    for (int b = threadIdx.x; b < A.aux_nblk; b += blockDim.x) {
+      dax += A.aux_blkdot[b];
+      ddx += A.aux_blkddot[b];
+      mxa = fmaxf(mxa, A.aux_blkmax[b]);
     }
-    din = block_sum_d(din, sbd2);
-    mxin = block_max_f(mxin, sbf2);
+    dax = block_sum_d(dax, sbd2);
+    ddx = block_sum_d(ddx, sbd2 + 8);
+    mxa = block_max_f(mxa, sbf2);
   }
   if (threadIdx.x == 0) {
     DevState* st = A.st;
-    if (A.in_blkdot) {
-      st->dots[A.in_dot_slot] = din;
-      st->maxabs[A.ma_in] = mxin;
+    if (A.aux_blkdot) {
+      st->dots[A.aux_dot_slot] = dax;
+      st->maxabs[A.aux_ma_slot] = mxa;
     }
     if (A.Uold) {
       if (A.mdiff) st->err_aux = e; else st->err = e;
@@ -75,10 +77,12 @@ __global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
       }
       st->armed = 1;
     }
-    if (A.flags & F_ACCEPT_TEST) {
-      double q1 = st->dots[DOT_FP] + st->dots[DOT_GP];
-      double q0 = st->dots[DOT_F] + st->dots[DOT_GT];
-      int acc = (st->chol_ok && q1 > q0) ? 1 : 0;
+    if (A.flags & F_ACCEPT_DQ) {
+      // Q(f') - Q(f) = <f' - f, a> - sum_o b_o eps log1p(w_o): both terms are
+      // accurate relative to themselves, so the sign is reliable where the
+      // difference of two FP32 c-transform sums is not
+      const double dq = ddx - e;
+      int acc = (st->chol_ok && dq > 0) ? 1 : 0;
       st->accept = acc;
       st->newton_accepted += acc;
     }
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
   const int d = (COST == 1 && D > 0) ? D : dg;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = sweep_offset(A.cmax, sweep_in_maxabs(A));
+  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
 
   // sU[r] = (h, l K) of the offset potential U_r + L = h + l
   float2* sU = reinterpret_cast<float2*>(smem);
@@ -301,7 +305,7 @@ __global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) {
   constexpr int EL = ELL > 0 ? ELL : 1;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = sweep_offset(A.cmax, sweep_in_maxabs(A));
+  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
   const int n_out = A.n_out;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int col = gid >> 2, part4 = gid & 3;
@@ -945,13 +949,14 @@ __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, 
 template <int ELL>
 __global__ __launch_bounds__(256) void k_nr_apply(const float2* F, const float* V, const float* coef,
                                                   const double* a, float2* Fp, int n, double* blk, float* blkmax,
-                                                  DevState* st, int gate) {
+                                                  double* blkd, float* E1, DevState* st, int gate) {
   if (gate_closed(st, gate)) return;
   __shared__ float c[ELL];
   if (threadIdx.x < ELL) c[threadIdx.x] = coef[threadIdx.x];
   __syncthreads();
+  const float inv_eps = st->inv_eps;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double dot = 0;
+  double dot = 0, dd = 0;
   float mx = 0.f;
   if (i < n) {
     float dl = 0.f;
@@ -961,37 +966,25 @@ __global__ __launch_bounds__(256) void k_nr_apply(const float2* F, const float* 
     float2 u = df_add_f(F[i], dl);
     Fp[i] = u;
     dot = a[i] * ((double)u.x + (double)u.y);
+    dd = a[i] * (double)dl;
     mx = fabsf(u.x);
+    float4* e = reinterpret_cast<float4*>(E1 + (size_t)i * 8);
+    e[0] = make_float4(expm1f(dl * inv_eps), 0.f, 0.f, 0.f);
+    e[1] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __shared__ double sbd[16];
+  __shared__ double sbd2[16];
   __shared__ float sbf[8];
   dot = block_sum_d(dot, sbd);
+  dd = block_sum_d(dd, sbd2);
   mx = block_max_f(mx, sbf);
   if (threadIdx.x == 0) {
     blk[blockIdx.x] = dot;
+    blkd[blockIdx.x] = dd;
     blkmax[blockIdx.x] = mx;
   }
 }
 
-// one workgroup: st->dots[dot_slot] = sum of blk, st->maxabs[ma_slot] = max of blkmax
-__global__ __launch_bounds__(256) void k_scalars_finish(const double* blk, const float* blkmax, int nblk,
-                                                        DevState* st, int gate, int dot_slot, int ma_slot) {
-  if (gate_closed(st, gate)) return;
-  __shared__ double sbd[16];
-  __shared__ float sbf[8];
-  double d = 0;
-  float m = 0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    d += blk[b];
-    m = fmaxf(m, blkmax[b]);
-  }
-  d = block_sum_d(d, sbd);
-  m = block_max_f(m, sbf);
-  if (threadIdx.x == 0) {
-    st->dots[dot_slot] = d;
-    st->maxabs[ma_slot] = m;
-  }
-}
 
 template <int E>
 static void nr_assemble_e(const float* V, const float* mdiff, const double* a, int n, const float* W, const double* b,
@@ -1026,19 +1019,17 @@ hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32,
 }
 template <int E>
 static void nr_apply_e(const float2* F, const float* V, const float* coef, const double* a, float2* Fp, int n,
-                       double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot, hipStream_t s,
-                       bool with_finish) {
+                       double* blk, float* blkmax, double* blkd, float* E1, DevState* st, int gate, hipStream_t s) {
   int nb = (n + 255) / 256;
-  hipLaunchKernelGGL((k_nr_apply<E>), dim3(nb), dim3(256), 0, s, F, V, coef, a, Fp, n, blk, blkmax, st, gate);
-  if (with_finish)
-    hipLaunchKernelGGL(k_scalars_finish, dim3(1), dim3(256), 0, s, blk, blkmax, nb, st, gate, dot_slot, ma_slot);
+  hipLaunchKernelGGL((k_nr_apply<E>), dim3(nb), dim3(256), 0, s, F, V, coef, a, Fp, n, blk, blkmax, blkd, E1, st,
+                     gate);
 }
 hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a, float2* Fp,
-                           int n, double* blk, float* blkmax, DevState* st, int gate, int dot_slot, int ma_slot,
-                           hipStream_t s, bool with_finish) {
-  if (ell <= 8) nr_apply_e<8>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s, with_finish);
-  else if (ell <= 16) nr_apply_e<16>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s, with_finish);
-  else nr_apply_e<32>(F, V, coef, a, Fp, n, blk, blkmax, st, gate, dot_slot, ma_slot, s, with_finish);
+                           int n, double* blk, float* blkmax, double* blkd, float* E1, DevState* st, int gate,
+                           hipStream_t s) {
+  if (ell <= 8) nr_apply_e<8>(F, V, coef, a, Fp, n, blk, blkmax, blkd, E1, st, gate, s);
+  else if (ell <= 16) nr_apply_e<16>(F, V, coef, a, Fp, n, blk, blkmax, blkd, E1, st, gate, s);
+  else nr_apply_e<32>(F, V, coef, a, Fp, n, blk, blkmax, blkd, E1, st, gate, s);
   return hipGetLastError();
 }
 

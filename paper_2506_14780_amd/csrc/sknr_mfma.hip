@@ -169,7 +169,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int nr = min(A.rows_per_split, A.n_red - r0);
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = sweep_offset(A.cmax, sweep_in_maxabs(A));
+  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
   const int ks = KS > 0 ? KS : (A.dpad >> 5);
   const int dq = A.dpad >> 3;  // uint4 per packed point
   const float m2cs = A.m2cs;

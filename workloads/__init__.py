@@ -26,6 +26,9 @@ __all__ = [
     "grid_histograms",
     "gaussian_clouds",
     "paper_2d_gaussians",
+    "square_vs_annulus",
+    "two_moons",
+    "wot_shaped",
     "separable_cost",
     "serving_trace",
     "EPS_LADDER_C2",
@@ -156,6 +159,65 @@ def paper_2d_gaussians(n: int = 200, seed: int = 5) -> Problem:
     return Problem(a=np.full(n, 1.0 / n), b=np.full(2 * n, 1.0 / (2 * n)),
                    x=x.astype(np.float32), y=y.astype(np.float32),
                    name=f"paper_2d_gaussians_{n}")
+
+
+def square_vs_annulus(n: int = 300, m: int | None = None, seed: int = 8, r_in: float = 0.5,
+                      r_out: float = 1.0) -> Problem:
+    """Sec. 3's square / annulus pair: x uniform on [-1,1]^2, y uniform on
+    the annulus r_in <= |y| <= r_out (radius drawn with density ~ r),
+    uniform weights."""
+    m = n if m is None else m
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, size=(n, 2))
+    r = np.sqrt(rng.uniform(r_in ** 2, r_out ** 2, size=m))
+    t = rng.uniform(0.0, 2.0 * math.pi, size=m)
+    y = np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+    return Problem(a=np.full(n, 1.0 / n), b=np.full(m, 1.0 / m), x=x.astype(np.float32),
+                   y=y.astype(np.float32), name=f"square_vs_annulus_{n}x{m}")
+
+
+def two_moons(n: int = 300, m: int | None = None, seed: int = 9, noise: float = 0.05) -> Problem:
+    """Sec. 3's two-moons pair: x uniform on the upper half circle of radius
+    1 centred at 0, y uniform on the lower half circle centred at (1, 0.5),
+    both with isotropic Gaussian jitter `noise`; uniform weights."""
+    m = n if m is None else m
+    rng = np.random.default_rng(seed)
+    t1 = rng.uniform(0.0, math.pi, size=n)
+    x = np.stack([np.cos(t1), np.sin(t1)], axis=1) + noise * rng.standard_normal((n, 2))
+    t2 = rng.uniform(0.0, math.pi, size=m)
+    y = np.stack([1.0 - np.cos(t2), 0.5 - np.sin(t2)], axis=1) + noise * rng.standard_normal((m, 2))
+    return Problem(a=np.full(n, 1.0 / n), b=np.full(m, 1.0 / m), x=x.astype(np.float32),
+                   y=y.astype(np.float32), name=f"two_moons_{n}x{m}")
+
+
+def wot_shaped(n: int = 6507, m: int = 3815, d: int = 30, seed: int = 10, components: int = 6,
+               drift: float = 0.35) -> Problem:
+    """A synthetic stand-in at the shape of Sec. 5's single-cell maps (day 7
+    -> 8: 6507 x 3815; day 8 -> 9: 3815 x 2982; PCA to R^30, normalised).
+    Each side is a Gaussian mixture in R^d whose per-axis variances decay
+    like the spectrum of a PCA (sigma_k^2 ~ 1/k); the second time point
+    moves every component mean by `drift` along a random direction and adds
+    one new component.  Both clouds are centred on their joint mean and
+    scaled by one factor so that the mean squared norm is 1 (the cost
+    ||x - y||^2 is then O(1)).  Uniform weights.  No data of the original
+    study is used."""
+    rng = np.random.default_rng(seed)
+    sd = 1.0 / np.sqrt(np.arange(1, d + 1))
+    means = rng.standard_normal((components, d)) * sd * 1.5
+    wx = rng.dirichlet(np.full(components, 3.0))
+    cx = rng.choice(components, size=n, p=wx)
+    x = means[cx] + 0.5 * rng.standard_normal((n, d)) * sd
+    step = rng.standard_normal((components, d)) * sd
+    step *= drift / np.linalg.norm(step, axis=1, keepdims=True)
+    means2 = np.concatenate([means + step, rng.standard_normal((1, d)) * sd * 1.5])
+    wy = rng.dirichlet(np.full(components + 1, 3.0))
+    cy = rng.choice(components + 1, size=m, p=wy)
+    y = means2[cy] + 0.5 * rng.standard_normal((m, d)) * sd
+    mu = np.concatenate([x, y]).mean(axis=0)
+    x, y = x - mu, y - mu
+    s = math.sqrt(np.concatenate([(x ** 2).sum(1), (y ** 2).sum(1)]).mean())
+    return Problem(a=np.full(n, 1.0 / n), b=np.full(m, 1.0 / m), x=(x / s).astype(np.float32),
+                   y=(y / s).astype(np.float32), name=f"wot_shaped_{n}x{m}_d{d}")
 
 
 def separable_cost(n: int, m: int, seed: int = 7) -> tuple[Problem, np.ndarray, np.ndarray]:
