@@ -62,14 +62,14 @@ def algorithmic_work(kind: str):
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2.0, WRITE_SIZE 1 GiB
 # -> x1.0); see profiles/.  Valid only for the kernel sources they were
 # taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip).
-TRAFFIC_KERNEL_SHA1 = "8ab8666a4a385f5580abf60a2076fd1b0ab66dd1"
+TRAFFIC_KERNEL_SHA1 = "6631aa873bb81835e677613013dfb9ba49bd5103"
 TRAFFIC_BYTES = {
-    "sweep_stream_points_l0:main": (222.19 * 1.9999 + 2072.50 * 1.0000) * 1024,
-    "sweep_stream_stored_l0:main": (524980.33 * 1.9999 + 6144.00 * 1.0000) * 1024,
-    "sweep_rows_stored_l0:main": (525907.89 * 1.9999 + 531.21 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x3_l0:main": (91561.05 * 1.9999 + 6224.04 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x6_l0:main": (140509.32 * 1.9999 + 6225.81 * 1.0000) * 1024,
-    "sweep_stream_points_bf16_l0:main": (25468.08 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_l0:main": (215.68 * 1.9999 + 2003.92 * 1.0000) * 1024,
+    "sweep_stream_stored_l0:main": (524977.28 * 1.9999 + 6144.00 * 1.0000) * 1024,
+    "sweep_rows_stored_l0:main": (525906.69 * 1.9999 + 528.98 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x3_l0:main": (91679.29 * 1.9999 + 6224.02 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x6_l0:main": (140416.37 * 1.9999 + 6226.22 * 1.0000) * 1024,
+    "sweep_stream_points_bf16_l0:main": (25700.99 * 1.9999 + 6223.96 * 1.0000) * 1024,
 }
 
 
@@ -121,6 +121,40 @@ def mfma_sweep_roofline(sk, W, torch, reps=4):
                      "work_per_element": slots, "traffic": kernel_traffic(main["name"]),
                      "mfma_tflops": flops / avg_s / 1e12,
                      "mfma_frac": flops / avg_s / 1e12 / PEAK_MFMA_BF16_TFLOPS}
+    ctx.close()
+    return out
+
+
+def paper_workloads_bench(sk, W, torch, tol, reps=3):
+    """Sec. 5's workloads on the GPU, SK-NR against plain SK (median of
+    `reps` solves each, after one warm-up): Fig. 5.1's 200 vs 400 Gaussians
+    (eps 1 -> 1/8 by halving, l = 10) and the synthetic stand-ins at the
+    single-cell shapes (6507 x 3815 and 3815 x 2982, d = 30, l = 30,
+    eps 1 -> 1/16 by halving; plain SK at eps = 1 first)."""
+    dev = torch.device("cuda:0")
+    ctx = sk.Context(0)
+    cases = [("fig5.1 gaussians 200x400 d=2", W.paper_2d_gaussians(200), [1.0, 0.5, 0.25, 0.125], 10),
+             ("wot-shaped 6507x3815 d=30", W.wot_shaped(6507, 3815), [1.0, 0.5, 0.25, 0.125, 0.0625], 30),
+             ("wot-shaped 3815x2982 d=30", W.wot_shaped(3815, 2982, seed=11), [1.0, 0.5, 0.25, 0.125, 0.0625], 30)]
+    out = {}
+    for name, prob, ladder, ell in cases:
+        gp = sk.Problem(a=torch.from_numpy(prob.a).to(dev), b=torch.from_numpy(prob.b).to(dev),
+                        x=torch.from_numpy(prob.x).to(dev), y=torch.from_numpy(prob.y).to(dev))
+        row = {"eps_ladder": ladder, "ell": ell}
+        for mode, kw in (("sknr", dict(ell=ell, warm_mode=sk.WARM_SEQUENTIAL)), ("sk", {})):
+            sk.solve(ctx, gp, ladder, tol=tol, max_iter=100000, **kw)
+            torch.cuda.synchronize()
+            ts, res = [], None
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                res = sk.solve(ctx, gp, ladder, tol=tol, max_iter=100000, **kw)[2]
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[mode] = {"ms": 1e3 * float(np.median(ts)), "iters_per_stage": [st["iters"] for st in res["stages"]],
+                         "newton_accepted": [st["newton_accepted"] for st in res["stages"]],
+                         "marginal_err": res["marginal_err"], "status": res["status"]}
+        row["speedup"] = row["sk"]["ms"] / row["sknr"]["ms"]
+        out[name] = row
     ctx.close()
     return out
 
@@ -278,6 +312,7 @@ def main():
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-cost HBM sweep measurement")
     ap.add_argument("--no-mfma", action="store_true", help="skip the d = 64 matrix-core sweep measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the mixed-request serving run")
+    ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 5 workloads (Fig. 5.1, single-cell shapes)")
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-lanes", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -403,6 +438,8 @@ def main():
         out["roofline_mfma_cost"] = mfma_sweep_roofline(sk, W, torch)
     if not args.no_serve:
         out["serving"] = serving_bench(sk, W, torch, args.serve_requests, args.serve_lanes, args.tol)
+    if not args.no_paper:
+        out["paper_workloads"] = paper_workloads_bench(sk, W, torch, args.tol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, ladder, args.tol, args.ell, iters_nr)
     ctx.close()
