@@ -40,6 +40,7 @@ __all__ = [
     "semidual_value",
     "transport_cost",
     "primal_value",
+    "dual_partials",
     "semidual_gradient",
     "semidual_hessian",
     "semidual_hessian_apply",
@@ -130,6 +131,33 @@ def primal_value(f, g, C, a, b, eps) -> float:
     P = coupling(f, g, C, a, b, eps)
     logratio = (f[:, None] + g[None, :] - C) / eps
     return float((P * C).sum() + eps * ((P * logratio).sum() - P.sum() + 1.0))
+
+
+def dual_partials(f, g, x, y, a, b, eps, scale=1.0) -> dict:
+    """Partial derivatives of Q_eps(f, g) (eq. def_Q) with respect to the
+    problem data at fixed potentials, for the squared Euclidean cost
+    C_ij = scale ||x_i - y_j||^2.  At the optimum they are the derivatives
+    of W_eps (eq. primal_EOT / dual_EOT) by the envelope theorem (the
+    potentials are stationary), so no implicit differentiation is needed
+    for W_eps itself:
+      dQ/dC_ij = pi_ij
+      dQ/dx_i  = 2 scale sum_j pi_ij (x_i - y_j)
+      dQ/dy_j  = 2 scale sum_i pi_ij (y_j - x_i)
+      dQ/da_i  = f_i - eps sum_j b_j exp((f_i + g_j - C_ij)/eps)  (= f_i - eps r_i / a_i)
+      dQ/db_j  = g_j - eps c_j / b_j
+    with r, c the row and column sums of pi."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    C = sqeuclid_cost(x, y, scale)
+    P = coupling(f, g, C, a, b, eps)
+    r, c = P.sum(1), P.sum(0)
+    return {
+        "C": P,
+        "x": 2.0 * scale * (r[:, None] * x - P @ y),
+        "y": 2.0 * scale * (c[:, None] * y - P.T @ x),
+        "a": f - eps * r / a,
+        "b": g - eps * c / b,
+    }
 
 
 # ------------------------------------- semi-dual derivatives, App. A.1

@@ -425,3 +425,65 @@ def test_schedule_sknr_reaches_the_same_optimum_as_sk():
     assert np.max(np.abs(f0 - f1)) < 1e-6 and np.max(np.abs(g0 - g1)) < 1e-6
     assert sum(r.iters for r in r1[1:]) < sum(r.iters for r in r0[1:])
     assert all(r.newton_accepted > 0 for r in r1[1:])
+
+
+# ------------------------------------------------ gradients of W_eps (N3)
+
+def test_dual_partials_by_finite_differences_and_envelope():
+    """dual_partials against central differences of Q_eps at fixed (f, g)
+    (a definition check), and at the optimum against central differences of
+    W_eps itself, re-solved at each perturbed input (the envelope theorem)."""
+    rng = np.random.default_rng(31)
+    n, m, d, eps, s = 7, 9, 2, 0.3, 0.7
+    x = rng.random((n, d))
+    y = rng.random((m, d))
+    a = rng.dirichlet(np.full(n, 3.0))
+    b = rng.dirichlet(np.full(m, 3.0))
+    f = 0.2 * rng.standard_normal(n)
+    g = 0.2 * rng.standard_normal(m)
+    D = O.dual_partials(f, g, x, y, a, b, eps, s)
+    Q = lambda xx, yy, aa, bb: O.dual_value(f, g, O.sqeuclid_cost(xx, yy, s), aa, bb, eps)
+    h = 1e-6
+    for (i, k) in [(0, 0), (3, 1), (6, 0)]:
+        xp, xm = x.copy(), x.copy()
+        xp[i, k] += h
+        xm[i, k] -= h
+        assert (Q(xp, y, a, b) - Q(xm, y, a, b)) / (2 * h) == pytest.approx(D["x"][i, k], rel=1e-6, abs=1e-9)
+    for (j, k) in [(0, 1), (8, 0)]:
+        yp, ym = y.copy(), y.copy()
+        yp[j, k] += h
+        ym[j, k] -= h
+        assert (Q(x, yp, a, b) - Q(x, ym, a, b)) / (2 * h) == pytest.approx(D["y"][j, k], rel=1e-6, abs=1e-9)
+    for i in (1, 5):
+        ap, am = a.copy(), a.copy()
+        ap[i] += h
+        am[i] -= h
+        assert (Q(x, y, ap, b) - Q(x, y, am, b)) / (2 * h) == pytest.approx(D["a"][i], rel=1e-6, abs=1e-9)
+    for j in (2, 7):
+        bp, bm = b.copy(), b.copy()
+        bp[j] += h
+        bm[j] -= h
+        assert (Q(x, y, a, bp) - Q(x, y, a, bm)) / (2 * h) == pytest.approx(D["b"][j], rel=1e-6, abs=1e-9)
+    # the coupling is dQ/dC
+    Cb = O.sqeuclid_cost(x, y, s)
+    Cp = Cb.copy()
+    Cp[2, 3] += h
+    Cm = Cb.copy()
+    Cm[2, 3] -= h
+    dq = (O.dual_value(f, g, Cp, a, b, eps) - O.dual_value(f, g, Cm, a, b, eps)) / (2 * h)
+    assert dq == pytest.approx(D["C"][2, 3], rel=1e-6)
+
+    # envelope: W_eps(x) = max Q; its derivative is the partial at the optimum
+    def W(xx):
+        C = O.sqeuclid_cost(xx, y, s)
+        r = O.sinkhorn(C, a, b, eps, tol=1e-14, max_iter=100000)
+        return O.dual_value(r.f, r.g, C, a, b, eps), r
+    _, r0 = W(x)
+    D0 = O.dual_partials(r0.f, r0.g, x, y, a, b, eps, s)
+    h = 1e-5
+    for (i, k) in [(0, 0), (4, 1)]:
+        xp, xm = x.copy(), x.copy()
+        xp[i, k] += h
+        xm[i, k] -= h
+        fd = (W(xp)[0] - W(xm)[0]) / (2 * h)
+        assert fd == pytest.approx(D0["x"][i, k], rel=1e-6, abs=1e-10)
