@@ -266,6 +266,25 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps,
 int sknr_coupling(void* ctx, const sknr_problem* prob, double eps,
                   const double* f, const double* g, float* P_out, void* stream);
 
+/* Gradients of W_eps (eq. primal_EOT / dual_EOT) with respect to the
+ * problem data: the partial derivatives of Q_eps (eq. def_Q) at the given
+ * potentials, which at the optimum are the derivatives of W_eps (the
+ * potentials are stationary, so no implicit differentiation of the solver
+ * is needed; the paper notes SK-NR cannot be differentiated through its
+ * loop).  On the solver's cost C~:
+ *   grad_x[i,k] = 2 s (r_i x_ik - sum_j pi_ij y_jk)     (n x d, SQEUCLID only)
+ *   grad_y[j,k] = 2 s (c_j y_jk - sum_i pi_ij x_ik)     (m x d, SQEUCLID only)
+ *   grad_a[i]   = f_i - eps r_i / a_i,  grad_b[j] = g_j - eps c_j / b_j
+ * with s = cost_scale and r, c the row and column sums of pi; dW/dC is the
+ * coupling (sknr_coupling).  f, g [device] FP64 in the caller's
+ * orientation; each output [device] FP64 row-major, or NULL to skip it.
+ * The weighted sums run in the sweep kernels, 32 coordinates per pass.
+ * Errors: SKNR_EINVAL for a missing f or g, or point gradients of a stored
+ * cost. */
+int sknr_gradient(void* ctx, const sknr_problem* prob, double eps,
+                  const double* f, const double* g, double* grad_x, double* grad_y,
+                  double* grad_a, double* grad_b, void* stream);
+
 /* -------------------------------------------------------------- serving */
 /* Continuous batching of independent solves (mixed n, m, d, cost kind and
  * eps schedule) on one device.  The context runs `max_active` worker lanes,

@@ -14,7 +14,8 @@ import os
 
 __all__ = [
     "lib", "Context", "Problem", "solve", "c_transform_row", "c_transform_col",
-    "projected_system", "newton_step", "spectral_basis", "evaluate", "coupling",
+    "projected_system", "newton_step", "spectral_basis", "evaluate", "coupling", "gradient",
+    "entropic_ot_loss",
     "SknrError", "COST_STORED", "COST_SQEUCLID", "XTERM_AUTO", "XTERM_FP32",
     "XTERM_BF16", "XTERM_BF16X3", "XTERM_BF16X6", "WARM_SEQUENTIAL", "WARM_STATIC", "WARM_USER",
     "LIB_PATH", "MAX_STAGES", "MAX_ELL", "serve_config", "submit", "poll", "wait", "cancel",
@@ -111,6 +112,7 @@ _sig("sknr_spectral_basis", [_p, _P(_Problem), _d, _p, _i32, _i32, _i32, _d, cty
                              _P(_d), _P(_i32), _p])
 _sig("sknr_evaluate", [_p, _P(_Problem), _d, _p, _p, _P(_Eval), _p])
 _sig("sknr_coupling", [_p, _P(_Problem), _d, _p, _p, _p, _p])
+_sig("sknr_gradient", [_p, _P(_Problem), _d, _p, _p, _p, _p, _p, _p, _p])
 _sig("sknr_profile", [_p, _i32])
 _sig("sknr_serve_config", [_p, _i32, ctypes.c_uint64])
 _sig("sknr_submit", [_p, _P(_Problem), _P(_Opts), _P(ctypes.c_uint64)])
@@ -392,6 +394,65 @@ def evaluate(ctx, prob: Problem, eps: float, f, g, stream=None) -> dict:
     _check(lib.sknr_evaluate(ctx.handle, ctypes.byref(ps), eps, _ptr(f), _ptr(g), ctypes.byref(e),
                              _stream(stream)), "sknr_evaluate")
     return {k: getattr(e, k) for k, _ in _Eval._fields_}
+
+
+def gradient(ctx, prob: Problem, eps: float, f, g, x: bool = True, y: bool = True, a: bool = True,
+             b: bool = True, stream=None) -> dict:
+    """sknr_gradient: the gradients of W_eps with respect to the requested
+    data at the potentials (f, g); float64 device tensors keyed "x", "y"
+    (n x d, m x d; squared-Euclidean problems), "a", "b"."""
+    import torch
+    n, m = int(prob.a.shape[0]), int(prob.b.shape[0])
+    d = int(prob.x.shape[1]) if prob.x is not None else 0
+    dev = f.device
+    out = {}
+    if x:
+        out["x"] = torch.empty((n, d), dtype=torch.float64, device=dev)
+    if y:
+        out["y"] = torch.empty((m, d), dtype=torch.float64, device=dev)
+    if a:
+        out["a"] = torch.empty(n, dtype=torch.float64, device=dev)
+    if b:
+        out["b"] = torch.empty(m, dtype=torch.float64, device=dev)
+    ps = prob.c_struct()
+    _check(lib.sknr_gradient(ctx.handle, ctypes.byref(ps), eps, _ptr(f), _ptr(g), _ptr(out.get("x")),
+                             _ptr(out.get("y")), _ptr(out.get("a")), _ptr(out.get("b")), _stream(stream)),
+           "sknr_gradient")
+    return out
+
+
+class _EntropicOTLoss(torch.autograd.Function):
+    """W_eps(a, b, x, y) by a solve; its gradients by sknr_gradient at the
+    solution (envelope theorem: the solver loop is not differentiated)."""
+
+    @staticmethod
+    def forward(actx, ctx, x, y, a, b, eps_ladder, tol, max_iter, ell, warm_mode, cost_scale):
+        prob = Problem(a=a.detach().contiguous(), b=b.detach().contiguous(), x=x.detach().contiguous(),
+                       y=y.detach().contiguous(), cost_scale=cost_scale)
+        f, g, res = solve(ctx, prob, eps_ladder, tol=tol, max_iter=max_iter, ell=ell, warm_mode=warm_mode)
+        actx.save_for_backward(f, g)
+        actx.sk = (ctx, prob, float(eps_ladder[-1]))
+        return torch.tensor(res["dual_value"], dtype=torch.float64, device=x.device)
+
+    @staticmethod
+    def backward(actx, gout):
+        f, g = actx.saved_tensors
+        ctx, prob, eps = actx.sk
+        need = actx.needs_input_grad
+        gr = gradient(ctx, prob, eps, f, g, x=need[1], y=need[2], a=need[3], b=need[4])
+        conv = lambda k, t: (gout * gr[k]).to(t.dtype) if k in gr else None
+        return (None, conv("x", prob.x), conv("y", prob.y), conv("a", prob.a), conv("b", prob.b),
+                None, None, None, None, None, None)
+
+
+def entropic_ot_loss(ctx, x, y, a, b, eps, tol: float = 1e-6, max_iter: int = 100000, ell: int = 0,
+                     warm_mode: int = WARM_SEQUENTIAL, cost_scale: float = 1.0):
+    """W_eps between the weighted point clouds (a, x) and (b, y) (squared
+    Euclidean cost times cost_scale) as a differentiable torch scalar: x, y
+    float32 (n x d, m x d), a, b float64 device tensors; eps a value or a
+    ladder (the last entry is the target)."""
+    ladder = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
+    return _EntropicOTLoss.apply(ctx, x, y, a, b, ladder, tol, max_iter, ell, warm_mode, cost_scale)
 
 
 def coupling(ctx, prob: Problem, eps: float, f, g, stream=None):

@@ -29,6 +29,7 @@ thread_local std::string g_last_error;
 struct WS {
   float2 *F, *Fsk, *Fp, *G[2], *Gt, *Gp;
   float* mdiff;
+  float* mdiffY;  // column-side marginal differences (gradients)
   float *V, *W;
   int ellp;
   float* part;
@@ -200,7 +201,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   // weighted sweeps run l-wide (Newton) or up to 32-wide (warm start)
   const int ellw = ellp > 0 ? 32 : 0;
   // T_c (output Y), with and without weights
-  for (int e : {0, ellp > 0 ? 8 : 0, ellp, ellw}) {
+  for (int e : {0, ellp > 0 ? 8 : 0, ellp > 0 ? 16 : 0, ellp, ellw}) {
     size_t p = sweep_part_floats(m, n, e, sweep_kind(P), P.d, stream_vec(P, m), &ns, &rps, &nb, col_is_stream(P));
     pmax = std::max(pmax, p);
     nbmax = std::max(nbmax, nb);
@@ -214,6 +215,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   add(sizeof(float2) * m);
   add(sizeof(float2) * m * 2);
   add(sizeof(float) * n);
+  add(sizeof(float) * m);
   add(sizeof(float) * (size_t)n * std::max(ellp, 1));
   add(sizeof(float) * (size_t)m * std::max(ellp, 1));
   add(sizeof(float) * pmax + 16);
@@ -287,12 +289,13 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
   w.Gt = (float2*)A.take(sizeof(float2) * m);
   w.Gp = (float2*)A.take(sizeof(float2) * m);
   w.mdiff = (float*)A.take(sizeof(float) * n);
+  w.mdiffY = (float*)A.take(sizeof(float) * m);
   w.V = (float*)A.take(sizeof(float) * (size_t)n * std::max(ellp, 1));
   w.W = (float*)A.take(sizeof(float) * (size_t)m * std::max(ellp, 1));
   int ns, rps, nb, nbmax = 0;
   size_t pmax = 0;
   const int ellw = ellp > 0 ? 32 : 0;
-  for (int e : {0, ellp > 0 ? 8 : 0, ellp, ellw}) {
+  for (int e : {0, ellp > 0 ? 8 : 0, ellp > 0 ? 16 : 0, ellp, ellw}) {
     pmax = std::max(pmax, sweep_part_floats(m, n, e, sweep_kind(P), P.d, stream_vec(P, m), &ns, &rps, &nb,
                                             col_is_stream(P)));
     nbmax = std::max(nbmax, nb);
@@ -444,6 +447,8 @@ struct Engine {
   }
 
   // g_out = T_c(U_in) on side Y (eq. foc_g), hat form
+  float* col_mdiff = nullptr;  // optional column-side w_o expm1((Uold_o - Uout_o)/eps)
+
   void sweep_col(const float2* Fin, int ma_in, const float2* Gold, float2* Gout, int dot_slot, int ma_out, int ell,
                  const float* Vred, float* Wout, int wmode, int gate, int flags, int gsel_val = 0) {
     SweepArgs a{};
@@ -477,7 +482,7 @@ struct Engine {
     a.w_out64 = P.wY;
     a.Uold = Gold;
     a.Uout = Gout;
-    a.mdiff = nullptr;
+    a.mdiff = col_mdiff;
     a.dot_slot = dot_slot;
     a.ma_out = ma_out;
     a.ell = ell;
@@ -1257,6 +1262,58 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps, const double*
       out->marginal_err_exact = out->marginal_err;
       out->transport_cost_exact = out->transport_cost;
     }
+    return SKNR_OK;
+  });
+}
+
+int sknr_gradient(void* ctx, const sknr_problem* prob, double eps, const double* f, const double* g, double* grad_x,
+                  double* grad_y, double* grad_a, double* grad_b, void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(f && g, "f and g are required");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    REQUIRE(!(grad_x || grad_y) || P.kind == SKNR_COST_SQEUCLID, "point gradients need a squared-Euclidean problem");
+    WS w = make_ws(&c->lane, P, 32, s);
+    Engine E(&c->lane, P, w, s);
+    E.eps = eps;
+    E.init_state();
+    E.load_f(f);
+    E.load_g(g, w.G[0], MA_G, DOT_G);
+    const int d = P.kind == SKNR_COST_SQEUCLID ? P.d : 0;
+    const double two_s = 2.0 * P.cscale64;
+    // rows: r_i - a_i (mdiff) and sum_j pi_ij y_j, 32 coordinates per pass
+    if (grad_x || grad_a) {
+      int c0 = 0;
+      do {
+        const int dc = grad_x ? std::min(32, d - c0) : 0;
+        const int ellp = ell_pad(dc);
+        if (dc > 0) HIPCHK(launch_pack_cols(P.Y, P.m, d, c0, dc, ellp, w.Utw, s));
+        E.sweep_row(w.G[0], MA_G, w.F, w.Fsk, w.mdiff, -1, -1, ellp, dc > 0 ? w.Utw : nullptr, dc > 0 ? w.Zw : nullptr,
+                    dc > 0 ? W_SCALE_MASS : W_NONE, 0, 0);
+        if (dc > 0) HIPCHK(launch_grad_points(P.X, P.n, d, c0, dc, P.wX, w.mdiff, w.Zw, ellp, two_s, grad_x, s));
+        if (c0 == 0 && grad_a) HIPCHK(launch_grad_weights(f, P.wX, w.mdiff, P.n, eps, grad_a, s));
+        c0 += 32;
+      } while (grad_x && c0 < d);
+    }
+    // columns: c_j - b_j and sum_i pi_ij x_i
+    if (grad_y || grad_b) {
+      E.col_mdiff = w.mdiffY;
+      int c0 = 0;
+      do {
+        const int dc = grad_y ? std::min(32, d - c0) : 0;
+        const int ellp = ell_pad(dc);
+        if (dc > 0) HIPCHK(launch_pack_cols(P.X, P.n, d, c0, dc, ellp, w.Vw, s));
+        E.sweep_col(w.F, MA_F, w.G[0], w.Gt, -1, -1, ellp, dc > 0 ? w.Vw : nullptr, dc > 0 ? w.Uw : nullptr,
+                    dc > 0 ? W_SCALE_MASS : W_NONE, 0, 0);
+        if (dc > 0) HIPCHK(launch_grad_points(P.Y, P.m, d, c0, dc, P.wY, w.mdiffY, w.Uw, ellp, two_s, grad_y, s));
+        if (c0 == 0 && grad_b) HIPCHK(launch_grad_weights(g, P.wY, w.mdiffY, P.m, eps, grad_b, s));
+        c0 += 32;
+      } while (grad_y && c0 < d);
+      E.col_mdiff = nullptr;
+    }
+    HIPCHK(hipStreamSynchronize(s));
     return SKNR_OK;
   });
 }

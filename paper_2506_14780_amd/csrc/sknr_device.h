@@ -212,7 +212,10 @@ __device__ __forceinline__ void finalize_output(const SweepArgs& A, const EpsCon
   mx = fmaxf(mx, fabsf(out.x));
   if (ELL > 0 && A.wmode != W_CAND) {
     float inv = 1.f / (S + Sc);
-    float scale = A.wmode == W_SCALE_WEIGHT ? A.w_out[o] : (A.wmode == W_SCALE_RATIO ? 1.f + ratio_m1 : 1.f);
+    float scale = A.wmode == W_SCALE_WEIGHT ? A.w_out[o]
+                  : A.wmode == W_SCALE_RATIO ? 1.f + ratio_m1
+                  : A.wmode == W_SCALE_MASS  ? A.w_out[o] * (1.f + ratio_m1)
+                                             : 1.f;
     scale *= inv;
 #pragma unroll
     for (int l = 0; l < ELL; ++l) A.Wout[(size_t)o * ELL + l] = acc[l] * scale;

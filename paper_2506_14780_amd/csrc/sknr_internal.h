@@ -51,7 +51,9 @@ enum SweepFlag {
 };
 // W_CAND: the sweep runs on f with the single basis column expm1((f' - f)/eps)
 // and writes the candidate T_c(f') = T_c(f) - eps log1p(w) instead of W
-enum WMode { W_NONE = 0, W_SCALE_WEIGHT = 1, W_SCALE_RATIO = 2, W_CAND = 3 };
+// W_SCALE_MASS: W_o = sum_r pi_ro V_r (the softmax average times the
+// output's marginal w_o (1 + ratio_m1) against Uold)
+enum WMode { W_NONE = 0, W_SCALE_WEIGHT = 1, W_SCALE_RATIO = 2, W_CAND = 3, W_SCALE_MASS = 4 };
 
 // ---------------------------------------------------------- sweep arguments
 // One c-transform sweep: out_o = eps*lw_o - eps*log sum_r exp((Uin_r - C_ro)/eps)
@@ -172,6 +174,14 @@ hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32,
 hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a,
                            float2* Fp, int n, double* blk, float* blkmax, double* blkd, float* E1, DevState* st,
                            int gate, hipStream_t s);
+// gradients of W_eps: pack columns c0 .. c0+dc of an np x d point array into
+// an np x ellp block (zero-padded); grad[p, c0+k] = two_s ((w_p + mdiff_p)
+// P[p, c0+k] - Wsum[p, k]); gradw[p] = pot[p] - eps (w_p + mdiff_p) / w_p
+hipError_t launch_pack_cols(const float* P, int np, int d, int c0, int dc, int ellp, float* out, hipStream_t s);
+hipError_t launch_grad_points(const float* P, int np, int d, int c0, int dc, const double* w, const float* mdiff,
+                              const float* Wsum, int ellp, double two_s, double* grad, hipStream_t s);
+hipError_t launch_grad_weights(const double* pot, const double* w, const float* mdiff, int np, double eps,
+                               double* grad, hipStream_t s);
 hipError_t launch_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp,
                          const float2* Gt, float2* G, int m, DevState* st, int gate, hipStream_t s);
 

@@ -1033,6 +1033,52 @@ hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float
   return hipGetLastError();
 }
 
+// ---------------------------------------------------- gradients of W_eps
+__global__ void k_pack_cols(const float* P, int np, int d, int c0, int dc, int ellp, float* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  for (int k = 0; k < ellp; ++k) out[(size_t)p * ellp + k] = k < dc ? P[(size_t)p * d + c0 + k] : 0.f;
+}
+hipError_t launch_pack_cols(const float* P, int np, int d, int c0, int dc, int ellp, float* out, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_cols, dim3((np + 255) / 256), dim3(256), 0, s, P, np, d, c0, dc, ellp, out);
+  return hipGetLastError();
+}
+
+// grad[p, c0+k] = two_s ((w_p + mdiff_p) P[p, c0+k] - Wsum[p, k]): the
+// output marginal is w_p + mdiff_p, Wsum the pi-weighted sum of the other
+// side's coordinates
+__global__ void k_grad_points(const float* P, int np, int d, int c0, int dc, const double* w, const float* mdiff,
+                              const float* Wsum, int ellp, double two_s, double* grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const double mass = w[p] + (double)mdiff[p];
+  for (int k = 0; k < dc; ++k)
+    grad[(size_t)p * d + c0 + k] =
+        two_s * (mass * (double)P[(size_t)p * d + c0 + k] - (double)Wsum[(size_t)p * ellp + k]);
+}
+hipError_t launch_grad_points(const float* P, int np, int d, int c0, int dc, const double* w, const float* mdiff,
+                              const float* Wsum, int ellp, double two_s, double* grad, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_points, dim3((np + 255) / 256), dim3(256), 0, s, P, np, d, c0, dc, w, mdiff, Wsum,
+                     ellp, two_s, grad);
+  return hipGetLastError();
+}
+
+// gradw[p] = pot[p] - eps (w_p + mdiff_p) / w_p
+__global__ void k_grad_weights(const double* pot, const double* w, const float* mdiff, int np, double eps,
+                               double* grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  grad[p] = pot[p] - eps * (1.0 + (double)mdiff[p] / w[p]);
+}
+hipError_t launch_grad_weights(const double* pot, const double* w, const float* mdiff, int np, double eps,
+                               double* grad, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_weights, dim3((np + 255) / 256), dim3(256), 0, s, pot, w, mdiff, np, eps, grad);
+  return hipGetLastError();
+}
+
 // ============================================================================
 // FP64 evaluation of (f, g): row / column sums of pi, <C,pi>, sum pi,
 // sum pi*log(pi/(a b)).  Tiles of 64 rows x 256 columns; deterministic
