@@ -432,6 +432,16 @@ def main():
     out["kernel_profile"] = [{"name": e["name"], "launches": e["launches"],
                               "avg_us": 1e3 * e["total_ms"] / max(1, e["launches"]),
                               "total_ms": e["total_ms"]} for e in sorted(prof, key=lambda e: -e["total_ms"])]
+    # gradients of W_eps at the solution (x, y, a, b): the envelope gradients
+    # cost two weighted sweeps
+    sk.gradient(ctx, gp, ladder[-1], f_out, g_out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        sk.gradient(ctx, gp, ladder[-1], f_out, g_out)
+    torch.cuda.synchronize()
+    out["gradient"] = {"ms": 1e3 * (time.perf_counter() - t0) / 10,
+                       "what": "sknr_gradient of W_eps with respect to x, y, a, b at the solution"}
     if not args.no_stored:
         out["roofline_stored_cost"] = stored_sweep_roofline(sk, ctx)
     if not args.no_mfma:
