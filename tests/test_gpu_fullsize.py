@@ -99,3 +99,36 @@ def test_fullsize_clouds_matrix_core_cost(sk, ctx, parts):
     df = np.abs(f[rows] - fr).max()
     print(f"rows: max|f - T_r(g)| = {df:.3e}  (cost bound {bound.max():.3e})", flush=True)
     assert df <= bound.max() + 64 * U32 * ladder[-1] + 1e-12 * np.abs(f).max()
+
+
+def test_fullsize_gradient_on_sampled_rows_and_columns(sk, ctx):
+    """sknr_gradient at the 4096 x 4096 d = 2 benchmark solution: for sampled
+    rows i the oracle forms row i of the coupling of the GPU's own (f, g)
+    on the FP32 cost and evaluates 2 (r_i x_i - sum_j pi_ij y_j) and
+    f_i - eps r_i / a_i; likewise for sampled columns."""
+    prob = W.gmm_vs_uniform(4096, seed=1)
+    ladder = list(W.EPS_LADDER_C2)
+    gp = sk.Problem(a=to_dev(prob.a), b=to_dev(prob.b), x=to_dev(prob.x), y=to_dev(prob.y))
+    f, g, res = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=200000, ell=16, warm_mode=sk.WARM_SEQUENTIAL)
+    eps = ladder[-1]
+    gr = {k: v.cpu().numpy() for k, v in sk.gradient(ctx, gp, eps, f, g).items()}
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    x, y = prob.x.astype(np.float64), prob.y.astype(np.float64)
+    rows = _rows(prob.n, k=16, seed=3)
+    Pr = O.coupling(f[rows], g, fp32_sqeuclid(prob.x[rows], prob.y).astype(np.float64), prob.a[rows], prob.b, eps)
+    r = Pr.sum(1)
+    gx = 2 * (r[:, None] * x[rows] - Pr @ y)
+    ga = f[rows] - eps * r / prob.a[rows]
+    cols = _rows(prob.m, k=16, seed=4)
+    Pc = O.coupling(f, g[cols], fp32_sqeuclid(prob.x, prob.y[cols]).astype(np.float64), prob.a, prob.b[cols], eps)
+    c = Pc.sum(0)
+    gy = 2 * (c[:, None] * y[cols] - Pc.T @ x)
+    gb = g[cols] - eps * c / prob.b[cols]
+    scale = 2 * np.abs(x).max() * prob.a.max()
+    ex = np.abs(gr["x"][rows] - gx).max()
+    ey = np.abs(gr["y"][cols] - gy).max()
+    ea = np.abs(gr["a"][rows] - ga).max()
+    eb = np.abs(gr["b"][cols] - gb).max()
+    print(f"grad errors x {ex:.3e} y {ey:.3e} (scale {scale:.3e}); a {ea:.3e} b {eb:.3e}", flush=True)
+    assert ex <= 1e-5 * scale and ey <= 1e-5 * scale
+    assert ea <= 1e-5 * eps and eb <= 1e-5 * eps
