@@ -159,6 +159,36 @@ def paper_workloads_bench(sk, W, torch, tol, reps=3):
     return out
 
 
+def points_sweep_large(sk, W, torch, n=20000, m=30000, reps=4):
+    """The d = 2 points sweep of the benchmark workload's kind at a size
+    where the launch and per-workgroup costs no longer dominate (20000 x
+    30000: 37x the elements of 4096^2): main-kernel duration of the column
+    and row c-transforms against the same VALU roofline."""
+    prob = W.gmm_vs_uniform(n, m, seed=1)
+    dev = torch.device("cuda:0")
+    gp = sk.Problem(a=torch.from_numpy(prob.a).to(dev), b=torch.from_numpy(prob.b).to(dev),
+                    x=torch.from_numpy(prob.x).to(dev), y=torch.from_numpy(prob.y).to(dev))
+    ctx = sk.Context(0)
+    f = torch.zeros(prob.n, dtype=torch.float64, device=dev)
+    g, _, _ = sk.c_transform_col(ctx, gp, 1e-2, f)
+    ctx.profile(True)
+    for _ in range(reps):
+        g, _, _ = sk.c_transform_col(ctx, gp, 1e-2, f)
+        sk.c_transform_row(ctx, gp, 1e-2, g)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    main = [e for e in prof if e["name"].endswith(":main")][0]
+    avg_s = main["total_ms"] / main["launches"] / 1e3
+    elems = main["units"] / main["launches"]
+    _, slots, _ = algorithmic_work(main["name"])
+    ach = slots * elems / avg_s / 1e12
+    return {"workload": f"gmm_vs_uniform {n}x{m} d=2, one column + one row c-transform per rep",
+            "kernel": main["name"], "avg_launch_us": avg_s * 1e6, "elements_per_launch": elems,
+            "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": ach / PEAK_VALU_TOPS}
+
+
 def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4):
     """Mixed-request serving: Poisson arrivals, n, m log-uniform on
     [64, 8192], d in {2, 3, 64}, target eps in {1e-1, 1e-2, 1e-3} reached by
@@ -446,6 +476,8 @@ def main():
         out["roofline_stored_cost"] = stored_sweep_roofline(sk, ctx)
     if not args.no_mfma:
         out["roofline_mfma_cost"] = mfma_sweep_roofline(sk, W, torch)
+    if not args.no_stored:
+        out["roofline_points_large"] = points_sweep_large(sk, W, torch)
     if not args.no_serve:
         out["serving"] = serving_bench(sk, W, torch, args.serve_requests, args.serve_lanes, args.tol)
     if not args.no_paper:
