@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) when no device is visible, so that
-    # the CPU suite can be collected anywhere; on the GPU machine they run.
+    # the CPU suite can be collected anywhere; with a device they run.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
