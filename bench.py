@@ -62,14 +62,14 @@ def algorithmic_work(kind: str):
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2.0, WRITE_SIZE 1 GiB
 # -> x1.0); see profiles/.  Valid only for the kernel sources they were
 # taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip).
-TRAFFIC_KERNEL_SHA1 = "6631aa873bb81835e677613013dfb9ba49bd5103"
+TRAFFIC_KERNEL_SHA1 = "ade29e7ca4b2e5794aeac2782259f5e2677b0459"
 TRAFFIC_BYTES = {
-    "sweep_stream_points_l0:main": (215.68 * 1.9999 + 2003.92 * 1.0000) * 1024,
-    "sweep_stream_stored_l0:main": (524977.28 * 1.9999 + 6144.00 * 1.0000) * 1024,
-    "sweep_rows_stored_l0:main": (525906.69 * 1.9999 + 528.98 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x3_l0:main": (91679.29 * 1.9999 + 6224.02 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x6_l0:main": (140416.37 * 1.9999 + 6226.22 * 1.0000) * 1024,
-    "sweep_stream_points_bf16_l0:main": (25700.99 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_l0:main": (243.95 * 1.9999 + 2065.88 * 1.0000) * 1024,
+    "sweep_stream_stored_l0:main": (524978.79 * 1.9999 + 6144.00 * 1.0000) * 1024,
+    "sweep_rows_stored_l0:main": (525906.00 * 1.9999 + 529.27 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x3_l0:main": (91846.42 * 1.9999 + 6224.01 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x6_l0:main": (140445.15 * 1.9999 + 6226.42 * 1.0000) * 1024,
+    "sweep_stream_points_bf16_l0:main": (25535.27 * 1.9999 + 6223.96 * 1.0000) * 1024,
 }
 
 
