@@ -136,3 +136,33 @@ def test_gradient_of_a_stored_cost_problem(sk, ctx):
                               ctypes.c_void_p(gd.data_ptr()), ctypes.c_void_p(dummy.data_ptr()), None, None, None,
                               None)
     assert st == sk.EINVAL
+
+
+def test_gradient_matrix_core_cost_d64(sk, ctx):
+    """The default cost for d >= 16 (three bf16 parts on matrix cores): the
+    gradient against the oracle's formula on the modelled cost C_model
+    (tests._helpers.bf16_cost_model), with the coupling's relative slack
+    exp(bound / eps) - 1 from the model's per-element bound."""
+    from tests._helpers import bf16_cost_model
+    n, m, d, eps, scale = 240, 310, 64, 0.05, 1.0 / 64
+    rng = np.random.default_rng(64)
+    x = rng.standard_normal((n, d)).astype(np.float32)
+    y = (rng.standard_normal((m, d)) + 0.3).astype(np.float32)
+    a = rng.dirichlet(np.full(n, 3.0))
+    b = rng.dirichlet(np.full(m, 3.0))
+    Cm, bound = bf16_cost_model(x, y, scale, parts=3)
+    r = O.sinkhorn(Cm, a, b, eps, tol=1e-4, max_iter=5000)
+    gp = sk.Problem(a=to_dev(a), b=to_dev(b), x=to_dev(x), y=to_dev(y), cost_scale=scale)  # AUTO -> BF16X6
+    gr = {k: v.cpu().numpy() for k, v in sk.gradient(ctx, gp, eps, to_dev(r.f), to_dev(r.g)).items()}
+    P = O.coupling(r.f, r.g, Cm, a, b, eps)
+    rr, cc = P.sum(1), P.sum(0)
+    xo, yo = x.astype(np.float64), y.astype(np.float64)
+    rel = np.expm1(bound.max() / eps) + 1e-5
+    for k, ref, M in (("x", 2 * scale * (rr[:, None] * xo - P @ yo), 2 * scale * (rr[:, None] * np.abs(xo) + np.abs(P) @ np.abs(yo))),
+                      ("y", 2 * scale * (cc[:, None] * yo - P.T @ xo), 2 * scale * (cc[:, None] * np.abs(yo) + np.abs(P).T @ np.abs(xo)))):
+        err = np.abs(gr[k] - ref)
+        print(f"grad_{k}: max err {err.max():.3e}, max allowed {(2 * rel * M).max():.3e}", flush=True)
+        assert np.all(err <= 2 * rel * M + 1e-12)
+    for k, ref, q in (("a", r.f - eps * rr / a, rr / a), ("b", r.g - eps * cc / b, cc / b)):
+        err = np.abs(gr[k] - ref)
+        assert np.all(err <= 2 * rel * eps * q + 1e-9)
