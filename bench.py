@@ -189,13 +189,15 @@ def points_sweep_large(sk, W, torch, n=20000, m=30000, reps=4):
             "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": ach / PEAK_VALU_TOPS}
 
 
-def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4):
+def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4, switch_iters=10):
     """Mixed-request serving: Poisson arrivals, n, m log-uniform on
     [64, 8192], d in {2, 3, 64}, target eps in {1e-1, 1e-2, 1e-3} reached by
     halving from 1, l = min(30, min(n, m) - 1).  A closed-loop run (all
     requests submitted at once) calibrates the arrival rate to 0.8 x the
-    SK-NR capacity; the same arrival trace then runs with SK-NR and with
-    plain SK.  Latency = completion - scheduled arrival."""
+    SK-NR capacity; the same arrival trace then runs with SK-NR (every stage
+    after the first), with SK-NR switched on after the first stage that
+    needs more than `switch_iters` SK iterations, and with plain SK.
+    Latency = completion - scheduled arrival."""
     trace = W.serving_trace(n_requests=n_req, rate=1.0, seed=seed)
     dev = torch.device("cuda:0")
     probs = [sk.Problem(a=torch.from_numpy(q.problem.a).to(dev), b=torch.from_numpy(q.problem.b).to(dev),
@@ -205,7 +207,7 @@ def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4):
     base = np.array([q.arrival for q in trace])
     base = base - base[0]
 
-    def run(nr, rate):
+    def run(nr, rate, switch=0):
         ctx = sk.Context(0)
         sk.serve_config(ctx, max_active=lanes, pool_bytes=8 << 30)
         arr = base / rate if rate else np.zeros(n_req)
@@ -217,7 +219,8 @@ def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4):
                 time.sleep(wait_s)
             n, m = q.problem.n, q.problem.m
             tk = sk.submit(ctx, gp, W.request_ladder(q.eps), tol=tol, max_iter=20000,
-                           ell=min(30, min(n, m) - 1) if nr else 0, warm_mode=sk.WARM_SEQUENTIAL, seed=q.rid)
+                           ell=min(30, min(n, m) - 1) if nr else 0, warm_mode=sk.WARM_SEQUENTIAL, seed=q.rid,
+                           nr_switch_iters=switch if nr else 0)
             sub.append((tk, ta, time.monotonic() - t0))
         lat, ends, status, iters = [], [], [], []
         for q, (tk, ta, tret) in zip(trace, sub):
@@ -235,11 +238,13 @@ def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4):
                 "failed": int(sum(1 for v in status if v < 0)), "mean_iters": float(np.mean(iters))}
 
     closed = run(True, 0.0)
+    closed_ad = run(True, 0.0, switch_iters)
     rate = 0.8 * closed["solves_per_s"]
     return {"workload": f"serving_trace {n_req} requests, n,m log-uniform [64,8192], d in {{2,3,64}}, "
                         f"eps in {{1e-1,1e-2,1e-3}} by halving from 1, tol {tol:g}, l=min(30,min(n,m)-1)",
-            "lanes": lanes, "closed_loop_sknr": closed, "arrival_rate_per_s": rate,
-            "sknr": run(True, rate), "sk": run(False, rate)}
+            "lanes": lanes, "closed_loop_sknr": closed, "closed_loop_sknr_adaptive": closed_ad,
+            "arrival_rate_per_s": rate, "nr_switch_iters": switch_iters,
+            "sknr": run(True, rate), "sknr_adaptive": run(True, rate, switch_iters), "sk": run(False, rate)}
 
 
 def percentile(xs, q):
@@ -343,6 +348,7 @@ def main():
     ap.add_argument("--no-mfma", action="store_true", help="skip the d = 64 matrix-core sweep measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the mixed-request serving run")
     ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 5 workloads (Fig. 5.1, single-cell shapes)")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the W_eps gradient timing")
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-lanes", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -464,14 +470,15 @@ def main():
                               "total_ms": e["total_ms"]} for e in sorted(prof, key=lambda e: -e["total_ms"])]
     # gradients of W_eps at the solution (x, y, a, b): the envelope gradients
     # cost two weighted sweeps
-    sk.gradient(ctx, gp, ladder[-1], f_out, g_out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(10):
+    if not args.no_gradient:
         sk.gradient(ctx, gp, ladder[-1], f_out, g_out)
-    torch.cuda.synchronize()
-    out["gradient"] = {"ms": 1e3 * (time.perf_counter() - t0) / 10,
-                       "what": "sknr_gradient of W_eps with respect to x, y, a, b at the solution"}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            sk.gradient(ctx, gp, ladder[-1], f_out, g_out)
+        torch.cuda.synchronize()
+        out["gradient"] = {"ms": 1e3 * (time.perf_counter() - t0) / 10,
+                           "what": "sknr_gradient of W_eps with respect to x, y, a, b at the solution"}
     if not args.no_stored:
         out["roofline_stored_cost"] = stored_sweep_roofline(sk, ctx)
     if not args.no_mfma:

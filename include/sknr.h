@@ -131,6 +131,14 @@ typedef struct sknr_opts {
   const double* V0;       /* [device] optional n x ell FP64 basis (WARM_USER) */
   uint64_t seed;          /* seed of the subspace-iteration start block */
   void* stream;           /* hipStream_t */
+  int32_t nr_switch_iters;/* WARM_SEQUENTIAL only.  0: every stage after the
+                             first runs SK-NR (the protocol of Sec. 5).  T > 0:
+                             stages run plain SK until one needs more than T
+                             iterations; the stages after it run SK-NR, each
+                             with V_l from the optimum of the stage before.
+                             SK counts grow as eps falls (Lemma 3.2, rate
+                             rho_1^2), so the switch happens once.  The optimum
+                             is the same; only the iterates differ. */
 } sknr_opts;
 
 typedef struct sknr_stage_stats {
@@ -183,6 +191,9 @@ int sknr_ctx_destroy(void* ctx);
  * ell > 0 stages run Algorithm 4.1 with V_l from the spectral warm start
  * (Sec. 4) chosen by warm_mode, otherwise plain SK (eq. SK_iterations).
  * The first stage is plain SK unless first_stage_nr is set with WARM_USER.
+ * With nr_switch_iters = T > 0 (WARM_SEQUENTIAL) easy stages stay plain SK:
+ * the warm start and the Newton steps begin at the stage after the first
+ * one that needs more than T SK iterations.
  * f_out [device] n FP64 and g_out [device] m FP64 receive the potentials of
  * the last stage, res [host] the statistics.  When n > m the solve runs on
  * the transposed problem (semi-dual on the smaller side, Sec. 2); outputs

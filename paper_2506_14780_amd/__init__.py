@@ -56,7 +56,7 @@ class _Opts(ctypes.Structure):
                 ("ell", _i32), ("warm_mode", _i32), ("eps_prime", _d), ("eig_oversample", _i32),
                 ("eig_max_iter", _i32), ("eig_tol", _d), ("check_every", _i32),
                 ("first_stage_nr", _i32), ("f0", _p), ("V0", _p), ("seed", ctypes.c_uint64),
-                ("stream", _p)]
+                ("stream", _p), ("nr_switch_iters", _i32)]
 
 
 class _Stage(ctypes.Structure):
@@ -226,7 +226,7 @@ class Problem:
 
 
 def _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr, eig_oversample,
-          eig_max_iter, eig_tol, seed, stream):
+          eig_max_iter, eig_tol, seed, stream, nr_switch_iters=0):
     earr = (_d * len(eps))(*eps)
     o = _Opts()
     o.eps = ctypes.cast(earr, _P(_d))
@@ -245,6 +245,7 @@ def _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, fi
     o.V0 = _ptr(V0)
     o.seed = seed
     o.stream = _stream(stream)
+    o.nr_switch_iters = int(nr_switch_iters)
     return o, earr  # earr must outlive the call
 
 
@@ -257,7 +258,7 @@ def _result_dict(r):
 def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,
           warm_mode: int = WARM_USER, V0=None, f0=None, eps_prime: float = 0.0, check_every: int = 0,
           first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
-          eig_tol: float = 0.0, seed: int = 0, stream=None, f_out=None, g_out=None):
+          eig_tol: float = 0.0, seed: int = 0, stream=None, f_out=None, g_out=None, nr_switch_iters: int = 0):
     """sknr_solve.  Returns (f, g, result dict); f, g are float64 device
     tensors in the caller's orientation."""
     import torch
@@ -267,7 +268,7 @@ def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 1
     f = f_out if f_out is not None else torch.empty(n, dtype=torch.float64, device=dev)
     g = g_out if g_out is not None else torch.empty(m, dtype=torch.float64, device=dev)
     o, earr = _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr,
-                    eig_oversample, eig_max_iter, eig_tol, seed, stream)
+                    eig_oversample, eig_max_iter, eig_tol, seed, stream, nr_switch_iters)
     r = _Result()
     ps = prob.c_struct()
     st = lib.sknr_solve(ctx.handle, ctypes.byref(ps), ctypes.byref(o), _ptr(f), _ptr(g), ctypes.byref(r))
@@ -284,12 +285,12 @@ def serve_config(ctx: Context, max_active: int = 0, pool_bytes: int = 0):
 def submit(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,
            warm_mode: int = WARM_SEQUENTIAL, eps_prime: float = 0.0, check_every: int = 0,
            first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
-           eig_tol: float = 0.0, seed: int = 0, stream=None) -> int:
+           eig_tol: float = 0.0, seed: int = 0, stream=None, nr_switch_iters: int = 0) -> int:
     """sknr_submit: queue a solve (inputs are copied before returning);
     returns the ticket."""
     eps = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
     o, earr = _opts(eps, tol, max_iter, ell, warm_mode, None, None, eps_prime, check_every, first_stage_nr,
-                    eig_oversample, eig_max_iter, eig_tol, seed, stream)
+                    eig_oversample, eig_max_iter, eig_tol, seed, stream, nr_switch_iters)
     ps = prob.c_struct()
     t = ctypes.c_uint64()
     _check(lib.sknr_submit(ctx.handle, ctypes.byref(ps), ctypes.byref(o), ctypes.byref(t)), "sknr_submit")

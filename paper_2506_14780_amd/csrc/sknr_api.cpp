@@ -806,22 +806,28 @@ struct Engine {
     const int nbn = std::min(128, std::max(1, (n + 63) / 64));
     const int nbm = std::min(128, std::max(1, (m + 63) / 64));
     const int plen = kp * kp + kp;
+    // okw[2]: positions of zero (dropped) columns in the Ritz block.  Each
+    // Gram of Z refills them with fresh random values, so the block keeps
+    // its full width (at smaller eps more modes are resolved, and the
+    // oversampling columns speed up the iteration).
+    unsigned* zmask = reinterpret_cast<unsigned*>(w.okw + 2);
     if (w.have_Vw) HIPCHK(hipMemcpyAsync(w.Zw, w.Vw, sizeof(float) * (size_t)n * kp, hipMemcpyDeviceToDevice, s));
-    else HIPCHK(launch_random_block(kp, w.Zw, n, 0, seed, s));
+    else HIPCHK(launch_random_block(kp, w.Zw, n, 0, seed, zmask, s));
     std::vector<double> lp(kp, 0.0), lc(kp, 0.0);
     int it = 0;
     for (it = 1; it <= max_it; ++it) {
       // V = orthonormalised (Z - 1 s^T) in L2(a)
-      HIPCHK(launch_wgram(kp, w.Zw, P.wX, 0, n, w.nrpart, nbn, s));
+      HIPCHK(launch_wgram(kp, w.Zw, P.wX, 0, n, w.nrpart, nbn, zmask, ~0u,
+                          seed ^ (0x632BE59BD9B4E019ull * (uint64_t)it), s));
       HIPCHK(launch_sum_partials(w.nrpart, nbn, plen, w.nrsum, s));
       HIPCHK(launch_orth(kp, w.nrsum, 1, w.Rw, w.sw, w.okw, s));
       HIPCHK(launch_affine(kp, w.Zw, w.sw, w.Rw, nullptr, 0, n, w.Vw, s));
       // U = P~^T V (and G~ = T_c(F))
       sweep_col(w.F, MA_F, nullptr, w.Gt, DOT_GT, MA_GT, kp, w.Vw, w.Uw, W_SCALE_WEIGHT, 0, 0);
       // Rayleigh-Ritz: T = U^T D_b^-1 U = V^T D_a M V
-      HIPCHK(launch_wgram(kp, w.Uw, P.wY, 1, m, w.nrpart, nbm, s));
+      HIPCHK(launch_wgram(kp, w.Uw, P.wY, 1, m, w.nrpart, nbm, nullptr, 0u, 0, s));
       HIPCHK(launch_sum_partials(w.nrpart, nbm, plen, w.nrsum, s));
-      HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, w.lamw, w.okw + 1, s));
+      HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, w.lamw, w.okw + 1, zmask, s));
       HIPCHK(launch_affine(kp, w.Vw, nullptr, w.Qw, nullptr, 0, n, w.Zw, s));
       std::swap(w.Vw, w.Zw);  // V <- V Q (Ritz vectors)
       HIPCHK(launch_affine(kp, w.Uw, nullptr, w.Qw, P.wY, 1, m, w.Utw, s));  // D_b^-1 U Q
@@ -920,11 +926,15 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
   res->n_stages = opts->n_eps;
   res->transposed = P.transposed ? 1 : 0;
   int status = SKNR_OK;
+  // adaptive switch: plain SK until a stage needs more than T iterations,
+  // SK-NR with the sequential warm start on every stage after it
+  const bool adaptive = opts->nr_switch_iters > 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_SEQUENTIAL;
+  bool nr_on = !adaptive;
   for (int st = 0; st < opts->n_eps; ++st) {
     auto ts = std::chrono::steady_clock::now();
     double eps = opts->eps[st];
     int eig_iters = 0;
-    if (st > 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_SEQUENTIAL) {
+    if (st > 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_SEQUENTIAL && nr_on) {
       // V_l from the optimum of the previous stage (its eps), Sec. 4
       eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed + st, nullptr);
       E.use_warm_V(opts->ell, eig_os);
@@ -937,7 +947,7 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
       HIPCHK(launch_rebase(w.G[0], w.lYdf, split_df(de), P.m, w.st, MA_G, s));
       E.eps = eps;
     }
-    bool use_nr = opts->ell > 0 && (st > 0 || opts->first_stage_nr);
+    bool use_nr = opts->ell > 0 && (st > 0 || opts->first_stage_nr) && nr_on;
     bool conv = false;
     int tried = 0, acc = 0, it = 0;
     sknr_eval ev{};
@@ -958,6 +968,7 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
       E.tol = E.tol * std::min(0.9, opts->tol / ev.marginal_err);
     }
     if (!conv) status = SKNR_NOT_CONVERGED;
+    if (!nr_on && it > opts->nr_switch_iters) nr_on = true;
     sknr_stage_stats& ss = res->stage[st];
     ss.eps = eps;
     ss.iters = it;
@@ -999,6 +1010,9 @@ void check_opts(const sknr_opts* opts, const Prepared& P) {
   REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
   REQUIRE(opts->ell >= 0 && opts->ell <= SKNR_MAX_ELL, "ell out of range");
   REQUIRE(opts->ell < std::min(P.n0, P.m0), "ell must be < min(n, m)");
+  REQUIRE(opts->nr_switch_iters >= 0, "nr_switch_iters must be >= 0");
+  REQUIRE(opts->nr_switch_iters == 0 || opts->ell == 0 || opts->warm_mode == SKNR_WARM_SEQUENTIAL,
+          "nr_switch_iters needs WARM_SEQUENTIAL");
   if (opts->ell > 0) {
     REQUIRE(opts->warm_mode == SKNR_WARM_USER || opts->warm_mode == SKNR_WARM_SEQUENTIAL ||
                 opts->warm_mode == SKNR_WARM_STATIC, "unknown warm_mode");

@@ -868,7 +868,12 @@ __device__ __forceinline__ double sum_partials(const double* part, int nblk, int
 // One workgroup: the l x l Newton system (Algorithm 4.1, NR update) from the
 // block partials of k_nr_assemble.  The partials are summed per entry in
 // block order (chunks of 32 blocks); G is symmetrised and modes beyond
-// ell_real (zero columns of V) become identity rows.  [G | grad] is then
+// ell_real (zero columns of V) become identity rows.  So do basis columns
+// without numerical mass, |G_ii| <= 1e-12 max_j G_jj (||v_i||_a below
+// ~1e-6): the warm start leaves such columns where the spectrum of M lies
+// below FP32 resolution (large eps).  Their coefficients are zero and the
+// step is the Newton step on the span of the other columns; the modes they
+// miss have rho_k^2 ~ 0, which SK already removes.  [G | grad] is then
 // reduced by Gauss-Jordan elimination without pivoting, one barrier per
 // column: step k updates the entries (i, j), i != k, j > k, and reads only
 // column k and row k, which it does not write.  Its pivots are those of
@@ -894,11 +899,14 @@ __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, 
   __syncthreads();
   double dmax = 0;
   for (int j = 0; j < ell_real; ++j) dmax = fmax(dmax, R[j * ELL + j]);
+  // column i takes part unless it is padding or carries no mass (a NaN or
+  // negative diagonal still fails the pivot test below)
+  auto active = [&](int i) { return i < ell_real && !(fabs(R[i * ELL + i]) <= 1e-12 * dmax); };
   for (int e = tid; e < ELL * NA; e += 256) {
     const int i = e / NA, j = e - i * NA;
     double v;
-    if (j == ELL) v = i < ell_real ? R[NE + i] : 0.0;
-    else if (i >= ell_real || j >= ell_real) v = (i == j) ? 1.0 : 0.0;
+    if (j == ELL) v = active(i) ? R[NE + i] : 0.0;
+    else if (!active(i) || !active(j)) v = (i == j) ? 1.0 : 0.0;
     else v = 0.5 * (R[i * ELL + j] + R[j * ELL + i]);
     A[i][j] = v;
   }

@@ -14,6 +14,15 @@
 
 namespace sknr {
 
+// counter-based uniform(-1, 1) value number e of stream `seed` (splitmix64)
+__device__ __forceinline__ float uniform_pm1(unsigned long long seed, unsigned long long e) {
+  unsigned long long x = seed + 0x9E3779B97F4A7C15ull * (e + 1);
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (float)((double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+}
+
 // sum over nblk (<= 32) partial blocks of entry e, loads issued together
 __device__ __forceinline__ double sum_parts(const double* part, int nblk, int stride, int e) {
   double v[32];
@@ -44,9 +53,14 @@ hipError_t launch_sum_partials(const double* part, int nblk, int len, double* ou
 // ----------------------------------------------------------------- Gram
 // part[blk] = ( sum_i w_i Z_i Z_i^T  (k x k),  sum_i w_i Z_i  (k) ),
 // w_i = wgt[i] or 1/wgt[i] (invert), over a contiguous block of rows.
+// refill (nullable): bit l of *refill & refill_bits set -> column l of Z
+// is first overwritten with fresh uniform(-1, 1) values of stream `seed`
+// (zero columns that the orthonormalisation dropped get a new start).
 template <int KP>
-__global__ __launch_bounds__(256) void k_wgram(const float* Z, const double* wgt, int invert, int n, double* part,
-                                               int rows_per_blk) {
+__global__ __launch_bounds__(256) void k_wgram(float* Z, const double* wgt, int invert, int n, double* part,
+                                               int rows_per_blk, const unsigned* refill, unsigned refill_bits,
+                                               unsigned long long seed) {
+  const unsigned rmask = refill ? (*refill & refill_bits) : 0u;
   constexpr int NE = KP * KP;
   constexpr int PER = (NE + 255) / 256;
   __shared__ float tile[64][KP];
@@ -62,7 +76,17 @@ __global__ __launch_bounds__(256) void k_wgram(const float* Z, const double* wgt
     __syncthreads();
     for (int q = threadIdx.x; q < 64 * KP; q += 256) {
       int rr = q / KP, l = q % KP;
-      tile[rr][l] = rr < nt ? Z[(size_t)(t0 + rr) * KP + l] : 0.f;
+      float v = 0.f;
+      if (rr < nt) {
+        const size_t e = (size_t)(t0 + rr) * KP + l;
+        if ((rmask >> l) & 1u) {
+          v = uniform_pm1(seed, e);
+          Z[e] = v;
+        } else {
+          v = Z[e];
+        }
+      }
+      tile[rr][l] = v;
     }
     if (threadIdx.x < 64) {
       int rr = threadIdx.x;
@@ -95,8 +119,17 @@ __global__ __launch_bounds__(256) void k_wgram(const float* Z, const double* wgt
 // Projecting out the constant (Z - 1 s^T, since sum a = 1) gives
 // B' = B - s s^T; with B' = L L^T, V = (Z - 1 s^T) L^-T is orthonormal in
 // L2(a) and orthogonal to the constants.  Writes R = L^-T (k x k), s.
-// One wavefront, matrix in LDS: right-looking Cholesky with the trailing
-// update spread over the lanes, then column j of L^-1 by lane j with
+// Rank revealing: a column whose pivot (its squared distance to the span
+// of the columns before it) is at most 1e-8 of the largest diagonal entry
+// of B', or 1e-12 in absolute terms, carries no information that the FP32
+// products Z = M V resolve (for Z = M V, pivots are ~rho^4, rounding noise
+// ~1e-14): it is dropped, i.e. its column of V is exactly zero and no other
+// column is orthogonalised against it, so the kept columns stay
+// orthonormal.  (A ridge on the diagonal instead shrinks such columns and,
+// after the Rayleigh-Ritz rotation, mixes the shrinkage into the good
+// ones.)  *ok_out = 0 when every column is dropped.
+// 256 threads, matrix in LDS: right-looking Cholesky with the trailing
+// update spread over the threads, then column j of L^-1 by thread j with
 // broadcast LDS reads of L.
 template <int KP>
 __global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out) {
@@ -105,44 +138,42 @@ __global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, doub
   __shared__ double B[KP][KP + 1];
   __shared__ double s[KP];
   __shared__ double lcol[KP];
-  __shared__ double tr_s;
-  __shared__ int ok_s;
+  __shared__ int drop[KP];
+  __shared__ double bmax_s;
   const int tid = threadIdx.x;
   for (int e = tid; e < NE + KP; e += NT) {
     double v = sum_parts(part, nblk, NE + KP, e);
     if (e < NE) B[e / KP][e % KP] = v;
     else s[e - NE] = v;
   }
-  if (tid == 0) ok_s = 1;
   __syncthreads();
   if (tid == 0) {
-    double tr = 0;
-    for (int k = 0; k < KP; ++k) tr += B[k][k] - s[k] * s[k];
-    tr_s = tr;
+    double bm = 0;
+    for (int k = 0; k < KP; ++k) bm = fmax(bm, B[k][k] - s[k] * s[k]);
+    bmax_s = bm;
   }
   __syncthreads();
-  const double tr = tr_s;
-  // B' = sym(B) - s s^T (+ tiny ridge), lower triangle suffices
+  const double dcut = fmax(1e-8 * bmax_s, 1e-12);
+  // B' = sym(B) - s s^T, lower triangle suffices
   for (int e = tid; e < NE; e += NT) {
     const int i = e / KP, j = e % KP;
-    if (j <= i) {
-      double v = 0.5 * (B[i][j] + B[j][i]) - s[i] * s[j];
-      if (i == j) v += 1e-13 * tr / KP;
-      B[i][j] = v;
-    }
+    if (j <= i) B[i][j] = 0.5 * (B[i][j] + B[j][i]) - s[i] * s[j];
   }
   __syncthreads();
   // right-looking Cholesky: column k of L from the current B, then the
-  // trailing update; two barriers per column
+  // trailing update; two barriers per column.  A dropped column gets
+  // L_kk = 1 and a zero column below the diagonal (no trailing update).
   for (int k = 0; k < KP; ++k) {
     if (tid >= k && tid < KP) {
-      double d = B[k][k];
-      if (!(d > 1e-30 * tr)) {
-        d = 1e-30 * tr + 1e-300;
-        if (tid == k) ok_s = 0;
+      const double d = B[k][k];
+      const bool dk = !(d > dcut);  // also NaN
+      if (dk) {
+        lcol[tid] = tid == k ? 1.0 : 0.0;
+      } else {
+        const double lk = sqrt(d);
+        lcol[tid] = tid == k ? lk : B[tid][k] / lk;
       }
-      const double lk = sqrt(d);
-      lcol[tid] = tid == k ? lk : B[tid][k] / lk;
+      if (tid == k) drop[k] = dk ? 1 : 0;
     }
     __syncthreads();
     const int rem = KP - 1 - k;
@@ -164,11 +195,20 @@ __global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, doub
       for (int t = 0; t < r; ++t) acc -= B[r][t] * x[t];
       x[r] = acc / B[r][r];
     }
+    // a dropped column r: row r of L^-1 is zero (V_r = 0); later rows do
+    // not read x[r] (L_ir = 0 for i > r)
+#pragma unroll
+    for (int r = 0; r < KP; ++r)
+      if (drop[r]) x[r] = 0.0;
 #pragma unroll
     for (int t = 0; t < KP; ++t) R[j * KP + t] = x[t];  // R = L^-T
     s_out[j] = s[j];
   }
-  if (tid == 0) *ok_out = ok_s;
+  if (tid == 0) {
+    int kept = 0;
+    for (int k = 0; k < KP; ++k) kept += drop[k] ? 0 : 1;
+    *ok_out = kept > 0 ? 1 : 0;
+  }
 }
 
 // ------------------------------------------------------ Rayleigh-Ritz
@@ -179,9 +219,12 @@ __global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, doub
 // column pair t), so one thread updates one block (and one row pair of the
 // accumulated Q) per step: two barriers per step.  Then eigenpairs sorted
 // descending: Q (k x k, columns = eigenvectors, row-major), lam (k).
+// Zero rows of T (columns of V that the orthonormalisation dropped) stay
+// untouched (their rotations are the identity); *zmask_out (nullable) gets
+// bit p set when sorted position p holds such a column.
 template <int KP>
 __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, double* Qout, double* lam, int sweeps,
-                                                int* sweeps_out) {
+                                                int* sweeps_out, unsigned* zmask_out) {
   constexpr int NE = KP * KP;
   constexpr int NP = KP / 2;
   constexpr int NT = 256;
@@ -191,12 +234,15 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
   __shared__ int pr[NP][2];
   __shared__ double red[2][NT / 64];
   __shared__ int stop_s;
+  __shared__ int zin[KP];
   const int tid = threadIdx.x;
   for (int e = tid; e < NE; e += NT) {
     A[e / KP][e % KP] = sum_parts(part, nblk, NE + KP, e);
     Q[e / KP][e % KP] = (e / KP == e % KP) ? 1.0 : 0.0;
   }
   __syncthreads();
+  // T is a Gram matrix: T_kk == 0 exactly iff column k of U (and of V) is 0
+  if (tid < KP) zin[tid] = A[tid][tid] == 0.0 ? 1 : 0;
   for (int e = tid; e < NE; e += NT) {
     const int i = e / KP, j = e % KP;
     if (i < j) {
@@ -246,13 +292,15 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
         }
         pr[r][0] = p;
         pr[r][1] = q;
-        // rotation angle in FP32; (c, s) normalised to FP64 accuracy (one
-        // Newton step on the FP32 reciprocal square root) so that the
-        // accumulated Q stays orthogonal to FP64 rounding
+        // rotation angle in FP32 (the quotient too: th only sets the angle;
+        // an apq below FP32 range is no rotation, an overflow of th to inf
+        // gives the identity); (c, s) normalised to FP64
+        // accuracy (one Newton step on the FP32 reciprocal square root) so
+        // that the accumulated Q stays orthogonal to FP64 rounding
         const double apq = A[p][q], dqp = A[q][q] - A[p][p];
         double c = 1.0, sn = 0.0;
-        if (fabs(apq) > 1e-30 * (fabs(A[p][p]) + fabs(A[q][q])) && fabs(apq) > 1e-300) {
-          const float th = (float)(dqp / (2.0 * apq));
+        if (fabs(apq) > 1e-30 * (fabs(A[p][p]) + fabs(A[q][q])) && (float)apq != 0.0f) {
+          const float th = (float)dqp / (2.0f * (float)apq);
           const float t = copysignf(1.0f, th) / (fabsf(th) + sqrtf(fmaf(th, th, 1.0f)));
           const double td = (double)t;
           const double x = fma(td, td, 1.0);
@@ -307,6 +355,12 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
   }
   __syncthreads();
   if (tid < KP) lam[tid] = A[order[tid]][order[tid]];
+  if (tid == 0 && zmask_out) {
+    unsigned msk = 0;
+    for (int p = 0; p < KP; ++p)
+      if (zin[order[p]]) msk |= 1u << p;
+    *zmask_out = msk;
+  }
   for (int e = tid; e < NE; e += NT) {
     const int r = e / KP, i = e % KP;
     Qout[r * KP + i] = Q[r][order[i]];
@@ -341,17 +395,15 @@ __global__ __launch_bounds__(64) void k_affine(const float* Z, const double* s, 
   for (int j = 0; j < KP; ++j) out[(size_t)i * KP + j] = o[j];
 }
 
-// counter-based uniform(-1, 1) start block for columns >= col0 (splitmix64)
-__global__ void k_random_block(float* Z, int n, int KP, int col0, unsigned long long seed) {
+// counter-based uniform(-1, 1) start block for columns >= col0; clears the
+// refill mask (nullable): the block has no zero columns
+__global__ void k_random_block(float* Z, int n, int KP, int col0, unsigned long long seed, unsigned* zmask) {
   long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (zmask && e == 0) *zmask = 0u;
   if (e >= (long long)n * KP) return;
   int l = (int)(e % KP);
   if (l < col0) return;
-  unsigned long long x = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(e + 1);
-  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-  x ^= x >> 31;
-  Z[e] = (float)((double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+  Z[e] = uniform_pm1(seed, (unsigned long long)e);
 }
 
 // out (n x ell FP64) = first ell columns of V (n x KP FP32)
@@ -376,12 +428,19 @@ hipError_t launch_repack(const float* V, int kp, int n, int ell, int ellp, float
   hipLaunchKernelGGL(k_repack, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, V, kp, n, ell, ellp, out);
   return hipGetLastError();
 }
-hipError_t launch_wgram(int kp, const float* Z, const double* w, int invert, int n, double* part, int nblk,
-                        hipStream_t s) {
+hipError_t launch_wgram(int kp, float* Z, const double* w, int invert, int n, double* part, int nblk,
+                        const unsigned* refill, unsigned refill_bits, uint64_t seed, hipStream_t s) {
   int rpb = (n + nblk - 1) / nblk;
-  if (kp == 8) hipLaunchKernelGGL((k_wgram<8>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb);
-  else if (kp == 16) hipLaunchKernelGGL((k_wgram<16>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb);
-  else hipLaunchKernelGGL((k_wgram<32>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb);
+  unsigned long long sd = (unsigned long long)seed;
+  if (kp == 8)
+    hipLaunchKernelGGL((k_wgram<8>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb, refill, refill_bits,
+                       sd);
+  else if (kp == 16)
+    hipLaunchKernelGGL((k_wgram<16>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb, refill, refill_bits,
+                       sd);
+  else
+    hipLaunchKernelGGL((k_wgram<32>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb, refill, refill_bits,
+                       sd);
   return hipGetLastError();
 }
 hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok, hipStream_t s) {
@@ -391,10 +450,13 @@ hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* 
   return hipGetLastError();
 }
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
-                         hipStream_t s) {
-  if (kp == 8) hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out);
-  else if (kp == 16) hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out);
-  else hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out);
+                         unsigned* zmask_out, hipStream_t s) {
+  if (kp == 8)
+    hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out);
+  else if (kp == 16)
+    hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out);
+  else
+    hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out);
   return hipGetLastError();
 }
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
@@ -405,10 +467,10 @@ hipError_t launch_affine(int kp, const float* Z, const double* sv, const double*
   else hipLaunchKernelGGL((k_affine<32>), dim3(nb), dim3(64), 0, s, Z, sv, R, rs, rs_invert, n, out);
   return hipGetLastError();
 }
-hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, hipStream_t s) {
+hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, unsigned* zmask, hipStream_t s) {
   long long cnt = (long long)n * kp;
   hipLaunchKernelGGL(k_random_block, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, Z, n, kp, col0,
-                     (unsigned long long)seed);
+                     (unsigned long long)seed, zmask);
   return hipGetLastError();
 }
 hipError_t launch_take_cols(const float* V, int kp, int n, int ell, double* out, hipStream_t s) {

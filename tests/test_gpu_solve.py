@@ -142,3 +142,34 @@ def test_sknr_static_warm_start(sk, ctx):
     print("static SK-NR", r["stages"][0], "SK", r0["stages"][0]["iters"], flush=True)
     assert r["status"] == 0 and r["marginal_err"] < 1e-6
     assert r["stages"][0]["iters"] < r0["stages"][0]["iters"]
+
+
+def test_sknr_large_eps_stages_take_newton_steps(sk, ctx):
+    """A request of the mixed serving trace (484 x 1447, d = 2, cost
+    |x - y|^2 / 2, eps from 1 halving to 1e-2, l = 30).  At the large-eps
+    stages the spectrum of M falls below FP32 resolution after a few modes,
+    so most warm-start columns carry no mass; the Newton steps must still
+    be taken on the others, as the oracle (exact eigenvectors) takes every
+    one of them."""
+    tr = W.serving_trace(n_requests=64, rate=1.0, seed=4)
+    req = sorted(tr, key=lambda r: r.problem.a.shape[0] * r.problem.b.shape[0])[32]
+    p = req.problem
+    assert (p.n, p.m, p.x.shape[1]) == (484, 1447, 2)
+    lad = W.request_ladder(req.eps)
+    ell = 30
+    C = fp32_sqeuclid(p.x, p.y, p.cost_scale).astype(np.float64)
+    fo, go, rs = O.solve_schedule(C, p.a, p.b, lad, 1e-6, 20000, ell=ell)
+    print("case serving request 484x1447 l=30 eps 1 -> 1e-2", flush=True)
+    f, g, res = sk.solve(ctx, gpu_problem(p), lad, tol=1e-6, max_iter=20000, ell=ell,
+                         warm_mode=sk.WARM_SEQUENTIAL)
+    it = [s["iters"] for s in res["stages"]]
+    tried = [s["newton_tried"] for s in res["stages"]]
+    acc = [s["newton_accepted"] for s in res["stages"]]
+    print(it, tried, acc, [r.iters for r in rs], flush=True)
+    assert res["status"] == 0 and res["marginal_err"] < 1e-6
+    for s in range(1, len(lad)):
+        assert rs[s].newton_accepted == rs[s].newton_tried
+        assert acc[s] >= tried[s] - 1, (s, tried, acc)
+        assert it[s] <= rs[s].iters + 2, (s, it, [r.iters for r in rs])
+    fo, go = O.normalize_gauge(fo, go, p.a, p.b)
+    assert e_pot(f.cpu().numpy(), g.cpu().numpy(), fo, go, C) < 1e-5

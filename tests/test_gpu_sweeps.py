@@ -197,6 +197,33 @@ def test_newton_step_matches_oracle(sk, ctx):
         assert np.abs(fd.cpu().numpy() - (r.f + step["delta"])).max() < 1e-5 * np.abs(step["delta"]).max() + 1e-9
 
 
+def test_newton_step_drops_massless_basis_columns(sk, ctx):
+    """A basis with columns that carry no mass (one exactly zero, one at
+    1e-9, as the warm start leaves where the spectrum of M lies below FP32
+    resolution) gives the Newton step on the span of the other columns,
+    where the plain Cholesky of the full projected Hessian would fail and
+    lose the step."""
+    prob = _stored_problem(300, 420, seed=7)
+    C = prob.C.astype(np.float64)
+    eps = 0.03
+    r = O.sinkhorn(C, prob.a, prob.b, eps, tol=1e-3, max_iter=2000)
+    ref = O.sinkhorn(C, prob.a, prob.b, eps, tol=1e-12, max_iter=100000)
+    V, _ = O.spectral_basis(ref.f, ref.g, C, prob.a, prob.b, eps, 6, method="dense")
+    noise = 1e-9 * np.random.default_rng(3).standard_normal(V.shape[0])
+    Vaug = np.column_stack([V[:, 0], np.zeros(V.shape[0]), V[:, 1:4], noise, V[:, 4:]])
+    assert O.projected_newton(r.f, C, prob.a, prob.b, eps, V)["ok"]
+    fd = to_dev(r.f.copy())
+    print("case newton_step massless columns 300x420", flush=True)
+    acc, q0, q1 = sk.newton_step(ctx, gpu_problem(prob, stored=True), eps, fd, to_dev(Vaug))
+    step = O.projected_newton(r.f, C, prob.a, prob.b, eps, V)
+    q1_ref = O.semidual_value(r.f + step["delta"], C, prob.a, prob.b, eps)
+    q0_ref = O.semidual_value(r.f, C, prob.a, prob.b, eps)
+    assert q1_ref > q0_ref
+    assert acc
+    assert abs(q1 - q1_ref) <= 64 * U32 * eps + 1e-6 * abs(q1_ref - q0_ref)
+    assert np.abs(fd.cpu().numpy() - (r.f + step["delta"])).max() < 1e-5 * np.abs(step["delta"]).max() + 1e-9
+
+
 def _principal_cosines(V1, V2, a):
     sa = np.sqrt(a)[:, None]
     Q1, _ = np.linalg.qr(sa * V1)
