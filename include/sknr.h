@@ -124,7 +124,9 @@ typedef struct sknr_opts {
   double eps_prime;       /* STATIC: eps' of the warm-start solve */
   int32_t eig_oversample; /* extra subspace columns (0 -> 8) */
   int32_t eig_max_iter;   /* subspace iterations cap (0 -> 100) */
-  double eig_tol;         /* Ritz-value stagnation tolerance (0 -> 1e-4) */
+  double eig_tol;         /* subspace iteration stops when every leading Ritz
+                             value rho_i^2 moves by less than
+                             eig_tol * (1 - rho_i^2) (0 -> 0.1) */
   int32_t check_every;    /* iterations per host convergence poll (0 -> auto) */
   int32_t first_stage_nr; /* 1: SK-NR also on stage 0 (WARM_USER or WARM_STATIC) */
   const double* f0;       /* [device] optional n FP64 initial f at eps[0] (NULL -> 0) */
@@ -246,7 +248,10 @@ int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps,
  * ell non-constant eigenvectors of M = diag(a)^-1 P diag(b)^-1 P^T (the
  * semi-dual Hessian at the optimum is -(1/eps) diag(a) (Id - M), eq.
  * semidual_Hessian) by block subspace iteration with ell + oversample
- * columns and FP64 Rayleigh-Ritz.  V_out [device] n x ell FP64 (columns
+ * columns and FP64 Rayleigh-Ritz, stopped when every leading Ritz value
+ * rho_i^2 moves by less than tol * (1 - rho_i^2) or after max_iter.  Modes
+ * below what the FP32 products resolve (rho_i^2 below ~1e-4 rho_1^2) come
+ * back as zero columns.  V_out [device] n x ell FP64 (nonzero columns
  * orthonormal in L2(a), orthogonal to constants, descending rho);
  * rho_out [host] ell+1 values sqrt(eigenvalue), rho_out[0] = 1 for the
  * constant mode; iters_out [host] subspace iterations used (may be NULL). */

@@ -80,9 +80,11 @@ __global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
     if (A.flags & F_ACCEPT_DQ) {
       // Q(f') - Q(f) = <f' - f, a> - sum_o b_o eps log1p(w_o): both terms are
       // accurate relative to themselves, so the sign is reliable where the
-      // difference of two FP32 c-transform sums is not
+      // difference of two FP32 c-transform sums is not.  A step so large
+      // that some w_o rounds to -1 (or overflows) gives a non-finite gain:
+      // rejected, the SK step is taken
       const double dq = ddx - e;
-      int acc = (st->chol_ok && dq > 0) ? 1 : 0;
+      int acc = (st->chol_ok && dq > 0 && dq < INFINITY) ? 1 : 0;
       st->accept = acc;
       st->newton_accepted += acc;
     }

@@ -145,6 +145,8 @@ def test_argument_validation(sk, ctx):
     Cn[2, 3] = float("inf")
     print(rejects(dict(a=ok["a"], b=ok["b"], C=Cn)), flush=True)         # non-finite cost
     print(rejects(dict(a=ok["a"], b=ok["b"], C=torch.ones(n, m, device="cuda"), ldc=m - 1)), flush=True)
+    print(rejects(ell=5, warm_mode=sk.WARM_SEQUENTIAL, nr_switch_iters=-1), flush=True)
+    print(rejects(ell=5, warm_mode=sk.WARM_STATIC, eps_prime=0.2, nr_switch_iters=10), flush=True)
     # the context still works afterwards
     f, g, res = sk.solve(ctx, sk.Problem(**ok), [0.1], tol=1e-6)
     assert res["status"] == 0

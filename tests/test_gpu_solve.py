@@ -173,3 +173,36 @@ def test_sknr_large_eps_stages_take_newton_steps(sk, ctx):
         assert it[s] <= rs[s].iters + 2, (s, it, [r.iters for r in rs])
     fo, go = O.normalize_gauge(fo, go, p.a, p.b)
     assert e_pot(f.cpu().numpy(), g.cpu().numpy(), fo, go, C) < 1e-5
+
+
+def test_adaptive_switch_to_sknr(sk, ctx):
+    """nr_switch_iters = T: the stages are plain SK (the same iterates as an
+    SK solve, no Newton step tried) up to and including the first one that
+    needs more than T iterations; every later stage runs SK-NR with the
+    sequential warm start, and the optimum is the oracle's."""
+    tr = W.serving_trace(n_requests=64, rate=1.0, seed=4)
+    req = sorted(tr, key=lambda r: r.problem.a.shape[0] * r.problem.b.shape[0])[32]
+    p = req.problem
+    lad = W.request_ladder(req.eps)
+    T = 10
+    print("case adaptive switch 484x1447 T=10", flush=True)
+    _, _, rsk = sk.solve(ctx, gpu_problem(p), lad, tol=1e-6, max_iter=20000, ell=0)
+    f, g, res = sk.solve(ctx, gpu_problem(p), lad, tol=1e-6, max_iter=20000, ell=30,
+                         warm_mode=sk.WARM_SEQUENTIAL, nr_switch_iters=T)
+    it_sk = [s["iters"] for s in rsk["stages"]]
+    it = [s["iters"] for s in res["stages"]]
+    tried = [s["newton_tried"] for s in res["stages"]]
+    print(it_sk, it, tried, flush=True)
+    sw = next(s for s, k in enumerate(it_sk) if k > T)
+    assert sw + 1 < len(lad)
+    assert it[:sw + 1] == it_sk[:sw + 1]
+    assert all(t == 0 for t in tried[:sw + 1])
+    assert all(s["eig_iters"] == 0 for s in res["stages"][:sw + 1])
+    assert all(t > 0 for t in tried[sw + 1:])
+    assert all(s["eig_iters"] > 0 for s in res["stages"][sw + 1:])
+    assert sum(it[sw + 1:]) < sum(it_sk[sw + 1:])
+    assert res["status"] == 0 and res["marginal_err"] < 1e-6
+    C = fp32_sqeuclid(p.x, p.y, p.cost_scale).astype(np.float64)
+    fo, go, _ = O.solve_schedule(C, p.a, p.b, lad, 1e-9, 100000)
+    fo, go = O.normalize_gauge(fo, go, p.a, p.b)
+    assert e_pot(f.cpu().numpy(), g.cpu().numpy(), fo, go, C) < 1e-5
