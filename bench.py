@@ -62,14 +62,14 @@ def algorithmic_work(kind: str):
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2.0, WRITE_SIZE 1 GiB
 # -> x1.0); see profiles/.  Valid only for the kernel sources they were
 # taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip).
-TRAFFIC_KERNEL_SHA1 = "ade29e7ca4b2e5794aeac2782259f5e2677b0459"
+TRAFFIC_KERNEL_SHA1 = "03a148350c08d6ed594616526ee26460ddff488f"
 TRAFFIC_BYTES = {
-    "sweep_stream_points_l0:main": (243.95 * 1.9999 + 2065.88 * 1.0000) * 1024,
-    "sweep_stream_stored_l0:main": (524978.79 * 1.9999 + 6144.00 * 1.0000) * 1024,
-    "sweep_rows_stored_l0:main": (525906.00 * 1.9999 + 529.27 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x3_l0:main": (91846.42 * 1.9999 + 6224.01 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x6_l0:main": (140445.15 * 1.9999 + 6226.42 * 1.0000) * 1024,
-    "sweep_stream_points_bf16_l0:main": (25535.27 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_l0:main": (243.02 * 1.9999 + 2062.17 * 1.0000) * 1024,
+    "sweep_stream_stored_l0:main": (524979.54 * 1.9999 + 6144.00 * 1.0000) * 1024,
+    "sweep_rows_stored_l0:main": (525905.74 * 1.9999 + 530.00 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x3_l0:main": (91854.47 * 1.9999 + 6223.99 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x6_l0:main": (140410.91 * 1.9999 + 6226.26 * 1.0000) * 1024,
+    "sweep_stream_points_bf16_l0:main": (25527.18 * 1.9999 + 6223.96 * 1.0000) * 1024,
 }
 
 
