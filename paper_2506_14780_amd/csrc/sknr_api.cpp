@@ -247,7 +247,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   if (ellp > 0) {
     add(sizeof(float) * (size_t)n * 32 * 2);
     add(sizeof(float) * (size_t)m * 32 * 2);
-    add(sizeof(double) * 32 * 32 * 2 + sizeof(double) * 64 + 64);
+    add(sizeof(double) * 32 * 32 * 2 + sizeof(double) * 96 + 64);
   }
   if (P.xmode >= SKNR_XTERM_BF16) {
     const int parts = P.xmode - 1;
@@ -347,7 +347,7 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
     w.Rw = (double*)A.take(sizeof(double) * 32 * 32);
     w.Qw = (double*)A.take(sizeof(double) * 32 * 32);
     w.sw = (double*)A.take(sizeof(double) * 32);
-    w.lamw = (double*)A.take(sizeof(double) * 32);
+    w.lamw = (double*)A.take(sizeof(double) * 64);  // this iteration's Ritz values, then the first's
     w.okw = (int*)A.take(64);
   }
   w.HX = w.MX = w.LX = w.HY = w.MY = w.LY = nullptr;
@@ -820,21 +820,35 @@ struct Engine {
       HIPCHK(launch_wgram(kp, w.Zw, P.wX, 0, n, w.nrpart, nbn, zmask, ~0u,
                           seed ^ (0x632BE59BD9B4E019ull * (uint64_t)it), s));
       HIPCHK(launch_sum_partials(w.nrpart, nbn, plen, w.nrsum, s));
-      HIPCHK(launch_orth(kp, w.nrsum, 1, w.Rw, w.sw, w.okw, s));
+      HIPCHK(launch_orth(kp, w.nrsum, 1, w.Rw, w.sw, w.okw, zmask, s));
       HIPCHK(launch_affine(kp, w.Zw, w.sw, w.Rw, nullptr, 0, n, w.Vw, s));
       // U = P~^T V (and G~ = T_c(F))
       sweep_col(w.F, MA_F, nullptr, w.Gt, DOT_GT, MA_GT, kp, w.Vw, w.Uw, W_SCALE_WEIGHT, 0, 0);
       // Rayleigh-Ritz: T = U^T D_b^-1 U = V^T D_a M V
       HIPCHK(launch_wgram(kp, w.Uw, P.wY, 1, m, w.nrpart, nbm, nullptr, 0u, 0, s));
       HIPCHK(launch_sum_partials(w.nrpart, nbm, plen, w.nrsum, s));
-      HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, w.lamw, w.okw + 1, zmask, s));
+      // the stop test needs two iterations: the first one's Ritz values stay
+      // on the device (lamw + 32) and come back with the second's, one host
+      // round trip fewer per warm start
+      const bool defer = it == 1 && max_it > 1;
+      HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, defer ? w.lamw + 32 : w.lamw, w.okw + 1, zmask, s));
       HIPCHK(launch_affine(kp, w.Vw, nullptr, w.Qw, nullptr, 0, n, w.Zw, s));
       std::swap(w.Vw, w.Zw);  // V <- V Q (Ritz vectors)
       HIPCHK(launch_affine(kp, w.Uw, nullptr, w.Qw, P.wY, 1, m, w.Utw, s));  // D_b^-1 U Q
-      HIPCHK(hipMemcpyAsync(lc.data(), w.lamw, sizeof(double) * kp, hipMemcpyDeviceToHost, s));
+      if (defer) {
+        check_cancel();
+        // Z = M V = D_a^-1 P~ (D_b^-1 U Q)
+        sweep_row(w.Gt, MA_GT, w.F, w.Fsk, nullptr, DOT_FSK, MA_FSK, kp, w.Utw, w.Zw, W_SCALE_RATIO, 0, 0);
+        continue;
+      }
+      double both[64];
+      const bool first_pair = it == 2 && max_it > 1;  // iteration 1 was deferred
+      HIPCHK(hipMemcpyAsync(both, w.lamw, sizeof(double) * (first_pair ? 64 : kp), hipMemcpyDeviceToHost, s));
       int jsw = 0;
       HIPCHK(hipMemcpyAsync(&jsw, w.okw + 1, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      std::copy(both, both + kp, lc.begin());
+      if (first_pair) std::copy(both + 32, both + 32 + kp, lp.begin());
       check_cancel();
       if (getenv("SKNR_DEBUG_EIG")) std::fprintf(stderr, "eig it %d jacobi sweeps %d lam0 %.6f lam%d %.6f\n", it, jsw, lc[0], ell - 1, lc[ell - 1]);
       // the move of each leading Ritz value rho_i^2 relative to its gap
@@ -1409,10 +1423,19 @@ int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps, const d
     std::vector<double> lam;
     int it = E.spectral(ell, oversample, max_iter, tol, seed, &lam);
     int kp = E.spectral_kp(ell, oversample);
-    HIPCHK(launch_take_cols(w.Vw, kp, P.n, ell, V_out, s));
+    // Ritz pairs below what the FP32 products resolve (the bound of the
+    // rank-revealing orthonormalisation: ||M v||^2 = rho^4 at most 1e-8 of
+    // the top one's, or 1e-12) come back as zero columns with rho = 0; the
+    // block may hold random refill directions there
+    const double top = lam.empty() ? 0.0 : std::max(0.0, lam[0]);
+    const double cut = std::max(1e-8 * top * top, 1e-12);
+    unsigned zero = 0;
+    for (int i = 0; i < ell; ++i)
+      if (!(lam[i] > 0.0 && lam[i] * lam[i] > cut)) zero |= 1u << i;
+    HIPCHK(launch_take_cols(w.Vw, kp, P.n, ell, zero, V_out, s));
     HIPCHK(hipStreamSynchronize(s));
     rho_out[0] = 1.0;
-    for (int i = 0; i < ell; ++i) rho_out[i + 1] = std::sqrt(std::max(0.0, lam[i]));
+    for (int i = 0; i < ell; ++i) rho_out[i + 1] = ((zero >> i) & 1u) ? 0.0 : std::sqrt(lam[i]);
     if (iters_out) *iters_out = it;
     return SKNR_OK;
   });

@@ -201,13 +201,14 @@ hipError_t launch_eval_finish(const double* rowpart, const double* colpart, cons
 // positions whose Ritz vector is a dropped (zero) column
 hipError_t launch_wgram(int kp, float* Z, const double* w, int invert, int n, double* part, int nblk,
                         const unsigned* refill, unsigned refill_bits, uint64_t seed, hipStream_t s);
-hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok, hipStream_t s);
+hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok,
+                       const unsigned* refill, hipStream_t s);
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
                          unsigned* zmask_out, hipStream_t s);
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
                          int n, float* out, hipStream_t s);
 hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, unsigned* zmask, hipStream_t s);
-hipError_t launch_take_cols(const float* V, int kp, int n, int ell, double* out, hipStream_t s);
+hipError_t launch_take_cols(const float* V, int kp, int n, int ell, unsigned zero, double* out, hipStream_t s);
 hipError_t launch_sum_partials(const double* part, int nblk, int len, double* out, hipStream_t s);
 hipError_t launch_repack(const float* V, int kp, int n, int ell, int ellp, float* out, hipStream_t s);
 hipError_t launch_f32_to_f64(const float* src, double* dst, long long count, hipStream_t s);

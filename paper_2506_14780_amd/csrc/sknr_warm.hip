@@ -121,7 +121,9 @@ __global__ __launch_bounds__(256) void k_wgram(float* Z, const double* wgt, int 
 // L2(a) and orthogonal to the constants.  Writes R = L^-T (k x k), s.
 // Rank revealing: a column whose pivot (its squared distance to the span
 // of the columns before it) is at most 1e-8 of the largest diagonal entry
-// of B', or 1e-12 in absolute terms, carries no information that the FP32
+// of B' over the columns that were not just refilled (refill mask,
+// nullable: fresh random columns are not products M V and would set the
+// scale), or 1e-12 in absolute terms, carries no information that the FP32
 // products Z = M V resolve (for Z = M V, pivots are ~rho^4, rounding noise
 // ~1e-14): it is dropped, i.e. its column of V is exactly zero and no other
 // column is orthogonalised against it, so the kept columns stay
@@ -132,7 +134,8 @@ __global__ __launch_bounds__(256) void k_wgram(float* Z, const double* wgt, int 
 // update spread over the threads, then column j of L^-1 by thread j with
 // broadcast LDS reads of L.
 template <int KP>
-__global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out) {
+__global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out,
+                                              const unsigned* refill) {
   constexpr int NE = KP * KP;
   constexpr int NT = 256;
   __shared__ double B[KP][KP + 1];
@@ -148,8 +151,10 @@ __global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, doub
   }
   __syncthreads();
   if (tid == 0) {
+    const unsigned fresh = refill ? *refill : 0u;
     double bm = 0;
-    for (int k = 0; k < KP; ++k) bm = fmax(bm, B[k][k] - s[k] * s[k]);
+    for (int k = 0; k < KP; ++k)
+      if (!((fresh >> k) & 1u)) bm = fmax(bm, B[k][k] - s[k] * s[k]);
     bmax_s = bm;
   }
   __syncthreads();
@@ -406,12 +411,13 @@ __global__ void k_random_block(float* Z, int n, int KP, int col0, unsigned long 
   Z[e] = uniform_pm1(seed, (unsigned long long)e);
 }
 
-// out (n x ell FP64) = first ell columns of V (n x KP FP32)
-__global__ void k_take_cols(const float* V, int KP, int n, int ell, double* out) {
+// out (n x ell FP64) = first ell columns of V (n x KP FP32); columns with
+// bit l of `zero` set are written as zeros
+__global__ void k_take_cols(const float* V, int KP, int n, int ell, unsigned zero, double* out) {
   long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e >= (long long)n * ell) return;
   int i = (int)(e / ell), l = (int)(e % ell);
-  out[e] = (double)V[(size_t)i * KP + l];
+  out[e] = ((zero >> l) & 1u) ? 0.0 : (double)V[(size_t)i * KP + l];
 }
 
 // out (n x ellp) = first ell columns of V (n x kp), zero padded
@@ -443,10 +449,11 @@ hipError_t launch_wgram(int kp, float* Z, const double* w, int invert, int n, do
                        sd);
   return hipGetLastError();
 }
-hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok, hipStream_t s) {
-  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
-  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
-  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok);
+hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok,
+                       const unsigned* refill, hipStream_t s) {
+  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok, refill);
+  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok, refill);
+  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok, refill);
   return hipGetLastError();
 }
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
@@ -473,9 +480,9 @@ hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed,
                      (unsigned long long)seed, zmask);
   return hipGetLastError();
 }
-hipError_t launch_take_cols(const float* V, int kp, int n, int ell, double* out, hipStream_t s) {
+hipError_t launch_take_cols(const float* V, int kp, int n, int ell, unsigned zero, double* out, hipStream_t s) {
   long long cnt = (long long)n * ell;
-  hipLaunchKernelGGL(k_take_cols, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, V, kp, n, ell, out);
+  hipLaunchKernelGGL(k_take_cols, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, V, kp, n, ell, zero, out);
   return hipGetLastError();
 }
 

@@ -258,6 +258,39 @@ def test_spectral_basis_matches_oracle(sk, ctx, ell):
         assert cos.min() > 1 - 1e-4
 
 
+def test_spectral_basis_drops_unresolved_modes(sk, ctx):
+    """At large eps most of the top-30 eigenvalues of M lie below what the
+    FP32 products resolve (here rho_7^2 ~ 1e-14 at eps = 1).  The basis
+    returns them as exact zero columns; the other columns are orthonormal
+    in L2(a) and contain the oracle's resolved modes (dense eigh), with
+    their rho."""
+    tr = W.serving_trace(n_requests=64, rate=1.0, seed=4)
+    p = sorted(tr, key=lambda r: r.problem.a.shape[0] * r.problem.b.shape[0])[32].problem
+    C = fp32_sqeuclid(p.x, p.y, p.cost_scale).astype(np.float64)
+    eps, ell = 1.0, 30
+    ref = O.sinkhorn(C, p.a, p.b, eps, tol=1e-11, max_iter=100000)
+    Vr, rho_r = O.spectral_basis(ref.f, ref.g, C, p.a, p.b, eps, ell + 1, method="dense")
+    print("case spectral basis 484x1447 eps=1 l=30", flush=True)
+    V, rho, it = sk.spectral_basis(ctx, gpu_problem(p), eps, to_dev(ref.f), ell, oversample=8, max_iter=300,
+                                   tol=1e-8)
+    V = V.cpu().numpy()
+    nz = np.abs(V).max(axis=0) > 0
+    k = int(nz.sum())
+    print("kept", k, "rho gpu", rho[:k + 2], "oracle", rho_r[:k + 2], "iters", it, flush=True)
+    assert 0 < k < ell
+    assert np.all(nz[:k]) and not np.any(nz[k:])          # zero columns sort last
+    assert np.all(rho[k + 1:] == 0.0)
+    Vk = V[:, :k]
+    assert np.allclose(Vk.T @ (p.a[:, None] * Vk), np.eye(k), atol=1e-5)
+    assert np.abs(p.a @ Vk).max() < 1e-5
+    resolved = int(np.sum(rho_r[1:] ** 2 >= 1e-3 * rho_r[1] ** 2))
+    assert 1 <= resolved <= k
+    assert np.allclose(rho[1:resolved + 1], rho_r[1:resolved + 1], atol=1e-5)
+    cos = _principal_cosines(Vk, Vr[:, :resolved], p.a)
+    print("resolved", resolved, "min cos", cos.min(), flush=True)
+    assert cos[:resolved].min() > 1 - 1e-4
+
+
 def test_spectral_basis_points(sk, ctx):
     """The warm-start basis on a cost built from points (its products run
     the 32-wide weighted sweeps in both orientations) against the oracle's
