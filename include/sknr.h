@@ -149,7 +149,9 @@ typedef struct sknr_stage_stats {
   int32_t newton_tried;   /* projected Newton steps attempted */
   int32_t newton_accepted;/* ... and accepted by the Q^semi test */
   int32_t eig_iters;      /* subspace iterations of the warm start feeding this stage */
-  double marginal_err;    /* FP64 L1 marginal error at the end of the stage */
+  double marginal_err;    /* L1 marginal error at the end of the stage: the FP64
+                             check for the last stage, the sweeps' FP32
+                             estimate for the others */
   double seconds;         /* wall time of the stage (incl. its warm start) */
 } sknr_stage_stats;
 

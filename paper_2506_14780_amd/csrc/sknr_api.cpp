@@ -655,6 +655,7 @@ struct Engine {
 
   // Run one stage of Algorithm 4.1 from the current (F, G[0]); returns
   // iterations and sets *converged.  G ends in w.G[0].
+  double last_err = 0;  // the sweeps' FP32 marginal-error estimate at the end of run_stage
   int run_stage(int ell, int max_iter, int check_every, bool resume, bool* converged, int* tried, int* accepted) {
     init_state_keep();
     const bool graphs = c->use_graphs && !c->profile;
@@ -703,6 +704,7 @@ struct Engine {
     *converged = st.done != 0;
     *tried = st.newton_tried;
     *accepted = st.newton_accepted;
+    last_err = st.err;
     // bring g_k into G[0]
     int gidx = ell > 0 ? 0 : (st.done ? st.gsel : p);
     if (gidx != 0) HIPCHK(hipMemcpyAsync(w.G[0], w.G[gidx], sizeof(float2) * P.m, hipMemcpyDeviceToDevice, s));
@@ -969,8 +971,10 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
     int tried = 0, acc = 0, it = 0;
     sknr_eval ev{};
     // The sweeps estimate the error in FP32 (column marginal via the next
-    // c-transform); the FP64 check decides.  If it disagrees, continue
-    // the stage with a tighter FP32 threshold.
+    // c-transform); that ends an intermediate stage, whose potentials only
+    // start the next one.  After the last stage the FP64 check decides: if
+    // it disagrees, the stage continues with a tighter FP32 threshold.
+    const bool last = st == opts->n_eps - 1;
     E.tol = opts->tol;
     for (int attempt = 0; attempt < 8; ++attempt) {
       int tr = 0, ac = 0;
@@ -978,6 +982,12 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
       it += E.run_stage(use_nr ? opts->ell : 0, opts->max_iter - it, opts->check_every, attempt > 0, &cv, &tr, &ac);
       tried += tr;
       acc += ac;
+      if (!last) {
+        conv = cv;
+        ev = sknr_eval{};
+        ev.marginal_err = E.last_err;
+        break;
+      }
       E.export_fg(f_out, g_out);
       ev = E.evaluate(prob, f_out, g_out);
       conv = cv && ev.marginal_err < opts->tol;
