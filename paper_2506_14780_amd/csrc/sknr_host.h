@@ -114,8 +114,11 @@ struct Lane {
       evpool.pop_back();
       return e;
     }
+    // timing only, between records on one stream: no system-scope fence
+    // (it would add a write-back of L2 to every bracket)
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) throw Err{SKNR_EDEVICE, "hipEventCreate failed"};
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+      throw Err{SKNR_EDEVICE, "hipEventCreate failed"};
     return e;
   }
   int kind_of(const std::string& name) {
