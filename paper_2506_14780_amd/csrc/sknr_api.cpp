@@ -545,12 +545,11 @@ struct Engine {
     z.eps_df = split_df(eps);
     z.eln2_df = split_df(eps * 0.6931471805599453);
   }
+  // fresh state for the current eps, written by a kernel (no host wait)
   void init_state() {
     DevState z{};
     set_consts(z);
-    std::memcpy(c->st_host, &z, sizeof(DevState));
-    HIPCHK(hipMemcpyAsync(w.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(launch_state_reset(w.st, z, false, s));
   }
   void check_cancel() const {
     if (c->cancel && c->cancel->load(std::memory_order_relaxed)) throw Err{SKNR_ECANCELED, "request cancelled"};
@@ -713,16 +712,9 @@ struct Engine {
 
   // state re-initialisation that keeps the maxabs / dot slots of (F, G[0])
   void init_state_keep() {
-    DevState cur = read_state();
     DevState z{};
-    z.maxabs[MA_F] = cur.maxabs[MA_F];
-    z.maxabs[MA_G] = cur.maxabs[MA_G];
-    z.dots[DOT_F] = cur.dots[DOT_F];
-    z.dots[DOT_G] = cur.dots[DOT_G];
     set_consts(z);
-    std::memcpy(c->st_host, &z, sizeof(DevState));
-    HIPCHK(hipMemcpyAsync(w.st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(launch_state_reset(w.st, z, true, s));
   }
 
   // FP64 potentials in the caller's orientation -> f_out, g_out (device)

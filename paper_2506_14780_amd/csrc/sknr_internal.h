@@ -159,6 +159,9 @@ hipError_t launch_to_hat(const double* f, const double* logw, double eps, float2
                          DevState* st, int ma_slot, const double* w, int dot_slot, double* scratch, hipStream_t s);
 hipError_t launch_from_hat(const float2* U, const double* logw, double eps, double* f, int n, hipStream_t s);
 hipError_t launch_rebase(float2* U, const float2* lw, float2 deps_df, int n, DevState* st, int ma, hipStream_t s);
+// *st = z on the device; keep: carry over maxabs[MA_F], maxabs[MA_G],
+// dots[DOT_F], dots[DOT_G] from the current state
+hipError_t launch_state_reset(DevState* st, const DevState& z, bool keep, hipStream_t s);
 hipError_t launch_copy_state_slot(DevState* st, int dst_dot, int src_dot, int dst_ma, int src_ma, hipStream_t s);
 
 // Newton step pieces (FP64 small system)
