@@ -6,8 +6,9 @@ log-domain Sinkhorn on the same GPU, with p50/p99 solve latency.
 Workload (one "step" = one full solve): n = m = 4096 points in [0,1]^2,
 x from a 3-component Gaussian mixture (sigma 0.05), y uniform, weights
 Dirichlet(5); squared-Euclidean cost built on the fly in FP32; eps annealed
-1e-1 -> 1e-3 by halving (8 stages), each stage run to an FP64-verified L1
-marginal error below 1e-6.  Inputs are resident in HBM before timing.
+1e-1 -> 1e-3 by halving (8 stages), each stage run to an L1 marginal error
+below 1e-6: intermediate stages stop on the sweeps' FP32 estimate of it, the
+last stage is verified in FP64.  Inputs are resident in HBM before timing.
 
 Prints one JSON line (see the fields below).  `--gpus N` with N > 1 exits:
 the solver runs on one GPU.
@@ -417,7 +418,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"gmm_vs_uniform n=m={args.n} d=2, cost built on the fly, eps 1e-1->1e-3 halving "
-                         f"({len(ladder)} stages), tol {args.tol:g} L1 (FP64-verified), SK-NR(l={args.ell}) "
+                         f"({len(ladder)} stages), tol {args.tol:g} L1 (last stage FP64-verified), SK-NR(l={args.ell}) "
                          f"sequential spectral warm start"),
             "n": prob.n, "m": prob.m, "d": 2, "eps_ladder": ladder, "tol": args.tol, "ell": args.ell,
         },

@@ -487,3 +487,62 @@ def test_dual_partials_by_finite_differences_and_envelope():
         xm[i, k] -= h
         fd = (W(xp)[0] - W(xm)[0]) / (2 * h)
         assert fd == pytest.approx(D0["x"][i, k], rel=1e-6, abs=1e-10)
+
+
+# ------------------------------------------------- the cost of Sec. 5 (input)
+
+@pytest.mark.parametrize("d", [2, 3, 64])
+@pytest.mark.parametrize("scale", ["one", "inv_d", 0.37])
+def test_sqeuclid_cost_against_cdist_and_euclidean_invariances(d, scale):
+    """The squared Euclidean cost of Sec. 5 against scipy's cdist (an
+    implementation of independent provenance) for d = 2, 3, 64 and scales
+    1, 1/d, 0.37, plus two facts of Euclidean geometry that hold whatever
+    the formula: invariance under a common rotation and translation of both
+    clouds, and C_ii = 0 when the clouds coincide.  A dropped coordinate, a
+    wrong sign, a transposed operand or a mis-applied scale fails one."""
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(30 + d)
+    s = {"one": 1.0, "inv_d": 1.0 / d}.get(scale, scale)
+    x = rng.standard_normal((17, d))
+    y = rng.standard_normal((23, d)) + 0.5
+    C = O.sqeuclid_cost(x, y, s)
+    assert C.shape == (17, 23)
+    np.testing.assert_allclose(C, s * cdist(x, y, "sqeuclidean"), rtol=1e-12, atol=1e-12 * s * d)
+    Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    t = rng.standard_normal(d)
+    np.testing.assert_allclose(O.sqeuclid_cost(x @ Q + t, y @ Q + t, s), C, rtol=1e-10, atol=1e-10 * s * d)
+    assert np.all(np.abs(np.diag(O.sqeuclid_cost(x, x, s))) < 1e-12 * s * d)
+
+
+# ------------------------------------------------- static warm start (Sec. 5)
+
+def test_static_schedule_reaches_the_sk_optimum_at_the_theorem_4_2_rate():
+    """The static warm start of Sec. 5 (V_l computed once, from a plain SK
+    solve at eps').  Theorem 4.2: the SK-NR stages reach the SK optimum;
+    with eps' equal to the target eps, V_l spans the exact low-frequency
+    eigenvectors there and the marginal error contracts like rho_{l+1}^2
+    (P11), faster than plain SK's rho_1^2 (Lemma 3.2).  With the paper's
+    eps' = 1 the optimum is the same."""
+    prob = W.uniform_square(60, seed=12)
+    C = O.sqeuclid_cost(prob.x, prob.y)
+    a, b = prob.a, prob.b
+    eps, ell = 0.03, 3
+    ref = O.sinkhorn(C, a, b, eps, tol=1e-14, max_iter=200000)
+    fr, gr = O.normalize_gauge(ref.f, ref.g, a, b)
+    _, rho = O.spectral_basis(ref.f, ref.g, C, a, b, eps, ell + 1, method="dense")
+    f, g, rs = O.solve_schedule(C, a, b, [0.06, eps], 1e-13, 100000, ell=ell, mode="static", eps_prime=eps)
+    assert all(r.converged for r in rs)
+    assert rs[0].newton_tried == 0 and rs[1].newton_accepted > 0
+    f, g = O.normalize_gauge(f, g, a, b)
+    assert np.max(np.abs(f - fr)) < 1e-10 and np.max(np.abs(g - gr)) < 1e-10
+    e = np.array(rs[1].errs)
+    ok = (e > 1e-11) & (e < 1e-5)
+    ratios = e[1:][ok[1:] & ok[:-1]] / e[:-1][ok[1:] & ok[:-1]]
+    assert len(ratios) >= 3
+    assert ratios[-1] == pytest.approx(rho[ell + 1] ** 2, rel=0.15)
+    sk = O.sinkhorn(C, a, b, eps, tol=1e-13, max_iter=200000, f0=rs[0].f)
+    assert rs[1].iters < sk.iters
+    f1, g1, r1 = O.solve_schedule(C, a, b, [0.06, eps], 1e-13, 100000, ell=ell, mode="static", eps_prime=1.0)
+    f1, g1 = O.normalize_gauge(f1, g1, a, b)
+    assert all(r.converged for r in r1)
+    assert np.max(np.abs(f1 - fr)) < 1e-10 and np.max(np.abs(g1 - gr)) < 1e-10
