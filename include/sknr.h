@@ -141,7 +141,42 @@ typedef struct sknr_opts {
                              SK counts grow as eps falls (Lemma 3.2, rate
                              rho_1^2), so the switch happens once.  The optimum
                              is the same; only the iterates differ. */
+  int32_t newton_solver;  /* enum sknr_newton_solver: how the l x l Newton
+                             system is solved (0 = Gauss-Jordan with the
+                             Cholesky pivot test) */
+  int32_t newton_max_iter;/* iterative solvers: step cap (0 -> 2 l for CG,
+                             64 for Newton-Schulz) */
+  double newton_rtol;     /* iterative solvers: CG stops at ||grad - G z|| <=
+                             rtol ||grad||, Newton-Schulz at ||I - G^ X||_F <=
+                             rtol (0 -> 1e-12) */
+  double nr_min_gain;     /* WARM_SEQUENTIAL only.  0: off.  g > 0: a stage runs
+                             its Newton steps only when the warm start's Ritz
+                             values promise a rate gain (1 - rho_{l+1}^2) /
+                             (1 - rho_1^2) >= g, the ratio of the SK-NR rate of
+                             Theorem 4.2 to the SK rate of Lemma 3.2 (iteration
+                             counts scale with 1 / (1 - rate)); otherwise the
+                             stage runs plain SK.  rho_{l+1} is the first Ritz
+                             value past the basis (rho_l when l = 32).  On a
+                             spectrum that is flat past l (many near-degenerate
+                             modes) the Newton steps cost more than they save. */
 } sknr_opts;
+
+/* Solvers of the projected Newton system G c = eps grad (Algorithm 4.1, NR
+ * update).  DIRECT eliminates (Gauss-Jordan without pivoting; its pivots
+ * are those of G = L D L^T, so the positive-definiteness test is
+ * Cholesky's).  CG and NEWTON_SCHULZ are the GPU friendly alternatives the
+ * paper names for the NR step (Sec. 4, disadvantages of the algorithm):
+ * Jacobi-preconditioned conjugate gradients, and Newton-Schulz iterative
+ * inversion X <- X (2 I - G^ X) of the Jacobi-scaled G^ = D^-1/2 G D^-1/2;
+ * both use only products of G with vectors or matrices and need no
+ * pivoting.  A direction with p^T G p <= 0 (CG), a residual above 1e-6
+ * after the step cap (Newton-Schulz) or a non-positive diagonal fails the
+ * positive-definiteness test, and the step is not tried. */
+enum sknr_newton_solver {
+  SKNR_NEWTON_DIRECT = 0,
+  SKNR_NEWTON_CG = 1,
+  SKNR_NEWTON_SCHULZ = 2
+};
 
 typedef struct sknr_stage_stats {
   double eps;
@@ -153,6 +188,10 @@ typedef struct sknr_stage_stats {
                              check for the last stage, the sweeps' FP32
                              estimate for the others */
   double seconds;         /* wall time of the stage (incl. its warm start) */
+  double rate_gain;       /* (1 - rho_{l+1}^2) / (1 - rho_1^2) from the Ritz values
+                             of this stage's sequential warm start (0: none) */
+  int32_t nr_skipped;     /* 1: the nr_min_gain test ran this stage as plain SK */
+  int32_t reserved0;
 } sknr_stage_stats;
 
 typedef struct sknr_result {
@@ -245,6 +284,19 @@ int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps,
 int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps,
                      double* f_inout, const double* V, int32_t ell,
                      int32_t* accepted, double* q0, double* q1, void* stream);
+
+/* The coefficients c of the projected Newton step Delta f = V c (Algorithm
+ * 4.1, NR update; G and grad as in sknr_projected_system), c = eps G^-1
+ * grad, computed by `solver` (enum sknr_newton_solver; max_iter and rtol
+ * as in sknr_opts, 0 for the defaults).  f [device] n FP64, V [device]
+ * n x ell FP64; coef_out [host] ell; ok_out [host] 1 when G passed the
+ * solver's positive-definiteness test (0: coef_out is not a step);
+ * iters_out [host] iterations of an iterative solver (0 for DIRECT), may
+ * be NULL. */
+int sknr_newton_coef(void* ctx, const sknr_problem* prob, double eps,
+                     const double* f, const double* V, int32_t ell, int32_t solver,
+                     int32_t max_iter, double rtol, double* coef_out, int32_t* ok_out,
+                     int32_t* iters_out, void* stream);
 
 /* Spectral warm-start basis (Sec. 4): at the pair (f, f^{C,eps}) the top
  * ell non-constant eigenvectors of M = diag(a)^-1 P diag(b)^-1 P^T (the

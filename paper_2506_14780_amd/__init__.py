@@ -14,7 +14,8 @@ import os
 
 __all__ = [
     "lib", "Context", "Problem", "solve", "c_transform_row", "c_transform_col",
-    "projected_system", "newton_step", "spectral_basis", "evaluate", "coupling", "gradient",
+    "projected_system", "newton_step", "newton_coef", "NEWTON_DIRECT", "NEWTON_CG", "NEWTON_SCHULZ",
+    "spectral_basis", "evaluate", "coupling", "gradient",
     "entropic_ot_loss",
     "SknrError", "COST_STORED", "COST_SQEUCLID", "XTERM_AUTO", "XTERM_FP32",
     "XTERM_BF16", "XTERM_BF16X3", "XTERM_BF16X6", "WARM_SEQUENTIAL", "WARM_STATIC", "WARM_USER",
@@ -56,12 +57,14 @@ class _Opts(ctypes.Structure):
                 ("ell", _i32), ("warm_mode", _i32), ("eps_prime", _d), ("eig_oversample", _i32),
                 ("eig_max_iter", _i32), ("eig_tol", _d), ("check_every", _i32),
                 ("first_stage_nr", _i32), ("f0", _p), ("V0", _p), ("seed", ctypes.c_uint64),
-                ("stream", _p), ("nr_switch_iters", _i32)]
+                ("stream", _p), ("nr_switch_iters", _i32), ("newton_solver", _i32),
+                ("newton_max_iter", _i32), ("newton_rtol", _d), ("nr_min_gain", _d)]
 
 
 class _Stage(ctypes.Structure):
     _fields_ = [("eps", _d), ("iters", _i32), ("newton_tried", _i32), ("newton_accepted", _i32),
-                ("eig_iters", _i32), ("marginal_err", _d), ("seconds", _d)]
+                ("eig_iters", _i32), ("marginal_err", _d), ("seconds", _d), ("rate_gain", _d),
+                ("nr_skipped", _i32), ("reserved0", _i32)]
 
 
 class _Result(ctypes.Structure):
@@ -108,6 +111,7 @@ _sig("sknr_c_transform_row", [_p, _P(_Problem), _d, _p, _p, _p])
 _sig("sknr_c_transform_col", [_p, _P(_Problem), _d, _p, _p, _p, _P(_d), _P(_d), _p])
 _sig("sknr_projected_system", [_p, _P(_Problem), _d, _p, _p, _i32, _P(_d), _P(_d), _P(_d), _p])
 _sig("sknr_newton_step", [_p, _P(_Problem), _d, _p, _p, _i32, _P(_i32), _P(_d), _P(_d), _p])
+_sig("sknr_newton_coef", [_p, _P(_Problem), _d, _p, _p, _i32, _i32, _i32, _d, _P(_d), _P(_i32), _P(_i32), _p])
 _sig("sknr_spectral_basis", [_p, _P(_Problem), _d, _p, _i32, _i32, _i32, _d, ctypes.c_uint64, _p,
                              _P(_d), _P(_i32), _p])
 _sig("sknr_evaluate", [_p, _P(_Problem), _d, _p, _p, _P(_Eval), _p])
@@ -226,7 +230,8 @@ class Problem:
 
 
 def _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr, eig_oversample,
-          eig_max_iter, eig_tol, seed, stream, nr_switch_iters=0):
+          eig_max_iter, eig_tol, seed, stream, nr_switch_iters=0, newton_solver=0, newton_max_iter=0,
+          newton_rtol=0.0, nr_min_gain=0.0):
     earr = (_d * len(eps))(*eps)
     o = _Opts()
     o.eps = ctypes.cast(earr, _P(_d))
@@ -246,6 +251,10 @@ def _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, fi
     o.seed = seed
     o.stream = _stream(stream)
     o.nr_switch_iters = int(nr_switch_iters)
+    o.newton_solver = int(newton_solver)
+    o.newton_max_iter = int(newton_max_iter)
+    o.newton_rtol = float(newton_rtol)
+    o.nr_min_gain = float(nr_min_gain)
     return o, earr  # earr must outlive the call
 
 
@@ -258,7 +267,8 @@ def _result_dict(r):
 def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,
           warm_mode: int = WARM_USER, V0=None, f0=None, eps_prime: float = 0.0, check_every: int = 0,
           first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
-          eig_tol: float = 0.0, seed: int = 0, stream=None, f_out=None, g_out=None, nr_switch_iters: int = 0):
+          eig_tol: float = 0.0, seed: int = 0, stream=None, f_out=None, g_out=None, nr_switch_iters: int = 0,
+          newton_solver: int = 0, newton_max_iter: int = 0, newton_rtol: float = 0.0, nr_min_gain: float = 0.0):
     """sknr_solve.  Returns (f, g, result dict); f, g are float64 device
     tensors in the caller's orientation."""
     import torch
@@ -268,7 +278,8 @@ def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 1
     f = f_out if f_out is not None else torch.empty(n, dtype=torch.float64, device=dev)
     g = g_out if g_out is not None else torch.empty(m, dtype=torch.float64, device=dev)
     o, earr = _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr,
-                    eig_oversample, eig_max_iter, eig_tol, seed, stream, nr_switch_iters)
+                    eig_oversample, eig_max_iter, eig_tol, seed, stream, nr_switch_iters, newton_solver,
+                    newton_max_iter, newton_rtol, nr_min_gain)
     r = _Result()
     ps = prob.c_struct()
     st = lib.sknr_solve(ctx.handle, ctypes.byref(ps), ctypes.byref(o), _ptr(f), _ptr(g), ctypes.byref(r))
@@ -285,12 +296,14 @@ def serve_config(ctx: Context, max_active: int = 0, pool_bytes: int = 0):
 def submit(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,
            warm_mode: int = WARM_SEQUENTIAL, eps_prime: float = 0.0, check_every: int = 0,
            first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
-           eig_tol: float = 0.0, seed: int = 0, stream=None, nr_switch_iters: int = 0) -> int:
+           eig_tol: float = 0.0, seed: int = 0, stream=None, nr_switch_iters: int = 0, newton_solver: int = 0,
+           newton_max_iter: int = 0, newton_rtol: float = 0.0, nr_min_gain: float = 0.0) -> int:
     """sknr_submit: queue a solve (inputs are copied before returning);
     returns the ticket."""
     eps = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
     o, earr = _opts(eps, tol, max_iter, ell, warm_mode, None, None, eps_prime, check_every, first_stage_nr,
-                    eig_oversample, eig_max_iter, eig_tol, seed, stream, nr_switch_iters)
+                    eig_oversample, eig_max_iter, eig_tol, seed, stream, nr_switch_iters, newton_solver,
+                    newton_max_iter, newton_rtol, nr_min_gain)
     ps = prob.c_struct()
     t = ctypes.c_uint64()
     _check(lib.sknr_submit(ctx.handle, ctypes.byref(ps), ctypes.byref(o), ctypes.byref(t)), "sknr_submit")
@@ -372,6 +385,24 @@ def newton_step(ctx, prob: Problem, eps: float, f, V, stream=None):
                                 ctypes.byref(acc), ctypes.byref(q0), ctypes.byref(q1), _stream(stream)),
            "sknr_newton_step")
     return bool(acc.value), q0.value, q1.value
+
+
+NEWTON_DIRECT, NEWTON_CG, NEWTON_SCHULZ = 0, 1, 2
+
+
+def newton_coef(ctx, prob: Problem, eps: float, f, V, solver: int = NEWTON_DIRECT, max_iter: int = 0,
+                rtol: float = 0.0, stream=None):
+    """sknr_newton_coef: the coefficients c = eps G^-1 grad of the
+    projected Newton step by the chosen solver.  Returns (c [ell] numpy,
+    ok, iterations)."""
+    import numpy as np
+    ell = int(V.shape[1])
+    c = (_d * ell)()
+    ok, it = _i32(), _i32()
+    ps = prob.c_struct()
+    _check(lib.sknr_newton_coef(ctx.handle, ctypes.byref(ps), eps, _ptr(f), _ptr(V), ell, solver, max_iter, rtol,
+                                c, ctypes.byref(ok), ctypes.byref(it), _stream(stream)), "sknr_newton_coef")
+    return np.array(c[:]), bool(ok.value), it.value
 
 
 def spectral_basis(ctx, prob: Problem, eps: float, f, ell: int, oversample: int = 8, max_iter: int = 200,

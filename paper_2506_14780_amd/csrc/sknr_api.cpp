@@ -90,7 +90,7 @@ float bf16_round(double v) {
 }
 
 // --------------------------------------------------------------- prepare
-Prepared prepare(const sknr_problem* pr, hipStream_t s) {
+Prepared prepare(const sknr_problem* pr, hipStream_t s, float* dmax_dev) {
   REQUIRE(pr, "problem is NULL");
   REQUIRE(pr->n >= 1 && pr->m >= 1, "n and m must be >= 1");
   REQUIRE(pr->n <= (1 << 26) && pr->m <= (1 << 26), "n, m too large");
@@ -148,13 +148,12 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s) {
   P.hY = P.transposed ? ha : hb;
   // cost bound
   if (pr->kind == SKNR_COST_STORED) {
-    float* dmax;
-    HIPCHK(hipMallocAsync((void**)&dmax, sizeof(float), s));
-    HIPCHK(hipMemsetAsync(dmax, 0, sizeof(float), s));
+    float* dmax = dmax_dev;
+    if (!dmax) HIPCHK(hipMallocAsync((void**)&dmax, sizeof(float), s));
     HIPCHK(launch_cost_max(0, pr->C, pr->ldc, P.n0, P.m0, nullptr, nullptr, 0, dmax, s));
     float hm = 0;
     HIPCHK(hipMemcpyAsync(&hm, dmax, sizeof(float), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipFreeAsync(dmax, s));
+    if (!dmax_dev) HIPCHK(hipFreeAsync(dmax, s));
     HIPCHK(hipStreamSynchronize(s));
     REQUIRE(std::isfinite(hm), "cost has non-finite entries");
     P.cmax = hm;
@@ -404,6 +403,7 @@ struct Engine {
   hipStream_t s;
   double eps = 1.0;
   double tol = 1e-6;
+  NrSolver nrs;  // solver of the l x l Newton system
 
   Engine(Lane* c_, const Prepared& P_, WS& w_, hipStream_t s_) : c(c_), P(P_), w(w_), s(s_) {}
 
@@ -576,7 +576,7 @@ struct Engine {
     HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
                               w.st, gate_base, s));
     HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout, w.st,
-                           gate_base, s));
+                           gate_base, s, nrs));
     HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.ap_dot, w.ap_max, w.ap_ddot, w.E1, w.st,
                            gate_base | G_CHOL_OK, s));
   }
@@ -899,6 +899,15 @@ Prepared prepare_caller_orientation(const sknr_problem* prob, hipStream_t s) {
 }
 
 
+// solver of the l x l Newton system with its defaults filled in
+NrSolver nr_solver_of(int kind, int max_iter, double rtol, int ell) {
+  NrSolver v;
+  v.kind = kind;
+  v.max_iter = max_iter > 0 ? max_iter : (kind == NR_CG ? 2 * std::max(ell, 1) : 64);
+  v.rtol = rtol > 0 ? rtol : 1e-12;
+  return v;
+}
+
 // The eps schedule of sknr_solve on one lane (see the header for the
 // stage protocol): optional static warm start, per stage the spectral warm
 // start (sequential), the rebase of the potentials to the new eps, the SK /
@@ -916,6 +925,7 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
   const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 0.1;
   std::memset(res, 0, sizeof(*res));
   E.tol = opts->tol;
+  E.nrs = nr_solver_of(opts->newton_solver, opts->newton_max_iter, opts->newton_rtol, opts->ell);
   int static_eig_iters = 0;
   if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) {
     // plain SK at eps' from the initial potential, then V_l once
@@ -945,10 +955,20 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
     auto ts = std::chrono::steady_clock::now();
     double eps = opts->eps[st];
     int eig_iters = 0;
+    double gain = 0;
+    bool gain_ok = true;
     if (st > 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_SEQUENTIAL && nr_on) {
       // V_l from the optimum of the previous stage (its eps), Sec. 4
-      eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed + st, nullptr);
+      std::vector<double> lam;
+      eig_iters = E.spectral(opts->ell, eig_os, eig_it, eig_tol, opts->seed + st, &lam);
       E.use_warm_V(opts->ell, eig_os);
+      // rate gain of Theorem 4.2 over Lemma 3.2 predicted by the Ritz values
+      if (!lam.empty()) {
+        const double r1 = lam[0];
+        const double rl = lam[std::min<size_t>((size_t)opts->ell, lam.size() - 1)];
+        gain = (1.0 - rl) / std::max(1.0 - r1, 1e-300);
+        if (opts->nr_min_gain > 0 && gain < opts->nr_min_gain) gain_ok = false;
+      }
     }
     if (st == 0 && opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) eig_iters = static_eig_iters;
     if (st > 0) {
@@ -958,7 +978,7 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
       HIPCHK(launch_rebase(w.G[0], w.lYdf, split_df(de), P.m, w.st, MA_G, s));
       E.eps = eps;
     }
-    bool use_nr = opts->ell > 0 && (st > 0 || opts->first_stage_nr) && nr_on;
+    bool use_nr = opts->ell > 0 && (st > 0 || opts->first_stage_nr) && nr_on && gain_ok;
     bool conv = false;
     int tried = 0, acc = 0, it = 0;
     sknr_eval ev{};
@@ -994,6 +1014,8 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
     ss.newton_tried = tried;
     ss.newton_accepted = acc;
     ss.eig_iters = eig_iters;
+    ss.rate_gain = gain;
+    ss.nr_skipped = gain_ok ? 0 : 1;
     ss.marginal_err = ev.marginal_err;
     ss.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
     res->total_iters += it;
@@ -1044,6 +1066,11 @@ void check_opts(const sknr_opts* opts, const Prepared& P) {
             "first_stage_nr needs WARM_USER or WARM_STATIC");
   }
   if (opts->f0) REQUIRE(!P.transposed, "f0 needs n <= m");
+  REQUIRE(opts->newton_solver >= SKNR_NEWTON_DIRECT && opts->newton_solver <= SKNR_NEWTON_SCHULZ,
+          "unknown newton_solver");
+  REQUIRE(opts->newton_max_iter >= 0 && opts->newton_rtol >= 0 && std::isfinite(opts->newton_rtol),
+          "newton_max_iter and newton_rtol must be >= 0");
+  REQUIRE(opts->nr_min_gain >= 0 && std::isfinite(opts->nr_min_gain), "nr_min_gain must be >= 0");
 }
 
 void rebind(Prepared& P, const sknr_problem* pr) {
@@ -1111,12 +1138,19 @@ int sknr_ctx_create(int device, uint64_t hbm_budget_bytes, void** out) {
     REQUIRE(device >= 0 && device < cnt, "no such device");
     HIPCHK(hipSetDevice(device));
     Ctx* c = new Ctx();
-    c->device = device;
-    size_t fr = 0, tot = 0;
-    HIPCHK(hipMemGetInfo(&fr, &tot));
-    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * fr);
-    lane_init(&c->lane, device);
-    HIPCHK(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming));
+    try {
+      c->device = device;
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot));
+      c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * fr);
+      lane_init(&c->lane, device);
+      HIPCHK(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming));
+    } catch (...) {
+      lane_release(&c->lane);
+      if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+      delete c;
+      throw;
+    }
     *out = c;
     return SKNR_OK;
   });
@@ -1267,6 +1301,42 @@ int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps, double* f_
     if (accepted) *accepted = st.accept;
     if (st.accept) HIPCHK(launch_from_hat(w.Fp, w.lX64, eps, f_inout, P.n, s));
     HIPCHK(hipStreamSynchronize(s));
+    return SKNR_OK;
+  });
+}
+
+int sknr_newton_coef(void* ctx, const sknr_problem* prob, double eps, const double* f, const double* V, int32_t ell,
+                     int32_t solver, int32_t max_iter, double rtol, double* coef_out, int32_t* ok_out,
+                     int32_t* iters_out, void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    check_eps(eps);
+    REQUIRE(f && V && coef_out && ok_out && ell >= 1 && ell <= SKNR_MAX_ELL,
+            "f, V, coef_out, ok_out and 1 <= ell <= 32 are required");
+    REQUIRE(solver >= SKNR_NEWTON_DIRECT && solver <= SKNR_NEWTON_SCHULZ, "unknown solver");
+    REQUIRE(max_iter >= 0 && rtol >= 0 && std::isfinite(rtol), "max_iter and rtol must be >= 0");
+    hipStream_t s = as_stream(stream);
+    Prepared P = prepare_caller_orientation(prob, s);
+    int ellp = ell_pad(ell);
+    WS w = make_ws(&c->lane, P, ellp, s);
+    Engine E(&c->lane, P, w, s);
+    E.eps = eps;
+    E.nrs = nr_solver_of(solver, max_iter, rtol, ell);
+    E.init_state();
+    E.load_f(f);
+    E.load_V(V, ell);
+    E.sweep_col(w.F, MA_F, nullptr, w.Gt, DOT_GT, MA_GT, ellp, w.V, w.W, W_SCALE_WEIGHT, 0, 0);
+    E.sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, 0, 0);
+    HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
+                              w.st, 0, s));
+    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, nullptr, nullptr, w.st,
+                           0, s, E.nrs));
+    std::vector<double> hc(ell);
+    HIPCHK(hipMemcpyAsync(hc.data(), w.coef64, 8 * (size_t)ell, hipMemcpyDeviceToHost, s));
+    DevState st = E.read_state();
+    std::memcpy(coef_out, hc.data(), 8 * (size_t)ell);
+    *ok_out = st.chol_ok;
+    if (iters_out) *iters_out = st.nr_iters;
     return SKNR_OK;
   });
 }

@@ -191,7 +191,9 @@ void lane_release(Lane* L);
 
 int ell_pad(int ell);
 void check_eps(double eps);
-Prepared prepare(const sknr_problem* pr, hipStream_t s);
+// dmax_dev: optional device float for the stored-cost bound (null: a
+// stream-ordered allocation of 4 bytes)
+Prepared prepare(const sknr_problem* pr, hipStream_t s, float* dmax_dev = nullptr);
 // point the device pointers of P at another copy of the same problem
 void rebind(Prepared& P, const sknr_problem* pr);
 size_t ws_bytes(const Prepared& P, int ellp, int* geo);

@@ -36,7 +36,19 @@ struct DevState {
   float inv_eps;        // 1/eps
   float2 eps_df;        // eps as double-float
   float2 eln2_df;       // eps*ln2 as double-float
-  int pad[6];
+  int nr_iters;         // iterations of the last iterative Newton solve (0 for the direct one)
+  int pad[5];
+};
+
+// Solver of the l x l Newton system (k_nr_solve): Gauss-Jordan with
+// Cholesky's pivot test, or the iterative alternatives of Sec. 4
+// (disadvantages paragraph): Jacobi-preconditioned conjugate gradients, or
+// Newton-Schulz iterative inversion.
+enum NrSolverKind { NR_DIRECT = 0, NR_CG = 1, NR_NEWTON_SCHULZ = 2 };
+struct NrSolver {
+  int kind = NR_DIRECT;
+  int max_iter = 0;   // iterative solvers: step cap
+  double rtol = 0;    // iterative solvers: stopping threshold
 };
 
 // gating bits: a kernel returns immediately unless all requested hold
@@ -170,7 +182,7 @@ hipError_t launch_nr_assemble(int ell, const float* V, const float* rdiff, const
                               int ncol_blk, DevState* st, int gate, hipStream_t s);
 hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32,
                            double* coef64, double* Gout, double* gout, DevState* st, int gate,
-                           hipStream_t s);
+                           hipStream_t s, const NrSolver& solver = NrSolver());
 // Newton update f' = f + V c (hat form), per-block partials blk = <f', a>,
 // blkmax = max|f'.hi|, blkd = <f' - f, a>, and E1[i * 8] = expm1((f' - f)_i /
 // eps) (columns 1..7 zero: the single basis column of the W_CAND sweep)

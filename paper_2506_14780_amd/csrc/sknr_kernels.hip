@@ -881,10 +881,158 @@ __device__ __forceinline__ double sum_partials(const double* part, int nblk, int
 // column k and row k, which it does not write.  Its pivots are those of
 // G = L D L^T, so the positive-definiteness test (every pivot > 1e-15 of
 // the largest diagonal entry) is the one of a Cholesky factorisation.
+//
+// solver = NR_CG or NR_NEWTON_SCHULZ replaces the elimination by the GPU
+// friendly alternatives the paper names for the NR step (Sec. 4,
+// disadvantages of the algorithm): no pivoting, only products of G with
+// vectors or matrices.
+//   NR_CG: conjugate gradients on [G | grad] with the Jacobi (diagonal)
+//     preconditioner, one wave, lane i owning row i; stops when
+//     ||grad - G z|| <= rtol ||grad|| (in the scaled system) or after max_it
+//     steps; a direction with p^T G^ p <= 1e-15 |p|^2 fails the
+//     positive-definiteness test.
+//   NR_NEWTON_SCHULZ: iterative inversion X <- X (2 I - G^ X) of the
+//     Jacobi-scaled G^ = D^-1/2 G D^-1/2 (unit diagonal) from X0 = I /
+//     ||G^||_inf, whose error squares every step for an SPD G^; stops when
+//     ||I - G^ X||_F <= rtol or after max_it steps, and fails the test when
+//     the residual has not fallen below 1e-6 by then.
+// Both start with the same per-column checks (padding, massless columns,
+// positive diagonal) as the elimination.
+template <int ELL>
+__device__ void nr_iterative(double (*A)[ELL + 2], int solver, int max_it, double rtol, double* z, int* ok_io,
+                             int* iters_out) {
+  constexpr int NA = ELL + 1;
+  const int tid = threadIdx.x;
+  __shared__ double X[ELL][ELL + 1], Y[ELL][ELL + 1], dsc[ELL];
+  __shared__ double s_x0, s_res;
+  // Jacobi scaling: d_i = 1/sqrt(A_ii) (a non-positive diagonal fails)
+  if (tid < ELL) {
+    const double dii = A[tid][tid];
+    dsc[tid] = dii > 0 ? 1.0 / sqrt(dii) : 1.0;
+    if (!(dii > 0)) atomicAnd(ok_io, 0);
+  }
+  __syncthreads();
+  if (solver == NR_CG) {
+    if (tid < 64) {
+      const int i = tid < ELL ? tid : 0;
+      const bool own = tid < ELL;
+      // scaled system  G^ y = b^,  G^ = D A D,  b^ = D grad,  z = D y
+      double x = 0, r = own ? dsc[i] * A[i][ELL] : 0.0, zz = r, p = zz;
+      double rz = wave_sum(r * zz);
+      const double bn = sqrt(wave_sum(r * r));
+      int it = 0, good = 1;
+      for (; it < max_it; ++it) {
+        if (!(sqrt(wave_sum(r * r)) > rtol * bn)) break;
+        double q = 0;
+#pragma unroll
+        for (int j = 0; j < ELL; ++j) q += (own ? dsc[i] * A[i][j] * dsc[j] : 0.0) * __shfl(p, j, 64);
+        // G^ has a unit diagonal: a curvature below 1e-15 |p|^2 is the
+        // elimination's pivot test (pivot > 1e-15 of the largest diagonal)
+        const double pq = wave_sum(own ? p * q : 0.0);
+        const double pp = wave_sum(p * p);
+        if (!(pq > 1e-15 * pp)) {
+          good = 0;
+          break;
+        }
+        const double alpha = rz / pq;
+        x += alpha * p;
+        r -= alpha * q;
+        zz = r;
+        const double rz2 = wave_sum(r * zz);
+        const double beta = rz2 / rz;
+        rz = rz2;
+        p = zz + beta * p;
+      }
+      if (own) z[i] = dsc[i] * x;
+      if (tid == 0) {
+        if (!good) atomicAnd(ok_io, 0);
+        *iters_out = it;
+      }
+    }
+    __syncthreads();
+    return;
+  }
+  // Newton-Schulz: X0 = I / ||G^||_inf
+  if (tid == 0) {
+    double nrm = 0;
+    for (int i = 0; i < ELL; ++i) {
+      double rs = 0;
+      for (int j = 0; j < ELL; ++j) rs += fabs(dsc[i] * A[i][j] * dsc[j]);
+      nrm = fmax(nrm, rs);
+    }
+    s_x0 = nrm > 0 ? 1.0 / nrm : 1.0;
+  }
+  __syncthreads();
+  const double x0 = s_x0;
+  for (int e = tid; e < ELL * ELL; e += 256) {
+    const int i = e / ELL, j = e - i * ELL;
+    X[i][j] = i == j ? x0 : 0.0;
+  }
+  __syncthreads();
+  double res = 1.0;
+  int it = 0;
+  for (; it < max_it; ++it) {
+    // Y = G^ X
+    for (int e = tid; e < ELL * ELL; e += 256) {
+      const int i = e / ELL, j = e - i * ELL;
+      double v = 0;
+#pragma unroll 8
+      for (int k = 0; k < ELL; ++k) v += dsc[i] * A[i][k] * dsc[k] * X[k][j];
+      Y[i][j] = v;
+    }
+    __syncthreads();
+    // residual ||I - Y||_F (all threads read the same sum: fixed order)
+    if (tid == 0) {
+      double acc = 0;
+      for (int i = 0; i < ELL; ++i)
+        for (int j = 0; j < ELL; ++j) {
+          const double d = (i == j ? 1.0 : 0.0) - Y[i][j];
+          acc += d * d;
+        }
+      s_res = sqrt(acc);
+    }
+    __syncthreads();
+    res = s_res;
+    if (!(res > rtol)) break;
+    // X <- X (2 I - Y): entries (i, j) = 2 X_ij - sum_k X_ik Y_kj
+    double nv[(ELL * ELL + 255) / 256];
+#pragma unroll
+    for (int q = 0; q < (ELL * ELL + 255) / 256; ++q) {
+      const int e = tid + 256 * q;
+      nv[q] = 0;
+      if (e < ELL * ELL) {
+        const int i = e / ELL, j = e - i * ELL;
+        double v = 2.0 * X[i][j];
+#pragma unroll 8
+        for (int k = 0; k < ELL; ++k) v -= X[i][k] * Y[k][j];
+        nv[q] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (ELL * ELL + 255) / 256; ++q) {
+      const int e = tid + 256 * q;
+      if (e < ELL * ELL) X[e / ELL][e % ELL] = nv[q];
+    }
+    __syncthreads();
+  }
+  if (tid < ELL) {
+    double v = 0;
+    for (int j = 0; j < ELL; ++j) v += X[tid][j] * dsc[j] * A[j][ELL];
+    z[tid] = dsc[tid] * v;
+  }
+  if (tid == 0) {
+    if (!(res <= 1e-6)) atomicAnd(ok_io, 0);
+    *iters_out = it;
+  }
+  __syncthreads();
+  (void)NA;
+}
+
 template <int ELL>
 __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, int ell_real, float* coef32,
                                                   double* coef64, double* Gout, double* gout, DevState* st,
-                                                  int gate) {
+                                                  int gate, int solver, int max_it, double rtol) {
   if (gate_closed(st, gate)) return;
   constexpr int NE = ELL * ELL;
   constexpr int NA = ELL + 1;  // augmented width
@@ -920,6 +1068,33 @@ __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, 
     for (int e = tid; e < ell_real; e += 256) gout[e] = R[NE + e];
   }
   __syncthreads();
+  if (solver != NR_DIRECT) {
+    __shared__ double zs[ELL];
+    __shared__ int s_ok, s_its;
+    if (tid == 0) {
+      s_ok = 1;
+      s_its = 0;
+    }
+    __syncthreads();
+    nr_iterative<ELL>(A, solver, max_it, rtol, zs, &s_ok, &s_its);
+    if (tid < 64) {
+      const int i = tid < ELL ? tid : ELL - 1;
+      const double c = eps * zs[i];
+      const int bad = (tid < ELL) && !(fabs(c) < 1e30);
+      const int ok = s_ok && !__any(bad);
+      if (tid < ELL) {
+        coef64[tid] = c;
+        coef32[tid] = ok ? (float)c : 0.f;
+      }
+      if (tid == 0) {
+        st->chol_ok = ok;
+        st->accept = 0;
+        st->newton_tried += 1;
+        st->nr_iters = s_its;
+      }
+    }
+    return;
+  }
   int ok = 1;
   for (int k = 0; k < ELL; ++k) {
     double piv = A[k][k];
@@ -952,6 +1127,7 @@ __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, 
       st->chol_ok = ok;
       st->accept = 0;
       st->newton_tried += 1;
+      st->nr_iters = 0;
     }
   }
 }
@@ -1016,15 +1192,15 @@ hipError_t launch_nr_assemble(int ell, const float* V, const float* mdiff, const
 }
 template <int E>
 static void nr_solve_e(const double* part, int nblk, int ell, float* coef32, double* coef64, double* Gout,
-                       double* gout, DevState* st, int gate, hipStream_t s) {
+                       double* gout, DevState* st, int gate, const NrSolver& sv, hipStream_t s) {
   hipLaunchKernelGGL((k_nr_solve<E>), dim3(1), dim3(256), 0, s, part, nblk, ell, coef32, coef64, Gout, gout, st,
-                     gate);
+                     gate, sv.kind, sv.max_iter, sv.rtol);
 }
 hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32, double* coef64, double* Gout,
-                           double* gout, DevState* st, int gate, hipStream_t s) {
-  if (ell <= 8) nr_solve_e<8>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, s);
-  else if (ell <= 16) nr_solve_e<16>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, s);
-  else nr_solve_e<32>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, s);
+                           double* gout, DevState* st, int gate, hipStream_t s, const NrSolver& sv) {
+  if (ell <= 8) nr_solve_e<8>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, sv, s);
+  else if (ell <= 16) nr_solve_e<16>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, sv, s);
+  else nr_solve_e<32>(part, nblk, ell, coef32, coef64, Gout, gout, st, gate, sv, s);
   return hipGetLastError();
 }
 template <int E>
@@ -1294,18 +1470,28 @@ hipError_t launch_shift64(double* x, int n, const double* dots, double sign, hip
   return hipGetLastError();
 }
 
+// max |C_ij| as the bit pattern of a non-negative float (atomic max on the
+// bits is order independent); a NaN or infinite entry gives +inf, which the
+// host rejects
 __global__ void k_cost_absmax(const float* C, long long ldc, int n, int m, unsigned* out) {
   __shared__ float sbf[8];
   float mx = 0.f;
   int i = blockIdx.x;
-  for (int j = threadIdx.x; j < m; j += blockDim.x) mx = fmaxf(mx, fabsf(C[(size_t)i * ldc + j]));
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const float v = fabsf(C[(size_t)i * ldc + j]);
+    mx = v <= FLT_MAX ? fmaxf(mx, v) : INFINITY;
+  }
   mx = block_max_f(mx, sbf);
   if (threadIdx.x == 0) atomicMax(out, __float_as_uint(mx));
+}
+__global__ void k_zero_u32(unsigned* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
 }
 hipError_t launch_cost_max(int cost_kind, const float* C, long long ldc, int n, int m, const float* x, const float* y,
                            int d, float* out2, hipStream_t s) {
   (void)x; (void)y; (void)d;
   if (cost_kind != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned*>(out2));
   hipLaunchKernelGGL(k_cost_absmax, dim3(n), dim3(256), 0, s, C, ldc, n, m, reinterpret_cast<unsigned*>(out2));
   return hipGetLastError();
 }
