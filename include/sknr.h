@@ -245,6 +245,23 @@ int sknr_ctx_destroy(void* ctx);
 int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts,
                double* f_out, double* g_out, sknr_result* res);
 
+/* The same solve without device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Arguments, results and errors
+ * as sknr_solve; the caller still provides the inputs and f_out / g_out.
+ * The workspace lives in a static device array of the library (64 MiB per
+ * device, held from the first context on that device until the process
+ * ends) instead of the context's workspace allocation, and no iteration
+ * graphs are captured (instantiation may allocate).  A problem whose
+ * workspace exceeds the array is rejected with SKNR_EINVAL and a message
+ * naming its size (about (n + m) (100 + 64 l) bytes plus the split
+ * partials: a 4096 x 4096 problem with l = 16 needs about 12 MiB).
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (from several contexts or threads) race, so issue them one
+ * at a time per device. */
+int sknr_solve_noalloc(void* ctx, const sknr_problem* prob, const sknr_opts* opts,
+                       double* f_out, double* g_out, sknr_result* res);
+
 /* ------------------------------------------- single steps of the path */
 
 /* Row c-transform f = g^{C,eps} (eq. foc_f), one FP32 sweep with

@@ -13,7 +13,7 @@ import dataclasses
 import os
 
 __all__ = [
-    "lib", "Context", "Problem", "solve", "c_transform_row", "c_transform_col",
+    "lib", "Context", "Problem", "solve", "solve_noalloc", "c_transform_row", "c_transform_col",
     "projected_system", "newton_step", "newton_coef", "NEWTON_DIRECT", "NEWTON_CG", "NEWTON_SCHULZ",
     "spectral_basis", "evaluate", "coupling", "gradient",
     "entropic_ot_loss",
@@ -107,6 +107,7 @@ lib.sknr_version.restype = ctypes.c_char_p
 _sig("sknr_ctx_create", [ctypes.c_int, ctypes.c_uint64, _P(_p)])
 _sig("sknr_ctx_destroy", [_p])
 _sig("sknr_solve", [_p, _P(_Problem), _P(_Opts), _p, _p, _P(_Result)])
+_sig("sknr_solve_noalloc", [_p, _P(_Problem), _P(_Opts), _p, _p, _P(_Result)])
 _sig("sknr_c_transform_row", [_p, _P(_Problem), _d, _p, _p, _p])
 _sig("sknr_c_transform_col", [_p, _P(_Problem), _d, _p, _p, _p, _P(_d), _P(_d), _p])
 _sig("sknr_projected_system", [_p, _P(_Problem), _d, _p, _p, _i32, _P(_d), _P(_d), _P(_d), _p])
@@ -285,6 +286,27 @@ def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 1
     st = lib.sknr_solve(ctx.handle, ctypes.byref(ps), ctypes.byref(o), _ptr(f), _ptr(g), ctypes.byref(r))
     _check(st, "sknr_solve")
     return f, g, _result_dict(r)
+
+
+def solve_noalloc(ctx: Context, prob: Problem, eps, f_out, g_out, tol: float = 1e-6, max_iter: int = 10000,
+                  ell: int = 0, warm_mode: int = WARM_USER, V0=None, f0=None, eps_prime: float = 0.0,
+                  check_every: int = 0, first_stage_nr: bool = False, eig_oversample: int = 0,
+                  eig_max_iter: int = 0, eig_tol: float = 0.0, seed: int = 0, stream=None,
+                  nr_switch_iters: int = 0, newton_solver: int = 0, newton_max_iter: int = 0,
+                  newton_rtol: float = 0.0, nr_min_gain: float = 0.0) -> dict:
+    """sknr_solve_noalloc: sknr_solve with the workspace in the library's
+    static device array (no device allocation).  f_out (n) and g_out (m)
+    are caller-provided float64 device tensors; returns the result dict."""
+    eps = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
+    o, earr = _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr,
+                    eig_oversample, eig_max_iter, eig_tol, seed, stream, nr_switch_iters, newton_solver,
+                    newton_max_iter, newton_rtol, nr_min_gain)
+    r = _Result()
+    ps = prob.c_struct()
+    st = lib.sknr_solve_noalloc(ctx.handle, ctypes.byref(ps), ctypes.byref(o), _ptr(f_out), _ptr(g_out),
+                                ctypes.byref(r))
+    _check(st, "sknr_solve_noalloc")
+    return _result_dict(r)
 
 
 # ------------------------------------------------------------------ serving

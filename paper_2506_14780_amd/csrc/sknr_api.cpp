@@ -1144,9 +1144,13 @@ int sknr_ctx_create(int device, uint64_t hbm_budget_bytes, void** out) {
       HIPCHK(hipMemGetInfo(&fr, &tot));
       c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * fr);
       lane_init(&c->lane, device);
+      lane_init(&c->lane_na, device);
+      c->lane_na.use_graphs = false;
+      noalloc_setup(device);
       HIPCHK(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming));
     } catch (...) {
       lane_release(&c->lane);
+      lane_release(&c->lane_na);
       if (c->order_ev) (void)hipEventDestroy(c->order_ev);
       delete c;
       throw;
@@ -1164,6 +1168,9 @@ int sknr_ctx_destroy(void* ctx) {
     server_destroy(c);
     HIPCHK(hipDeviceSynchronize());
     lane_release(&c->lane);
+    c->lane_na.arena.base = nullptr;  // the static array, never freed
+    c->lane_na.arena.cap = 0;
+    lane_release(&c->lane_na);
     if (c->order_ev) (void)hipEventDestroy(c->order_ev);
     delete c;
     return SKNR_OK;

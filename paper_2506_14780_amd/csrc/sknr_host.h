@@ -181,6 +181,7 @@ struct Ctx {
   int device = 0;
   uint64_t budget = 0;
   Lane lane;
+  Lane lane_na;  // sknr_solve_noalloc: workspace in the library's static device array, no graphs
   hipEvent_t order_ev = nullptr;  // orders the solver stream after the caller's stream
   Server* server = nullptr;
 };
@@ -206,6 +207,12 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
                   double* g_out, sknr_result* res);
 
 void server_destroy(Ctx* c);
+
+// sknr_noalloc.hip: the device address of the static workspace array on
+// `device`, taken once per device with hipGetSymbolAddress (called by
+// sknr_ctx_create with the device current), and its size in bytes
+void noalloc_setup(int device);
+char* noalloc_scratch(int device, size_t* bytes);
 
 inline hipStream_t as_stream(void* p) { return reinterpret_cast<hipStream_t>(p); }
 
