@@ -248,6 +248,93 @@ def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4, switch_iters=10):
             "sknr": run(True, rate), "sknr_adaptive": run(True, rate, switch_iters), "sk": run(False, rate)}
 
 
+def c1_bench(sk, W, torch, reps=5):
+    """The 256 x 256 workload (uniform points, uniform weights, eps =
+    1e-2): GPU time per SK iteration of a cold plain SK solve (tol 1e-6) and
+    the SK-NR(30) solve from eps' = 2e-2 (sequential warm start); this size
+    is bound by launch latency (131,072 cost elements per iteration)."""
+    prob = W.uniform_square(256, seed=0)
+    dev = torch.device("cuda:0")
+    gp = sk.Problem(a=torch.from_numpy(prob.a).to(dev), b=torch.from_numpy(prob.b).to(dev),
+                    x=torch.from_numpy(prob.x).to(dev), y=torch.from_numpy(prob.y).to(dev))
+    ctx = sk.Context(0)
+    out = {"workload": "uniform_square 256x256 d=2, eps 1e-2, tol 1e-6"}
+    for name, ladder, kw in (("cold_sk", [1e-2], {}),
+                             ("sknr30_from_2e-2", [2e-2, 1e-2], dict(ell=30, warm_mode=sk.WARM_SEQUENTIAL))):
+        ts, res = [], None
+        for rep in range(reps + 1):
+            t0 = time.perf_counter()
+            res = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=100000, **kw)[2]
+            torch.cuda.synchronize()
+            if rep:
+                ts.append(time.perf_counter() - t0)
+        st = res["stages"][-1]
+        out[name] = {"ms": 1e3 * float(np.median(ts)), "iters_per_stage": [x["iters"] for x in res["stages"]],
+                     "last_stage_us_per_iter": 1e6 * st["seconds"] / max(1, st["iters"]),
+                     "status": res["status"]}
+    ctx.close()
+    return out
+
+
+def newton_solvers_bench(sk, gp, ladder, tol, reps=3):
+    """The projected Newton system solved by Gauss-Jordan, by conjugate
+    gradients and by Newton-Schulz iterative inversion (Sec. 4,
+    disadvantages paragraph) inside the benchmark solve, l = 16 and 30."""
+    import torch
+    ctx = sk.Context(0)
+    out = {}
+    for ell in (16, 30):
+        for name, solver in (("direct", sk.NEWTON_DIRECT), ("cg", sk.NEWTON_CG), ("newton_schulz", sk.NEWTON_SCHULZ)):
+            ts, res = [], None
+            for rep in range(reps + 1):
+                t0 = time.perf_counter()
+                res = sk.solve(ctx, gp, ladder, tol=tol, max_iter=200000, ell=ell, warm_mode=sk.WARM_SEQUENTIAL,
+                               newton_solver=solver)[2]
+                torch.cuda.synchronize()
+                if rep:
+                    ts.append(time.perf_counter() - t0)
+            out[f"l{ell}_{name}"] = {"ms": 1e3 * float(np.median(ts)),
+                                     "iters_per_stage": [x["iters"] for x in res["stages"]],
+                                     "newton_accepted": sum(x["newton_accepted"] for x in res["stages"]),
+                                     "status": res["status"]}
+    ctx.close()
+    return out
+
+
+def c4_ladder(sk, W, torch, cap):
+    """20000 x 30000 d = 64 Gaussian clouds (matrix-core cost, three bf16
+    parts), eps 1e-1 -> 1e-2 -> 2e-3, tol 1e-6, at most `cap` iterations a
+    stage: plain SK, SK-NR(16) with the sequential warm start, and SK-NR(16)
+    with the Ritz-value gain test (nr_min_gain = 2).  Each stage is its own
+    call (ladder [previous eps, eps] from the previous potentials), so the
+    run prints as it goes."""
+    prob = W.gaussian_clouds()
+    dev = torch.device("cuda:0")
+    gp = sk.Problem(a=torch.from_numpy(prob.a).to(dev), b=torch.from_numpy(prob.b).to(dev),
+                    x=torch.from_numpy(prob.x).to(dev), y=torch.from_numpy(prob.y).to(dev))
+    ctx = sk.Context(0)
+    ladder = [1e-1, 1e-2, 2e-3]
+    out = {"workload": f"gaussian_clouds {prob.n}x{prob.m} d={prob.d}, eps {ladder}, tol 1e-6, cap {cap}/stage"}
+    for name, kw in (("sk", {}), ("sknr16", dict(ell=16)), ("sknr16_gain2", dict(ell=16, nr_min_gain=2.0))):
+        f, rows = None, []
+        for s_, eps in enumerate(ladder):
+            lad = [eps] if s_ == 0 else [ladder[s_ - 1], eps]
+            kws = dict(kw) if s_ > 0 else {}
+            t0 = time.perf_counter()
+            f, g, r = sk.solve(ctx, gp, lad, tol=1e-6, max_iter=cap, f0=f, warm_mode=sk.WARM_SEQUENTIAL, **kws)
+            torch.cuda.synchronize()
+            st = r["stages"][-1]
+            rows.append({"eps": eps, "iters": st["iters"], "newton_tried": st["newton_tried"],
+                         "newton_accepted": st["newton_accepted"], "rate_gain": st["rate_gain"],
+                         "nr_skipped": st["nr_skipped"], "marginal_err": r["marginal_err"],
+                         "marginal_err_exact": r["marginal_err_exact"], "status": r["status"],
+                         "seconds": time.perf_counter() - t0})
+            print(f"c4 {name} eps {eps}: {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
+        out[name] = rows
+    ctx.close()
+    return out
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     k = (len(xs) - 1) * q / 100.0
@@ -285,52 +372,115 @@ def stored_sweep_roofline(sk, ctx, side=128, reps=10):
         out[e["name"]] = {"avg_launch_us": avg_s * 1e6, "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                           "frac": gbs / PEAK_HBM_GBS, "bytes_per_launch": 4.0 * n * m,
                           "traffic": kernel_traffic(e["name"])}
+    # the workload's solves: cold plain SK at eps' = 1e-3, then eps = 5e-4 with
+    # warm SK or warm SK-NR(16) (sequential warm start), tol 1e-6
+    solves = {}
+    for name, ell in (("sk", 0), ("sknr16", 16)):
+        ts, res = [], None
+        for rep in range(3):
+            t0 = time.perf_counter()
+            res = sk.solve(ctx, gp, [1e-3, 5e-4], tol=1e-6, max_iter=100000, ell=ell, warm_mode=sk.WARM_SEQUENTIAL)[2]
+            torch.cuda.synchronize()
+            if rep:
+                ts.append(time.perf_counter() - t0)
+        st = res["stages"]
+        solves[name] = {"solves_per_s": 1.0 / float(np.median(ts)), "ms": 1e3 * float(np.median(ts)),
+                        "iters_per_stage": [x["iters"] for x in st], "stage_ms": [1e3 * x["seconds"] for x in st],
+                        "newton_accepted": [x["newton_accepted"] for x in st], "status": res["status"],
+                        "marginal_err": res["marginal_err"],
+                        "stage2_iters_per_s": st[1]["iters"] / st[1]["seconds"]}
+    solves["speedup_sknr_vs_sk"] = solves["sknr16"]["solves_per_s"] / solves["sk"]["solves_per_s"]
     del gp
     torch.cuda.empty_cache()
     return {"workload": f"grid_histograms {side}x{side} (n=m={side*side}), stored FP32 cost, eps 5e-4",
-            "kernels": out}
+            "kernels": out, "solves": solves}
 
 
-def cpu_baseline(prob, ladder, tol, ell, iters_per_stage):
-    """The FP64 oracle, untuned, timed on a bounded sample of the same
-    workload on the host: two plain SK iterations, two SK-NR(l)
-    iterations and one warm-start eigensolve at the 4096 x 4096 size,
-    scaled to one full solve with the per-stage iteration counts of the
-    GPU run (which match the oracle's on smaller instances)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_counts(gpu_counts):
+    """Per-stage iteration counts of the oracle's own solve of this workload
+    (stored by tests/golden/make_c2_oracle.py), else the GPU's."""
+    try:
+        g = np.load(os.path.join(ROOT, "tests", "golden", "c2_oracle.npz"))
+        return [int(v) for v in g["iters_tol1e6"]], "the oracle's own full solve"
+    except OSError:
+        return list(gpu_counts), "the GPU run"
+
+
+def cpu_baseline(prob, ladder, tol, ell, gpu_counts, full=False):
+    """The FP64 oracle, untuned, on the host cores: the same workload and
+    schedule (Algorithm 4.1, sequential spectral warm start, l = ell).
+
+    Default (bounded, about a minute): the schedule's first stage (plain SK
+    at eps_1 to tol, 15 iterations) timed on all cores and on one core,
+    plus one warm-start eigensolve and one SK-NR(l) iteration at eps_2 on
+    one core; a full solve is then estimated from the oracle's own
+    per-stage iteration counts.  full=True times the whole 8-stage oracle
+    solve on all cores and on one core (several minutes each) and reports
+    that."""
     import oracle as O
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
-    except Exception:  # pragma: no cover
-        limiter = None
-    try:
-        C = O.sqeuclid_cost(prob.x, prob.y)
-        a, b = prob.a, prob.b
-        eps = ladder[1]
-        f = np.zeros(prob.n)
+    from threadpoolctl import threadpool_info, threadpool_limits
+    C = O.sqeuclid_cost(prob.x, prob.y)
+    a, b = prob.a, prob.b
+    np.ones((64, 64)) @ np.ones((64, 64))  # load the BLAS pool
+    all_threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    host = {"cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+    if full:
+        out = {}
+        for th in (all_threads, 1):
+            with threadpool_limits(limits=th):
+                t0 = time.perf_counter()
+                _, _, rs = O.solve_schedule(C, a, b, ladder, tol, 100000, ell=ell, mode="sequential")
+                out[th] = (time.perf_counter() - t0, [r.iters for r in rs])
+        t_all, it_all = out[all_threads]
+        t_one, _ = out[1]
+        return {"value": 1.0 / t_all, "unit": "solves/s", "cores": all_threads, "kind": "oracle",
+                "value_1core": 1.0 / t_one, "seconds_per_solve": t_all, "seconds_per_solve_1core": t_one,
+                "oracle_iters_per_stage": it_all, **host,
+                "sample": (f"one full FP64 oracle solve of the {prob.n}x{prob.m} workload (8 stages, SK-NR(l={ell}) "
+                           f"with the sequential warm start, tol {tol:g}), timed on {all_threads} BLAS threads "
+                           f"and on 1")}
+    counts, src = _oracle_counts(gpu_counts)
+    t0 = time.perf_counter()
+    r = O.sinkhorn(C, a, b, ladder[0], tol=tol, max_iter=100000)
+    t_stage1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    V, _ = O.spectral_basis(r.f, r.g, C, a, b, ladder[0], ell)
+    t_eig = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.sknr(C, a, b, ladder[1], tol=0.0, max_iter=1, V=V, f0=r.f)
+    t_nr = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        r = O.sinkhorn(C, a, b, ladder[0], tol=0.0, max_iter=2, f0=f)
-        t_sk = (time.perf_counter() - t0) / 2
+        O.sinkhorn(C, a, b, ladder[0], tol=0.0, max_iter=3)
+        t_sk1 = (time.perf_counter() - t0) / 3
         t0 = time.perf_counter()
-        V, _ = O.spectral_basis(r.f, r.g, C, a, b, ladder[0], ell, method="arpack")
-        t_eig = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        O.sknr(C, a, b, eps, tol=0.0, max_iter=2, V=V, f0=r.f)
-        t_nr = (time.perf_counter() - t0) / 2
-    finally:
-        if limiter is not None:
-            limiter.unregister() if hasattr(limiter, "unregister") else None
-    est = t_sk * iters_per_stage[0] + t_nr * sum(iters_per_stage[1:]) + t_eig * (len(ladder) - 1)
-    return {
-        "value": 1.0 / est,
-        "unit": "solves/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"FP64 numpy oracle on the {prob.n}x{prob.m} workload, 1 thread: 2 SK iterations "
-                   f"({t_sk:.2f} s each), 2 SK-NR(l={ell}) iterations ({t_nr:.2f} s each), 1 ARPACK "
-                   f"warm-start eigensolve ({t_eig:.2f} s); scaled to one solve with the GPU run's "
-                   f"per-stage iteration counts {iters_per_stage}"),
-    }
+        O.spectral_basis(r.f, r.g, C, a, b, ladder[0], ell)
+        t_eig1 = time.perf_counter() - t0
+    per_sk = t_stage1 / max(1, r.iters)
+    est = per_sk * counts[0] + t_nr * sum(counts[1:]) + t_eig * (len(ladder) - 1)
+    est1 = t_sk1 * counts[0] + t_nr * (t_sk1 / per_sk) * sum(counts[1:]) + t_eig1 * (len(ladder) - 1)
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": all_threads, "kind": "oracle",
+            "value_1core": 1.0 / est1, **host,
+            "measured": {"stage1_seconds": t_stage1, "stage1_iters": r.iters, "eigensolve_s": t_eig,
+                         "sknr_iteration_s": t_nr, "sk_iteration_s_1core": t_sk1, "eigensolve_s_1core": t_eig1},
+            "sample": (f"FP64 oracle on the {prob.n}x{prob.m} workload, {all_threads} BLAS threads: stage 1 "
+                       f"(plain SK, eps {ladder[0]:g}, {r.iters} iterations to tol {tol:g}), one ARPACK warm-start "
+                       f"eigensolve and one SK-NR(l={ell}) iteration; one core: 3 SK iterations and the "
+                       f"eigensolve; a solve estimated with the per-stage counts {counts} of {src}; "
+                       f"bench.py --cpu-full times a whole solve")}
 
 
 def main():
@@ -344,6 +494,11 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="cpu_baseline: time one whole oracle solve on all cores and on one core (slow)")
+    ap.add_argument("--c4", action="store_true",
+                    help="run the 20000 x 30000 d = 64 eps ladder (SK, SK-NR(16), SK-NR(16) with the gain test)")
+    ap.add_argument("--c4-cap", type=int, default=20000, help="iteration cap per stage of --c4")
     ap.add_argument("--no-sk", action="store_true")
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-cost HBM sweep measurement")
     ap.add_argument("--no-mfma", action="store_true", help="skip the d = 64 matrix-core sweep measurement")
@@ -490,8 +645,13 @@ def main():
         out["serving"] = serving_bench(sk, W, torch, args.serve_requests, args.serve_lanes, args.tol)
     if not args.no_paper:
         out["paper_workloads"] = paper_workloads_bench(sk, W, torch, args.tol)
+    if not args.no_paper:
+        out["c1"] = c1_bench(sk, W, torch)
+        out["newton_solvers"] = newton_solvers_bench(sk, gp, ladder, args.tol)
+    if args.c4:
+        out["c4"] = c4_ladder(sk, W, torch, args.c4_cap)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, ladder, args.tol, args.ell, iters_nr)
+        out["cpu_baseline"] = cpu_baseline(prob, ladder, args.tol, args.ell, iters_nr, full=args.cpu_full)
     ctx.close()
     print(json.dumps(out), flush=True)
 
