@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsknr.so")
-SOURCES = ["sknr_kernels.hip", "sknr_mfma.hip", "sknr_warm.hip", "sknr_state.hip", "sknr_noalloc.hip", "sknr_api.cpp", "sknr_serve.cpp"]
+SOURCES = ["sknr_kernels.hip", "sknr_mfma.hip", "sknr_warm.hip", "sknr_state.hip", "sknr_fused.hip", "sknr_noalloc.hip", "sknr_api.cpp", "sknr_serve.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

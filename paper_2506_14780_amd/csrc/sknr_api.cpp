@@ -63,7 +63,18 @@ struct WS {
   float *NX, *NY, *mu;
   // sweep geometry
   int ns_c, rps_c, nb_c, ns_r, rps_r, nb_r, ns_cw, rps_cw, nb_cw;
+  // fused single-read SK pass (stored cost): per-split row scalars, and
+  // max|log a| + max|log b| for the bound on |f^|
+  double* fz_dot;
+  float* fz_max;
+  float lwb;
 };
+
+// split partials of the fused single-read pass (floats), 0 when not eligible
+size_t fused_part_floats(const Prepared& P) {
+  if (P.kind != SKNR_COST_STORED || P.ctrans || !fused_stored_ok(P.n, P.m, P.ldc, P.C)) return 0;
+  return (size_t)fused_stored_splits(P.n, P.m) * 3 * (size_t)P.m;
+}
 
 int ell_pad(int ell) { return ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32)); }
 
@@ -209,6 +220,9 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
     nbmax = std::max(nbmax, nb);
   }
   nbmax = std::max(nbmax, (std::max(n, m) + 255) / 256 + 1);
+  pmax = std::max(pmax, fused_part_floats(P));
+  add(sizeof(double) * 256);
+  add(sizeof(float) * 256);
   add(sizeof(float2) * n * 3);
   add(sizeof(float2) * m);
   add(sizeof(float2) * m);
@@ -303,6 +317,9 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
     nbmax = std::max(nbmax, nb);
   }
   nbmax = std::max(nbmax, (std::max(n, m) + 255) / 256 + 1);
+  pmax = std::max(pmax, fused_part_floats(P));
+  w.fz_dot = (double*)A.take(sizeof(double) * 256);
+  w.fz_max = (float*)A.take(sizeof(float) * 256);
   w.part = (float*)A.take(sizeof(float) * pmax + 16);
   w.blk_err = (double*)A.take(sizeof(double) * nbmax);
   w.blk_dot = (double*)A.take(sizeof(double) * nbmax);
@@ -384,6 +401,12 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
     fy[j] = (float)P.hY[j];
     ly[j] = std::log(P.hY[j]);
     dy[j] = split_df(ly[j]);
+  }
+  {
+    double mx = 0, my = 0;
+    for (int i = 0; i < n; ++i) mx = std::max(mx, std::fabs(lx[i]));
+    for (int j = 0; j < m; ++j) my = std::max(my, std::fabs(ly[j]));
+    w.lwb = (float)(mx + my);
   }
   HIPCHK(hipMemcpyAsync(w.wX32, fx.data(), 4 * n, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(w.wY32, fy.data(), 4 * m, hipMemcpyHostToDevice, s));
@@ -588,6 +611,103 @@ struct Engine {
     sweep_col(w.F, MA_F, nullptr, w.Gp, DOT_GP, MA_GP, 8, w.E1, nullptr, W_CAND, gate, F_ACCEPT_DQ);
   }
 
+  // Fused single-read SK pass over a stored cost: f = T_r(G[p]) into F and
+  // G[1-p] = T_c(f), testing the pair (f, G[p]) (Sec. 2, eq. SK_iterations)
+  bool fused = false;  // plain SK stages use the fused pass (set by the solve)
+  bool fused_eligible() const {
+    if (P.kind != SKNR_COST_STORED || P.ctrans || !fused_stored_ok(P.n, P.m, P.ldc, P.C)) return false;
+    const char* off = getenv("SKNR_NO_FUSED");
+    if (off && off[0] == '1') return false;
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return false;
+    const int ns = fused_stored_splits(P.n, P.m);
+    return (size_t)lds >= fused_stored_lds(P.m, (P.n + ns - 1) / ns);
+  }
+  void sk_fused(int p) {
+    SweepArgs a{};
+    fill_common(a);
+    a.n_out = P.m;
+    a.n_red = P.n;
+    a.Uin = w.F;
+    a.ma_in = MA_G;
+    a.lw_red = w.lXdf;
+    a.w_red64 = P.wX;
+    a.lpad_c = P.cmax;
+    a.lpad_e = w.lwb * 1.01f;
+    a.aux_blkdot = w.fz_dot;
+    a.aux_blkmax = w.fz_max;
+    a.aux_blkddot = nullptr;
+    a.aux_dot_slot = DOT_F;
+    a.aux_ma_slot = MA_F;
+    a.lw_out = w.lYdf;
+    a.w_out = w.wY32;
+    a.w_out64 = P.wY;
+    a.Uold = w.G[p];
+    a.Uout = w.G[1 - p];
+    a.mdiff = nullptr;
+    a.dot_slot = DOT_G;
+    a.ma_out = MA_G;
+    a.ell = 0;
+    a.wmode = W_NONE;
+    a.nsplit = fused_stored_splits(P.n, P.m);
+    a.rows_per_split = (P.n + a.nsplit - 1) / a.nsplit;
+    a.aux_nblk = a.nsplit;
+    a.nblk = (P.m + 63) / 64;
+    a.gate = G_NOT_DONE;
+    a.flags = F_CHECK | F_COUNT | F_GSEL;
+    a.gsel_val = p;
+    hipEvent_t e0 = nullptr, em = nullptr, e1 = nullptr;
+    if (c->profile) {
+      e0 = c->get_event();
+      em = c->get_event();
+      e1 = c->get_event();
+      HIPCHK(hipEventRecord(e0, s));
+    }
+    HIPCHK(launch_sk_fused_stored(a, s, em));
+    if (c->profile) {
+      HIPCHK(hipEventRecord(e1, s));
+      const double units = (double)P.n * (double)P.m;
+      c->pending.push_back(Pending{c->kind_of("sk_fused_stored"), e0, e1, units});
+      c->pending.push_back(Pending{c->kind_of("sk_fused_stored:main"), nullptr, em, units});
+    }
+  }
+  // A plain SK stage with fused passes: one column sweep g_1 = T_c(f_0)
+  // (unarmed test), then pass k computes f_k = T_r(g_k) and g_{k+1} and
+  // tests (f_k, g_k) -- the pairs, tests and counts of the two-pass loop,
+  // with one read of C per iteration.  G ends in w.G[0].
+  int run_stage_fused(int max_iter, int check_every, bool* converged) {
+    init_state_keep();
+    sweep_col(w.F, MA_F, w.G[0], w.G[1], DOT_G, MA_G, 0, nullptr, nullptr, W_NONE, G_NOT_DONE,
+              F_CHECK | F_COUNT | F_GSEL, 0);
+    int p = 1, launched = 0, chunk = check_every > 0 ? check_every : 4;
+    const int chunk_max = check_every > 0 ? check_every : 32;
+    DevState st{};
+    bool done = false;
+    while (launched < max_iter) {
+      const int k = std::min(chunk, max_iter - launched);
+      for (int t = 0; t < k; ++t) {
+        sk_fused(p);
+        p = 1 - p;
+      }
+      launched += k;
+      st = read_state();
+      check_cancel();
+      if (st.done) {
+        done = true;
+        break;
+      }
+      chunk = std::min(chunk * 2, chunk_max);
+    }
+    *converged = done;
+    last_err = st.err;
+    // g_k of the last tested pair: G[gsel] when converged, else the input of
+    // the last pass, G[1 - p]
+    const int gidx = done ? st.gsel : 1 - p;
+    if (gidx != 0) HIPCHK(hipMemcpyAsync(w.G[0], w.G[gidx], sizeof(float2) * P.m, hipMemcpyDeviceToDevice, s));
+    return std::max(0, st.npass - 1);
+  }
+
   // One SK iteration (ping-pong on G[p]).
   void sk_iter(int p) {
     sweep_col(w.F, MA_F, w.G[p], w.G[1 - p], DOT_G, MA_G, 0, nullptr, nullptr, W_NONE, G_NOT_DONE,
@@ -656,6 +776,10 @@ struct Engine {
   // iterations and sets *converged.  G ends in w.G[0].
   double last_err = 0;  // the sweeps' FP32 marginal-error estimate at the end of run_stage
   int run_stage(int ell, int max_iter, int check_every, bool resume, bool* converged, int* tried, int* accepted) {
+    if (ell == 0 && fused && max_iter >= 1) {
+      *tried = *accepted = 0;
+      return run_stage_fused(max_iter, check_every, converged);
+    }
     init_state_keep();
     const bool graphs = c->use_graphs && !c->profile;
     int launched = 0;  // iterations launched (each = one column sweep)
@@ -926,6 +1050,7 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
   std::memset(res, 0, sizeof(*res));
   E.tol = opts->tol;
   E.nrs = nr_solver_of(opts->newton_solver, opts->newton_max_iter, opts->newton_rtol, opts->ell);
+  E.fused = E.fused_eligible();
   int static_eig_iters = 0;
   if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) {
     // plain SK at eps' from the initial potential, then V_l once

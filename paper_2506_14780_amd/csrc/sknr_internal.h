@@ -136,7 +136,24 @@ struct SweepArgs {
   int gate;
   int flags;
   int gsel_val;
+  // fused single-read SK pass over a stored cost (k_sk_fused_stored): the
+  // row transform of Uold is written to Uin (the reduce side of this
+  // column sweep), with these reduce-side log weights and FP64 weights; the
+  // column part's offset L bounds |Uin| by maxabs[ma_in] + lpad_c +
+  // eps * lpad_e (a bound known before Uin exists; merge and kernel form it
+  // in the same order)
+  const float2* lw_red;
+  const double* w_red64;
+  float lpad_c;
+  float lpad_e;
 };
+
+// offset L of a sweep: 3 (cmax + bound on |Uin|), with the fused pass's
+// bound when lpad_c / lpad_e are set
+__host__ __device__ inline float sweep_offset_bound(const SweepArgs& A, float maxabs_in, double eps) {
+  const float b = maxabs_in + A.lpad_c + (float)eps * A.lpad_e;
+  return 3.f * (A.cmax + b);
+}
 
 // ----------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
@@ -145,6 +162,14 @@ struct SweepArgs {
 hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t stream,
                                hipEvent_t mid = nullptr);
 hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t stream, hipEvent_t mid = nullptr);
+// One SK iteration over a stored cost with a single read of C: rows of C
+// (side X, not transposed) produce f = T_r(Uold) into Uin, and each row's
+// terms join the column log-sum-exp of T_c(f); merge and finish as a
+// streaming column sweep.  Eligible: fused_stored_ok().
+bool fused_stored_ok(int n_red, int n_out, long long ldc, const float* C);
+int fused_stored_splits(int n_red, int n_out);
+size_t fused_stored_lds(int n_out, int rows_per_split);  // dynamic LDS bytes of the pass
+hipError_t launch_sk_fused_stored(const SweepArgs& a, hipStream_t stream, hipEvent_t mid = nullptr);
 size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bool vec, int* nsplit, int* rps,
                          int* nblk, bool stream_kernel);
 // split merge + scalar finishing kernels of a streaming sweep

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
     __shared__ float sbf2[8];
     for (int b = threadIdx.x; b < A.aux_nblk; b += blockDim.x) {
       dax += A.aux_blkdot[b];
-      ddx += A.aux_blkddot[b];
+      if (A.aux_blkddot) ddx += A.aux_blkddot[b];
       mxa = fmaxf(mxa, A.aux_blkmax[b]);
     }
     dax = block_sum_d(dax, sbd2);
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) {
   constexpr int EL = ELL > 0 ? ELL : 1;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
-  const float L = sweep_offset(A.cmax, A.st->maxabs[A.ma_in]);
+  const float L = sweep_offset_bound(A, A.st->maxabs[A.ma_in], A.st->eps);
   const int n_out = A.n_out;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int col = gid >> 2, part4 = gid & 3;

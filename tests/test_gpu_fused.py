@@ -1,0 +1,80 @@
+"""The single-read SK pass over a stored cost (one read of C per iteration:
+f = T_r(g) by rows, and each row's terms join the column log-sum-exp of
+T_c(f)) against the two-pass iteration (SKNR_NO_FUSED=1) and against the
+FP64 oracle: the same pairs are tested, so the iteration counts agree, and
+both reach the oracle's optimum.  Shapes cover one, two and four float4
+groups of columns per thread, a ragged last group, a single row per split
+and splits of unequal length."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests._helpers import e_pot, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2506_14780_amd as sk
+    return sk
+
+
+@pytest.fixture(scope="module")
+def ctx(sk):
+    c = sk.Context(0)
+    yield c
+    c.close()
+
+
+def _stored(n, m, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.random((n, 2))
+    y = rng.random((m, 2))
+    C = O.sqeuclid_cost(x, y).astype(np.float32)
+    a = rng.dirichlet(np.full(n, 3.0))
+    b = rng.dirichlet(np.full(m, 3.0))
+    return C, a, b
+
+
+@pytest.mark.parametrize("n,m,ladder,full_oracle", [(300, 400, [5e-2, 2e-2], True),
+                                                    (1000, 4100, [5e-2, 2e-2, 1e-2], True),
+                                                    (4097, 8192, [5e-2, 2e-2], False), (9, 12, [1e-1, 5e-2], True),
+                                                    (700, 16384, [5e-2], False)])
+def test_fused_pass_matches_two_pass_and_oracle(sk, ctx, n, m, ladder, full_oracle):
+    C, a, b = _stored(n, m, seed=n + m)
+    gp = sk.Problem(a=to_dev(a), b=to_dev(b), C=to_dev(C))
+    print(f"case {n}x{m} ladder {ladder}", flush=True)
+    try:
+        os.environ["SKNR_NO_FUSED"] = "1"
+        f0, g0, r0 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=100000)
+    finally:
+        os.environ.pop("SKNR_NO_FUSED", None)
+    f1, g1, r1 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=100000)
+    it0 = [s["iters"] for s in r0["stages"]]
+    it1 = [s["iters"] for s in r1["stages"]]
+    C64 = C.astype(np.float64)
+    assert r0["status"] == 0 and r1["status"] == 0 and r1["marginal_err"] < 1e-6
+    f1h, g1h = f1.cpu().numpy(), g1.cpu().numpy()
+    e01 = e_pot(f0.cpu().numpy(), g0.cpu().numpy(), f1h, g1h, C64)
+    print(f"two-pass {it0}, fused {it1}, e_pot between them {e01:.2e}", flush=True)
+    for x, y in zip(it1, it0):
+        assert abs(x - y) <= 1
+    assert e01 <= 1e-5
+    if full_oracle:
+        _, _, ro = O.solve_schedule(C64, a, b, ladder, 1e-6, 1000000)
+        fs, gs, _ = O.solve_schedule(C64, a, b, ladder, 1e-11, 1000000)
+        e1 = e_pot(f1h, g1h, fs, gs, C64)
+        print(f"oracle {[r.iters for r in ro]}, fused e_pot vs the oracle's optimum {e1:.2e}", flush=True)
+        for x, z in zip(it1, [r.iters for r in ro]):
+            assert abs(x - z) <= 0.1 * z + 2
+        assert e1 <= 1e-5
+    else:
+        # the oracle on sampled rows: the exported pair satisfies f = T_r(g)
+        rows = np.sort(np.random.default_rng(1).choice(n, 32, replace=False))
+        fr = O.c_transform_row(g1h, C64[rows], b, ladder[-1])
+        d = np.abs(f1h[rows] - fr).max()
+        print(f"rows: max|f - T_r(g)| = {d:.2e}", flush=True)
+        assert d <= 64 * 2.0 ** -24 * ladder[-1] + 1e-12 * np.abs(f1h).max()
