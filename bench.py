@@ -208,9 +208,9 @@ def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4, switch_iters=10):
     base = np.array([q.arrival for q in trace])
     base = base - base[0]
 
-    def run(nr, rate, switch=0):
+    def run(nr, rate, switch=0, batched=True):
         ctx = sk.Context(0)
-        sk.serve_config(ctx, max_active=lanes, pool_bytes=8 << 30)
+        sk.serve_config(ctx, max_active=lanes, pool_bytes=8 << 30, batched=batched)
         arr = base / rate if rate else np.zeros(n_req)
         t0 = time.monotonic()
         sub = []
@@ -231,21 +231,30 @@ def serving_bench(sk, W, torch, n_req, lanes, tol, seed=4, switch_iters=10):
             ends.append(ta + l)
             status.append(r["status"])
             iters.append(r["total_iters"])
+        st = sk.serve_stats(ctx)
         ctx.close()
         makespan = max(ends) - arr[0]
-        return {"solves_per_s": n_req / makespan, "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
-                "makespan_s": makespan, "converged": int(sum(1 for v in status if v == 0)),
-                "not_converged": int(sum(1 for v in status if v == 1)),
-                "failed": int(sum(1 for v in status if v < 0)), "mean_iters": float(np.mean(iters))}
+        out = {"solves_per_s": n_req / makespan, "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+               "makespan_s": makespan, "converged": int(sum(1 for v in status if v == 0)),
+               "not_converged": int(sum(1 for v in status if v == 1)),
+               "failed": int(sum(1 for v in status if v < 0)), "mean_iters": float(np.mean(iters))}
+        if batched:
+            out["batches"] = st["batches"]
+            out["requests_per_batch"] = st["batched_jobs"] / max(1, st["batches"])
+            out["batched_launches"] = st["batched_launches"]
+        return out
 
-    closed = run(True, 0.0)
-    closed_ad = run(True, 0.0, switch_iters)
+    closed = run(True, 0.0, batched=False)
+    closed_batched = run(True, 0.0, batched=True)
+    closed_ad = run(True, 0.0, switch_iters, batched=False)
     rate = 0.8 * closed["solves_per_s"]
     return {"workload": f"serving_trace {n_req} requests, n,m log-uniform [64,8192], d in {{2,3,64}}, "
                         f"eps in {{1e-1,1e-2,1e-3}} by halving from 1, tol {tol:g}, l=min(30,min(n,m)-1)",
-            "lanes": lanes, "closed_loop_sknr": closed, "closed_loop_sknr_adaptive": closed_ad,
+            "lanes": lanes, "closed_loop_sknr": closed, "closed_loop_sknr_batched": closed_batched,
+            "closed_loop_sknr_adaptive": closed_ad,
             "arrival_rate_per_s": rate, "nr_switch_iters": switch_iters,
-            "sknr": run(True, rate), "sknr_adaptive": run(True, rate, switch_iters), "sk": run(False, rate)}
+            "sknr": run(True, rate, batched=False), "sknr_adaptive": run(True, rate, switch_iters, batched=False),
+            "sk": run(False, rate, batched=False)}
 
 
 def c1_bench(sk, W, torch, reps=5):

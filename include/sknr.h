@@ -390,6 +390,24 @@ int sknr_gradient(void* ctx, const sknr_problem* prob, double eps,
  * min(budget, 8 GiB)).  Errors: EBUSY once serving has started, EINVAL. */
 int sknr_serve_config(void* ctx, int32_t max_active, uint64_t pool_bytes);
 
+/* Batched execution (1) or per-lane launches (0, the default), before the
+ * first submit on ctx.  Batched: the lanes still drive their requests'
+ * schedules, but their iteration chunks (SK and SK-NR iterations of
+ * Algorithm 4.1) are handed to one batcher thread, which runs the same
+ * phase of all requests with the same kernel sequence as one launch per
+ * kernel over a tile table (Sec. 4: several EOT problems solved
+ * simultaneously); every request is gated by its own device state and
+ * computes exactly what its own launches would.  Requests whose chunks
+ * use a kernel without a batched form (the row sweep of a stored cost)
+ * launch on their lane.  Measured on the 2048-request mixed trace (closed
+ * loop, SK-NR): 190-215 solves/s batched (3.6-9 requests per batch with
+ * 8-32 lanes) against 370 with per-lane launches: a batch still runs each
+ * iteration as a chain of about 16 dependent launches on one stream, where
+ * per-lane launches overlap 8 such chains on the hardware queues, and the
+ * warm starts stay per lane.  Errors: EBUSY once serving has started,
+ * EINVAL. */
+int sknr_serve_batching(void* ctx, int32_t batched);
+
 /* Queue one solve.  prob and opts as for sknr_solve (opts.f0, opts.V0 and
  * WARM_USER are not accepted; opts.stream orders the copy of the inputs).
  * The inputs are validated and deep-copied before the call returns, so
@@ -422,6 +440,9 @@ typedef struct sknr_serve_info {
   uint64_t pool_bytes;  /* size of the device pool */
   uint64_t pool_used;   /* bytes reserved now */
   uint64_t pool_peak;   /* largest reservation so far */
+  int64_t batches;          /* batched execution: batches launched */
+  int64_t batched_jobs;     /* ... iteration chunks (one per request) they carried */
+  int64_t batched_launches; /* ... kernel launches they took */
 } sknr_serve_info;
 
 /* Snapshot of the serving runtime (all zero before the first submit). */

@@ -85,7 +85,8 @@ class _Eval(ctypes.Structure):
 class _ServeInfo(ctypes.Structure):
     _fields_ = [("lanes", _i32), ("queued", _i32), ("running", _i32), ("reserved0", _i32),
                 ("completed", _i64), ("pool_bytes", ctypes.c_uint64), ("pool_used", ctypes.c_uint64),
-                ("pool_peak", ctypes.c_uint64)]
+                ("pool_peak", ctypes.c_uint64), ("batches", _i64), ("batched_jobs", _i64),
+                ("batched_launches", _i64)]
 
 
 class _KProf(ctypes.Structure):
@@ -120,6 +121,7 @@ _sig("sknr_coupling", [_p, _P(_Problem), _d, _p, _p, _p, _p])
 _sig("sknr_gradient", [_p, _P(_Problem), _d, _p, _p, _p, _p, _p, _p, _p])
 _sig("sknr_profile", [_p, _i32])
 _sig("sknr_serve_config", [_p, _i32, ctypes.c_uint64])
+_sig("sknr_serve_batching", [_p, _i32])
 _sig("sknr_submit", [_p, _P(_Problem), _P(_Opts), _P(ctypes.c_uint64)])
 _sig("sknr_poll", [_p, ctypes.c_uint64, _P(_i32)])
 _sig("sknr_wait", [_p, ctypes.c_uint64, _p, _p, _P(_Result)])
@@ -310,9 +312,11 @@ def solve_noalloc(ctx: Context, prob: Problem, eps, f_out, g_out, tol: float = 1
 
 
 # ------------------------------------------------------------------ serving
-def serve_config(ctx: Context, max_active: int = 0, pool_bytes: int = 0):
-    """sknr_serve_config: lanes and pool size, before the first submit."""
+def serve_config(ctx: Context, max_active: int = 0, pool_bytes: int = 0, batched: bool = False):
+    """sknr_serve_config and sknr_serve_batching: lanes, pool size and
+    batched execution, before the first submit."""
     _check(lib.sknr_serve_config(ctx.handle, max_active, pool_bytes), "sknr_serve_config")
+    _check(lib.sknr_serve_batching(ctx.handle, 1 if batched else 0), "sknr_serve_batching")
 
 
 def submit(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 10000, ell: int = 0,

@@ -68,6 +68,7 @@ struct WS {
   double* fz_dot;
   float* fz_max;
   float lwb;
+  unsigned char* argbank;  // argument blocks of a recorded batch unit
 };
 
 // split partials of the fused single-read pass (floats), 0 when not eligible
@@ -223,6 +224,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   pmax = std::max(pmax, fused_part_floats(P));
   add(sizeof(double) * 256);
   add(sizeof(float) * 256);
+  add((size_t)kMaxUnitLaunches * kMaxArgBytes);
   add(sizeof(float2) * n * 3);
   add(sizeof(float2) * m);
   add(sizeof(float2) * m);
@@ -320,6 +322,7 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
   pmax = std::max(pmax, fused_part_floats(P));
   w.fz_dot = (double*)A.take(sizeof(double) * 256);
   w.fz_max = (float*)A.take(sizeof(float) * 256);
+  w.argbank = (unsigned char*)A.take((size_t)kMaxUnitLaunches * kMaxArgBytes);
   w.part = (float*)A.take(sizeof(float) * pmax + 16);
   w.blk_err = (double*)A.take(sizeof(double) * nbmax);
   w.blk_dot = (double*)A.take(sizeof(double) * nbmax);
@@ -731,6 +734,50 @@ struct Engine {
                 G_NOT_DONE | G_ACCEPT, 0);
   }
 
+  // k iterations through the batcher: record one unit (one SK-NR iteration,
+  // or the SK pair from parity 0), upload its argument blocks, run it `k /
+  // unit` times together with the other requests' units of the same kernel
+  // sequence.  Returns the iterations run, or 0 when some launch of the unit
+  // has no batched twin (the caller then launches as usual).
+  int batch_chunk(int ell, int k) {
+    const int u = ell > 0 ? 1 : 2;
+    if (!c->batcher || k < u) return 0;
+    Recorder rec;
+    rec.recs = c->recbuf;
+    rec.cap = kMaxUnitLaunches;
+    g_recorder = &rec;
+    try {
+      if (ell > 0) sknr_iter(ell, false);
+      else {
+        sk_iter(0);
+        sk_iter(1);
+      }
+    } catch (...) {
+      g_recorder = nullptr;
+      throw;
+    }
+    g_recorder = nullptr;
+    if (rec.unsupported || rec.n == 0) return 0;
+    for (int i = 0; i < rec.n; ++i) {
+      const LaunchRec& r = rec.recs[i];
+      std::memcpy(c->arg_pinned + (size_t)i * kMaxArgBytes, r.args, r.arg_bytes);
+      c->units[i] = BatchLaunch{r.bfunc, w.argbank + (size_t)i * kMaxArgBytes, r.gx, r.gy, r.block, r.lds};
+    }
+    HIPCHK(hipMemcpyAsync(w.argbank, c->arg_pinned, (size_t)rec.n * kMaxArgBytes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(c->ev_in, s));
+    BatchJob job;
+    job.unit = c->units;
+    job.nrec = rec.n;
+    job.reps = k / u;
+    job.ev_in = c->ev_in;
+    job.ev_done = c->ev_done;
+    const int reps = batcher_run(c->batcher, &job);
+    if (job.status != 0) throw Err{SKNR_EDEVICE, std::string("batched launch: ") +
+                                                      hipGetErrorString((hipError_t)job.status)};
+    HIPCHK(hipStreamWaitEvent(s, c->ev_done, 0));
+    return reps * u;
+  }
+
   // k iterations as one captured graph (k even for the SK ping-pong, which
   // then starts and ends on parity 0)
   hipGraphExec_t chunk_graph(int ell, int k) {
@@ -780,6 +827,17 @@ struct Engine {
       *tried = *accepted = 0;
       return run_stage_fused(max_iter, check_every, converged);
     }
+    if (!c->batcher) return run_stage_impl(ell, max_iter, check_every, resume, converged, tried, accepted);
+    // batched chunks: count this lane as iterating while in the loop
+    struct Iterating {
+      Batcher* b;
+      explicit Iterating(Batcher* b_) : b(b_) { batcher_iterating(b, +1); }
+      ~Iterating() { batcher_iterating(b, -1); }
+    } guard(c->batcher);
+    return run_stage_impl(ell, max_iter, check_every, resume, converged, tried, accepted);
+  }
+  int run_stage_impl(int ell, int max_iter, int check_every, bool resume, bool* converged, int* tried,
+                     int* accepted) {
     init_state_keep();
     const bool graphs = c->use_graphs && !c->profile;
     int launched = 0;  // iterations launched (each = one column sweep)
@@ -797,7 +855,11 @@ struct Engine {
       if (remaining <= 0) break;
       int k = std::min(chunk, remaining);
       if (ell == 0 && (k & 1) && k > 1) --k;
-      if (graphs && k >= 2 && p == 0) {
+      int kb = 0;
+      if (c->batcher && (ell > 0 || p == 0)) kb = batch_chunk(ell, k);
+      if (kb > 0) {
+        k = kb;
+      } else if (graphs && k >= 2 && p == 0) {
         HIPCHK(hipGraphLaunch(chunk_graph(ell, k), s));
       } else {
         for (int t = 0; t < k; ++t) {
@@ -1209,6 +1271,11 @@ void rebind(Prepared& P, const sknr_problem* pr) {
 void lane_init(Lane* L, int device) {
   L->device = device;
   HIPCHK(hipHostMalloc((void**)&L->st_host, sizeof(DevState), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&L->arg_pinned, (size_t)kMaxUnitLaunches * kMaxArgBytes, hipHostMallocDefault));
+  L->recbuf = new LaunchRec[kMaxUnitLaunches];
+  L->units = new BatchLaunch[kMaxUnitLaunches];
+  HIPCHK(hipEventCreateWithFlags(&L->ev_in, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&L->ev_done, hipEventDisableTiming));
   HIPCHK(hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking));
   const char* ng = getenv("SKNR_NO_GRAPHS");
   L->use_graphs = !(ng && ng[0] == '1');
@@ -1222,6 +1289,15 @@ void lane_release(Lane* L) {
   L->arena.cap = 0;
   if (L->st_host) (void)hipHostFree(L->st_host);
   L->st_host = nullptr;
+  if (L->arg_pinned) (void)hipHostFree(L->arg_pinned);
+  L->arg_pinned = nullptr;
+  delete[] L->recbuf;
+  L->recbuf = nullptr;
+  delete[] L->units;
+  L->units = nullptr;
+  if (L->ev_in) (void)hipEventDestroy(L->ev_in);
+  if (L->ev_done) (void)hipEventDestroy(L->ev_done);
+  L->ev_in = L->ev_done = nullptr;
   L->drain();
   if (L->own) (void)hipStreamDestroy(L->own);
   L->own = nullptr;

@@ -279,6 +279,10 @@ static hipError_t go_fused(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
 }
 
 hipError_t launch_sk_fused_stored(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
+  if (g_recorder) {  // no batched twin
+    g_recorder->unsupported = true;
+    return hipSuccess;
+  }
   if (!fused_stored_ok(a.n_red, a.n_out, a.ldc, a.C) || a.ell != 0 || a.rows_per_split > kMaxRowsPerSplit)
     return hipErrorInvalidValue;
   if (a.rows_per_split * (long long)(a.nsplit - 1) >= a.n_red || a.rows_per_split * (long long)a.nsplit < a.n_red)

@@ -91,8 +91,44 @@ struct CachedGraph {
   GraphKey key;
   hipGraphExec_t exec;
 };
+// Batched execution of iteration chunks (serving): a lane records one unit
+// (one SK-NR iteration, or two SK iterations) of its request's launches,
+// uploads the argument blocks, and hands the batcher a job; the batcher
+// runs the units of every job with the same kernel sequence as one launch
+// per kernel over a tile table, `reps` times.
+struct BatchLaunch {
+  const void* bfunc;     // batched twin kernel
+  const void* args_dev;  // the request's argument block (device)
+  int gx, gy, block;
+  unsigned lds;
+};
+struct BatchJob {
+  const BatchLaunch* unit = nullptr;
+  int nrec = 0;
+  int reps = 0;            // repetitions of the unit requested
+  hipEvent_t ev_in = nullptr;    // the request's stream up to the job
+  hipEvent_t ev_done = nullptr;  // recorded by the batcher after the job's launches
+  int reps_done = 0;       // set by the batcher
+  bool launched = false;
+  int status = 0;          // 0 or a HIP error
+};
+struct Batcher;
+// Submit a job and block until the batcher has enqueued it together with
+// the other requests' jobs; returns the repetitions run (>= 1).
+int batcher_run(Batcher* b, BatchJob* job);
+// A lane entering (+1) or leaving (-1) a stage's iteration loop: a batch
+// waits (briefly) until every lane in an iteration loop has submitted, so
+// the iterating requests fall into step and share their launches.
+void batcher_iterating(Batcher* b, int delta);
+constexpr int kMaxUnitLaunches = 64;
+
 struct Lane {
   int device = 0;
+  Batcher* batcher = nullptr;    // serving: batched iteration chunks
+  LaunchRec* recbuf = nullptr;   // kMaxUnitLaunches records (host)
+  BatchLaunch* units = nullptr;  // kMaxUnitLaunches (host)
+  unsigned char* arg_pinned = nullptr;  // kMaxUnitLaunches * kMaxArgBytes (pinned)
+  hipEvent_t ev_in = nullptr, ev_done = nullptr;
   Arena arena;                   // workspace (owned, or a block lent by the serving pool)
   bool arena_external = false;   // true: never reallocated or freed here
   hipStream_t own = nullptr;     // solver stream (default priority); graphs are captured on it

@@ -155,6 +155,122 @@ __host__ __device__ inline float sweep_offset_bound(const SweepArgs& A, float ma
   return 3.f * (A.cmax + b);
 }
 
+// ------------------------------------------------- batched execution
+// A tile table spreads one launch over many requests: tile b of the launch
+// belongs to slot s with off[s] <= b < off[s + 1], and within the slot it is
+// block (x, y) = ((b - off[s]) % gx[s], (b - off[s]) / gx[s]) of that
+// request's own grid; args[s] points at the slot's argument block (device
+// memory).  Every kernel of an iteration has such a batched twin, and runs
+// the same body with the request's own arguments and block coordinates,
+// so a request computes exactly what its own launch would.
+struct BatchTab {
+  const void* const* args;  // [nslot] device pointers to argument blocks
+  const int* off;           // [nslot + 1] prefix sums of the slots' tiles
+  const int* gx;            // [nslot] grid width of each slot
+  int nslot;
+};
+__device__ __forceinline__ int batch_slot(const BatchTab& T, int b, int* bx, int* by) {
+  int lo = 0, hi = T.nslot - 1;
+  while (lo < hi) {  // the last slot whose offset is <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (T.off[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int local = b - T.off[lo];
+  const int g = T.gx[lo];
+  *bx = local % g;
+  *by = local / g;
+  return lo;
+}
+
+// While a recorder is installed on the calling thread, the launchers of the
+// iteration kernels append a record (batched twin, argument block, grid,
+// block, LDS bytes) instead of launching.
+constexpr int kMaxArgBytes = 512;
+struct LaunchRec {
+  const void* bfunc;  // __global__ void(BatchTab)
+  int arg_bytes;
+  int gx, gy, block;
+  unsigned lds;
+  alignas(16) unsigned char args[kMaxArgBytes];
+};
+struct Recorder {
+  LaunchRec* recs = nullptr;  // caller-owned storage
+  int cap = 0;
+  int n = 0;
+  bool unsupported = false;   // a launch without a batched twin was requested
+};
+extern thread_local Recorder* g_recorder;
+template <typename T>
+inline void record_launch(const void* bfunc, const T& a, dim3 grid, int block, size_t lds) {
+  static_assert(sizeof(T) <= kMaxArgBytes, "argument block too large");
+  Recorder* r = g_recorder;
+  if (r->n >= r->cap) {
+    r->unsupported = true;
+    return;
+  }
+  LaunchRec& L = r->recs[r->n++];
+  L.bfunc = bfunc;
+  L.arg_bytes = (int)sizeof(T);
+  L.gx = (int)grid.x;
+  L.gy = (int)grid.y;
+  L.block = block;
+  L.lds = (unsigned)lds;
+  __builtin_memcpy(L.args, &a, sizeof(T));
+}
+
+// argument blocks of the kernels without SweepArgs
+struct NrAssembleArgs {
+  const float* V;
+  const float* mdiff;
+  const double* a;
+  int n;
+  const float* W;
+  const double* b;
+  int m;
+  double* part;
+  int nrow_blk, rows_per_blk;
+  DevState* st;
+  int gate;
+};
+struct NrSolveArgs {
+  const double* part;
+  int nblk, ell_real;
+  float* coef32;
+  double* coef64;
+  double* Gout;
+  double* gout;
+  DevState* st;
+  int gate, solver, max_it;
+  double rtol;
+};
+struct NrApplyArgs {
+  const float2* F;
+  const float* V;
+  const float* coef;
+  const double* a;
+  float2* Fp;
+  int n;
+  double* blk;
+  float* blkmax;
+  double* blkd;
+  float* E1;
+  DevState* st;
+  int gate;
+};
+struct SelectArgs {
+  const float2* Fp;
+  const float2* Fsk;
+  float2* F;
+  int n;
+  const float2* Gp;
+  const float2* Gt;
+  float2* G;
+  int m;
+  DevState* st;
+  int gate;
+};
+
 // ----------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
 // vec: the stored cost allows float4 access along the output axis

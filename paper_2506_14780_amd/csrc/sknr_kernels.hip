@@ -25,10 +25,12 @@
 
 namespace sknr {
 
+thread_local Recorder* g_recorder = nullptr;
+
 // One workgroup: reduce the per-block scalars of a sweep in block order and
 // update the solver state (error, dots, max, convergence and acceptance
 // decisions).  Runs after the sweep, so its writes are visible.
-__global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
+__device__ __forceinline__ void sweep_finish_body(const SweepArgs& A) {
   if (gate_closed(A.st, A.gate)) return;
   __shared__ double sbd[16];
   __shared__ float sbf[8];
@@ -91,6 +93,13 @@ __global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) { sweep_finish_body(A); }
+__global__ __launch_bounds__(256) void k_sweep_finish_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  sweep_finish_body(*static_cast<const SweepArgs*>(T.args[slot]));
+}
+
 // ============================================================================
 // Streaming sweep: each workgroup owns NC = 64*CPT outputs (lane-contiguous
 // groups of CPT) and a contiguous range of the reduce side (split-K).  Its 4
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) {
 // combines the splits of each output in split order (deterministic).
 // ============================================================================
 template <int CPT, int ELL, int COST, int D, int R, bool SCALE>
-__global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
+__device__ __forceinline__ void sweep_stream_body(const SweepArgs& A, const int bx, const int by) {
   if (gate_closed(A.st, A.gate)) return;
   extern __shared__ float4 smem4[];
   char* smem = reinterpret_cast<char*>(smem4);
@@ -110,7 +119,7 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
   constexpr int DD = (COST == 1) ? (D > 0 ? D : 1) : 1;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int r0 = blockIdx.y * A.rows_per_split;
+  const int r0 = by * A.rows_per_split;
   const int nr = min(A.rows_per_split, A.n_red - r0);
   // points: dg coordinates in memory; d = the compile-time width D >= dg
   // (rows zero-padded in LDS and registers, which leaves the FP32 cost
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
   }
   __syncthreads();
 
-  const int colbase = blockIdx.x * NC + lane * CPT;
+  const int colbase = bx * NC + lane * CPT;
   float q[CPT][DD];
   const float* crow0 = nullptr;
   int ccol[CPT];
@@ -287,9 +296,9 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
   }
   const int n_out = A.n_out;
   for (int t = threadIdx.x; t < NC; t += TPB) {
-    int col = blockIdx.x * NC + t;
+    int col = bx * NC + t;
     if (col < n_out) {
-      size_t base = (size_t)blockIdx.y * NQ * n_out + col;
+      size_t base = (size_t)by * NQ * n_out + col;
 #pragma unroll
       for (int q2 = 0; q2 < NQ; ++q2) A.part[base + q2 * (size_t)n_out] = cmb[q2 * NC + t];
     }
@@ -297,11 +306,22 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
 
 }
 
+template <int CPT, int ELL, int COST, int D, int R, bool SCALE>
+__global__ __launch_bounds__(TPB) void k_sweep_stream(SweepArgs A) {
+  sweep_stream_body<CPT, ELL, COST, D, R, SCALE>(A, blockIdx.x, blockIdx.y);
+}
+template <int CPT, int ELL, int COST, int D, int R, bool SCALE>
+__global__ __launch_bounds__(TPB) void k_sweep_stream_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  sweep_stream_body<CPT, ELL, COST, D, R, SCALE>(*static_cast<const SweepArgs*>(T.args[slot]), bx, by);
+}
+
 // Merge the split-K partials of a streaming sweep: 4 lanes per output,
 // each merging a contiguous quarter of the splits in order, then a fixed
 // shuffle tree across the 4 lanes (deterministic), and finalise.
 template <int ELL>
-__global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) {
+__device__ __forceinline__ void sweep_merge_body(const SweepArgs& A, const int bx) {
   if (gate_closed(A.st, A.gate)) return;
   constexpr int NQ = 3 + (ELL > 0 ? ELL : 0);
   constexpr int EL = ELL > 0 ? ELL : 1;
@@ -309,7 +329,7 @@ __global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) {
   const float K = EC.K;
   const float L = sweep_offset_bound(A, A.st->maxabs[A.ma_in], A.st->eps);
   const int n_out = A.n_out;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = bx * blockDim.x + threadIdx.x;
   const int col = gid >> 2, part4 = gid & 3;
   const int colc = min(col, n_out - 1);
   const int ns = A.nsplit;
@@ -376,7 +396,16 @@ __global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) {
   err = block_sum_d(err, sbd);
   dot = block_sum_d(dot, sbd + 8);
   mxo = block_max_f(mxo, sbf);
-  write_block_scalars(A, blockIdx.x, err, dot, mxo);
+  write_block_scalars(A, bx, err, dot, mxo);
+}
+
+template <int ELL>
+__global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) { sweep_merge_body<ELL>(A, blockIdx.x); }
+template <int ELL>
+__global__ __launch_bounds__(256) void k_sweep_merge_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  sweep_merge_body<ELL>(*static_cast<const SweepArgs*>(T.args[slot]), bx);
 }
 
 // ============================================================================
@@ -606,6 +635,14 @@ static hipError_t go_stream(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
   size_t cmb_bytes = (size_t)(3 + ELL) * NC * 4;
   size_t sm = rows_bytes > cmb_bytes ? rows_bytes : cmb_bytes;
   bool scale = (COST == 1) && a.cscale != 1.0f;
+  if (g_recorder) {
+    record_launch(scale ? (const void*)k_sweep_stream_b<CPT, ELL, COST, D, R, true>
+                        : (const void*)k_sweep_stream_b<CPT, ELL, COST, D, R, false>,
+                  a, grid, TPB, sm);
+    record_launch((const void*)k_sweep_merge_b<ELL>, a, dim3((a.n_out + 63) / 64), 256, 0);
+    record_launch((const void*)k_sweep_finish_b, a, dim3(1), 256, 0);
+    return hipSuccess;
+  }
   if (scale)
     hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, true>), grid, dim3(TPB), sm, s, a);
   else
@@ -637,6 +674,15 @@ static hipError_t go_stream_points(const SweepArgs& a, hipStream_t s, hipEvent_t
 
 hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t s) {
   dim3 grid((a.n_out + 63) / 64);
+  if (g_recorder) {
+    record_launch(a.ell == 0 ? (const void*)k_sweep_merge_b<0>
+                  : a.ell <= 8 ? (const void*)k_sweep_merge_b<8>
+                  : a.ell <= 16 ? (const void*)k_sweep_merge_b<16>
+                                : (const void*)k_sweep_merge_b<32>,
+                  a, grid, 256, 0);
+    record_launch((const void*)k_sweep_finish_b, a, dim3(1), 256, 0);
+    return hipSuccess;
+  }
   if (a.ell == 0) hipLaunchKernelGGL((k_sweep_merge<0>), grid, dim3(256), 0, s, a);
   else if (a.ell <= 8) hipLaunchKernelGGL((k_sweep_merge<8>), grid, dim3(256), 0, s, a);
   else if (a.ell <= 16) hipLaunchKernelGGL((k_sweep_merge<16>), grid, dim3(256), 0, s, a);
@@ -662,6 +708,10 @@ hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipS
 }
 
 hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
+  if (g_recorder) {  // stored-cost row sweeps have no batched twin
+    g_recorder->unsupported = true;
+    return hipSuccess;
+  }
   bool vec = (a.n_red % 4 == 0) && (a.ldc % 4 == 0) && ((uintptr_t)a.C % 16 == 0) && ((uintptr_t)a.Uin % 16 == 0);
   if (a.ell == 0) {
     dim3 grid((a.n_out + 3) / 4);
@@ -774,23 +824,43 @@ hipError_t launch_copy_state_slot(DevState* st, int dst_dot, int src_dot, int ds
 
 // Newton acceptance selection: accepted -> (F, G) = (F', G'); rejected ->
 // (F, G) = (F_sk, G~), i.e. the plain SK iterate.
-__global__ void k_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp, const float2* Gt,
-                         float2* G, int m, DevState* st, int gate) {
-  if (gate_closed(st, gate)) return;
+__device__ __forceinline__ void select_body(const SelectArgs& q, const int bx) {
+  const float2* Fp = q.Fp;
+  const float2* Fsk = q.Fsk;
+  float2* F = q.F;
+  const int n = q.n;
+  const float2* Gp = q.Gp;
+  const float2* Gt = q.Gt;
+  float2* G = q.G;
+  const int m = q.m;
+  DevState* st = q.st;
+  if (gate_closed(st, q.gate)) return;
   const int acc = ((volatile DevState*)st)->accept;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = bx * blockDim.x + threadIdx.x;
   if (i < n) F[i] = acc ? Fp[i] : Fsk[i];
   else if (i < n + m) G[i - n] = acc ? Gp[i - n] : Gt[i - n];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bx == 0 && threadIdx.x == 0) {
     st->dots[DOT_F] = acc ? st->dots[DOT_FP] : st->dots[DOT_FSK];
     st->dots[DOT_G] = acc ? st->dots[DOT_GP] : st->dots[DOT_GT];
     st->maxabs[MA_F] = acc ? st->maxabs[MA_FP] : st->maxabs[MA_FSK];
     st->maxabs[MA_G] = acc ? st->maxabs[MA_GP] : st->maxabs[MA_GT];
   }
 }
+__global__ void k_select(SelectArgs q) { select_body(q, blockIdx.x); }
+__global__ void k_select_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  select_body(*static_cast<const SelectArgs*>(T.args[slot]), bx);
+}
 hipError_t launch_select(const float2* Fp, const float2* Fsk, float2* F, int n, const float2* Gp, const float2* Gt,
                          float2* G, int m, DevState* st, int gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3((n + m + 255) / 256), dim3(256), 0, s, Fp, Fsk, F, n, Gp, Gt, G, m, st, gate);
+  const SelectArgs q{Fp, Fsk, F, n, Gp, Gt, G, m, st, gate};
+  const dim3 grid((n + m + 255) / 256);
+  if (g_recorder) {
+    record_launch((const void*)k_select_b, q, grid, 256, 0);
+    return hipSuccess;
+  }
+  hipLaunchKernelGGL(k_select, grid, dim3(256), 0, s, q);
   return hipGetLastError();
 }
 
@@ -801,10 +871,17 @@ hipError_t launch_select(const float2* Fp, const float2* Fsk, float2* F, int n, 
 // r = a + mdiff is the row marginal of P~ = pi(f, f^{C,eps}).
 // ============================================================================
 template <int ELL>
-__global__ __launch_bounds__(256) void k_nr_assemble(const float* V, const float* mdiff, const double* a, int n,
-                                                     const float* W, const double* b, int m, double* part,
-                                                     int nrow_blk, int rows_per_blk, DevState* st, int gate) {
-  if (gate_closed(st, gate)) return;
+__device__ __forceinline__ void nr_assemble_body(const NrAssembleArgs& q, const int bx) {
+  const float* V = q.V;
+  const float* mdiff = q.mdiff;
+  const double* a = q.a;
+  const int n = q.n;
+  const float* W = q.W;
+  const double* b = q.b;
+  const int m = q.m;
+  double* part = q.part;
+  const int nrow_blk = q.nrow_blk, rows_per_blk = q.rows_per_blk;
+  if (gate_closed(q.st, q.gate)) return;
   constexpr int NE = ELL * ELL;
   constexpr int PER = (NE + 255) / 256;
   __shared__ float tile[64][ELL];
@@ -813,8 +890,8 @@ __global__ __launch_bounds__(256) void k_nr_assemble(const float* V, const float
 #pragma unroll
   for (int p = 0; p < PER; ++p) accv[p] = 0;
   double gacc = 0;
-  const bool rows = (int)blockIdx.x < nrow_blk;
-  const int blk = rows ? blockIdx.x : blockIdx.x - nrow_blk;
+  const bool rows = (int)bx < nrow_blk;
+  const int blk = rows ? bx : bx - nrow_blk;
   const int beg = blk * rows_per_blk;
   const int cnt = rows ? n : m;
   const int end = min(beg + rows_per_blk, cnt);
@@ -847,13 +924,22 @@ __global__ __launch_bounds__(256) void k_nr_assemble(const float* V, const float
       if (rows && (int)threadIdx.x < ELL) gacc -= (double)tile[rr][threadIdx.x] * (double)mdiff[t0 + rr];
     }
   }
-  double* out = part + (size_t)blockIdx.x * (NE + ELL);
+  double* out = part + (size_t)bx * (NE + ELL);
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     int e = threadIdx.x + 256 * p;
     if (e < NE) out[e] = accv[p];
   }
   if ((int)threadIdx.x < ELL) out[NE + threadIdx.x] = gacc;
+}
+
+template <int ELL>
+__global__ __launch_bounds__(256) void k_nr_assemble(NrAssembleArgs q) { nr_assemble_body<ELL>(q, blockIdx.x); }
+template <int ELL>
+__global__ __launch_bounds__(256) void k_nr_assemble_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  nr_assemble_body<ELL>(*static_cast<const NrAssembleArgs*>(T.args[slot]), bx);
 }
 
 // sum over nblk (<= 32) partial blocks of entry e, loads issued together
@@ -1030,10 +1116,17 @@ __device__ void nr_iterative(double (*A)[ELL + 2], int solver, int max_it, doubl
 }
 
 template <int ELL>
-__global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, int ell_real, float* coef32,
-                                                  double* coef64, double* Gout, double* gout, DevState* st,
-                                                  int gate, int solver, int max_it, double rtol) {
-  if (gate_closed(st, gate)) return;
+__device__ __forceinline__ void nr_solve_body(const NrSolveArgs& q) {
+  const double* part = q.part;
+  const int nblk = q.nblk, ell_real = q.ell_real;
+  float* coef32 = q.coef32;
+  double* coef64 = q.coef64;
+  double* Gout = q.Gout;
+  double* gout = q.gout;
+  DevState* st = q.st;
+  const int solver = q.solver, max_it = q.max_it;
+  const double rtol = q.rtol;
+  if (gate_closed(st, q.gate)) return;
   constexpr int NE = ELL * ELL;
   constexpr int NA = ELL + 1;  // augmented width
   const int tid = threadIdx.x;
@@ -1133,15 +1226,33 @@ __global__ __launch_bounds__(256) void k_nr_solve(const double* part, int nblk, 
 }
 
 template <int ELL>
-__global__ __launch_bounds__(256) void k_nr_apply(const float2* F, const float* V, const float* coef,
-                                                  const double* a, float2* Fp, int n, double* blk, float* blkmax,
-                                                  double* blkd, float* E1, DevState* st, int gate) {
-  if (gate_closed(st, gate)) return;
+__global__ __launch_bounds__(256) void k_nr_solve(NrSolveArgs q) { nr_solve_body<ELL>(q); }
+template <int ELL>
+__global__ __launch_bounds__(256) void k_nr_solve_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  nr_solve_body<ELL>(*static_cast<const NrSolveArgs*>(T.args[slot]));
+}
+
+template <int ELL>
+__device__ __forceinline__ void nr_apply_body(const NrApplyArgs& q, const int bx) {
+  const float2* F = q.F;
+  const float* V = q.V;
+  const float* coef = q.coef;
+  const double* a = q.a;
+  float2* Fp = q.Fp;
+  const int n = q.n;
+  double* blk = q.blk;
+  float* blkmax = q.blkmax;
+  double* blkd = q.blkd;
+  float* E1 = q.E1;
+  DevState* st = q.st;
+  if (gate_closed(st, q.gate)) return;
   __shared__ float c[ELL];
   if (threadIdx.x < ELL) c[threadIdx.x] = coef[threadIdx.x];
   __syncthreads();
   const float inv_eps = st->inv_eps;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = bx * blockDim.x + threadIdx.x;
   double dot = 0, dd = 0;
   float mx = 0.f;
   if (i < n) {
@@ -1165,19 +1276,29 @@ __global__ __launch_bounds__(256) void k_nr_apply(const float2* F, const float* 
   dd = block_sum_d(dd, sbd2);
   mx = block_max_f(mx, sbf);
   if (threadIdx.x == 0) {
-    blk[blockIdx.x] = dot;
-    blkd[blockIdx.x] = dd;
-    blkmax[blockIdx.x] = mx;
+    blk[bx] = dot;
+    blkd[bx] = dd;
+    blkmax[bx] = mx;
   }
 }
 
+template <int ELL>
+__global__ __launch_bounds__(256) void k_nr_apply(NrApplyArgs q) { nr_apply_body<ELL>(q, blockIdx.x); }
+template <int ELL>
+__global__ __launch_bounds__(256) void k_nr_apply_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  nr_apply_body<ELL>(*static_cast<const NrApplyArgs*>(T.args[slot]), bx);
+}
 
 template <int E>
 static void nr_assemble_e(const float* V, const float* mdiff, const double* a, int n, const float* W, const double* b,
                           int m, double* part, int nrow_blk, int ncol_blk, int rpb, DevState* st, int gate,
                           hipStream_t s) {
-  hipLaunchKernelGGL((k_nr_assemble<E>), dim3(nrow_blk + ncol_blk), dim3(256), 0, s, V, mdiff, a, n, W, b, m, part,
-                     nrow_blk, rpb, st, gate);
+  const NrAssembleArgs q{V, mdiff, a, n, W, b, m, part, nrow_blk, rpb, st, gate};
+  const dim3 grid(nrow_blk + ncol_blk);
+  if (g_recorder) record_launch((const void*)k_nr_assemble_b<E>, q, grid, 256, 0);
+  else hipLaunchKernelGGL((k_nr_assemble<E>), grid, dim3(256), 0, s, q);
 }
 hipError_t launch_nr_assemble(int ell, const float* V, const float* mdiff, const double* a, int n, const float* W,
                               const double* b, int m, double* part, int nrow_blk, int ncol_blk, DevState* st, int gate,
@@ -1193,8 +1314,9 @@ hipError_t launch_nr_assemble(int ell, const float* V, const float* mdiff, const
 template <int E>
 static void nr_solve_e(const double* part, int nblk, int ell, float* coef32, double* coef64, double* Gout,
                        double* gout, DevState* st, int gate, const NrSolver& sv, hipStream_t s) {
-  hipLaunchKernelGGL((k_nr_solve<E>), dim3(1), dim3(256), 0, s, part, nblk, ell, coef32, coef64, Gout, gout, st,
-                     gate, sv.kind, sv.max_iter, sv.rtol);
+  const NrSolveArgs q{part, nblk, ell, coef32, coef64, Gout, gout, st, gate, sv.kind, sv.max_iter, sv.rtol};
+  if (g_recorder) record_launch((const void*)k_nr_solve_b<E>, q, dim3(1), 256, 0);
+  else hipLaunchKernelGGL((k_nr_solve<E>), dim3(1), dim3(256), 0, s, q);
 }
 hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32, double* coef64, double* Gout,
                            double* gout, DevState* st, int gate, hipStream_t s, const NrSolver& sv) {
@@ -1206,9 +1328,10 @@ hipError_t launch_nr_solve(int ell, const double* part, int nblk, float* coef32,
 template <int E>
 static void nr_apply_e(const float2* F, const float* V, const float* coef, const double* a, float2* Fp, int n,
                        double* blk, float* blkmax, double* blkd, float* E1, DevState* st, int gate, hipStream_t s) {
-  int nb = (n + 255) / 256;
-  hipLaunchKernelGGL((k_nr_apply<E>), dim3(nb), dim3(256), 0, s, F, V, coef, a, Fp, n, blk, blkmax, blkd, E1, st,
-                     gate);
+  const NrApplyArgs q{F, V, coef, a, Fp, n, blk, blkmax, blkd, E1, st, gate};
+  const dim3 grid((n + 255) / 256);
+  if (g_recorder) record_launch((const void*)k_nr_apply_b<E>, q, grid, 256, 0);
+  else hipLaunchKernelGGL((k_nr_apply<E>), grid, dim3(256), 0, s, q);
 }
 hipError_t launch_nr_apply(int ell, const float2* F, const float* V, const float* coef, const double* a, float2* Fp,
                            int n, double* blk, float* blkmax, double* blkd, float* E1, DevState* st, int gate,

@@ -149,7 +149,7 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
 }
 
 template <int ELL, int KS, int XP, int NT, int DV = 0, bool SC = false>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_mfma(SweepArgs A) {
+__device__ __forceinline__ void sweep_mfma_body(const SweepArgs& A, const int bx, const int by) {
   if (gate_closed(A.st, A.gate)) return;
   extern __shared__ float4 smem4[];
   constexpr int EL = ELL > 0 ? ELL : 1;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, c16 = lane & 15;
-  const int r0 = blockIdx.y * A.rows_per_split;
+  const int r0 = by * A.rows_per_split;
   const int nr = min(A.rows_per_split, A.n_red - r0);
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   __syncthreads();
 
-  const int cb = blockIdx.x * NC + wave * NCW;
+  const int cb = bx * NC + wave * NCW;
   float hy[NT];
   int colc[NT];
   // parts of the output-side points: [0] hi, then lo (XP = 2) or mid, lo
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
   for (int t = 0; t < NT; ++t) {
     const int col = cb + 16 * t + c16;
     if (col < n_out) {
-      float* base = A.part + (size_t)blockIdx.y * NQ * n_out + col;
+      float* base = A.part + (size_t)by * NQ * n_out + col;
       if (g == 0) base[0] = sig[t];
       else if (g == 1) base[(size_t)n_out] = S[t];
       else if (g == 2) base[(size_t)2 * n_out] = Sc[t];
@@ -464,6 +464,17 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
     }
   }
+}
+
+template <int ELL, int KS, int XP, int NT, int DV = 0, bool SC = false>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_mfma(SweepArgs A) {
+  sweep_mfma_body<ELL, KS, XP, NT, DV, SC>(A, blockIdx.x, blockIdx.y);
+}
+template <int ELL, int KS, int XP, int NT, int DV = 0, bool SC = false>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k_sweep_mfma_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  sweep_mfma_body<ELL, KS, XP, NT, DV, SC>(*static_cast<const SweepArgs*>(T.args[slot]), bx, by);
 }
 
 // ----------------------------------------------------------- geometry
@@ -522,6 +533,13 @@ static void go_mfma(const SweepArgs& a, hipStream_t s) {
   dim3 grid((a.n_out + nc - 1) / nc, a.nsplit);
   const size_t sm = (size_t)a.rows_per_split * sizeof(float4);
   const int ks = a.dpad >> 5;
+  if (g_recorder) {
+    record_launch(ks == 1   ? (const void*)k_sweep_mfma_b<ELL, 1, XP, NT>
+                  : ks == 2 ? (const void*)k_sweep_mfma_b<ELL, 2, XP, NT>
+                            : (const void*)k_sweep_mfma_b<ELL, 0, XP, NT>,
+                  a, grid, TPB, sm);
+    return;
+  }
   if (ks == 1) hipLaunchKernelGGL((k_sweep_mfma<ELL, 1, XP, NT>), grid, dim3(TPB), sm, s, a);
   else if (ks == 2) hipLaunchKernelGGL((k_sweep_mfma<ELL, 2, XP, NT>), grid, dim3(TPB), sm, s, a);
   else hipLaunchKernelGGL((k_sweep_mfma<ELL, 0, XP, NT>), grid, dim3(TPB), sm, s, a);
@@ -551,6 +569,12 @@ static hipError_t go_pw(const SweepArgs& a, hipStream_t s) {
   const size_t sm = (size_t)a.rows_per_split * (sizeof(float4) + (DV > 2 ? (DV - 2) * sizeof(float) : 0)) +
                     (size_t)ELL * (a.rows_per_split + 4) * sizeof(float);
   if (sm > 49152 || (a.rows_per_split & 15)) return hipErrorInvalidValue;
+  if (g_recorder) {
+    record_launch(a.cscale != 1.0f ? (const void*)k_sweep_mfma_b<ELL, 1, 0, NT, DV, true>
+                                   : (const void*)k_sweep_mfma_b<ELL, 1, 0, NT, DV, false>,
+                  a, grid, TPB, sm);
+    return hipSuccess;
+  }
   if (a.cscale != 1.0f) hipLaunchKernelGGL((k_sweep_mfma<ELL, 1, 0, NT, DV, true>), grid, dim3(TPB), sm, s, a);
   else hipLaunchKernelGGL((k_sweep_mfma<ELL, 1, 0, NT, DV, false>), grid, dim3(TPB), sm, s, a);
   return hipSuccess;
@@ -568,7 +592,7 @@ hipError_t launch_sweep_pw(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
   if (!sweep_pw_eligible(a.ell, a.d) || a.ell > 32) return hipErrorInvalidValue;
   const hipError_t e = a.d == 2 ? go_pw_ell<2, kPwNT>(a, s) : go_pw_ell<3, kPwNT>(a, s);
   if (e != hipSuccess) return e;
-  if (mid) (void)hipEventRecord(mid, s);
+  if (mid && !g_recorder) (void)hipEventRecord(mid, s);
   return launch_sweep_tail(a, s);
 }
 
@@ -577,7 +601,7 @@ hipError_t launch_sweep_mfma(const SweepArgs& a, int parts, hipStream_t s, hipEv
   if (parts == 1) go_mfma_ell<1>(a, s);
   else if (parts == 2) go_mfma_ell<2>(a, s);
   else go_mfma_ell<3>(a, s);
-  if (mid) (void)hipEventRecord(mid, s);
+  if (mid && !g_recorder) (void)hipEventRecord(mid, s);
   return launch_sweep_tail(a, s);
 }
 

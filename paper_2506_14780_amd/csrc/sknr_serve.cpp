@@ -102,6 +102,187 @@ struct Request {
 
 }  // namespace
 
+// --------------------------------------------------------------- batcher
+// One host thread and one stream launch the iteration chunks of all lanes.
+// Jobs that arrive within a short window (or until every running lane has
+// submitted one) are grouped by their unit's kernel sequence; a group runs
+// min(reps) repetitions of its unit, each kernel of the unit as ONE launch
+// whose tile table covers every job of the group.  Each request's kernels
+// read only its own arguments and device state (gating included), so the
+// result of a request does not depend on the group it ran in.
+struct Batcher {
+  std::mutex mu;
+  std::condition_variable cv_job, cv_launched;
+  std::vector<BatchJob*> pending;
+  bool stop = false;
+  int expected = 1;   // lanes running a request (an upper bound on the jobs of a batch)
+  int iterating = 0;  // lanes inside a stage's iteration loop
+  hipStream_t stream = nullptr;
+  std::thread th;
+  // tile tables: a ring of pinned host / device buffer pairs, each reused
+  // only after the copy and the launches that used it before have finished
+  static constexpr int kRing = 4;
+  char* d_tab[kRing] = {};
+  char* h_tab[kRing] = {};
+  size_t tab_cap[kRing] = {};
+  hipEvent_t tab_ev[kRing] = {};
+  bool tab_used[kRing] = {};
+  int ring = 0;
+  int64_t batches = 0, jobs = 0, launches = 0;
+};
+
+int batcher_run(Batcher* b, BatchJob* job) {
+  std::unique_lock<std::mutex> lk(b->mu);
+  b->pending.push_back(job);
+  b->cv_job.notify_one();
+  b->cv_launched.wait(lk, [&] { return job->launched; });
+  return job->reps_done;
+}
+
+void batcher_iterating(Batcher* b, int delta) {
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->iterating += delta;
+  }
+  b->cv_job.notify_one();
+}
+
+namespace {
+
+// a batch waits for every iterating lane's job, at most this long
+constexpr auto kBatchWindow = std::chrono::microseconds(1500);
+
+// launch one group of jobs with identical unit kernel sequences
+hipError_t run_group(Batcher* b, std::vector<BatchJob*>& g) {
+  const int B = (int)g.size();
+  const int nrec = g[0]->nrec;
+  int reps = g[0]->reps;
+  for (BatchJob* j : g) reps = std::min(reps, j->reps);
+  for (BatchJob* j : g) {
+    hipError_t e = hipStreamWaitEvent(b->stream, j->ev_in, 0);
+    if (e != hipSuccess) return e;
+  }
+  // tables per unit launch i: args[B] pointers, off[B + 1], gx[B]
+  const size_t per = al((size_t)B * 8) + al((size_t)(B + 1) * 4) + al((size_t)B * 4);
+  const size_t bytes = per * (size_t)nrec;
+  const int k = b->ring;
+  b->ring = (b->ring + 1) % Batcher::kRing;
+  if (b->tab_used[k]) {
+    hipError_t e = hipEventSynchronize(b->tab_ev[k]);
+    if (e != hipSuccess) return e;
+  }
+  if (bytes > b->tab_cap[k]) {
+    if (b->d_tab[k]) (void)hipFree(b->d_tab[k]);
+    if (b->h_tab[k]) (void)hipHostFree(b->h_tab[k]);
+    b->d_tab[k] = b->h_tab[k] = nullptr;
+    b->tab_cap[k] = 0;
+    const size_t cap = std::max<size_t>(bytes * 2, 1 << 16);
+    hipError_t e = hipMalloc((void**)&b->d_tab[k], cap);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_tab[k], cap, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    b->tab_cap[k] = cap;
+  }
+  if (!b->tab_ev[k]) {
+    hipError_t e = hipEventCreateWithFlags(&b->tab_ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  std::memset(b->h_tab[k], 0, bytes);
+  std::vector<int> total(nrec, 0);
+  std::vector<unsigned> lds(nrec, 0);
+  for (int i = 0; i < nrec; ++i) {
+    char* base = b->h_tab[k] + per * i;
+    const void** args = reinterpret_cast<const void**>(base);
+    int* off = reinterpret_cast<int*>(base + al((size_t)B * 8));
+    int* gx = reinterpret_cast<int*>(base + al((size_t)B * 8) + al((size_t)(B + 1) * 4));
+    long long t = 0;
+    for (int j = 0; j < B; ++j) {
+      const BatchLaunch& L = g[j]->unit[i];
+      args[j] = L.args_dev;
+      off[j] = (int)t;
+      gx[j] = L.gx;
+      t += (long long)L.gx * L.gy;
+      lds[i] = std::max(lds[i], L.lds);
+    }
+    if (t > (1ll << 30)) return hipErrorInvalidValue;
+    off[B] = (int)t;
+    total[i] = (int)t;
+  }
+  hipError_t e = hipMemcpyAsync(b->d_tab[k], b->h_tab[k], bytes, hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return e;
+  for (int r = 0; r < reps; ++r) {
+    for (int i = 0; i < nrec; ++i) {
+      char* base = b->d_tab[k] + per * i;
+      BatchTab T;
+      T.args = reinterpret_cast<const void* const*>(base);
+      T.off = reinterpret_cast<const int*>(base + al((size_t)B * 8));
+      T.gx = reinterpret_cast<const int*>(base + al((size_t)B * 8) + al((size_t)(B + 1) * 4));
+      T.nslot = B;
+      void* kargs[] = {&T};
+      const BatchLaunch& L0 = g[0]->unit[i];
+      e = hipLaunchKernel(L0.bfunc, dim3(total[i]), dim3(L0.block), kargs, lds[i], b->stream);
+      if (e != hipSuccess) return e;
+      b->launches++;
+    }
+  }
+  e = hipEventRecord(b->tab_ev[k], b->stream);
+  if (e != hipSuccess) return e;
+  b->tab_used[k] = true;
+  for (BatchJob* j : g) {
+    e = hipEventRecord(j->ev_done, b->stream);
+    if (e != hipSuccess) return e;
+    j->reps_done = reps;
+  }
+  return hipSuccess;
+}
+
+bool same_sequence(const BatchJob* a, const BatchJob* b) {
+  if (a->nrec != b->nrec) return false;
+  for (int i = 0; i < a->nrec; ++i)
+    if (a->unit[i].bfunc != b->unit[i].bfunc || a->unit[i].block != b->unit[i].block) return false;
+  return true;
+}
+
+void batcher_main(Batcher* b, int device) {
+  (void)hipSetDevice(device);
+  for (;;) {
+    std::vector<BatchJob*> jobs;
+    {
+      std::unique_lock<std::mutex> lk(b->mu);
+      b->cv_job.wait(lk, [&] { return b->stop || !b->pending.empty(); });
+      if (b->pending.empty() && b->stop) return;
+      b->cv_job.wait_for(lk, kBatchWindow, [&] {
+        return b->stop || (int)b->pending.size() >= std::max(1, std::min(b->expected, b->iterating));
+      });
+      jobs.swap(b->pending);
+    }
+    std::vector<std::vector<BatchJob*>> groups;
+    for (BatchJob* j : jobs) {
+      bool placed = false;
+      for (auto& g : groups)
+        if (same_sequence(g[0], j)) {
+          g.push_back(j);
+          placed = true;
+          break;
+        }
+      if (!placed) groups.push_back({j});
+    }
+    for (auto& g : groups) {
+      const hipError_t e = run_group(b, g);
+      if (e != hipSuccess)
+        for (BatchJob* j : g) j->status = (int)e;
+    }
+    {
+      std::lock_guard<std::mutex> lk(b->mu);
+      b->batches++;
+      b->jobs += (int64_t)jobs.size();
+      for (BatchJob* j : jobs) j->launched = true;
+    }
+    b->cv_launched.notify_all();
+  }
+}
+
+}  // namespace
+
 struct Server {
   Ctx* ctx = nullptr;
   std::mutex mu;
@@ -118,6 +299,7 @@ struct Server {
   int64_t completed = 0;
   std::mutex copy_mu;           // serialises the output copies of wait()
   hipStream_t copy_stream = nullptr;
+  Batcher* batcher = nullptr;   // batched iteration chunks (null: lanes launch their own)
 
   // under mu: the next admissible request with its memory reserved, or null
   Request* pick_locked() {
@@ -197,6 +379,10 @@ void worker_main(Server* S, Lane* L) {
       r->state = RQ_RUNNING;
       r->t_start = Clock::now();
       S->running++;
+      if (S->batcher) {
+        std::lock_guard<std::mutex> bl(S->batcher->mu);
+        S->batcher->expected = std::max(1, S->running);
+      }
     }
     try {
       run_request(S, L, r);
@@ -220,7 +406,12 @@ void worker_main(Server* S, Lane* L) {
       r->state = RQ_DONE;
       S->running--;
       S->completed++;
+      if (S->batcher) {
+        std::lock_guard<std::mutex> bl(S->batcher->mu);
+        S->batcher->expected = std::max(1, S->running);
+      }
     }
+    if (S->batcher) S->batcher->cv_job.notify_one();
     S->cv_done.notify_all();
     S->cv_work.notify_all();
   }
@@ -229,6 +420,7 @@ void worker_main(Server* S, Lane* L) {
 struct ServeConfig {
   int max_active = 0;
   uint64_t pool_bytes = 0;
+  int batched = 0;
 };
 std::mutex g_cfg_mu;
 std::unordered_map<Ctx*, ServeConfig> g_cfg;
@@ -274,6 +466,16 @@ Server* ensure_server(Ctx* c) {
     delete S;
     throw;
   }
+  if (cfg.batched) {
+    Batcher* b = new Batcher();
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      throw Err{SKNR_EDEVICE, "batcher stream creation failed"};
+    }
+    b->th = std::thread(batcher_main, b, c->device);
+    S->batcher = b;
+    for (Lane* L : S->lanes) L->batcher = b;
+  }
   for (Lane* L : S->lanes) S->workers.emplace_back(worker_main, S, L);
   c->server = S;
   return S;
@@ -303,6 +505,24 @@ void server_destroy(Ctx* c) {
   S->cv_work.notify_all();
   S->cv_done.notify_all();
   for (auto& t : S->workers) t.join();
+  if (S->batcher) {
+    Batcher* b = S->batcher;
+    {
+      std::lock_guard<std::mutex> lk(b->mu);
+      b->stop = true;
+    }
+    b->cv_job.notify_all();
+    b->th.join();
+    (void)hipStreamSynchronize(b->stream);
+    for (int k = 0; k < Batcher::kRing; ++k) {
+      if (b->d_tab[k]) (void)hipFree(b->d_tab[k]);
+      if (b->h_tab[k]) (void)hipHostFree(b->h_tab[k]);
+      if (b->tab_ev[k]) (void)hipEventDestroy(b->tab_ev[k]);
+    }
+    (void)hipStreamDestroy(b->stream);
+    delete b;
+    S->batcher = nullptr;
+  }
   for (Lane* L : S->lanes) {
     L->arena.base = nullptr;
     L->arena.cap = 0;
@@ -331,7 +551,20 @@ int sknr_serve_config(void* ctx, int32_t max_active, uint64_t pool_bytes) {
     REQUIRE(max_active >= 0 && max_active <= 64, "max_active must be in [0, 64]");
     REQUIRE(pool_bytes == 0 || pool_bytes >= (1u << 20), "pool_bytes must be 0 or >= 1 MiB");
     std::lock_guard<std::mutex> lk(g_cfg_mu);
-    g_cfg[c] = ServeConfig{max_active, pool_bytes};
+    ServeConfig& cf = g_cfg[c];
+    cf.max_active = max_active;
+    cf.pool_bytes = pool_bytes;
+    return SKNR_OK;
+  });
+}
+
+int sknr_serve_batching(void* ctx, int32_t batched) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    if (c->server) throw Err{SKNR_EBUSY, "serving already started on this context"};
+    REQUIRE(batched == 0 || batched == 1, "batched must be 0 or 1");
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    g_cfg[c].batched = batched;
     return SKNR_OK;
   });
 }
@@ -495,6 +728,12 @@ int sknr_serve_stats(void* ctx, sknr_serve_info* out) {
     out->pool_bytes = S->pool.cap;
     out->pool_used = S->pool.used;
     out->pool_peak = S->pool.peak;
+    if (S->batcher) {
+      std::lock_guard<std::mutex> bl(S->batcher->mu);
+      out->batches = S->batcher->batches;
+      out->batched_jobs = S->batcher->jobs;
+      out->batched_launches = S->batcher->launches;
+    }
     return SKNR_OK;
   });
 }

@@ -59,7 +59,7 @@ def test_serve_alone_equals_mix(sk):
     ctx.close()
 
     ctx = sk.Context(0)
-    sk.serve_config(ctx, max_active=4, pool_bytes=256 << 20)
+    sk.serve_config(ctx, max_active=4, pool_bytes=256 << 20, batched=True)
     tickets = {}
     first, second = reqs[:5], reqs[5:]
     for q in first:
@@ -169,3 +169,64 @@ def test_serve_cancel_and_errors(sk):
     _, _, r3 = sk.wait(ctx, t3, 300, 200)
     assert r3["status"] == sk.OK and r3["marginal_err"] < 1e-6
     ctx.close()
+
+
+def test_batched_execution_equals_lanes_and_solo(sk):
+    """Batched serving (the lanes hand their iteration chunks to one
+    batcher, which launches each kernel once for every request with the
+    same kernel sequence, over a tile table) against per-lane launches and
+    against sknr_solve: the same potentials bit for bit, for a mix of point
+    clouds with d = 2, 3 and 64 (VALU, matrix-core-layout and bf16
+    matrix-core sweeps) arriving together.  The statistics must show
+    batches that carried several requests."""
+    trace = W.serving_trace(n_requests=12, rate=1000.0, seed=23, n_min=64, n_max=1200,
+                            eps_choices=(1e-1, 1e-2))
+    ctx = sk.Context(0)
+    solo = []
+    for q in trace:
+        kw = _kw(q)
+        f, g, res = sk.solve(ctx, _gp(sk, q.problem), kw.pop("eps"), **kw)
+        solo.append((f.cpu().numpy(), g.cpu().numpy(), res))
+    ctx.close()
+    for batched in (True, False):
+        ctx = sk.Context(0)
+        sk.serve_config(ctx, max_active=8, pool_bytes=512 << 20, batched=batched)
+        tickets = []
+        for q in trace:
+            kw = _kw(q)
+            tickets.append(sk.submit(ctx, _gp(sk, q.problem), kw.pop("eps"), **kw))
+        for q, t, (fs, gs, rs) in zip(trace, tickets, solo):
+            f, g, res = sk.wait(ctx, t, q.problem.n, q.problem.m)
+            assert res["status"] == rs["status"]
+            assert [s["iters"] for s in res["stages"]] == [s["iters"] for s in rs["stages"]]
+            assert np.array_equal(f.cpu().numpy(), fs) and np.array_equal(g.cpu().numpy(), gs)
+        st = sk.serve_stats(ctx)
+        print(f"batched={batched} d={[q.problem.d for q in trace]} stats {st}", flush=True)
+        if batched:
+            assert st["batches"] > 0 and st["batched_jobs"] > st["batches"]
+        else:
+            assert st["batches"] == 0
+        ctx.close()
+
+
+def test_served_result_matches_oracle(sk):
+    """A served request against the FP64 oracle's optimum of the same
+    problem (the oracle on the FP32 cost of the served points, eps ladder of
+    the request)."""
+    import oracle as O
+    from tests._helpers import e_pot, fp32_sqeuclid
+    q = [r for r in W.serving_trace(n_requests=40, rate=1000.0, seed=29, n_min=64, n_max=700,
+                                    eps_choices=(1e-2,)) if r.problem.d in (2, 3)][0]
+    ctx = sk.Context(0)
+    sk.serve_config(ctx, max_active=4, pool_bytes=128 << 20)
+    kw = _kw(q)
+    ladder = kw.pop("eps")
+    t = sk.submit(ctx, _gp(sk, q.problem), ladder, **kw)
+    f, g, res = sk.wait(ctx, t, q.problem.n, q.problem.m)
+    ctx.close()
+    C = fp32_sqeuclid(q.problem.x, q.problem.y, q.problem.cost_scale).astype(np.float64)
+    fo, go, _ = O.solve_schedule(C, q.problem.a, q.problem.b, ladder, 1e-11, 1000000)
+    e = e_pot(f.cpu().numpy(), g.cpu().numpy(), fo, go, C)
+    print(f"served {q.problem.name} eps {q.eps}: status {res['status']}, marginal {res['marginal_err']:.2e}, "
+          f"e_pot vs the oracle {e:.2e}", flush=True)
+    assert res["status"] == 0 and res["marginal_err"] < 1e-6 and e <= 1e-5
