@@ -499,7 +499,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sk-steps", type=int, default=3, help="timed plain-SK solves for the comparison")
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--ell", type=int, default=16)
+    ap.add_argument("--ell", type=int, default=30, help="low-frequency modes l (30: the paper's printed value)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -601,8 +601,9 @@ struct Engine {
   void newton(int ell, int gate_base) {
     HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
                               w.st, gate_base, s));
-    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout, w.st,
-                           gate_base, s, nrs));
+    HIPCHK(launch_sum_partials(w.nrpart, w.nr_rows_blk + w.nr_cols_blk, nr_part_len(ell), w.nrsum, s, w.st,
+                               gate_base));
+    HIPCHK(launch_nr_solve(ell, w.nrsum, 1, w.coef32, w.coef64, w.Gout, w.gout, w.st, gate_base, s, nrs));
     HIPCHK(launch_nr_apply(ell, w.F, w.V, w.coef32, P.wX, w.Fp, P.n, w.ap_dot, w.ap_max, w.ap_ddot, w.E1, w.st,
                            gate_base | G_CHOL_OK, s));
   }
@@ -1462,8 +1463,8 @@ int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps, const
     E.sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, 0, 0);
     HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
                               w.st, 0, s));
-    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, w.Gout, w.gout, w.st, 0,
-                           s));
+    HIPCHK(launch_sum_partials(w.nrpart, w.nr_rows_blk + w.nr_cols_blk, nr_part_len(ell), w.nrsum, s));
+    HIPCHK(launch_nr_solve(ell, w.nrsum, 1, w.coef32, w.coef64, w.Gout, w.gout, w.st, 0, s));
     std::vector<double> hG((size_t)ell * ell), hg(ell);
     HIPCHK(hipMemcpyAsync(hG.data(), w.Gout, 8 * hG.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hg.data(), w.gout, 8 * hg.size(), hipMemcpyDeviceToHost, s));
@@ -1537,8 +1538,8 @@ int sknr_newton_coef(void* ctx, const sknr_problem* prob, double eps, const doub
     E.sweep_row(w.Gt, MA_GT, w.F, w.Fsk, w.mdiff, DOT_FSK, MA_FSK, 0, nullptr, nullptr, W_NONE, 0, 0);
     HIPCHK(launch_nr_assemble(ell, w.V, w.mdiff, P.wX, P.n, w.W, P.wY, P.m, w.nrpart, w.nr_rows_blk, w.nr_cols_blk,
                               w.st, 0, s));
-    HIPCHK(launch_nr_solve(ell, w.nrpart, w.nr_rows_blk + w.nr_cols_blk, w.coef32, w.coef64, nullptr, nullptr, w.st,
-                           0, s, E.nrs));
+    HIPCHK(launch_sum_partials(w.nrpart, w.nr_rows_blk + w.nr_cols_blk, nr_part_len(ell), w.nrsum, s));
+    HIPCHK(launch_nr_solve(ell, w.nrsum, 1, w.coef32, w.coef64, nullptr, nullptr, w.st, 0, s, E.nrs));
     std::vector<double> hc(ell);
     HIPCHK(hipMemcpyAsync(hc.data(), w.coef64, 8 * (size_t)ell, hipMemcpyDeviceToHost, s));
     DevState st = E.read_state();

@@ -224,6 +224,36 @@ __device__ __forceinline__ void finalize_output(const SweepArgs& A, const EpsCon
 
 // Per-block scalar partials of a sweep (error, dot, max) for the scalar
 // finishing kernel.
+// value of a double in lane k of the wave (k wave-uniform)
+__device__ __forceinline__ double lane_read_d(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Grid-wide arrival count in st->tail_ctr: true in the workgroup that
+// arrives last of `nblk` (a block-uniform result), whose threads then see
+// every write the other workgroups made before their arrival.  That
+// workgroup resets the count, so it is zero again at the kernel's end (and
+// a state reset writes zero as well).  Every workgroup of the grid must
+// call it once.
+__device__ __forceinline__ bool arrive_last(DevState* st, int nblk) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();  // release this workgroup's writes device-wide
+    const unsigned prev = atomicAdd(&st->tail_ctr, 1u);
+    const int last = prev + 1u == (unsigned)nblk;
+    if (last) atomicExch(&st->tail_ctr, 0u);
+    s_last = last;
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __threadfence();  // acquire the other workgroups' writes
+  return last;
+}
+
 __device__ __forceinline__ void write_block_scalars(const SweepArgs& A, int bid, double err, double dot, float mx) {
   if (threadIdx.x == 0) {
     A.blk_err[bid] = err;

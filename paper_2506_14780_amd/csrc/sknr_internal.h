@@ -37,7 +37,8 @@ struct DevState {
   float2 eps_df;        // eps as double-float
   float2 eln2_df;       // eps*ln2 as double-float
   int nr_iters;         // iterations of the last iterative Newton solve (0 for the direct one)
-  int pad[5];
+  unsigned tail_ctr;    // arrivals of a sweep's tail workgroups (zero between kernels)
+  int pad[4];
 };
 
 // Solver of the l x l Newton system (k_nr_solve): Gauss-Jordan with
@@ -258,6 +259,13 @@ struct NrApplyArgs {
   DevState* st;
   int gate;
 };
+struct SumPartialsArgs {
+  const double* part;
+  int nblk, len;
+  double* out;
+  DevState* st;  // gating (nullable: always runs)
+  int gate;
+};
 struct SelectArgs {
   const float2* Fp;
   const float2* Fsk;
@@ -365,7 +373,14 @@ hipError_t launch_affine(int kp, const float* Z, const double* sv, const double*
                          int n, float* out, hipStream_t s);
 hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, unsigned* zmask, hipStream_t s);
 hipError_t launch_take_cols(const float* V, int kp, int n, int ell, unsigned zero, double* out, hipStream_t s);
-hipError_t launch_sum_partials(const double* part, int nblk, int len, double* out, hipStream_t s);
+hipError_t launch_sum_partials(const double* part, int nblk, int len, double* out, hipStream_t s,
+                               DevState* st = nullptr, int gate = 0);
+// length of the Newton system partials of k_nr_assemble: the upper triangle
+// of G (l (l + 1) / 2 entries) then grad (l), for the padded width l
+inline int nr_part_len(int ell) {
+  const int e = ell <= 8 ? 8 : (ell <= 16 ? 16 : 32);
+  return e * (e + 1) / 2 + e;
+}
 hipError_t launch_repack(const float* V, int kp, int n, int ell, int ellp, float* out, hipStream_t s);
 hipError_t launch_f32_to_f64(const float* src, double* dst, long long count, hipStream_t s);
 hipError_t launch_f64_to_f32(const double* src, float* dst, long long count, hipStream_t s);

@@ -27,9 +27,11 @@ namespace sknr {
 
 thread_local Recorder* g_recorder = nullptr;
 
-// One workgroup: reduce the per-block scalars of a sweep in block order and
+// The last workgroup of a sweep's output kernel (merge, or the row sweep of
+// a stored cost) to finish: reduce the per-block scalars in block order and
 // update the solver state (error, dots, max, convergence and acceptance
-// decisions).  Runs after the sweep, so its writes are visible.
+// decisions).  The arrival count makes the other workgroups' scalars
+// visible to it.
 __device__ __forceinline__ void sweep_finish_body(const SweepArgs& A) {
   if (gate_closed(A.st, A.gate)) return;
   __shared__ double sbd[16];
@@ -93,12 +95,6 @@ __device__ __forceinline__ void sweep_finish_body(const SweepArgs& A) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_sweep_finish(SweepArgs A) { sweep_finish_body(A); }
-__global__ __launch_bounds__(256) void k_sweep_finish_b(BatchTab T) {
-  int bx, by;
-  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
-  sweep_finish_body(*static_cast<const SweepArgs*>(T.args[slot]));
-}
 
 // ============================================================================
 // Streaming sweep: each workgroup owns NC = 64*CPT outputs (lane-contiguous
@@ -397,6 +393,7 @@ __device__ __forceinline__ void sweep_merge_body(const SweepArgs& A, const int b
   dot = block_sum_d(dot, sbd + 8);
   mxo = block_max_f(mxo, sbf);
   write_block_scalars(A, bx, err, dot, mxo);
+  if (arrive_last(A.st, A.nblk)) sweep_finish_body(A);
 }
 
 template <int ELL>
@@ -560,6 +557,7 @@ __global__ __launch_bounds__(TPB) void k_sweep_rows(SweepArgs A) {
   dot = block_sum_d(dot, sbd + 8);
   mxo = block_max_f(mxo, sbf);
   write_block_scalars(A, blockIdx.x, err, dot, mxo);
+  if (arrive_last(A.st, A.nblk)) sweep_finish_body(A);
 }
 
 // ----------------------------------------------------------- launch config
@@ -640,7 +638,6 @@ static hipError_t go_stream(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
                         : (const void*)k_sweep_stream_b<CPT, ELL, COST, D, R, false>,
                   a, grid, TPB, sm);
     record_launch((const void*)k_sweep_merge_b<ELL>, a, dim3((a.n_out + 63) / 64), 256, 0);
-    record_launch((const void*)k_sweep_finish_b, a, dim3(1), 256, 0);
     return hipSuccess;
   }
   if (scale)
@@ -649,7 +646,6 @@ static hipError_t go_stream(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
     hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, false>), grid, dim3(TPB), sm, s, a);
   if (mid) (void)hipEventRecord(mid, s);
   hipLaunchKernelGGL((k_sweep_merge<ELL>), dim3((a.n_out + 63) / 64), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_sweep_finish, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -680,14 +676,12 @@ hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t s) {
                   : a.ell <= 16 ? (const void*)k_sweep_merge_b<16>
                                 : (const void*)k_sweep_merge_b<32>,
                   a, grid, 256, 0);
-    record_launch((const void*)k_sweep_finish_b, a, dim3(1), 256, 0);
     return hipSuccess;
   }
   if (a.ell == 0) hipLaunchKernelGGL((k_sweep_merge<0>), grid, dim3(256), 0, s, a);
   else if (a.ell <= 8) hipLaunchKernelGGL((k_sweep_merge<8>), grid, dim3(256), 0, s, a);
   else if (a.ell <= 16) hipLaunchKernelGGL((k_sweep_merge<16>), grid, dim3(256), 0, s, a);
   else hipLaunchKernelGGL((k_sweep_merge<32>), grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_sweep_finish, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -731,7 +725,6 @@ hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t s, hipEvent_t mid) 
     }
   }
   if (mid) (void)hipEventRecord(mid, s);
-  hipLaunchKernelGGL(k_sweep_finish, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -882,13 +875,26 @@ __device__ __forceinline__ void nr_assemble_body(const NrAssembleArgs& q, const 
   double* part = q.part;
   const int nrow_blk = q.nrow_blk, rows_per_blk = q.rows_per_blk;
   if (gate_closed(q.st, q.gate)) return;
-  constexpr int NE = ELL * ELL;
-  constexpr int PER = (NE + 255) / 256;
+  // G is symmetric: only the upper triangle (k <= l) is summed, TRI entries
+  // in row-major order of the triangle
+  constexpr int TRI = ELL * (ELL + 1) / 2;
+  constexpr int PER = (TRI + 255) / 256;
   __shared__ float tile[64][ELL];
   __shared__ double wrow[64];
+  __shared__ double mrow[64];
   double accv[PER];
+  int ek[PER], el[PER];
 #pragma unroll
-  for (int p = 0; p < PER; ++p) accv[p] = 0;
+  for (int p = 0; p < PER; ++p) {
+    accv[p] = 0;
+    int e = threadIdx.x + 256 * p, k = 0;
+    while (k < ELL - 1 && e >= ELL - k) {  // row k of the triangle holds ELL - k entries
+      e -= ELL - k;
+      ++k;
+    }
+    ek[p] = k;
+    el[p] = k + e;
+  }
   double gacc = 0;
   const bool rows = (int)bx < nrow_blk;
   const int blk = rows ? bx : bx - nrow_blk;
@@ -907,30 +913,31 @@ __device__ __forceinline__ void nr_assemble_body(const NrAssembleArgs& q, const 
     if (threadIdx.x < 64) {
       int rr = threadIdx.x;
       double wv = 0;
-      if (rr < nt) wv = rows ? (a[t0 + rr] + (double)mdiff[t0 + rr]) : -1.0 / b[t0 + rr];
+      double md = 0;
+      if (rr < nt && rows) md = (double)mdiff[t0 + rr];
+      if (rr < nt) wv = rows ? (a[t0 + rr] + md) : -1.0 / b[t0 + rr];
       wrow[rr] = wv;
+      mrow[rr] = md;
     }
     __syncthreads();
-    for (int rr = 0; rr < nt; ++rr) {
+    // all 64 rows of the tile: rows past nt are zero and add exact zeros
+#pragma unroll 8
+    for (int rr = 0; rr < 64; ++rr) {
       double wv = wrow[rr];
 #pragma unroll
       for (int p = 0; p < PER; ++p) {
-        int e = threadIdx.x + 256 * p;
-        if (e < NE) {
-          int k = e / ELL, l = e % ELL;
-          accv[p] += wv * (double)tile[rr][k] * (double)tile[rr][l];
-        }
+        if ((int)threadIdx.x + 256 * p < TRI) accv[p] += wv * (double)tile[rr][ek[p]] * (double)tile[rr][el[p]];
       }
-      if (rows && (int)threadIdx.x < ELL) gacc -= (double)tile[rr][threadIdx.x] * (double)mdiff[t0 + rr];
+      if (rows && (int)threadIdx.x < ELL) gacc -= (double)tile[rr][threadIdx.x] * mrow[rr];
     }
   }
-  double* out = part + (size_t)bx * (NE + ELL);
+  double* out = part + (size_t)bx * (TRI + ELL);
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    int e = threadIdx.x + 256 * p;
-    if (e < NE) out[e] = accv[p];
+    const int e = threadIdx.x + 256 * p;
+    if (e < TRI) out[e] = accv[p];
   }
-  if ((int)threadIdx.x < ELL) out[NE + threadIdx.x] = gacc;
+  if ((int)threadIdx.x < ELL) out[TRI + threadIdx.x] = gacc;
 }
 
 template <int ELL>
@@ -962,9 +969,9 @@ __device__ __forceinline__ double sum_partials(const double* part, int nblk, int
 // below FP32 resolution (large eps).  Their coefficients are zero and the
 // step is the Newton step on the span of the other columns; the modes they
 // miss have rho_k^2 ~ 0, which SK already removes.  [G | grad] is then
-// reduced by Gauss-Jordan elimination without pivoting, one barrier per
-// column: step k updates the entries (i, j), i != k, j > k, and reads only
-// column k and row k, which it does not write.  Its pivots are those of
+// reduced by Gauss-Jordan elimination without pivoting in one wave (a row
+// per lane): step k updates the entries (i, j), i != k, j > k, from column
+// k and row k, which it does not write.  Its pivots are those of
 // G = L D L^T, so the positive-definiteness test (every pivot > 1e-15 of
 // the largest diagonal entry) is the one of a Cholesky factorisation.
 //
@@ -1128,16 +1135,31 @@ __device__ __forceinline__ void nr_solve_body(const NrSolveArgs& q) {
   const double rtol = q.rtol;
   if (gate_closed(st, q.gate)) return;
   constexpr int NE = ELL * ELL;
+  constexpr int TRI = ELL * (ELL + 1) / 2;
   constexpr int NA = ELL + 1;  // augmented width
   const int tid = threadIdx.x;
   const double eps = st->eps;
-  __shared__ double R[NE + ELL];   // raw sums: G row-major, then grad
+  __shared__ double R[NE + ELL];   // sums: G row-major (both triangles), then grad
   __shared__ double A[ELL][NA + 1];
-  for (int e = tid; e < NE + ELL; e += 256) {
+  // the partials hold the upper triangle of G then grad: sum them (block
+  // order) and mirror the triangle
+  for (int e = tid; e < TRI + ELL; e += 256) {
     double v = 0;
-    for (int b0 = 0; b0 < nblk; b0 += 32)
-      v += sum_partials(part + (size_t)b0 * (NE + ELL), min(32, nblk - b0), NE + ELL, e);
-    R[e] = v;
+    if (nblk == 1) v = part[e];  // summed beforehand
+    else
+      for (int b0 = 0; b0 < nblk; b0 += 32)
+        v += sum_partials(part + (size_t)b0 * (TRI + ELL), min(32, nblk - b0), TRI + ELL, e);
+    if (e >= TRI) {
+      R[NE + (e - TRI)] = v;
+    } else {
+      int k = 0, r = e;
+      while (k < ELL - 1 && r >= ELL - k) {
+        r -= ELL - k;
+        ++k;
+      }
+      R[k * ELL + k + r] = v;
+      R[(k + r) * ELL + k] = v;
+    }
   }
   __syncthreads();
   double dmax = 0;
@@ -1188,27 +1210,35 @@ __device__ __forceinline__ void nr_solve_body(const NrSolveArgs& q) {
     }
     return;
   }
+  // Gauss-Jordan in one wave: lane i < ELL holds row i of [A | grad] in
+  // registers (the steps are unrolled, so every index is a constant) and
+  // step k reads the pivot row from lane k.  Row i's diagonal is final once
+  // step i has used it as the pivot.
+  if (tid >= 64) return;
+  const int lane = tid;
+  const int row = lane < ELL ? lane : ELL - 1;
+  double x[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) x[j] = A[row][j];
   int ok = 1;
+  double dg = 1.0;
+#pragma unroll
   for (int k = 0; k < ELL; ++k) {
-    double piv = A[k][k];
+    double piv = lane_read_d(x[k], k);
     if (!(piv > 1e-300 && piv > 1e-15 * dmax)) {
       ok = 0;
       piv = 1.0;
     }
-    const double inv = 1.0 / piv;
-    const int w = NA - (k + 1);  // columns k+1 .. ELL (the last is grad)
-    for (int e = tid; e < ELL * w; e += 256) {
-      const int i = e / w, j = k + 1 + (e - i * w);
-      if (i != k) A[i][j] -= A[i][k] * (A[k][j] * inv);
-    }
-    __syncthreads();
+    if (row == k) dg = piv;
+    // row i subtracts (A_ik / A_kk) times row k; row k keeps its entries
+    // (a zero multiplier; a non-finite pivot row fails the test below)
+    const double mk = row == k ? 0.0 : x[k] * (1.0 / piv);
+#pragma unroll
+    for (int j = k + 1; j < NA; ++j) x[j] = fma(-mk, lane_read_d(x[j], k), x[j]);
   }
   // the system is now diagonal: z_i = A[i][ELL] / A[i][i]
-  if (tid < 64) {
-    const int i = tid < ELL ? tid : ELL - 1;
-    double di = A[i][i];
-    if (!(di > 1e-300 && di > 1e-15 * dmax)) di = 1.0;
-    const double c = eps * (A[i][ELL] / di);
+  {
+    const double c = eps * (x[ELL] / dg);
     const int bad = (tid < ELL) && !(fabs(c) < 1e30);
     const int anybad = __any(bad);
     ok = ok && !anybad;

@@ -9,6 +9,7 @@
 // constant mode projected out, cyclic Jacobi for the Rayleigh-Ritz step,
 // and the block rotations.
 #include "sknr_internal.h"
+#include "sknr_device.h"
 
 #include <math.h>
 
@@ -35,18 +36,32 @@ __device__ __forceinline__ double sum_parts(const double* part, int nblk, int st
 }
 
 // out[e] = sum over blocks (in block order) of part[b * len + e]
-__global__ __launch_bounds__(256) void k_sum_partials(const double* part, int nblk, int len, double* out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= len) return;
+__device__ __forceinline__ void sum_partials_body(const SumPartialsArgs& q, const int bx) {
+  if (q.st && gate_closed(q.st, q.gate)) return;
+  const int e = bx * blockDim.x + threadIdx.x;
+  if (e >= q.len) return;
   double s = 0;
-  for (int b0 = 0; b0 < nblk; b0 += 32) {
-    const int nb = min(32, nblk - b0);
-    s += sum_parts(part + (size_t)b0 * len, nb, len, e);
+  for (int b0 = 0; b0 < q.nblk; b0 += 32) {
+    const int nb = min(32, q.nblk - b0);
+    s += sum_parts(q.part + (size_t)b0 * q.len, nb, q.len, e);
   }
-  out[e] = s;
+  q.out[e] = s;
 }
-hipError_t launch_sum_partials(const double* part, int nblk, int len, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3((len + 255) / 256), dim3(256), 0, s, part, nblk, len, out);
+__global__ __launch_bounds__(256) void k_sum_partials(SumPartialsArgs q) { sum_partials_body(q, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_sum_partials_b(BatchTab T) {
+  int bx, by;
+  const int slot = batch_slot(T, blockIdx.x, &bx, &by);
+  sum_partials_body(*static_cast<const SumPartialsArgs*>(T.args[slot]), bx);
+}
+hipError_t launch_sum_partials(const double* part, int nblk, int len, double* out, hipStream_t s, DevState* st,
+                               int gate) {
+  const SumPartialsArgs q{part, nblk, len, out, st, gate};
+  const dim3 grid((len + 255) / 256);
+  if (g_recorder) {
+    record_launch((const void*)k_sum_partials_b, q, grid, 256, 0);
+    return hipSuccess;
+  }
+  hipLaunchKernelGGL(k_sum_partials, grid, dim3(256), 0, s, q);
   return hipGetLastError();
 }
 
@@ -95,7 +110,9 @@ __global__ __launch_bounds__(256) void k_wgram(float* Z, const double* wgt, int 
       wrow[rr] = w;
     }
     __syncthreads();
-    for (int rr = 0; rr < nt; ++rr) {
+    // all 64 rows of the tile: rows past nt are zero and add exact zeros
+#pragma unroll 8
+    for (int rr = 0; rr < 64; ++rr) {
       double w = wrow[rr];
 #pragma unroll
       for (int p = 0; p < PER; ++p) {
@@ -372,32 +389,43 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
   }
 }
 
-// out_i = ((Z_i - s) R) * rowscale_i   (k x k transform per row, FP64 math)
+// out_i = ((Z_i - s) R) * rowscale_i   (k x k transform per row, FP64 math).
+// KP/4 threads per row, each producing four adjacent outputs (one 16-byte
+// store; a row's threads write its KP floats contiguously); every thread
+// reads the whole row (L1 hits after the first) and sums over l in order.
 template <int KP>
-__global__ __launch_bounds__(64) void k_affine(const float* Z, const double* s, const double* R, const double* rs,
+__global__ __launch_bounds__(256) void k_affine(const float* Z, const double* s, const double* R, const double* rs,
                                                 int rs_invert, int n, float* out) {
+  constexpr int TPR = KP / 4;  // threads per row
   __shared__ double Rs[KP][KP];
   __shared__ double ss[KP];
   for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) Rs[e / KP][e % KP] = R[e];
   if ((int)threadIdx.x < KP) ss[threadIdx.x] = s ? s[threadIdx.x] : 0.0;
   __syncthreads();
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gt / TPR, j0 = 4 * (gt % TPR);
   if (i >= n) return;
-  double z[KP];
+  const float4* zr = reinterpret_cast<const float4*>(Z + (size_t)i * KP);
+  float zf[KP];
 #pragma unroll
-  for (int l = 0; l < KP; ++l) z[l] = (double)Z[(size_t)i * KP + l] - ss[l];
+  for (int q = 0; q < KP / 4; ++q) {
+    const float4 v = zr[q];
+    zf[4 * q] = v.x;
+    zf[4 * q + 1] = v.y;
+    zf[4 * q + 2] = v.z;
+    zf[4 * q + 3] = v.w;
+  }
   double sc = 1.0;
   if (rs) sc = rs_invert ? 1.0 / rs[i] : rs[i];
-  float o[KP];
+  double v[4] = {0, 0, 0, 0};
 #pragma unroll
-  for (int j = 0; j < KP; ++j) {
-    double v = 0;
+  for (int l = 0; l < KP; ++l) {
+    const double z = (double)zf[l] - ss[l];
 #pragma unroll
-    for (int l = 0; l < KP; ++l) v += z[l] * Rs[l][j];
-    o[j] = (float)(v * sc);
+    for (int c = 0; c < 4; ++c) v[c] += z * Rs[l][j0 + c];
   }
-#pragma unroll
-  for (int j = 0; j < KP; ++j) out[(size_t)i * KP + j] = o[j];
+  *reinterpret_cast<float4*>(out + (size_t)i * KP + j0) =
+      make_float4((float)(v[0] * sc), (float)(v[1] * sc), (float)(v[2] * sc), (float)(v[3] * sc));
 }
 
 // counter-based uniform(-1, 1) start block for columns >= col0; clears the
@@ -468,10 +496,14 @@ hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double
 }
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
                          int n, float* out, hipStream_t s) {
-  int nb = (n + 63) / 64;
-  if (kp == 8) hipLaunchKernelGGL((k_affine<8>), dim3(nb), dim3(64), 0, s, Z, sv, R, rs, rs_invert, n, out);
-  else if (kp == 16) hipLaunchKernelGGL((k_affine<16>), dim3(nb), dim3(64), 0, s, Z, sv, R, rs, rs_invert, n, out);
-  else hipLaunchKernelGGL((k_affine<32>), dim3(nb), dim3(64), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  // rows of kp floats: 16-byte aligned (kp a multiple of 4, buffers from
+  // 256-byte aligned carving)
+  if (((uintptr_t)Z | (uintptr_t)out) & 15) return hipErrorInvalidValue;
+  const long long thr = (long long)n * (kp / 4);
+  const dim3 grid((unsigned)((thr + 255) / 256));
+  if (kp == 8) hipLaunchKernelGGL((k_affine<8>), grid, dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  else if (kp == 16) hipLaunchKernelGGL((k_affine<16>), grid, dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
+  else hipLaunchKernelGGL((k_affine<32>), grid, dim3(256), 0, s, Z, sv, R, rs, rs_invert, n, out);
   return hipGetLastError();
 }
 hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, unsigned* zmask, hipStream_t s) {
