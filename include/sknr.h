@@ -97,7 +97,12 @@ typedef struct sknr_problem {
   int32_t d;            /* point dimension (SQEUCLID only, 1 <= d <= 1024) */
   int32_t kind;         /* enum sknr_cost_kind */
   int32_t xterm;        /* enum sknr_xterm (SQEUCLID only) */
-  int32_t reserved0;
+  int32_t on_host;      /* 0: C, x, y, a, b below are device pointers.  1: they
+                           are host pointers; the call first copies them into a
+                           staging block of device memory that the context
+                           holds (and regrows) until sknr_ctx_destroy, so the
+                           transfer over the host link is part of the call.
+                           Not accepted by sknr_solve_noalloc. */
   const float* C;       /* [device] STORED: n x m FP32, row stride ldc */
   int64_t ldc;          /* STORED: row stride in elements (>= m) */
   const float* x;       /* [device] SQEUCLID: n x d FP32 */
@@ -129,8 +134,12 @@ typedef struct sknr_opts {
                              eig_tol * (1 - rho_i^2) (0 -> 0.1) */
   int32_t check_every;    /* iterations per host convergence poll (0 -> auto) */
   int32_t first_stage_nr; /* 1: SK-NR also on stage 0 (WARM_USER or WARM_STATIC) */
-  const double* f0;       /* [device] optional n FP64 initial f at eps[0] (NULL -> 0) */
-  const double* V0;       /* [device] optional n x ell FP64 basis (WARM_USER) */
+  const double* f0;       /* [device] optional n FP64 initial f at eps[0] (NULL -> 0;
+                             see g0 for how the two combine) */
+  const double* V0;       /* [device] WARM_USER: FP64 basis of l columns on the
+                             semi-dual side (the smaller of n and m, Sec. 2):
+                             n x ell when n <= m, m x ell (a basis for g)
+                             otherwise; sknr_get_subspace returns one */
   uint64_t seed;          /* seed of the subspace-iteration start block */
   void* stream;           /* hipStream_t */
   int32_t nr_switch_iters;/* WARM_SEQUENTIAL only.  0: every stage after the
@@ -159,6 +168,14 @@ typedef struct sknr_opts {
                              value past the basis (rho_l when l = 32).  On a
                              spectrum that is flat past l (many near-degenerate
                              modes) the Newton steps cost more than they save. */
+  const double* g0;       /* [device] optional m FP64 initial g at eps[0].  The
+                             iteration runs on the potential of the semi-dual
+                             side (f when n <= m, g otherwise).  If that side's
+                             initial potential is given it is used and the other
+                             one is ignored; if only the other side's is given,
+                             the solve starts from its c-transform (eq. foc_f,
+                             or foc_g for n > m), half an SK step; with neither,
+                             from 0. */
 } sknr_opts;
 
 /* Solvers of the projected Newton system G c = eps grad (Algorithm 4.1, NR
@@ -331,6 +348,20 @@ int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps,
                         int32_t max_iter, double tol, uint64_t seed,
                         double* V_out, double* rho_out, int32_t* iters_out,
                         void* stream);
+
+/* The basis V_l that the last sknr_solve on this context held at its end:
+ * that of its last stage that ran SK-NR steps or a warm start (sequential
+ * or static warm start: Ritz vectors of M, orthonormal in L2(alpha) and
+ * orthogonal to the constants, Sec. 4; WARM_USER: opts.V0 rounded to FP32).
+ * It lives on the semi-dual side: rows = min(n, m) of that solve (the x
+ * side when n <= m, else the y side), columns = its ell.  V_out [device]
+ * rows x ell FP64, row-major; side_out [host] (nullable) gets 0 for the x
+ * side, 1 for the y side.  The basis can be passed back as opts.V0 with
+ * WARM_USER (Algorithm 4.1 takes V_l as an input; Sec. 4 reuses one basis
+ * across eps).  EINVAL when that solve ran no SK-NR stage, when rows / ell
+ * do not match, or when another call has used the context since (the
+ * basis lives in the context's workspace, which the next call reuses). */
+int sknr_get_subspace(void* ctx, double* V_out, int64_t rows, int32_t ell, int32_t* side_out, void* stream);
 
 typedef struct sknr_eval {
   double row_err, col_err, marginal_err;   /* L1 marginal errors */

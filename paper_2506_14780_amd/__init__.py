@@ -48,7 +48,7 @@ _i64 = ctypes.c_int64
 
 class _Problem(ctypes.Structure):
     _fields_ = [("n", _i64), ("m", _i64), ("d", _i32), ("kind", _i32), ("xterm", _i32),
-                ("reserved0", _i32), ("C", _p), ("ldc", _i64), ("x", _p), ("y", _p),
+                ("on_host", _i32), ("C", _p), ("ldc", _i64), ("x", _p), ("y", _p),
                 ("cost_scale", _d), ("a", _p), ("b", _p)]
 
 
@@ -58,7 +58,7 @@ class _Opts(ctypes.Structure):
                 ("eig_max_iter", _i32), ("eig_tol", _d), ("check_every", _i32),
                 ("first_stage_nr", _i32), ("f0", _p), ("V0", _p), ("seed", ctypes.c_uint64),
                 ("stream", _p), ("nr_switch_iters", _i32), ("newton_solver", _i32),
-                ("newton_max_iter", _i32), ("newton_rtol", _d), ("nr_min_gain", _d)]
+                ("newton_max_iter", _i32), ("newton_rtol", _d), ("nr_min_gain", _d), ("g0", _p)]
 
 
 class _Stage(ctypes.Structure):
@@ -116,6 +116,7 @@ _sig("sknr_newton_step", [_p, _P(_Problem), _d, _p, _p, _i32, _P(_i32), _P(_d), 
 _sig("sknr_newton_coef", [_p, _P(_Problem), _d, _p, _p, _i32, _i32, _i32, _d, _P(_d), _P(_i32), _P(_i32), _p])
 _sig("sknr_spectral_basis", [_p, _P(_Problem), _d, _p, _i32, _i32, _i32, _d, ctypes.c_uint64, _p,
                              _P(_d), _P(_i32), _p])
+_sig("sknr_get_subspace", [_p, _p, _i64, _i32, _P(_i32), _p])
 _sig("sknr_evaluate", [_p, _P(_Problem), _d, _p, _p, _P(_Eval), _p])
 _sig("sknr_coupling", [_p, _P(_Problem), _d, _p, _p, _p, _p])
 _sig("sknr_gradient", [_p, _P(_Problem), _d, _p, _p, _p, _p, _p, _p, _p])
@@ -144,7 +145,21 @@ def _check(st: int, where: str, allow_not_converged: bool = True) -> int:
 
 
 def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    """Address of a torch tensor's data, or of a numpy array's (host)."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(t.ctypes.data)
+
+
+def _on_host(t) -> bool:
+    """numpy arrays and CPU tensors are host memory."""
+    if t is None:
+        return False
+    if hasattr(t, "is_cuda"):  # torch tensor
+        return not t.is_cuda
+    return True
 
 
 def _stream(stream):
@@ -199,8 +214,10 @@ class Context:
 
 @dataclasses.dataclass
 class Problem:
-    """Device-resident problem: a, b float64 tensors; either C (n x m
-    float32, row stride ldc) or x (n x d), y (m x d) float32 tensors."""
+    """Problem arrays: a, b float64; either C (n x m float32, row stride
+    ldc) or x (n x d), y (m x d) float32.  Device tensors, or host arrays
+    (numpy, CPU tensors; contiguous rows) that each call copies to the
+    device."""
 
     a: object
     b: object
@@ -211,8 +228,19 @@ class Problem:
     xterm: int = XTERM_AUTO
     ldc: int | None = None
 
+    def on_host(self) -> bool:
+        """True for host arrays (numpy or CPU tensors): sknr_problem.on_host,
+        the call copies them to the device first.  All arrays of a problem
+        live on the same side."""
+        arrs = [t for t in (self.a, self.b, self.C, self.x, self.y) if t is not None]
+        side = {_on_host(t) for t in arrs}
+        if len(side) != 1:
+            raise ValueError("problem arrays must all be on the host or all on the device")
+        return side.pop()
+
     def c_struct(self) -> _Problem:
         p = _Problem()
+        p.on_host = 1 if self.on_host() else 0
         p.n = int(self.a.shape[0])
         p.m = int(self.b.shape[0])
         p.a = _ptr(self.a)
@@ -221,7 +249,12 @@ class Problem:
         if self.C is not None:
             p.kind = COST_STORED
             p.C = _ptr(self.C)
-            p.ldc = self.ldc if self.ldc is not None else int(self.C.stride(0))
+            if self.ldc is not None:
+                p.ldc = self.ldc
+            elif hasattr(self.C, "stride") and callable(self.C.stride):
+                p.ldc = int(self.C.stride(0))
+            else:  # numpy: strides in bytes
+                p.ldc = int(self.C.strides[0] // self.C.itemsize)
             p.d = 0
         else:
             p.kind = COST_SQEUCLID
@@ -234,7 +267,7 @@ class Problem:
 
 def _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr, eig_oversample,
           eig_max_iter, eig_tol, seed, stream, nr_switch_iters=0, newton_solver=0, newton_max_iter=0,
-          newton_rtol=0.0, nr_min_gain=0.0):
+          newton_rtol=0.0, nr_min_gain=0.0, g0=None):
     earr = (_d * len(eps))(*eps)
     o = _Opts()
     o.eps = ctypes.cast(earr, _P(_d))
@@ -258,6 +291,7 @@ def _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, fi
     o.newton_max_iter = int(newton_max_iter)
     o.newton_rtol = float(newton_rtol)
     o.nr_min_gain = float(nr_min_gain)
+    o.g0 = _ptr(g0)
     return o, earr  # earr must outlive the call
 
 
@@ -271,18 +305,21 @@ def solve(ctx: Context, prob: Problem, eps, tol: float = 1e-6, max_iter: int = 1
           warm_mode: int = WARM_USER, V0=None, f0=None, eps_prime: float = 0.0, check_every: int = 0,
           first_stage_nr: bool = False, eig_oversample: int = 0, eig_max_iter: int = 0,
           eig_tol: float = 0.0, seed: int = 0, stream=None, f_out=None, g_out=None, nr_switch_iters: int = 0,
-          newton_solver: int = 0, newton_max_iter: int = 0, newton_rtol: float = 0.0, nr_min_gain: float = 0.0):
+          newton_solver: int = 0, newton_max_iter: int = 0, newton_rtol: float = 0.0, nr_min_gain: float = 0.0,
+          g0=None):
     """sknr_solve.  Returns (f, g, result dict); f, g are float64 device
-    tensors in the caller's orientation."""
+    tensors in the caller's orientation.  The problem may hold host arrays
+    (numpy or CPU tensors: copied to the device by the call); f0, g0, V0
+    and the outputs are device tensors."""
     import torch
     eps = [float(e) for e in (eps if hasattr(eps, "__len__") else [eps])]
-    dev = prob.a.device
+    dev = torch.device("cuda", ctx.device) if prob.on_host() else prob.a.device
     n, m = int(prob.a.shape[0]), int(prob.b.shape[0])
     f = f_out if f_out is not None else torch.empty(n, dtype=torch.float64, device=dev)
     g = g_out if g_out is not None else torch.empty(m, dtype=torch.float64, device=dev)
     o, earr = _opts(eps, tol, max_iter, ell, warm_mode, V0, f0, eps_prime, check_every, first_stage_nr,
                     eig_oversample, eig_max_iter, eig_tol, seed, stream, nr_switch_iters, newton_solver,
-                    newton_max_iter, newton_rtol, nr_min_gain)
+                    newton_max_iter, newton_rtol, nr_min_gain, g0)
     r = _Result()
     ps = prob.c_struct()
     st = lib.sknr_solve(ctx.handle, ctypes.byref(ps), ctypes.byref(o), _ptr(f), _ptr(g), ctypes.byref(r))
@@ -444,6 +481,18 @@ def spectral_basis(ctx, prob: Problem, eps: float, f, ell: int, oversample: int 
     _check(lib.sknr_spectral_basis(ctx.handle, ctypes.byref(ps), eps, _ptr(f), ell, oversample, max_iter, tol,
                                    seed, _ptr(V), rho, ctypes.byref(it), _stream(stream)), "sknr_spectral_basis")
     return V, np.array(rho[:]), it.value
+
+
+def get_subspace(ctx, rows: int, ell: int, stream=None):
+    """sknr_get_subspace: the basis V_l of the last solve on ctx (rows =
+    min(n, m) of that solve).  Returns (V [rows x ell float64 device],
+    side: 0 = x side, 1 = y side)."""
+    import torch
+    V = torch.empty((rows, ell), dtype=torch.float64, device=torch.device("cuda", ctx.device))
+    side = _i32()
+    _check(lib.sknr_get_subspace(ctx.handle, _ptr(V), rows, ell, ctypes.byref(side), _stream(stream)),
+           "sknr_get_subspace")
+    return V, side.value
 
 
 def evaluate(ctx, prob: Problem, eps: float, f, g, stream=None) -> dict:

@@ -108,6 +108,7 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s, float* dmax_dev) {
   REQUIRE(pr->n <= (1 << 26) && pr->m <= (1 << 26), "n, m too large");
   REQUIRE(pr->kind == SKNR_COST_STORED || pr->kind == SKNR_COST_SQEUCLID, "unknown cost kind");
   REQUIRE(pr->a && pr->b, "weights a, b are required");
+  REQUIRE(!pr->on_host, "host-resident inputs (on_host) are not accepted by this entry point");
   Prepared P;
   P.n0 = (int)pr->n;
   P.m0 = (int)pr->m;
@@ -277,6 +278,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
 }
 
 WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
+  ++c->ws_gen;
   size_t need = ws_bytes(P, ellp, nullptr);
   if (need > c->arena.cap) {
     if (c->arena_external) throw Err{SKNR_EINTERNAL, "workspace exceeds the reserved block"};
@@ -596,6 +598,19 @@ struct Engine {
   void load_g(const double* g, float2* dst, int ma, int dot) {
     HIPCHK(launch_to_hat(g, w.lY64, eps, dst, P.m, w.st, ma, P.wY, dot, w.scratch, s));
   }
+  // initial potentials at the current eps (engine orientation): f0 when
+  // given; else, from g0, f = T_r(g0) (eq. foc_f) with g0 kept as the
+  // previous g; else zero
+  void start(const double* f0, const double* g0) {
+    if (f0 || !g0) {
+      load_f(f0);
+      load_g(nullptr, w.G[0], MA_G, DOT_G);
+      return;
+    }
+    load_g(g0, w.G[0], MA_G, DOT_G);
+    sweep_row(w.G[0], MA_G, nullptr, w.F, nullptr, DOT_F, MA_F, 0, nullptr, nullptr, W_NONE, 0, 0);
+  }
+  bool have_basis = false;  // w.V holds the basis of an SK-NR stage
 
   // ---- Newton pieces for one iteration (after Gt, Fsk, mdiff, W exist)
   void newton(int ell, int gate_base) {
@@ -1053,11 +1068,13 @@ struct Engine {
   }
   // Newton basis from the warm-start block: first ell columns, padded
   void use_warm_V(int ell, int oversample) {
+    have_basis = true;
     HIPCHK(launch_repack(w.Vw, spectral_kp(ell, oversample), P.n, ell, w.ellp, w.V, s));
   }
 
   // V (engine orientation, n x ell FP64 device) -> padded FP32 V
   void load_V(const double* V, int ell) {
+    have_basis = true;
     std::vector<double> hv((size_t)P.n * ell);
     HIPCHK(hipMemcpyAsync(hv.data(), V, 8 * hv.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1068,6 +1085,64 @@ struct Engine {
     HIPCHK(hipStreamSynchronize(s));
   }
 };
+
+const sknr_problem* stage_problem(Ctx* c, const sknr_problem* pr, hipStream_t s, sknr_problem* tmp) {
+  if (!pr || !pr->on_host) return pr;
+  REQUIRE(pr->a && pr->b, "weights a, b are required");
+  REQUIRE(pr->n >= 1 && pr->m >= 1 && pr->n <= (1 << 26) && pr->m <= (1 << 26), "n, m out of range");
+  const bool stored = pr->kind == SKNR_COST_STORED;
+  REQUIRE(stored || pr->kind == SKNR_COST_SQEUCLID, "unknown cost kind");
+  const size_t n = (size_t)pr->n, m = (size_t)pr->m;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t bytes = al(8 * n) + al(8 * m);
+  if (stored) {
+    REQUIRE(pr->C && pr->ldc >= pr->m, "stored cost C is NULL or ldc < m");
+    bytes += al(4 * n * m);
+  } else {
+    REQUIRE(pr->x && pr->y && pr->d >= 1 && pr->d <= 1024, "points x, y and 1 <= d <= 1024 are required");
+    bytes += al(4 * n * (size_t)pr->d) + al(4 * m * (size_t)pr->d);
+  }
+  if (bytes > c->stage_cap) {
+    HIPCHK(hipStreamSynchronize(s));
+    if (c->stage) HIPCHK(hipFree(c->stage));
+    c->stage = nullptr;
+    c->stage_cap = 0;
+    if (hipMalloc((void**)&c->stage, bytes) != hipSuccess) {
+      c->stage = nullptr;
+      throw Err{SKNR_ENOMEM, "device allocation of the input staging block failed"};
+    }
+    c->stage_cap = bytes;
+  }
+  *tmp = *pr;
+  tmp->on_host = 0;
+  char* q = c->stage;
+  auto take = [&](size_t b) {
+    char* r = q;
+    q += al(b);
+    return r;
+  };
+  double* da = (double*)take(8 * n);
+  double* db = (double*)take(8 * m);
+  HIPCHK(hipMemcpyAsync(da, pr->a, 8 * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(db, pr->b, 8 * m, hipMemcpyHostToDevice, s));
+  tmp->a = da;
+  tmp->b = db;
+  if (stored) {
+    float* dC = (float*)take(4 * n * m);
+    HIPCHK(hipMemcpy2DAsync(dC, 4 * m, pr->C, 4 * (size_t)pr->ldc, 4 * m, n, hipMemcpyHostToDevice, s));
+    tmp->C = dC;
+    tmp->ldc = (int64_t)m;
+  } else {
+    const size_t d = (size_t)pr->d;
+    float* dx = (float*)take(4 * n * d);
+    float* dy = (float*)take(4 * m * d);
+    HIPCHK(hipMemcpyAsync(dx, pr->x, 4 * n * d, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dy, pr->y, 4 * m * d, hipMemcpyHostToDevice, s));
+    tmp->x = dx;
+    tmp->y = dy;
+  }
+  return tmp;
+}
 
 Prepared prepare_caller_orientation(const sknr_problem* prob, hipStream_t s) {
   Prepared P = prepare(prob, s);
@@ -1115,12 +1190,16 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
   E.nrs = nr_solver_of(opts->newton_solver, opts->newton_max_iter, opts->newton_rtol, opts->ell);
   E.fused = E.fused_eligible();
   int static_eig_iters = 0;
+  // initial potentials: the iteration runs on the engine's f (the semi-dual
+  // side); the caller's f0 / g0 swap roles on a transposed problem
+  const double* ef0 = P.transposed ? opts->g0 : opts->f0;
+  const double* eg0 = P.transposed ? opts->f0 : opts->g0;
+  L->sub = Lane::Subspace{};
   if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_STATIC) {
     // plain SK at eps' from the initial potential, then V_l once
     E.eps = opts->eps_prime;
     E.init_state();
-    E.load_f(opts->f0);
-    E.load_g(nullptr, w.G[0], MA_G, DOT_G);
+    E.start(ef0, eg0);
     bool cv;
     int tr, ac;
     E.run_stage(0, opts->max_iter, opts->check_every, false, &cv, &tr, &ac);
@@ -1129,8 +1208,7 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
   }
   E.eps = opts->eps[0];
   E.init_state();
-  E.load_f(opts->f0);
-  E.load_g(nullptr, w.G[0], MA_G, DOT_G);
+  E.start(ef0, eg0);
   if (opts->ell > 0 && opts->warm_mode == SKNR_WARM_USER) E.load_V(opts->V0, opts->ell);
   res->n_stages = opts->n_eps;
   res->transposed = P.transposed ? 1 : 0;
@@ -1227,6 +1305,14 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
     }
   }
   HIPCHK(hipStreamSynchronize(s));
+  if (E.have_basis) {
+    L->sub.V = w.V;
+    L->sub.n = P.n;
+    L->sub.ellp = w.ellp;
+    L->sub.ell = opts->ell;
+    L->sub.transposed = P.transposed;
+    L->sub.gen = L->ws_gen;
+  }
   res->status = status;
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return status;
@@ -1245,15 +1331,11 @@ void check_opts(const sknr_opts* opts, const Prepared& P) {
   if (opts->ell > 0) {
     REQUIRE(opts->warm_mode == SKNR_WARM_USER || opts->warm_mode == SKNR_WARM_SEQUENTIAL ||
                 opts->warm_mode == SKNR_WARM_STATIC, "unknown warm_mode");
-    if (opts->warm_mode == SKNR_WARM_USER) {
-      REQUIRE(opts->V0, "WARM_USER needs V0");
-      REQUIRE(!P.transposed, "WARM_USER needs n <= m");
-    }
+    if (opts->warm_mode == SKNR_WARM_USER) REQUIRE(opts->V0, "WARM_USER needs V0");
     if (opts->warm_mode == SKNR_WARM_STATIC) check_eps(opts->eps_prime);
     REQUIRE(!opts->first_stage_nr || opts->warm_mode != SKNR_WARM_SEQUENTIAL,
             "first_stage_nr needs WARM_USER or WARM_STATIC");
   }
-  if (opts->f0) REQUIRE(!P.transposed, "f0 needs n <= m");
   REQUIRE(opts->newton_solver >= SKNR_NEWTON_DIRECT && opts->newton_solver <= SKNR_NEWTON_SCHULZ,
           "unknown newton_solver");
   REQUIRE(opts->newton_max_iter >= 0 && opts->newton_rtol >= 0 && std::isfinite(opts->newton_rtol),
@@ -1374,6 +1456,7 @@ int sknr_ctx_destroy(void* ctx) {
     c->lane_na.arena.cap = 0;
     lane_release(&c->lane_na);
     if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+    if (c->stage) (void)hipFree(c->stage);
     delete c;
     return SKNR_OK;
   });
@@ -1389,6 +1472,8 @@ int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts, doubl
     hipStream_t s = c->lane.own;
     HIPCHK(hipEventRecord(c->order_ev, cs));
     HIPCHK(hipStreamWaitEvent(s, c->order_ev, 0));
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare(prob, s);
     check_opts(opts, P);
     return solve_on_lane(&c->lane, prob, P, opts, f_out, g_out, res);
@@ -1402,6 +1487,8 @@ int sknr_c_transform_col(void* ctx, const sknr_problem* prob, double eps, const 
     check_eps(eps);
     REQUIRE(f && g_out, "f and g_out are required");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     WS w = make_ws(&c->lane, P, 0, s);
     Engine E(&c->lane, P, w, s);
@@ -1431,6 +1518,8 @@ int sknr_c_transform_row(void* ctx, const sknr_problem* prob, double eps, const 
     check_eps(eps);
     REQUIRE(g && f_out, "g and f_out are required");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     WS w = make_ws(&c->lane, P, 0, s);
     Engine E(&c->lane, P, w, s);
@@ -1451,6 +1540,8 @@ int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps, const
     check_eps(eps);
     REQUIRE(f && V && ell >= 1 && ell <= SKNR_MAX_ELL, "f, V and 1 <= ell <= 32 are required");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     int ellp = ell_pad(ell);
     WS w = make_ws(&c->lane, P, ellp, s);
@@ -1489,6 +1580,8 @@ int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps, double* f_
     check_eps(eps);
     REQUIRE(f_inout && V && ell >= 1 && ell <= SKNR_MAX_ELL, "f, V and 1 <= ell <= 32 are required");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     int ellp = ell_pad(ell);
     WS w = make_ws(&c->lane, P, ellp, s);
@@ -1525,6 +1618,8 @@ int sknr_newton_coef(void* ctx, const sknr_problem* prob, double eps, const doub
     REQUIRE(solver >= SKNR_NEWTON_DIRECT && solver <= SKNR_NEWTON_SCHULZ, "unknown solver");
     REQUIRE(max_iter >= 0 && rtol >= 0 && std::isfinite(rtol), "max_iter and rtol must be >= 0");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     int ellp = ell_pad(ell);
     WS w = make_ws(&c->lane, P, ellp, s);
@@ -1557,6 +1652,8 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps, const double*
     check_eps(eps);
     REQUIRE(f && g && out, "f, g, out are required");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     WS w = make_ws(&c->lane, P, 0, s);
     Engine E(&c->lane, P, w, s);
@@ -1585,6 +1682,8 @@ int sknr_gradient(void* ctx, const sknr_problem* prob, double eps, const double*
     check_eps(eps);
     REQUIRE(f && g, "f and g are required");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     REQUIRE(!(grad_x || grad_y) || P.kind == SKNR_COST_SQEUCLID, "point gradients need a squared-Euclidean problem");
     WS w = make_ws(&c->lane, P, 32, s);
@@ -1637,6 +1736,8 @@ int sknr_coupling(void* ctx, const sknr_problem* prob, double eps, const double*
     check_eps(eps);
     REQUIRE(f && g && P_out, "f, g, P_out are required");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     WS w = make_ws(&c->lane, P, 0, s);
     Engine E(&c->lane, P, w, s);
@@ -1694,6 +1795,8 @@ int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps, const d
     REQUIRE(ell >= 1 && ell <= SKNR_MAX_ELL, "1 <= ell <= 32 required");
     REQUIRE(max_iter >= 1 && tol > 0, "max_iter >= 1 and tol > 0 required");
     hipStream_t s = as_stream(stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, s, &staged);
     Prepared P = prepare_caller_orientation(prob, s);
     REQUIRE(ell < std::min(P.n, P.m), "ell must be < min(n, m)");
     WS w = make_ws(&c->lane, P, ell_pad(ell), s);
@@ -1718,6 +1821,24 @@ int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps, const d
     rho_out[0] = 1.0;
     for (int i = 0; i < ell; ++i) rho_out[i + 1] = ((zero >> i) & 1u) ? 0.0 : std::sqrt(lam[i]);
     if (iters_out) *iters_out = it;
+    return SKNR_OK;
+  });
+}
+
+int sknr_get_subspace(void* ctx, double* V_out, int64_t rows, int32_t ell, int32_t* side_out, void* stream) {
+  return guarded([&]() -> int {
+    Ctx* c = as_ctx(ctx);
+    REQUIRE(V_out, "V_out is required");
+    const Lane::Subspace& b = c->lane.sub;
+    REQUIRE(b.V && b.gen == c->lane.ws_gen,
+            "no basis: the last sknr_solve on this context ran no SK-NR stage, or another call has used the "
+            "context since");
+    REQUIRE(rows == b.n && ell == b.ell, "rows / ell differ from the basis of the last solve (rows = " +
+                                             std::to_string(b.n) + ", ell = " + std::to_string(b.ell) + ")");
+    hipStream_t s = as_stream(stream);
+    HIPCHK(launch_take_cols(b.V, b.ellp, b.n, b.ell, 0u, V_out, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (side_out) *side_out = b.transposed ? 1 : 0;
     return SKNR_OK;
   });
 }

@@ -139,6 +139,16 @@ struct Lane {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     graphs.clear();
   }
+  // workspace generation (make_ws counts up): a record of the arena's
+  // contents is valid while its generation is current
+  uint64_t ws_gen = 0;
+  // the basis of the last sknr_solve (engine orientation, padded FP32 rows)
+  struct Subspace {
+    const float* V = nullptr;
+    int n = 0, ellp = 0, ell = 0;
+    bool transposed = false;
+    uint64_t gen = 0;
+  } sub;
   DevState* st_host = nullptr;  // pinned mirror of the state
   bool profile = false;
   std::vector<ProfEntry> prof;
@@ -216,6 +226,9 @@ struct Server;
 struct Ctx {
   int device = 0;
   uint64_t budget = 0;
+  // device copies of host-resident problem arrays (sknr_problem.on_host)
+  char* stage = nullptr;
+  size_t stage_cap = 0;
   Lane lane;
   Lane lane_na;  // sknr_solve_noalloc: workspace in the library's static device array, no graphs
   hipEvent_t order_ev = nullptr;  // orders the solver stream after the caller's stream
@@ -231,6 +244,10 @@ void check_eps(double eps);
 // dmax_dev: optional device float for the stored-cost bound (null: a
 // stream-ordered allocation of 4 bytes)
 Prepared prepare(const sknr_problem* pr, hipStream_t s, float* dmax_dev = nullptr);
+// A problem with host-resident arrays (on_host): copies them into the
+// context's staging block on stream s and returns *tmp describing the
+// device copies; any other problem is returned unchanged.
+const sknr_problem* stage_problem(Ctx* c, const sknr_problem* pr, hipStream_t s, sknr_problem* tmp);
 // point the device pointers of P at another copy of the same problem
 void rebind(Prepared& P, const sknr_problem* pr);
 size_t ws_bytes(const Prepared& P, int ellp, int* geo);

@@ -58,6 +58,7 @@ extern "C" int sknr_solve_noalloc(void* ctx, const sknr_problem* prob, const skn
   return guarded([&]() -> int {
     Ctx* c = as_ctx(ctx);
     REQUIRE(opts && res && f_out && g_out, "opts, res, f_out, g_out are required");
+    REQUIRE(prob && !prob->on_host, "the allocation-free solve takes device-resident inputs only (on_host = 0)");
     size_t cap = 0;
     char* base = noalloc_scratch(c->device, &cap);
     Lane* L = &c->lane_na;

@@ -573,9 +573,11 @@ int sknr_submit(void* ctx, const sknr_problem* prob, const sknr_opts* opts, uint
   return guarded([&]() -> int {
     Ctx* c = as_ctx(ctx);
     REQUIRE(prob && opts && ticket, "prob, opts and ticket are required");
-    REQUIRE(!opts->f0 && !opts->V0, "serving requests take no f0 / V0");
+    REQUIRE(!opts->f0 && !opts->g0 && !opts->V0, "serving requests take no f0 / g0 / V0");
     REQUIRE(opts->ell == 0 || opts->warm_mode != SKNR_WARM_USER, "serving requests take no WARM_USER basis");
     hipStream_t cs = as_stream(opts->stream);
+    sknr_problem staged;
+    prob = stage_problem(c, prob, cs, &staged);
     Prepared P = prepare(prob, cs);
     check_opts(opts, P);
     Server* S = ensure_server(c);

@@ -23,7 +23,7 @@ def test_header_declares_the_boundary():
                      "sknr_c_transform_col", "sknr_projected_system", "sknr_newton_step",
                      "sknr_spectral_basis", "sknr_evaluate", "sknr_coupling", "sknr_status_str",
                      "sknr_last_error", "sknr_submit", "sknr_poll", "sknr_wait", "sknr_cancel",
-                     "sknr_serve_config", "sknr_serve_stats"):
+                     "sknr_serve_config", "sknr_serve_stats", "sknr_get_subspace"):
         assert required in names
 
 
