@@ -63,13 +63,16 @@ __device__ __forceinline__ float sweep_offset(float cmax, float maxabs) { return
 
 __device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
 
+// The flags are written by earlier kernels (visible at this kernel's
+// start; no workgroup of a kernel writes them before every workgroup has
+// read them): plain loads, issued together.
 __device__ __forceinline__ bool gate_closed(const DevState* st, int gate) {
   if (!gate) return false;
-  const volatile DevState* v = st;
-  if ((gate & G_NOT_DONE) && v->done) return true;
-  if ((gate & G_CHOL_OK) && !v->chol_ok) return true;
-  if ((gate & G_ACCEPT) && !v->accept) return true;
-  if ((gate & G_NOT_ACCEPT) && v->accept) return true;
+  const int done = st->done, chol = st->chol_ok, acc = st->accept;
+  if ((gate & G_NOT_DONE) && done) return true;
+  if ((gate & G_CHOL_OK) && !chol) return true;
+  if ((gate & G_ACCEPT) && !acc) return true;
+  if ((gate & G_NOT_ACCEPT) && acc) return true;
   return false;
 }
 
@@ -232,33 +235,50 @@ __device__ __forceinline__ double lane_read_d(double v, int k) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Grid-wide arrival count in st->tail_ctr: true in the workgroup that
-// arrives last of `nblk` (a block-uniform result), whose threads then see
-// every write the other workgroups made before their arrival.  That
-// workgroup resets the count, so it is zero again at the kernel's end (and
-// a state reset writes zero as well).  Every workgroup of the grid must
-// call it once.
-__device__ __forceinline__ bool arrive_last(DevState* st, int nblk) {
+// Store that is coherent across the device at once (agent scope; on
+// gfx950 written through the XCD's L2), so that another workgroup can read
+// it within the same kernel after an arrival count (arrive_count).
+__device__ __forceinline__ void store_wt(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_wt(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Arrival count in *ctr: true in the workgroup that arrives last of
+// `total` (a block-uniform result).  The data a workgroup hands on must
+// have been written with store_wt: every thread waits for its stores to
+// complete before the workgroup's arrival, and the last workgroup drops
+// stale cached lines (acquire) before it reads them, so no cache
+// write-back is needed.  The last workgroup resets the count, so it is
+// zero again at the kernel's end.  Each of the `total` workgroups calls it
+// once.  arrive_last counts a whole grid in st->tail_ctr (which a state
+// reset also zeroes).
+__device__ __forceinline__ bool arrive_count(unsigned* ctr, int total) {
   __shared__ int s_last;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();  // release this workgroup's writes device-wide
-    const unsigned prev = atomicAdd(&st->tail_ctr, 1u);
-    const int last = prev + 1u == (unsigned)nblk;
-    if (last) atomicExch(&st->tail_ctr, 0u);
+    const unsigned prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int last = prev + 1u == (unsigned)total;
+    if (last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_last = last;
   }
   __syncthreads();
   const bool last = s_last != 0;
-  if (last) __threadfence();  // acquire the other workgroups' writes
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // drop stale lines
   return last;
 }
+__device__ __forceinline__ bool arrive_last(DevState* st, int nblk) { return arrive_count(&st->tail_ctr, nblk); }
 
+// (read within the kernel by the finishing workgroup: coherent stores)
 __device__ __forceinline__ void write_block_scalars(const SweepArgs& A, int bid, double err, double dot, float mx) {
   if (threadIdx.x == 0) {
-    A.blk_err[bid] = err;
-    A.blk_dot[bid] = dot;
-    A.blk_max[bid] = mx;
+    store_wt(A.blk_err + bid, err);
+    store_wt(A.blk_dot + bid, dot);
+    store_wt(A.blk_max + bid, mx);
   }
 }
 

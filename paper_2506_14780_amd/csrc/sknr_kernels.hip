@@ -16,6 +16,7 @@
 // Everything else (cross-block merges, epilogues) works on O(n + m) data.
 #include "sknr_internal.h"
 #include "sknr_device.h"
+#include "sknr_sweep_tail.h"
 
 #include <float.h>
 #include <math.h>
@@ -26,75 +27,6 @@
 namespace sknr {
 
 thread_local Recorder* g_recorder = nullptr;
-
-// The last workgroup of a sweep's output kernel (merge, or the row sweep of
-// a stored cost) to finish: reduce the per-block scalars in block order and
-// update the solver state (error, dots, max, convergence and acceptance
-// decisions).  The arrival count makes the other workgroups' scalars
-// visible to it.
-__device__ __forceinline__ void sweep_finish_body(const SweepArgs& A) {
-  if (gate_closed(A.st, A.gate)) return;
-  __shared__ double sbd[16];
-  __shared__ float sbf[8];
-  double e = 0, d = 0;
-  float m = 0;
-  for (int b = threadIdx.x; b < A.nblk; b += blockDim.x) {
-    e += A.blk_err[b];
-    d += A.blk_dot[b];
-    m = fmaxf(m, A.blk_max[b]);
-  }
-  e = block_sum_d(e, sbd);
-  d = block_sum_d(d, sbd + 8);
-  m = block_max_f(m, sbf);
-  // the Newton update's scalars from its block partials (same order as a
-  // one-workgroup reduction of them)
-  double dax = 0, ddx = 0;
-  float mxa = 0.f;
-  if (A.aux_blkdot) {
-    __shared__ double sbd2[16];
-    __shared__ float sbf2[8];
-    for (int b = threadIdx.x; b < A.aux_nblk; b += blockDim.x) {
-      dax += A.aux_blkdot[b];
-      if (A.aux_blkddot) ddx += A.aux_blkddot[b];
-      mxa = fmaxf(mxa, A.aux_blkmax[b]);
-    }
-    dax = block_sum_d(dax, sbd2);
-    ddx = block_sum_d(ddx, sbd2 + 8);
-    mxa = block_max_f(mxa, sbf2);
-  }
-  if (threadIdx.x == 0) {
-    DevState* st = A.st;
-    if (A.aux_blkdot) {
-      st->dots[A.aux_dot_slot] = dax;
-      st->maxabs[A.aux_ma_slot] = mxa;
-    }
-    if (A.Uold) {
-      if (A.mdiff) st->err_aux = e; else st->err = e;
-    }
-    if (A.dot_slot >= 0) st->dots[A.dot_slot] = d;
-    if (A.ma_out >= 0) st->maxabs[A.ma_out] = m;
-    if (A.flags & F_COUNT) st->npass += 1;
-    if (A.flags & F_CHECK) {
-      if (st->armed && e < st->tol) {
-        st->done = 1;
-        if (A.flags & F_GSEL) st->gsel = A.gsel_val;
-      }
-      st->armed = 1;
-    }
-    if (A.flags & F_ACCEPT_DQ) {
-      // Q(f') - Q(f) = <f' - f, a> - sum_o b_o eps log1p(w_o): both terms are
-      // accurate relative to themselves, so the sign is reliable where the
-      // difference of two FP32 c-transform sums is not.  A step so large
-      // that some w_o rounds to -1 (or overflows) gives a non-finite gain:
-      // rejected, the SK step is taken
-      const double dq = ddx - e;
-      int acc = (st->chol_ok && dq > 0 && dq < INFINITY) ? 1 : 0;
-      st->accept = acc;
-      st->newton_accepted += acc;
-    }
-  }
-}
-
 
 // ============================================================================
 // Streaming sweep: each workgroup owns NC = 64*CPT outputs (lane-contiguous
@@ -296,10 +228,9 @@ __device__ __forceinline__ void sweep_stream_body(const SweepArgs& A, const int 
     if (col < n_out) {
       size_t base = (size_t)by * NQ * n_out + col;
 #pragma unroll
-      for (int q2 = 0; q2 < NQ; ++q2) A.part[base + q2 * (size_t)n_out] = cmb[q2 * NC + t];
+      for (int q2 = 0; q2 < NQ; ++q2) store_wt(A.part + base + q2 * (size_t)n_out, cmb[q2 * NC + t]);
     }
   }
-
 }
 
 template <int CPT, int ELL, int COST, int D, int R, bool SCALE>
@@ -313,86 +244,10 @@ __global__ __launch_bounds__(TPB) void k_sweep_stream_b(BatchTab T) {
   sweep_stream_body<CPT, ELL, COST, D, R, SCALE>(*static_cast<const SweepArgs*>(T.args[slot]), bx, by);
 }
 
-// Merge the split-K partials of a streaming sweep: 4 lanes per output,
-// each merging a contiguous quarter of the splits in order, then a fixed
-// shuffle tree across the 4 lanes (deterministic), and finalise.
 template <int ELL>
 __device__ __forceinline__ void sweep_merge_body(const SweepArgs& A, const int bx) {
   if (gate_closed(A.st, A.gate)) return;
-  constexpr int NQ = 3 + (ELL > 0 ? ELL : 0);
-  constexpr int EL = ELL > 0 ? ELL : 1;
-  const EpsConst EC = eps_const(A.st);
-  const float K = EC.K;
-  const float L = sweep_offset_bound(A, A.st->maxabs[A.ma_in], A.st->eps);
-  const int n_out = A.n_out;
-  const int gid = bx * blockDim.x + threadIdx.x;
-  const int col = gid >> 2, part4 = gid & 3;
-  const int colc = min(col, n_out - 1);
-  const int ns = A.nsplit;
-  const int per = (ns + 3) >> 2;
-  const int s0 = part4 * per, s1 = min(ns, s0 + per);
-  const float* pp = A.part + colc;
-  const size_t stride = (size_t)n_out;
-  float sg = SIG0, Ss = 0.f, Sx = 0.f;
-  float ac[EL];
-#pragma unroll
-  for (int l = 0; l < EL; ++l) ac[l] = 0.f;
-  constexpr int BATCH = ELL > 16 ? 2 : (ELL > 0 ? 4 : 16);
-  for (int sp0 = s0; sp0 < s1; sp0 += BATCH) {
-    float bs[BATCH], bS[BATCH], bC[BATCH];
-    float ba[BATCH][EL];
-#pragma unroll
-    for (int q = 0; q < BATCH; ++q) {
-      const int sp = min(sp0 + q, ns - 1);
-      const float* q2 = pp + (size_t)sp * NQ * stride;
-      bs[q] = q2[0];
-      bS[q] = q2[stride];
-      bC[q] = q2[2 * stride];
-#pragma unroll
-      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ba[q][l] = q2[(3 + l) * stride];
-    }
-#pragma unroll
-    for (int q = 0; q < BATCH; ++q) {
-      if (sp0 + q < s1) {
-        float f1, f2;
-        lse_merge(sg, Ss, Sx, bs[q], bS[q], bC[q], K, f1, f2);
-#pragma unroll
-        for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = ac[l] * f1 + ba[q][l] * f2;
-      }
-    }
-  }
-  // lanes (0,1) and (2,3), then (01, 23): split order is preserved
-#pragma unroll
-  for (int off = 1; off <= 2; off <<= 1) {
-    float sg2 = __shfl_xor(sg, off, 64), S2 = __shfl_xor(Ss, off, 64), C2 = __shfl_xor(Sx, off, 64);
-    float a2[EL];
-#pragma unroll
-    for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) a2[l] = __shfl_xor(ac[l], off, 64);
-    const bool lower = (part4 & off) == 0;
-    float f1, f2;
-    if (lower) {
-      lse_merge(sg, Ss, Sx, sg2, S2, C2, K, f1, f2);
-#pragma unroll
-      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = ac[l] * f1 + a2[l] * f2;
-    } else {
-      float t1 = sg2, t2 = S2, t3 = C2;
-      lse_merge(t1, t2, t3, sg, Ss, Sx, K, f1, f2);
-#pragma unroll
-      for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) ac[l] = a2[l] * f1 + ac[l] * f2;
-      sg = t1;
-      Ss = t2;
-      Sx = t3;
-    }
-  }
-  double err = 0, dot = 0;
-  float mxo = 0.f;
-  if (col < n_out && part4 == 0) finalize_output<ELL>(A, EC, col, L, sg, Ss, Sx, ac, err, dot, mxo);
-  __shared__ double sbd[16];
-  __shared__ float sbf[8];
-  err = block_sum_d(err, sbd);
-  dot = block_sum_d(dot, sbd + 8);
-  mxo = block_max_f(mxo, sbf);
-  write_block_scalars(A, bx, err, dot, mxo);
+  sweep_merge_block<ELL>(A, bx);
   if (arrive_last(A.st, A.nblk)) sweep_finish_body(A);
 }
 
@@ -879,7 +734,7 @@ __device__ __forceinline__ void nr_assemble_body(const NrAssembleArgs& q, const 
   // in row-major order of the triangle
   constexpr int TRI = ELL * (ELL + 1) / 2;
   constexpr int PER = (TRI + 255) / 256;
-  __shared__ float tile[64][ELL];
+  __shared__ __align__(16) float tile[64][ELL];
   __shared__ double wrow[64];
   __shared__ double mrow[64];
   double accv[PER];
@@ -894,6 +749,7 @@ __device__ __forceinline__ void nr_assemble_body(const NrAssembleArgs& q, const 
     }
     ek[p] = k;
     el[p] = k + e;
+    if ((int)threadIdx.x + 256 * p >= TRI) ek[p] = el[p] = 0;  // no entry: in-bounds reads, unused
   }
   double gacc = 0;
   const bool rows = (int)bx < nrow_blk;
@@ -904,11 +760,20 @@ __device__ __forceinline__ void nr_assemble_body(const NrAssembleArgs& q, const 
   for (int t0 = beg; t0 < end; t0 += 64) {
     int nt = min(64, end - t0);
     __syncthreads();
-    for (int q = threadIdx.x; q < 64 * ELL; q += 256) {
-      int rr = q / ELL, l = q % ELL;
-      float v = 0.f;
-      if (rr < nt) v = rows ? V[(size_t)(t0 + rr) * ELL + l] : W[(size_t)(t0 + rr) * ELL + l];
-      tile[rr][l] = v;
+    {
+      // rows t0 .. t0+nt-1 are one contiguous block (16-byte aligned): all
+      // of a thread's float4 loads in flight at once; rows past nt are zero
+      constexpr int T4 = 64 * ELL / 4, U4 = (T4 + 255) / 256;
+      const float4* s4 = reinterpret_cast<const float4*>((rows ? V : W) + (size_t)t0 * ELL);
+      const int valid4 = nt * ELL / 4;
+      float4 v[U4];
+#pragma unroll
+      for (int u = 0; u < U4; ++u) v[u] = s4[min((int)threadIdx.x + 256 * u, valid4 - 1)];
+#pragma unroll
+      for (int u = 0; u < U4; ++u) {
+        const int i4 = threadIdx.x + 256 * u;
+        if (i4 < T4) reinterpret_cast<float4*>(&tile[0][0])[i4] = i4 < valid4 ? v[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
     if (threadIdx.x < 64) {
       int rr = threadIdx.x;
@@ -920,15 +785,31 @@ __device__ __forceinline__ void nr_assemble_body(const NrAssembleArgs& q, const 
       mrow[rr] = md;
     }
     __syncthreads();
-    // all 64 rows of the tile: rows past nt are zero and add exact zeros
-#pragma unroll 8
-    for (int rr = 0; rr < 64; ++rr) {
-      double wv = wrow[rr];
+    // all 64 rows of the tile (rows past nt are zero and add exact zeros),
+    // eight at a time: the LDS reads of eight rows go out before the sums
+    const bool gpath = rows && (int)threadIdx.x < ELL;
+    const int gcol = (int)threadIdx.x < ELL ? (int)threadIdx.x : 0;
+    for (int r0 = 0; r0 < 64; r0 += 8) {
+      double wv[8], mr[8];
+      float ta[8][PER], tb[8][PER], tg[8];
 #pragma unroll
-      for (int p = 0; p < PER; ++p) {
-        if ((int)threadIdx.x + 256 * p < TRI) accv[p] += wv * (double)tile[rr][ek[p]] * (double)tile[rr][el[p]];
+      for (int u = 0; u < 8; ++u) {
+        wv[u] = wrow[r0 + u];
+        mr[u] = mrow[r0 + u];
+        tg[u] = tile[r0 + u][gcol];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+          ta[u][p] = tile[r0 + u][ek[p]];
+          tb[u][p] = tile[r0 + u][el[p]];
+        }
       }
-      if (rows && (int)threadIdx.x < ELL) gacc -= (double)tile[rr][threadIdx.x] * mrow[rr];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p)
+          if ((int)threadIdx.x + 256 * p < TRI) accv[p] += wv[u] * (double)ta[u][p] * (double)tb[u][p];
+        if (gpath) gacc -= (double)tg[u] * mr[u];
+      }
     }
   }
   double* out = part + (size_t)bx * (TRI + ELL);
@@ -1122,6 +1003,99 @@ __device__ void nr_iterative(double (*A)[ELL + 2], int solver, int max_it, doubl
   (void)NA;
 }
 
+// The direct solver in one wave: lane i < ELL sums row i of [G | grad]
+// from the partials (both triangles from the stored upper one) into
+// registers, the per-column checks become a ballot mask, and Gauss-Jordan
+// runs on the registers (the steps unrolled, so every index is a constant;
+// step k reads the pivot row from lane k; row i's diagonal is final once
+// step i has used it as the pivot).
+template <int ELL>
+__device__ __forceinline__ void nr_solve_direct(const NrSolveArgs& q, double eps) {
+  constexpr int TRI = ELL * (ELL + 1) / 2, NA = ELL + 1, LEN = TRI + ELL;
+  const int tid = threadIdx.x;
+  if (tid >= 64) return;
+  const int row = tid < ELL ? tid : ELL - 1;
+  const int ell_real = q.ell_real;
+  // entry (k, l), k <= l, of the upper triangle in row-major order
+  auto tri = [](int k, int l) { return k * ELL - (k * (k - 1)) / 2 + (l - k); };
+  double x[NA];
+  {
+    int idx[NA];
+#pragma unroll
+    for (int j = 0; j < ELL; ++j) idx[j] = j >= row ? tri(row, j) : tri(j, row);
+    idx[ELL] = TRI + row;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) x[j] = 0.0;
+    // sums in block order, in chunks of 32 blocks
+    for (int b0 = 0; b0 < q.nblk; b0 += 32) {
+      const int nb = min(32, q.nblk - b0);
+      double c[NA];
+#pragma unroll
+      for (int j = 0; j < NA; ++j) c[j] = 0.0;
+      for (int b = 0; b < nb; ++b) {
+        const double* pb = q.part + (size_t)(b0 + b) * LEN;
+#pragma unroll
+        for (int j = 0; j < NA; ++j) c[j] += pb[idx[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < NA; ++j) x[j] += c[j];
+    }
+  }
+  double dgo = 0.0;  // this row's diagonal entry
+#pragma unroll
+  for (int j = 0; j < ELL; ++j)
+    if (j == row) dgo = x[j];
+  double dmax = tid < ell_real ? dgo : 0.0;
+  for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+  if (q.Gout && tid < ell_real) {
+#pragma unroll
+    for (int j = 0; j < ELL; ++j)
+      if (j < ell_real) q.Gout[tid * ell_real + j] = 0.5 * (x[j] + x[j]);
+    q.gout[tid] = x[ELL];
+  }
+  // column i takes part unless it is padding or carries no mass (a NaN or
+  // negative diagonal still fails the pivot test below)
+  const bool act = row < ell_real && !(fabs(dgo) <= 1e-12 * dmax);
+  const unsigned long long am = __ballot(tid < ELL && act);
+#pragma unroll
+  for (int j = 0; j < ELL; ++j) {
+    const bool aj = (am >> j) & 1ull;
+    x[j] = (act && aj) ? 0.5 * (x[j] + x[j]) : (j == row ? 1.0 : 0.0);
+  }
+  x[ELL] = act ? x[ELL] : 0.0;
+  int ok = 1;
+  double dg = 1.0;
+#pragma unroll
+  for (int k = 0; k < ELL; ++k) {
+    double piv = lane_read_d(x[k], k);
+    if (!(piv > 1e-300 && piv > 1e-15 * dmax)) {
+      ok = 0;
+      piv = 1.0;
+    }
+    if (row == k) dg = piv;
+    // row i subtracts (A_ik / A_kk) times row k; row k keeps its entries
+    // (a zero multiplier; a non-finite pivot row fails the test below)
+    const double mk = row == k ? 0.0 : x[k] * (1.0 / piv);
+#pragma unroll
+    for (int j = k + 1; j < NA; ++j) x[j] = fma(-mk, lane_read_d(x[j], k), x[j]);
+  }
+  // the system is now diagonal: z_i = A[i][ELL] / A[i][i]
+  const double c = eps * (x[ELL] / dg);
+  const int bad = (tid < ELL) && !(fabs(c) < 1e30);
+  ok = ok && !__any(bad);
+  if (tid < ELL) {
+    q.coef64[tid] = c;
+    q.coef32[tid] = ok ? (float)c : 0.f;
+  }
+  if (tid == 0) {
+    DevState* st = q.st;
+    st->chol_ok = ok;
+    st->accept = 0;
+    st->newton_tried += 1;
+    st->nr_iters = 0;
+  }
+}
+
 template <int ELL>
 __device__ __forceinline__ void nr_solve_body(const NrSolveArgs& q) {
   const double* part = q.part;
@@ -1139,6 +1113,10 @@ __device__ __forceinline__ void nr_solve_body(const NrSolveArgs& q) {
   constexpr int NA = ELL + 1;  // augmented width
   const int tid = threadIdx.x;
   const double eps = st->eps;
+  if (solver == NR_DIRECT) {
+    nr_solve_direct<ELL>(q, eps);
+    return;
+  }
   __shared__ double R[NE + ELL];   // sums: G row-major (both triangles), then grad
   __shared__ double A[ELL][NA + 1];
   // the partials hold the upper triangle of G then grad: sum them (block
@@ -1209,49 +1187,6 @@ __device__ __forceinline__ void nr_solve_body(const NrSolveArgs& q) {
       }
     }
     return;
-  }
-  // Gauss-Jordan in one wave: lane i < ELL holds row i of [A | grad] in
-  // registers (the steps are unrolled, so every index is a constant) and
-  // step k reads the pivot row from lane k.  Row i's diagonal is final once
-  // step i has used it as the pivot.
-  if (tid >= 64) return;
-  const int lane = tid;
-  const int row = lane < ELL ? lane : ELL - 1;
-  double x[NA];
-#pragma unroll
-  for (int j = 0; j < NA; ++j) x[j] = A[row][j];
-  int ok = 1;
-  double dg = 1.0;
-#pragma unroll
-  for (int k = 0; k < ELL; ++k) {
-    double piv = lane_read_d(x[k], k);
-    if (!(piv > 1e-300 && piv > 1e-15 * dmax)) {
-      ok = 0;
-      piv = 1.0;
-    }
-    if (row == k) dg = piv;
-    // row i subtracts (A_ik / A_kk) times row k; row k keeps its entries
-    // (a zero multiplier; a non-finite pivot row fails the test below)
-    const double mk = row == k ? 0.0 : x[k] * (1.0 / piv);
-#pragma unroll
-    for (int j = k + 1; j < NA; ++j) x[j] = fma(-mk, lane_read_d(x[j], k), x[j]);
-  }
-  // the system is now diagonal: z_i = A[i][ELL] / A[i][i]
-  {
-    const double c = eps * (x[ELL] / dg);
-    const int bad = (tid < ELL) && !(fabs(c) < 1e30);
-    const int anybad = __any(bad);
-    ok = ok && !anybad;
-    if (tid < ELL) {
-      coef64[tid] = c;
-      coef32[tid] = ok ? (float)c : 0.f;
-    }
-    if (tid == 0) {
-      st->chol_ok = ok;
-      st->accept = 0;
-      st->newton_tried += 1;
-      st->nr_iters = 0;
-    }
   }
 }
 
@@ -1336,6 +1271,7 @@ hipError_t launch_nr_assemble(int ell, const float* V, const float* mdiff, const
   int rpb_r = (n + nrow_blk - 1) / nrow_blk;
   int rpb_c = (m + ncol_blk - 1) / ncol_blk;
   int rpb = rpb_r > rpb_c ? rpb_r : rpb_c;  // one block length for rows and columns
+  if (((uintptr_t)V | (uintptr_t)W) & 15) return hipErrorInvalidValue;  // float4 row loads
   if (ell <= 8) nr_assemble_e<8>(V, mdiff, a, n, W, b, m, part, nrow_blk, ncol_blk, rpb, st, gate, s);
   else if (ell <= 16) nr_assemble_e<16>(V, mdiff, a, n, W, b, m, part, nrow_blk, ncol_blk, rpb, st, gate, s);
   else nr_assemble_e<32>(V, mdiff, a, n, W, b, m, part, nrow_blk, ncol_blk, rpb, st, gate, s);

@@ -199,9 +199,26 @@ __device__ __forceinline__ void sweep_mfma_body(const SweepArgs& A, const int bx
     }
   }
   if (VLDS) {
-    for (int idx = threadIdx.x; idx < nr * EL; idx += TPB) {
-      const int r = idx / EL, l = idx - r * EL;
-      sV[l * vrs + r] = A.Vred[(size_t)(r0 + r) * EL + l];
+    // the split's rows of V are one contiguous block of nr * EL floats
+    // (EL a multiple of 8, r0 of 16: 16-byte aligned): eight float4 loads
+    // per thread in flight at once, then the transposed LDS writes
+    const float4* vb = reinterpret_cast<const float4*>(A.Vred + (size_t)r0 * EL);
+    const int total4 = nr * EL / 4;
+    for (int base = 0; base < total4; base += 8 * TPB) {
+      float4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = vb[min(base + u * TPB + (int)threadIdx.x, total4 - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i4 = base + u * TPB + (int)threadIdx.x;
+        if (i4 < total4) {
+          const int r = (4 * i4) / EL, l = 4 * i4 - r * EL;
+          sV[l * vrs + r] = v[u].x;
+          sV[(l + 1) * vrs + r] = v[u].y;
+          sV[(l + 2) * vrs + r] = v[u].z;
+          sV[(l + 3) * vrs + r] = v[u].w;
+        }
+      }
     }
   }
   __syncthreads();
@@ -452,15 +469,15 @@ __device__ __forceinline__ void sweep_mfma_body(const SweepArgs& A, const int bx
     const int col = cb + 16 * t + c16;
     if (col < n_out) {
       float* base = A.part + (size_t)by * NQ * n_out + col;
-      if (g == 0) base[0] = sig[t];
-      else if (g == 1) base[(size_t)n_out] = S[t];
-      else if (g == 2) base[(size_t)2 * n_out] = Sc[t];
+      if (g == 0) store_wt(base, sig[t]);
+      else if (g == 1) store_wt(base + (size_t)n_out, S[t]);
+      else if (g == 2) store_wt(base + (size_t)2 * n_out, Sc[t]);
 #pragma unroll
       for (int b = 0; b < (ELL > 0 ? NB : 0); ++b)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int l = 16 * b + 4 * g + i;
-          if (l < EL) base[(size_t)(3 + l) * n_out] = W[t][b][i];
+          if (l < EL) store_wt(base + (size_t)(3 + l) * n_out, W[t][b][i]);
         }
     }
   }
@@ -568,7 +585,7 @@ static hipError_t go_pw(const SweepArgs& a, hipStream_t s) {
   dim3 grid((a.n_out + 64 * NT - 1) / (64 * NT), a.nsplit);
   const size_t sm = (size_t)a.rows_per_split * (sizeof(float4) + (DV > 2 ? (DV - 2) * sizeof(float) : 0)) +
                     (size_t)ELL * (a.rows_per_split + 4) * sizeof(float);
-  if (sm > 49152 || (a.rows_per_split & 15)) return hipErrorInvalidValue;
+  if (sm > 49152 || (a.rows_per_split & 15) || ((uintptr_t)a.Vred & 15)) return hipErrorInvalidValue;
   if (g_recorder) {
     record_launch(a.cscale != 1.0f ? (const void*)k_sweep_mfma_b<ELL, 1, 0, NT, DV, true>
                                    : (const void*)k_sweep_mfma_b<ELL, 1, 0, NT, DV, false>,

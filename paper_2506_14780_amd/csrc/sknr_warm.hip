@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_wgram(float* Z, const double* wgt, int 
   const unsigned rmask = refill ? (*refill & refill_bits) : 0u;
   constexpr int NE = KP * KP;
   constexpr int PER = (NE + 255) / 256;
-  __shared__ float tile[64][KP];
+  __shared__ __align__(16) float tile[64][KP];
   __shared__ double wrow[64];
   double acc[PER];
 #pragma unroll
@@ -89,19 +89,36 @@ __global__ __launch_bounds__(256) void k_wgram(float* Z, const double* wgt, int 
   for (int t0 = beg; t0 < end; t0 += 64) {
     int nt = min(64, end - t0);
     __syncthreads();
-    for (int q = threadIdx.x; q < 64 * KP; q += 256) {
-      int rr = q / KP, l = q % KP;
-      float v = 0.f;
-      if (rr < nt) {
-        const size_t e = (size_t)(t0 + rr) * KP + l;
-        if ((rmask >> l) & 1u) {
-          v = uniform_pm1(seed, e);
-          Z[e] = v;
-        } else {
-          v = Z[e];
+    {
+      // rows t0 .. t0+nt-1 of Z are one contiguous block (16-byte
+      // aligned): all of a thread's float4 loads in flight at once; rows
+      // past nt are zero; refilled columns get their random values (also
+      // written back to Z)
+      constexpr int T4 = 64 * KP / 4, U4 = (T4 + 255) / 256;
+      float4* z4 = reinterpret_cast<float4*>(Z + (size_t)t0 * KP);
+      const int valid4 = nt * KP / 4;
+      float4 v[U4];
+#pragma unroll
+      for (int u = 0; u < U4; ++u) v[u] = z4[min((int)threadIdx.x + 256 * u, valid4 - 1)];
+#pragma unroll
+      for (int u = 0; u < U4; ++u) {
+        const int i4 = threadIdx.x + 256 * u;
+        if (i4 >= T4) continue;
+        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i4 < valid4) {
+          t = v[u];
+          const int l0 = (4 * i4) % KP;
+          if ((rmask >> l0) & 0xFu) {
+            const size_t e0 = (size_t)t0 * KP + 4 * (size_t)i4;
+            if ((rmask >> l0) & 1u) t.x = uniform_pm1(seed, e0);
+            if ((rmask >> (l0 + 1)) & 1u) t.y = uniform_pm1(seed, e0 + 1);
+            if ((rmask >> (l0 + 2)) & 1u) t.z = uniform_pm1(seed, e0 + 2);
+            if ((rmask >> (l0 + 3)) & 1u) t.w = uniform_pm1(seed, e0 + 3);
+            z4[i4] = t;
+          }
         }
+        reinterpret_cast<float4*>(&tile[0][0])[i4] = t;
       }
-      tile[rr][l] = v;
     }
     if (threadIdx.x < 64) {
       int rr = threadIdx.x;
@@ -465,6 +482,7 @@ hipError_t launch_repack(const float* V, int kp, int n, int ell, int ellp, float
 hipError_t launch_wgram(int kp, float* Z, const double* w, int invert, int n, double* part, int nblk,
                         const unsigned* refill, unsigned refill_bits, uint64_t seed, hipStream_t s) {
   int rpb = (n + nblk - 1) / nblk;
+  if ((uintptr_t)Z & 15) return hipErrorInvalidValue;  // float4 row loads
   unsigned long long sd = (unsigned long long)seed;
   if (kp == 8)
     hipLaunchKernelGGL((k_wgram<8>), dim3(nblk), dim3(256), 0, s, Z, w, invert, n, part, rpb, refill, refill_bits,
