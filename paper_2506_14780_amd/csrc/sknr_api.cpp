@@ -672,7 +672,7 @@ struct Engine {
     a.nsplit = fused_stored_splits(P.n, P.m);
     a.rows_per_split = (P.n + a.nsplit - 1) / a.nsplit;
     a.aux_nblk = a.nsplit;
-    a.nblk = (P.m + 63) / 64;
+    a.nblk = merge_blocks(P.m, 0);
     a.gate = G_NOT_DONE;
     a.flags = F_CHECK | F_COUNT | F_GSEL;
     a.gsel_val = p;
@@ -995,6 +995,12 @@ struct Engine {
   // Rayleigh-Ritz each iteration, stop when the leading ell Ritz values
   // move by less than tol.  Leaves the Ritz vectors in w.Vw (n x kp,
   // descending) and returns the iterations; lam gets the kp Ritz values.
+  // Rayleigh-Ritz accuracy (launch_jacobi's off2): 1e-14 (eigenvectors to
+  // ~1e-7, the FP32 basis' own resolution) for sknr_spectral_basis; the
+  // solve's warm start only needs a basis whose span carries the leading
+  // modes and Ritz values for its stop test, and takes 1e-8 (eigenvalues to
+  // ~1e-8 relative, eigenvectors to ~1e-4), a sweep fewer per call
+  double jacobi_off2 = 1e-14;
   int spectral(int ell, int oversample, int max_it, double tol, uint64_t seed, std::vector<double>* lam) {
     int kp = ell_pad(std::min(32, ell + std::max(0, oversample)));
     if (kp < ell_pad(ell)) kp = ell_pad(ell);
@@ -1027,7 +1033,7 @@ struct Engine {
       // on the device (lamw + 32) and come back with the second's, one host
       // round trip fewer per warm start
       const bool defer = it == 1 && max_it > 1;
-      HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, defer ? w.lamw + 32 : w.lamw, w.okw + 1, zmask, s));
+      HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, defer ? w.lamw + 32 : w.lamw, w.okw + 1, zmask, s, jacobi_off2));
       HIPCHK(launch_affine(kp, w.Vw, nullptr, w.Qw, nullptr, 0, n, w.Zw, s));
       std::swap(w.Vw, w.Zw);  // V <- V Q (Ritz vectors)
       HIPCHK(launch_affine(kp, w.Uw, nullptr, w.Qw, P.wY, 1, m, w.Utw, s));  // D_b^-1 U Q
@@ -1182,6 +1188,7 @@ int solve_on_lane(Lane* L, const sknr_problem* prob, const Prepared& P, const sk
   int ellp = ell_pad(opts->ell);
   WS w = make_ws(L, P, ellp, s);
   Engine E(L, P, w, s);
+  E.jacobi_off2 = 1e-8;
   const int eig_os = opts->eig_oversample > 0 ? opts->eig_oversample : 8;
   const int eig_it = opts->eig_max_iter > 0 ? opts->eig_max_iter : 100;
   const double eig_tol = opts->eig_tol > 0 ? opts->eig_tol : 0.1;

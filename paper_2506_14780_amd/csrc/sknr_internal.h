@@ -298,6 +298,17 @@ size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bo
                          int* nblk, bool stream_kernel);
 // split merge + scalar finishing kernels of a streaming sweep
 hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t stream);
+// The split merge (k_sweep_merge) gives each output merge_lanes(ell)
+// lanes, each merging a contiguous range of splits; a workgroup of
+// 64 * merge_lanes(ell) threads covers 64 outputs: merge_blocks(n_out)
+// blocks, which is also the number of block scalars of the sweep.
+// (4 for every width: more lanes per output, in larger workgroups or in
+// more of them, measured slower on the 4096^2 sweeps)
+constexpr int merge_lanes(int ell) { return ell < 0 ? 0 : 4; }
+inline int merge_blocks(int n_out, int ell) {
+  (void)ell;
+  return (n_out + 63) / 64;
+}
 
 // matrix-core cost (cost kinds 2, 3, 4 = bf16 cross term with 1, 2, 3 bf16
 // parts per coordinate; `parts` below)
@@ -367,8 +378,10 @@ hipError_t launch_wgram(int kp, float* Z, const double* w, int invert, int n, do
                         const unsigned* refill, unsigned refill_bits, uint64_t seed, hipStream_t s);
 hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok,
                        const unsigned* refill, hipStream_t s);
+// off2: the sweeps stop once the squared off-diagonal Frobenius norm is at
+// most off2 times the squared diagonal one
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
-                         unsigned* zmask_out, hipStream_t s);
+                         unsigned* zmask_out, hipStream_t s, double off2 = 1e-14);
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
                          int n, float* out, hipStream_t s);
 hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, unsigned* zmask, hipStream_t s);

@@ -252,9 +252,11 @@ __device__ __forceinline__ void sweep_merge_body(const SweepArgs& A, const int b
 }
 
 template <int ELL>
-__global__ __launch_bounds__(256) void k_sweep_merge(SweepArgs A) { sweep_merge_body<ELL>(A, blockIdx.x); }
+__global__ __launch_bounds__(64 * merge_lanes(ELL)) void k_sweep_merge(SweepArgs A) {
+  sweep_merge_body<ELL>(A, blockIdx.x);
+}
 template <int ELL>
-__global__ __launch_bounds__(256) void k_sweep_merge_b(BatchTab T) {
+__global__ __launch_bounds__(64 * merge_lanes(ELL)) void k_sweep_merge_b(BatchTab T) {
   int bx, by;
   const int slot = batch_slot(T, blockIdx.x, &bx, &by);
   sweep_merge_body<ELL>(*static_cast<const SweepArgs*>(T.args[slot]), bx);
@@ -473,7 +475,7 @@ size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bo
   ns = (n_red + r - 1) / r;
   *nsplit = ns;
   *rps = r;
-  *nblk = (n_out + 63) / 64;  // merge kernel blocks (4 lanes per output)
+  *nblk = merge_blocks(n_out, ell);
   (void)ncb;
   int ellp = ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32));
   return (size_t)ns * (3 + ellp) * n_out;
@@ -492,7 +494,7 @@ static hipError_t go_stream(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
     record_launch(scale ? (const void*)k_sweep_stream_b<CPT, ELL, COST, D, R, true>
                         : (const void*)k_sweep_stream_b<CPT, ELL, COST, D, R, false>,
                   a, grid, TPB, sm);
-    record_launch((const void*)k_sweep_merge_b<ELL>, a, dim3((a.n_out + 63) / 64), 256, 0);
+    record_launch((const void*)k_sweep_merge_b<ELL>, a, dim3(merge_blocks(a.n_out, ELL)), 64 * merge_lanes(ELL), 0);
     return hipSuccess;
   }
   if (scale)
@@ -500,7 +502,7 @@ static hipError_t go_stream(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
   else
     hipLaunchKernelGGL((k_sweep_stream<CPT, ELL, COST, D, R, false>), grid, dim3(TPB), sm, s, a);
   if (mid) (void)hipEventRecord(mid, s);
-  hipLaunchKernelGGL((k_sweep_merge<ELL>), dim3((a.n_out + 63) / 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_sweep_merge<ELL>), dim3(merge_blocks(a.n_out, ELL)), dim3(64 * merge_lanes(ELL)), 0, s, a);
   return hipGetLastError();
 }
 
@@ -524,19 +526,19 @@ static hipError_t go_stream_points(const SweepArgs& a, hipStream_t s, hipEvent_t
 }
 
 hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t s) {
-  dim3 grid((a.n_out + 63) / 64);
+  dim3 grid(merge_blocks(a.n_out, a.ell));
   if (g_recorder) {
     record_launch(a.ell == 0 ? (const void*)k_sweep_merge_b<0>
                   : a.ell <= 8 ? (const void*)k_sweep_merge_b<8>
                   : a.ell <= 16 ? (const void*)k_sweep_merge_b<16>
                                 : (const void*)k_sweep_merge_b<32>,
-                  a, grid, 256, 0);
+                  a, grid, 64 * merge_lanes(a.ell), 0);
     return hipSuccess;
   }
-  if (a.ell == 0) hipLaunchKernelGGL((k_sweep_merge<0>), grid, dim3(256), 0, s, a);
-  else if (a.ell <= 8) hipLaunchKernelGGL((k_sweep_merge<8>), grid, dim3(256), 0, s, a);
-  else if (a.ell <= 16) hipLaunchKernelGGL((k_sweep_merge<16>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_sweep_merge<32>), grid, dim3(256), 0, s, a);
+  if (a.ell == 0) hipLaunchKernelGGL((k_sweep_merge<0>), grid, dim3(64 * merge_lanes(0)), 0, s, a);
+  else if (a.ell <= 8) hipLaunchKernelGGL((k_sweep_merge<8>), grid, dim3(64 * merge_lanes(8)), 0, s, a);
+  else if (a.ell <= 16) hipLaunchKernelGGL((k_sweep_merge<16>), grid, dim3(64 * merge_lanes(16)), 0, s, a);
+  else hipLaunchKernelGGL((k_sweep_merge<32>), grid, dim3(64 * merge_lanes(32)), 0, s, a);
   return hipGetLastError();
 }
 

@@ -539,7 +539,7 @@ size_t mfma_part_floats(int n_out, int n_red, int ell, int parts, int* nsplit, i
   ns = (n_red + r - 1) / r;
   *nsplit = ns;
   *rps = r;
-  *nblk = (n_out + 63) / 64;
+  *nblk = merge_blocks(n_out, ell);
   const int ellp = ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32));
   return (size_t)ns * (3 + ellp) * n_out;
 }

@@ -13,8 +13,8 @@ namespace sknr {
 // visible to it.
 __device__ __forceinline__ void sweep_finish_body(const SweepArgs& A) {
   if (gate_closed(A.st, A.gate)) return;
-  __shared__ double sbd[16];
-  __shared__ float sbf[8];
+  __shared__ double sbd[32];  // up to 16 waves
+  __shared__ float sbf[16];
   double e = 0, d = 0;
   float m = 0;
   for (int b = threadIdx.x; b < A.nblk; b += blockDim.x) {
@@ -23,22 +23,22 @@ __device__ __forceinline__ void sweep_finish_body(const SweepArgs& A) {
     m = fmaxf(m, A.blk_max[b]);
   }
   e = block_sum_d(e, sbd);
-  d = block_sum_d(d, sbd + 8);
+  d = block_sum_d(d, sbd + 16);
   m = block_max_f(m, sbf);
   // the Newton update's scalars from its block partials (same order as a
   // one-workgroup reduction of them)
   double dax = 0, ddx = 0;
   float mxa = 0.f;
   if (A.aux_blkdot) {
-    __shared__ double sbd2[16];
-    __shared__ float sbf2[8];
+    __shared__ double sbd2[32];
+    __shared__ float sbf2[16];
     for (int b = threadIdx.x; b < A.aux_nblk; b += blockDim.x) {
       dax += A.aux_blkdot[b];
       if (A.aux_blkddot) ddx += A.aux_blkddot[b];
       mxa = fmaxf(mxa, A.aux_blkmax[b]);
     }
     dax = block_sum_d(dax, sbd2);
-    ddx = block_sum_d(ddx, sbd2 + 8);
+    ddx = block_sum_d(ddx, sbd2 + 16);
     mxa = block_max_f(mxa, sbf2);
   }
   if (threadIdx.x == 0) {
@@ -75,30 +75,33 @@ __device__ __forceinline__ void sweep_finish_body(const SweepArgs& A) {
 }
 
 
-// Merge the split-K partials of a streaming sweep: 4 lanes per output,
-// each merging a contiguous quarter of the splits in order, then a fixed
-// shuffle tree across the 4 lanes (deterministic), and finalise.
+// Merge the split-K partials of a sweep: LPO = merge_lanes(ELL) lanes per
+// output, each merging a contiguous range of the splits in order, then a
+// fixed shuffle tree across the LPO lanes (xor 1, 2, ...: neighbours first,
+// so split order is preserved and the result is deterministic), and
+// finalise.  A workgroup of 64 * LPO threads covers 64 outputs.
 template <int ELL>
 __device__ __forceinline__ void sweep_merge_block(const SweepArgs& A, const int bx) {
   constexpr int NQ = 3 + (ELL > 0 ? ELL : 0);
   constexpr int EL = ELL > 0 ? ELL : 1;
+  constexpr int LPO = merge_lanes(ELL);
+  constexpr int OPB = 64;
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
   const float L = sweep_offset_bound(A, A.st->maxabs[A.ma_in], A.st->eps);
   const int n_out = A.n_out;
-  const int gid = bx * blockDim.x + threadIdx.x;
-  const int col = gid >> 2, part4 = gid & 3;
+  const int col = bx * OPB + (int)threadIdx.x / LPO, part = (int)threadIdx.x % LPO;
   const int colc = min(col, n_out - 1);
   const int ns = A.nsplit;
-  const int per = (ns + 3) >> 2;
-  const int s0 = part4 * per, s1 = min(ns, s0 + per);
+  const int per = (ns + LPO - 1) / LPO;
+  const int s0 = part * per, s1 = min(ns, s0 + per);
   const float* pp = A.part + colc;
   const size_t stride = (size_t)n_out;
   float sg = SIG0, Ss = 0.f, Sx = 0.f;
   float ac[EL];
 #pragma unroll
   for (int l = 0; l < EL; ++l) ac[l] = 0.f;
-  constexpr int BATCH = ELL > 16 ? 2 : (ELL > 0 ? 4 : 16);
+  constexpr int BATCH = ELL > 0 ? 4 : 16;
   for (int sp0 = s0; sp0 < s1; sp0 += BATCH) {
     float bs[BATCH], bS[BATCH], bC[BATCH];
     float ba[BATCH][EL];
@@ -122,14 +125,14 @@ __device__ __forceinline__ void sweep_merge_block(const SweepArgs& A, const int 
       }
     }
   }
-  // lanes (0,1) and (2,3), then (01, 23): split order is preserved
+  // neighbouring lanes first: split order is preserved
 #pragma unroll
-  for (int off = 1; off <= 2; off <<= 1) {
+  for (int off = 1; off < LPO; off <<= 1) {
     float sg2 = __shfl_xor(sg, off, 64), S2 = __shfl_xor(Ss, off, 64), C2 = __shfl_xor(Sx, off, 64);
     float a2[EL];
 #pragma unroll
     for (int l = 0; l < (ELL > 0 ? ELL : 0); ++l) a2[l] = __shfl_xor(ac[l], off, 64);
-    const bool lower = (part4 & off) == 0;
+    const bool lower = (part & off) == 0;
     float f1, f2;
     if (lower) {
       lse_merge(sg, Ss, Sx, sg2, S2, C2, K, f1, f2);
@@ -147,11 +150,11 @@ __device__ __forceinline__ void sweep_merge_block(const SweepArgs& A, const int 
   }
   double err = 0, dot = 0;
   float mxo = 0.f;
-  if (col < n_out && part4 == 0) finalize_output<ELL>(A, EC, col, L, sg, Ss, Sx, ac, err, dot, mxo);
-  __shared__ double sbd[16];
-  __shared__ float sbf[8];
+  if (col < n_out && part == 0) finalize_output<ELL>(A, EC, col, L, sg, Ss, Sx, ac, err, dot, mxo);
+  __shared__ double sbd[32];  // up to 16 waves
+  __shared__ float sbf[16];
   err = block_sum_d(err, sbd);
-  dot = block_sum_d(dot, sbd + 8);
+  dot = block_sum_d(dot, sbd + 16);
   mxo = block_max_f(mxo, sbf);
   write_block_scalars(A, bx, err, dot, mxo);
 }

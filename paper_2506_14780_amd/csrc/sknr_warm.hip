@@ -127,16 +127,32 @@ __global__ __launch_bounds__(256) void k_wgram(float* Z, const double* wgt, int 
       wrow[rr] = w;
     }
     __syncthreads();
-    // all 64 rows of the tile: rows past nt are zero and add exact zeros
-#pragma unroll 8
-    for (int rr = 0; rr < 64; ++rr) {
-      double w = wrow[rr];
+    // all 64 rows of the tile (rows past nt are zero and add exact zeros),
+    // eight at a time: the LDS reads of eight rows go out before the sums
+    const int scol = (int)threadIdx.x < KP ? (int)threadIdx.x : 0;
+    for (int r0 = 0; r0 < 64; r0 += 8) {
+      double wv[8];
+      float ta[8][PER], tb[8][PER], ts[8];
 #pragma unroll
-      for (int p = 0; p < PER; ++p) {
-        int e = threadIdx.x + 256 * p;
-        if (e < NE) acc[p] += w * (double)tile[rr][e / KP] * (double)tile[rr][e % KP];
+      for (int u = 0; u < 8; ++u) {
+        wv[u] = wrow[r0 + u];
+        ts[u] = tile[r0 + u][scol];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+          const int e = min((int)threadIdx.x + 256 * p, NE - 1);
+          ta[u][p] = tile[r0 + u][e / KP];
+          tb[u][p] = tile[r0 + u][e % KP];
+        }
       }
-      if ((int)threadIdx.x < KP) sacc += w * (double)tile[rr][threadIdx.x];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+          const int e = threadIdx.x + 256 * p;
+          if (e < NE) acc[p] += wv[u] * (double)ta[u][p] * (double)tb[u][p];
+        }
+        if ((int)threadIdx.x < KP) sacc += wv[u] * (double)ts[u];
+      }
     }
   }
   double* out = part + (size_t)blockIdx.x * (NE + KP);
@@ -164,90 +180,92 @@ __global__ __launch_bounds__(256) void k_wgram(float* Z, const double* wgt, int 
 // orthonormal.  (A ridge on the diagonal instead shrinks such columns and,
 // after the Rayleigh-Ritz rotation, mixes the shrinkage into the good
 // ones.)  *ok_out = 0 when every column is dropped.
-// 256 threads, matrix in LDS: right-looking Cholesky with the trailing
-// update spread over the threads, then column j of L^-1 by thread j with
-// broadcast LDS reads of L.
+// One wave, matrix in registers: lane i holds row i of B' and, step by
+// step, of L (right-looking Cholesky; the steps unrolled, so every index is
+// a constant; step k reads the pivot and column k of L from the lanes that
+// hold them); then L goes to LDS and column j of L^-1 is formed by lane j
+// with broadcast LDS reads of L.
 template <int KP>
-__global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out,
-                                              const unsigned* refill) {
+__global__ __launch_bounds__(64) void k_orth(const double* part, int nblk, double* R, double* s_out, int* ok_out,
+                                             const unsigned* refill) {
   constexpr int NE = KP * KP;
-  constexpr int NT = 256;
-  __shared__ double B[KP][KP + 1];
-  __shared__ double s[KP];
-  __shared__ double lcol[KP];
-  __shared__ int drop[KP];
-  __shared__ double bmax_s;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NE + KP; e += NT) {
-    double v = sum_parts(part, nblk, NE + KP, e);
-    if (e < NE) B[e / KP][e % KP] = v;
-    else s[e - NE] = v;
+  const int lane = threadIdx.x;
+  const int row = lane < KP ? lane : KP - 1;
+  __shared__ double Ls[KP][KP + 1];
+  // the Gram sums (block order): row `row` of B, its transpose and s
+  auto total = [&](int e) {
+    if (nblk == 1) return part[e];
+    double v = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 32) {
+      double c = 0;
+      for (int b = b0; b < min(nblk, b0 + 32); ++b) c += part[(size_t)b * (NE + KP) + e];
+      v += c;
+    }
+    return v;
+  };
+  const double s_own = total(NE + row);
+  double x[KP];
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const double bij = total(row * KP + j), bji = total(j * KP + row);
+    const double sj = total(NE + j);
+    x[j] = 0.5 * (bij + bji) - s_own * sj;  // B' = sym(B) - s s^T
   }
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned fresh = refill ? *refill : 0u;
-    double bm = 0;
-    for (int k = 0; k < KP; ++k)
-      if (!((fresh >> k) & 1u)) bm = fmax(bm, B[k][k] - s[k] * s[k]);
-    bmax_s = bm;
-  }
-  __syncthreads();
-  const double dcut = fmax(1e-8 * bmax_s, 1e-12);
-  // B' = sym(B) - s s^T, lower triangle suffices
-  for (int e = tid; e < NE; e += NT) {
-    const int i = e / KP, j = e % KP;
-    if (j <= i) B[i][j] = 0.5 * (B[i][j] + B[j][i]) - s[i] * s[j];
-  }
-  __syncthreads();
-  // right-looking Cholesky: column k of L from the current B, then the
-  // trailing update; two barriers per column.  A dropped column gets
-  // L_kk = 1 and a zero column below the diagonal (no trailing update).
+  const unsigned fresh = refill ? *refill : 0u;
+  double dgo = 0.0;
+#pragma unroll
+  for (int j = 0; j < KP; ++j)
+    if (j == row) dgo = x[j];
+  double bm = (lane < KP && !((fresh >> lane) & 1u)) ? dgo : 0.0;
+  for (int o = 32; o > 0; o >>= 1) bm = fmax(bm, __shfl_xor(bm, o, 64));
+  const double dcut = fmax(1e-8 * bm, 1e-12);
+  // right-looking Cholesky: column k of L from the current B', then the
+  // trailing update (rows i > k, columns k < j <= i; the other entries of a
+  // lane's row are not used).  A dropped column gets L_kk = 1 and a zero
+  // column below the diagonal (no trailing update).
+  unsigned drop = 0u;
+#pragma unroll
   for (int k = 0; k < KP; ++k) {
-    if (tid >= k && tid < KP) {
-      const double d = B[k][k];
-      const bool dk = !(d > dcut);  // also NaN
-      if (dk) {
-        lcol[tid] = tid == k ? 1.0 : 0.0;
-      } else {
-        const double lk = sqrt(d);
-        lcol[tid] = tid == k ? lk : B[tid][k] / lk;
-      }
-      if (tid == k) drop[k] = dk ? 1 : 0;
+    const double d = lane_read_d(x[k], k);
+    const bool dk = !(d > dcut);  // also NaN
+    double lik;
+    if (dk) {
+      lik = row == k ? 1.0 : 0.0;
+    } else {
+      const double lk = sqrt(d);
+      lik = row == k ? lk : x[k] / lk;
     }
-    __syncthreads();
-    const int rem = KP - 1 - k;
-    for (int e = tid; e < rem * rem; e += NT) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j <= i) B[i][j] -= lcol[i] * lcol[j];
-    }
-    if (tid >= k && tid < KP) B[tid][k] = lcol[tid];
-    __syncthreads();
+    if (dk) drop |= 1u << k;
+#pragma unroll
+    for (int j = k + 1; j < KP; ++j) x[j] -= lik * lane_read_d(lik, j);
+    x[k] = lik;
   }
-  // L^-1, column j by thread j: x_r = (delta_rj - sum_{t<r} L_rt x_t) / L_rr
-  if (tid < KP) {
-    const int j = tid;
-    double x[KP];
+  if (lane < KP) {
+#pragma unroll
+    for (int t = 0; t < KP; ++t) Ls[lane][t] = x[t];
+  }
+  __syncthreads();
+  // L^-1, column j by lane j: x_r = (delta_rj - sum_{t<r} L_rt x_t) / L_rr
+  if (lane < KP) {
+    const int j = lane;
+    double y[KP];
 #pragma unroll
     for (int r = 0; r < KP; ++r) {
       double acc = (r == j) ? 1.0 : 0.0;
 #pragma unroll
-      for (int t = 0; t < r; ++t) acc -= B[r][t] * x[t];
-      x[r] = acc / B[r][r];
+      for (int t = 0; t < r; ++t) acc -= Ls[r][t] * y[t];
+      y[r] = acc / Ls[r][r];
     }
     // a dropped column r: row r of L^-1 is zero (V_r = 0); later rows do
-    // not read x[r] (L_ir = 0 for i > r)
+    // not read y[r] (L_ir = 0 for i > r)
 #pragma unroll
     for (int r = 0; r < KP; ++r)
-      if (drop[r]) x[r] = 0.0;
+      if ((drop >> r) & 1u) y[r] = 0.0;
 #pragma unroll
-    for (int t = 0; t < KP; ++t) R[j * KP + t] = x[t];  // R = L^-T
-    s_out[j] = s[j];
+    for (int t = 0; t < KP; ++t) R[j * KP + t] = y[t];  // R = L^-T
+    s_out[j] = s_own;
   }
-  if (tid == 0) {
-    int kept = 0;
-    for (int k = 0; k < KP; ++k) kept += drop[k] ? 0 : 1;
-    *ok_out = kept > 0 ? 1 : 0;
-  }
+  if (lane == 0) *ok_out = __popc(drop) < KP ? 1 : 0;
 }
 
 // ------------------------------------------------------ Rayleigh-Ritz
@@ -256,14 +274,17 @@ __global__ __launch_bounds__(256) void k_orth(const double* part, int nblk, doub
 // each step rotates k/2 disjoint index pairs at once.  With the pairs of a
 // step, A <- J^T A J splits into independent 2x2 blocks (row pair r,
 // column pair t), so one thread updates one block (and one row pair of the
-// accumulated Q) per step: two barriers per step.  Then eigenpairs sorted
-// descending: Q (k x k, columns = eigenvectors, row-major), lam (k).
+// accumulated Q) per step: two barriers per step.  The sweeps stop when
+// ||offdiag||_F^2 <= off2 ||diag||_F^2 (the eigenvalues are then exact to
+// about off2 relative, the eigenvectors to about sqrt(off2)).  Then
+// eigenpairs sorted descending: Q (k x k, columns = eigenvectors,
+// row-major), lam (k).
 // Zero rows of T (columns of V that the orthonormalisation dropped) stay
 // untouched (their rotations are the identity); *zmask_out (nullable) gets
 // bit p set when sorted position p holds such a column.
 template <int KP>
 __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, double* Qout, double* lam, int sweeps,
-                                                int* sweeps_out, unsigned* zmask_out) {
+                                                int* sweeps_out, unsigned* zmask_out, double off2) {
   constexpr int NE = KP * KP;
   constexpr int NP = KP / 2;
   constexpr int NT = 256;
@@ -314,8 +335,7 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
         o2 += red[0][w];
         d2 += red[1][w];
       }
-      // the basis it rotates is FP32: stop at off-diagonal ~1e-7 relative
-      stop_s = o2 <= 1e-14 * d2 ? 1 : 0;
+      stop_s = o2 <= off2 * d2 ? 1 : 0;
     }
     __syncthreads();
     if (stop_s) break;
@@ -497,19 +517,21 @@ hipError_t launch_wgram(int kp, float* Z, const double* w, int invert, int n, do
 }
 hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* s_out, int* ok,
                        const unsigned* refill, hipStream_t s) {
-  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok, refill);
-  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok, refill);
-  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(256), 0, s, part, nblk, R, s_out, ok, refill);
+  if (kp == 8) hipLaunchKernelGGL((k_orth<8>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok, refill);
+  else if (kp == 16) hipLaunchKernelGGL((k_orth<16>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok, refill);
+  else hipLaunchKernelGGL((k_orth<32>), dim3(1), dim3(64), 0, s, part, nblk, R, s_out, ok, refill);
   return hipGetLastError();
 }
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
-                         unsigned* zmask_out, hipStream_t s) {
+                         unsigned* zmask_out, hipStream_t s, double off2) {
   if (kp == 8)
-    hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out);
+    hipLaunchKernelGGL((k_jacobi<8>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out, off2);
   else if (kp == 16)
-    hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out);
+    hipLaunchKernelGGL((k_jacobi<16>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out,
+                       off2);
   else
-    hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out);
+    hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out,
+                       off2);
   return hipGetLastError();
 }
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
