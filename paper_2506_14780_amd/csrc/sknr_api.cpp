@@ -691,6 +691,39 @@ struct Engine {
       c->pending.push_back(Pending{c->kind_of("sk_fused_stored:main"), nullptr, em, units});
     }
   }
+  // Iterations until the next convergence poll.  A fixed check_every is
+  // kept.  Otherwise: the iterations that a geometric decay of the error, at
+  // the rate seen since the previous poll, needs to reach the stage's
+  // threshold (rounded up to one of a few graph sizes), so that a stage
+  // usually ends after two or three polls with few gated iterations; with
+  // no rate yet, the chunk doubles up to chunk_max.
+  static int next_chunk(int chunk, int chunk_max, int check_every, const DevState& st, double* err_prev,
+                        int* np_prev) {
+    // the first poll measures the rate from the stage's first check
+    if (*err_prev < 0 && st.npass > 1 && st.err1 > 0) {
+      *err_prev = st.err1;
+      *np_prev = 1;
+    }
+    int next = std::min(chunk * 2, chunk_max);
+    if (check_every <= 0 && *err_prev > 0 && st.err > 0 && st.err < *err_prev && st.npass > *np_prev &&
+        st.tol > 0 && st.err > st.tol) {
+      const double rate = std::pow(st.err / *err_prev, 1.0 / (st.npass - *np_prev));
+      const double need = std::log(st.tol / st.err) / std::log(rate);
+      if (std::isfinite(need) && need > 0) {
+        static const int sizes[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+        next = 32;
+        for (int z : sizes)
+          if (z >= need) {
+            next = z;
+            break;
+          }
+      }
+    }
+    *err_prev = st.err;
+    *np_prev = st.npass;
+    return next;
+  }
+
   // A plain SK stage with fused passes: one column sweep g_1 = T_c(f_0)
   // (unarmed test), then pass k computes f_k = T_r(g_k) and g_{k+1} and
   // tests (f_k, g_k) -- the pairs, tests and counts of the two-pass loop,
@@ -703,6 +736,8 @@ struct Engine {
     const int chunk_max = check_every > 0 ? check_every : 32;
     DevState st{};
     bool done = false;
+    double err_prev = -1.0;  // error at the previous poll, and the check count then
+    int np_prev = 0;
     while (launched < max_iter) {
       const int k = std::min(chunk, max_iter - launched);
       for (int t = 0; t < k; ++t) {
@@ -716,7 +751,7 @@ struct Engine {
         done = true;
         break;
       }
-      chunk = std::min(chunk * 2, chunk_max);
+      chunk = next_chunk(chunk, chunk_max, check_every, st, &err_prev, &np_prev);
     }
     *converged = done;
     last_err = st.err;
@@ -862,6 +897,8 @@ struct Engine {
     const int chunk_max = check_every > 0 ? check_every : (ell > 0 ? 8 : 32);
     bool done = false;
     DevState st{};
+    double err_prev = -1.0;  // error at the previous poll, and the check count then
+    int np_prev = 0;
     if (ell > 0 && !resume && max_iter >= 1) {
       sknr_iter(ell, true);  // the first iteration of Algorithm 4.1 has no Newton step
       ++launched;
@@ -894,7 +931,7 @@ struct Engine {
         done = true;
         break;
       }
-      chunk = std::min(chunk * 2, chunk_max);
+      chunk = next_chunk(chunk, chunk_max, check_every, st, &err_prev, &np_prev);
     }
     if (!done) {
       // the (max_iter+1)-th column sweep: convergence test of f_max_iter

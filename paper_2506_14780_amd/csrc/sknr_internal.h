@@ -38,7 +38,8 @@ struct DevState {
   float2 eln2_df;       // eps*ln2 as double-float
   int nr_iters;         // iterations of the last iterative Newton solve (0 for the direct one)
   unsigned tail_ctr;    // arrivals of a sweep's tail workgroups (zero between kernels)
-  int pad[4];
+  double err1;          // error of the stage's first checking sweep (npass == 1)
+  int pad[2];
 };
 
 // Solver of the l x l Newton system (k_nr_solve): Gauss-Jordan with

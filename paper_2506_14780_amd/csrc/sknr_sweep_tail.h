@@ -54,6 +54,7 @@ __device__ __forceinline__ void sweep_finish_body(const SweepArgs& A) {
     if (A.ma_out >= 0) st->maxabs[A.ma_out] = m;
     if (A.flags & F_COUNT) st->npass += 1;
     if (A.flags & F_CHECK) {
+      if (st->npass == 1) st->err1 = e;
       if (st->armed && e < st->tol) {
         st->done = 1;
         if (A.flags & F_GSEL) st->gsel = A.gsel_val;
