@@ -1029,8 +1029,9 @@ struct Engine {
   // iteration on M = D_a^-1 P~ D_b^-1 P~^T, P~ = pi(f, f^{C,eps}), with a
   // block of kp = pad(min(32, ell + oversample)) columns kept orthonormal in
   // L2(a) and orthogonal to the constants (rho_0 = 1 is excluded), FP64
-  // Rayleigh-Ritz each iteration, stop when the leading ell Ritz values
-  // move by less than tol.  Leaves the Ritz vectors in w.Vw (n x kp,
+  // Rayleigh-Ritz each iteration after the first (whose Rayleigh quotients
+  // stand in for Ritz values), stop when the leading ell Ritz values move
+  // by less than tol.  Leaves the Ritz vectors in w.Vw (n x kp,
   // descending) and returns the iterations; lam gets the kp Ritz values.
   // Rayleigh-Ritz accuracy (launch_jacobi's off2): 1e-14 (eigenvectors to
   // ~1e-7, the FP32 basis' own resolution) for sknr_spectral_basis; the
@@ -1070,9 +1071,15 @@ struct Engine {
       // on the device (lamw + 32) and come back with the second's, one host
       // round trip fewer per warm start
       const bool defer = it == 1 && max_it > 1;
-      HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, defer ? w.lamw + 32 : w.lamw, w.okw + 1, zmask, s, jacobi_off2));
-      HIPCHK(launch_affine(kp, w.Vw, nullptr, w.Qw, nullptr, 0, n, w.Zw, s));
-      std::swap(w.Vw, w.Zw);  // V <- V Q (Ritz vectors)
+      // the first iteration keeps its basis (a rotation would not change
+      // the span that the next iteration works on) and passes the Rayleigh
+      // quotients diag(T) to the stop test in place of its Ritz values
+      if (defer) HIPCHK(launch_ritz_diag(kp, w.nrsum, 1, w.Qw, w.lamw + 32, w.okw + 1, zmask, s));
+      else HIPCHK(launch_jacobi(kp, w.nrsum, 1, w.Qw, w.lamw, w.okw + 1, zmask, s, jacobi_off2));
+      if (!defer) {
+        HIPCHK(launch_affine(kp, w.Vw, nullptr, w.Qw, nullptr, 0, n, w.Zw, s));
+        std::swap(w.Vw, w.Zw);  // V <- V Q (Ritz vectors)
+      }
       HIPCHK(launch_affine(kp, w.Uw, nullptr, w.Qw, P.wY, 1, m, w.Utw, s));  // D_b^-1 U Q
       if (defer) {
         check_cancel();

@@ -383,6 +383,9 @@ hipError_t launch_orth(int kp, const double* part, int nblk, double* R, double* 
 // most off2 times the squared diagonal one
 hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
                          unsigned* zmask_out, hipStream_t s, double off2 = 1e-14);
+// the diagonal of T sorted as Ritz-value estimates, Q = I (see k_ritz_diag)
+hipError_t launch_ritz_diag(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
+                            unsigned* zmask_out, hipStream_t s);
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
                          int n, float* out, hipStream_t s);
 hipError_t launch_random_block(int kp, float* Z, int n, int col0, uint64_t seed, unsigned* zmask, hipStream_t s);

@@ -426,6 +426,35 @@ __global__ __launch_bounds__(256) void k_jacobi(const double* part, int nblk, do
   }
 }
 
+// Rayleigh quotients in place of a Rayleigh-Ritz step: from the Gram
+// partials of T (as k_jacobi), lam = the diagonal of T sorted descending,
+// Q = identity (the basis is kept as it is), *zmask_out = the columns whose
+// diagonal is exactly zero (columns the orthonormalisation dropped), in the
+// basis' own column order.
+template <int KP>
+__global__ __launch_bounds__(64) void k_ritz_diag(const double* part, int nblk, double* Qout, double* lam,
+                                                  int* sweeps_out, unsigned* zmask_out) {
+  constexpr int NE = KP * KP;
+  const int tid = threadIdx.x;
+  __shared__ double dg[KP];
+  if (tid < KP) dg[tid] = sum_parts(part, nblk, NE + KP, tid * KP + tid);
+  __syncthreads();
+  if (tid < KP) {
+    const double li = dg[tid];
+    int rank = 0;
+    for (int j = 0; j < KP; ++j) rank += (dg[j] > li) || (dg[j] == li && j < tid);
+    lam[rank] = li;
+  }
+  for (int e = tid; e < NE; e += 64) Qout[e] = (e / KP == e % KP) ? 1.0 : 0.0;
+  if (tid == 0) {
+    unsigned msk = 0;
+    for (int k = 0; k < KP; ++k)
+      if (dg[k] == 0.0) msk |= 1u << k;
+    if (zmask_out) *zmask_out = msk;
+    if (sweeps_out) *sweeps_out = 0;
+  }
+}
+
 // out_i = ((Z_i - s) R) * rowscale_i   (k x k transform per row, FP64 math).
 // KP/4 threads per row, each producing four adjacent outputs (one 16-byte
 // store; a row's threads write its KP floats contiguously); every thread
@@ -532,6 +561,14 @@ hipError_t launch_jacobi(int kp, const double* part, int nblk, double* Q, double
   else
     hipLaunchKernelGGL((k_jacobi<32>), dim3(1), dim3(256), 0, s, part, nblk, Q, lam, 10, sweeps_out, zmask_out,
                        off2);
+  return hipGetLastError();
+}
+hipError_t launch_ritz_diag(int kp, const double* part, int nblk, double* Q, double* lam, int* sweeps_out,
+                            unsigned* zmask_out, hipStream_t s) {
+  if (kp == 8) hipLaunchKernelGGL((k_ritz_diag<8>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, sweeps_out, zmask_out);
+  else if (kp == 16)
+    hipLaunchKernelGGL((k_ritz_diag<16>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, sweeps_out, zmask_out);
+  else hipLaunchKernelGGL((k_ritz_diag<32>), dim3(1), dim3(64), 0, s, part, nblk, Q, lam, sweeps_out, zmask_out);
   return hipGetLastError();
 }
 hipError_t launch_affine(int kp, const float* Z, const double* sv, const double* R, const double* rs, int rs_invert,
