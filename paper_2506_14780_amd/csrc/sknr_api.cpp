@@ -102,13 +102,14 @@ float bf16_round(double v) {
 }
 
 // --------------------------------------------------------------- prepare
-Prepared prepare(const sknr_problem* pr, hipStream_t s, float* dmax_dev) {
+Prepared prepare(const sknr_problem* pr, hipStream_t s, void* scratch) {
   REQUIRE(pr, "problem is NULL");
   REQUIRE(pr->n >= 1 && pr->m >= 1, "n and m must be >= 1");
   REQUIRE(pr->n <= (1 << 26) && pr->m <= (1 << 26), "n, m too large");
   REQUIRE(pr->kind == SKNR_COST_STORED || pr->kind == SKNR_COST_SQEUCLID, "unknown cost kind");
   REQUIRE(pr->a && pr->b, "weights a, b are required");
   REQUIRE(!pr->on_host, "host-resident inputs (on_host) are not accepted by this entry point");
+  REQUIRE(scratch, "internal: no scratch for prepare");
   Prepared P;
   P.n0 = (int)pr->n;
   P.m0 = (int)pr->m;
@@ -122,7 +123,8 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s, float* dmax_dev) {
   P.d = pr->d;
   P.cscale = 1.0f;
   P.cscale64 = 1.0;
-  if (pr->kind == SKNR_COST_STORED) {
+  const bool pts = pr->kind == SKNR_COST_SQEUCLID;
+  if (!pts) {
     REQUIRE(pr->C, "stored cost C is NULL");
     REQUIRE(pr->ldc >= pr->m, "ldc < m");
     P.X = P.Y = nullptr;
@@ -139,63 +141,52 @@ Prepared prepare(const sknr_problem* pr, hipStream_t s, float* dmax_dev) {
     P.X = P.transposed ? pr->y : pr->x;
     P.Y = P.transposed ? pr->x : pr->y;
   }
-  // weights: validate on the host
-  std::vector<double> ha(P.n0), hb(P.m0);
-  HIPCHK(hipMemcpyAsync(ha.data(), pr->a, sizeof(double) * P.n0, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hb.data(), pr->b, sizeof(double) * P.m0, hipMemcpyDeviceToHost, s));
+  // input statistics on the device (and the stored cost's bound), one read
+  const int d = pts ? pr->d : 0;
+  const int nrec = 2 + 2 * d;
+  double* dst = static_cast<double*>(scratch);
+  float* dmax = reinterpret_cast<float*>(static_cast<char*>(scratch) + kPrepBytes - 256);
+  HIPCHK(launch_input_stats(pr->a, P.n0, pr->b, P.m0, pts ? pr->x : nullptr, pts ? pr->y : nullptr, pts ? d : 1,
+                            dst, s));
+  if (!pts) HIPCHK(launch_cost_max(0, pr->C, pr->ldc, P.n0, P.m0, nullptr, nullptr, 0, dmax, s));
+  std::vector<double> h(5 * (size_t)nrec);
+  float hm = 0;
+  HIPCHK(hipMemcpyAsync(h.data(), dst, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  if (!pts) HIPCHK(hipMemcpyAsync(&hm, dmax, sizeof(float), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  auto check_w = [](const std::vector<double>& w, const char* name) {
-    double sum = 0;
-    for (double v : w) {
-      if (!(v > 0) || !std::isfinite(v)) throw Err{SKNR_EINVAL, std::string(name) + " has a non-positive or non-finite entry"};
-      sum += v;
-    }
-    if (std::fabs(sum - 1.0) > 1e-9 * std::max<double>(1.0, (double)w.size()))
+  auto check_w = [&](int r, int len, const char* name) {
+    const double* o = &h[5 * (size_t)r];
+    if (o[3] != 0) throw Err{SKNR_EINVAL, std::string(name) + " has a non-positive or non-finite entry"};
+    if (std::fabs(o[2] - 1.0) > 1e-9 * std::max<double>(1.0, (double)len))
       throw Err{SKNR_EINVAL, std::string(name) + " does not sum to 1"};
   };
-  check_w(ha, "a");
-  check_w(hb, "b");
+  check_w(0, P.n0, "a");
+  check_w(1, P.m0, "b");
+  const double* sa = &h[0];
+  const double* sb = &h[5];
   P.wX = P.transposed ? pr->b : pr->a;
   P.wY = P.transposed ? pr->a : pr->b;
-  P.hX = P.transposed ? hb : ha;
-  P.hY = P.transposed ? ha : hb;
-  // cost bound
-  if (pr->kind == SKNR_COST_STORED) {
-    float* dmax = dmax_dev;
-    if (!dmax) HIPCHK(hipMallocAsync((void**)&dmax, sizeof(float), s));
-    HIPCHK(launch_cost_max(0, pr->C, pr->ldc, P.n0, P.m0, nullptr, nullptr, 0, dmax, s));
-    float hm = 0;
-    HIPCHK(hipMemcpyAsync(&hm, dmax, sizeof(float), hipMemcpyDeviceToHost, s));
-    if (!dmax_dev) HIPCHK(hipFreeAsync(dmax, s));
-    HIPCHK(hipStreamSynchronize(s));
+  const double* sX = P.transposed ? sb : sa;
+  const double* sY = P.transposed ? sa : sb;
+  P.wminX = sX[0];
+  P.wmaxX = sX[1];
+  P.entX = sX[4];
+  P.wminY = sY[0];
+  P.wmaxY = sY[1];
+  P.entY = sY[4];
+  if (!pts) {
     REQUIRE(std::isfinite(hm), "cost has non-finite entries");
     P.cmax = hm;
   } else {
-    int d = pr->d;
-    std::vector<float> hx((size_t)P.n0 * d), hy((size_t)P.m0 * d);
-    HIPCHK(hipMemcpyAsync(hx.data(), pr->x, hx.size() * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hy.data(), pr->y, hy.size() * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
     double bound = 0;
     P.mu.assign(d, 0.f);
     for (int k = 0; k < d; ++k) {
-      double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY, sum = 0;
-      for (int i = 0; i < P.n0; ++i) {
-        double v = hx[(size_t)i * d + k];
-        REQUIRE(std::isfinite(v), "x has non-finite entries");
-        xl = std::min(xl, v);
-        xh = std::max(xh, v);
-        sum += v;
-      }
-      for (int j = 0; j < P.m0; ++j) {
-        double v = hy[(size_t)j * d + k];
-        REQUIRE(std::isfinite(v), "y has non-finite entries");
-        yl = std::min(yl, v);
-        yh = std::max(yh, v);
-        sum += v;
-      }
-      P.mu[k] = bf16_round(sum / (double)(P.n0 + P.m0));
-      double span = std::max(std::fabs(xh - yl), std::fabs(yh - xl));
+      const double* ox = &h[5 * (size_t)(2 + k)];
+      const double* oy = &h[5 * (size_t)(2 + d + k)];
+      REQUIRE(ox[3] == 0, "x has non-finite entries");
+      REQUIRE(oy[3] == 0, "y has non-finite entries");
+      P.mu[k] = bf16_round((ox[2] + oy[2]) / (double)(P.n0 + P.m0));
+      const double span = std::max(std::fabs(ox[1] - oy[0]), std::fabs(oy[1] - ox[0]));
       bound += span * span;
     }
     P.cmax = (float)(bound * P.cscale * 1.001 + 1e-30);
@@ -393,32 +384,12 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
     HIPCHK(launch_pack_points(P.X, n, P.d, w.mu, P.cscale64, P.dpad, parts, w.HX, w.MX, w.LX, w.NX, s));
     HIPCHK(launch_pack_points(P.Y, m, P.d, w.mu, P.cscale64, P.dpad, parts, w.HY, w.MY, w.LY, w.NY, s));
   }
-  // weights and log-weights (host FP64 log, uploaded)
-  std::vector<float> fx(n), fy(m);
-  std::vector<double> lx(n), ly(m);
-  std::vector<float2> dx(n), dy(m);
-  for (int i = 0; i < n; ++i) {
-    fx[i] = (float)P.hX[i];
-    lx[i] = std::log(P.hX[i]);
-    dx[i] = split_df(lx[i]);
-  }
-  for (int j = 0; j < m; ++j) {
-    fy[j] = (float)P.hY[j];
-    ly[j] = std::log(P.hY[j]);
-    dy[j] = split_df(ly[j]);
-  }
-  {
-    double mx = 0, my = 0;
-    for (int i = 0; i < n; ++i) mx = std::max(mx, std::fabs(lx[i]));
-    for (int j = 0; j < m; ++j) my = std::max(my, std::fabs(ly[j]));
-    w.lwb = (float)(mx + my);
-  }
-  HIPCHK(hipMemcpyAsync(w.wX32, fx.data(), 4 * n, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(w.wY32, fy.data(), 4 * m, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(w.lX64, lx.data(), 8 * n, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(w.lY64, ly.data(), 8 * m, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(w.lXdf, dx.data(), 8 * n, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(w.lYdf, dy.data(), 8 * m, hipMemcpyHostToDevice, s));
+  // weights: FP32 copies, FP64 logs and their double-float splits (device)
+  HIPCHK(launch_weight_prep(P.wX, n, w.wX32, w.lX64, w.lXdf, s));
+  HIPCHK(launch_weight_prep(P.wY, m, w.wY32, w.lY64, w.lYdf, s));
+  // max |log w| per side (log is monotone: at the smallest or largest weight)
+  w.lwb = (float)(std::max(std::fabs(std::log(P.wminX)), std::fabs(std::log(P.wmaxX))) +
+                  std::max(std::fabs(std::log(P.wminY)), std::fabs(std::log(P.wmaxY))));
   HIPCHK(hipStreamSynchronize(s));  // host vectors go out of scope
   return w;
 }
@@ -1194,8 +1165,8 @@ const sknr_problem* stage_problem(Ctx* c, const sknr_problem* pr, hipStream_t s,
   return tmp;
 }
 
-Prepared prepare_caller_orientation(const sknr_problem* prob, hipStream_t s) {
-  Prepared P = prepare(prob, s);
+Prepared prepare_caller_orientation(const sknr_problem* prob, hipStream_t s, void* scratch) {
+  Prepared P = prepare(prob, s, scratch);
   if (P.transposed) {
     P.transposed = false;
     P.n = P.n0;
@@ -1205,7 +1176,9 @@ Prepared prepare_caller_orientation(const sknr_problem* prob, hipStream_t s) {
     P.Y = prob->y;
     P.wX = prob->a;
     P.wY = prob->b;
-    std::swap(P.hX, P.hY);
+    std::swap(P.wminX, P.wminY);
+    std::swap(P.wmaxX, P.wmaxY);
+    std::swap(P.entX, P.entY);
   }
   return P;
 }
@@ -1478,6 +1451,7 @@ int sknr_ctx_create(int device, uint64_t hbm_budget_bytes, void** out) {
       size_t fr = 0, tot = 0;
       HIPCHK(hipMemGetInfo(&fr, &tot));
       c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * fr);
+      HIPCHK(hipMalloc(&c->prep, kPrepBytes));
       lane_init(&c->lane, device);
       lane_init(&c->lane_na, device);
       c->lane_na.use_graphs = false;
@@ -1487,6 +1461,7 @@ int sknr_ctx_create(int device, uint64_t hbm_budget_bytes, void** out) {
       lane_release(&c->lane);
       lane_release(&c->lane_na);
       if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+      if (c->prep) (void)hipFree(c->prep);
       delete c;
       throw;
     }
@@ -1508,6 +1483,7 @@ int sknr_ctx_destroy(void* ctx) {
     lane_release(&c->lane_na);
     if (c->order_ev) (void)hipEventDestroy(c->order_ev);
     if (c->stage) (void)hipFree(c->stage);
+    if (c->prep) (void)hipFree(c->prep);
     delete c;
     return SKNR_OK;
   });
@@ -1525,7 +1501,7 @@ int sknr_solve(void* ctx, const sknr_problem* prob, const sknr_opts* opts, doubl
     HIPCHK(hipStreamWaitEvent(s, c->order_ev, 0));
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare(prob, s);
+    Prepared P = prepare(prob, s, c->prep);
     check_opts(opts, P);
     return solve_on_lane(&c->lane, prob, P, opts, f_out, g_out, res);
   });
@@ -1540,7 +1516,7 @@ int sknr_c_transform_col(void* ctx, const sknr_problem* prob, double eps, const 
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     WS w = make_ws(&c->lane, P, 0, s);
     Engine E(&c->lane, P, w, s);
     E.eps = eps;
@@ -1571,7 +1547,7 @@ int sknr_c_transform_row(void* ctx, const sknr_problem* prob, double eps, const 
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     WS w = make_ws(&c->lane, P, 0, s);
     Engine E(&c->lane, P, w, s);
     E.eps = eps;
@@ -1593,7 +1569,7 @@ int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps, const
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     int ellp = ell_pad(ell);
     WS w = make_ws(&c->lane, P, ellp, s);
     Engine E(&c->lane, P, w, s);
@@ -1615,9 +1591,7 @@ int sknr_projected_system(void* ctx, const sknr_problem* prob, double eps, const
     if (grad_out) std::memcpy(grad_out, hg.data(), 8 * hg.size());
     if (qsemi_out) {
       // <f,a> + <g~,b> in paper convention: hat dots minus eps (<log a,a> + <log b,b>)
-      double ca = 0, cb = 0;
-      for (int i = 0; i < P.n; ++i) ca += P.hX[i] * std::log(P.hX[i]);
-      for (int j = 0; j < P.m; ++j) cb += P.hY[j] * std::log(P.hY[j]);
+      const double ca = P.entX, cb = P.entY;
       *qsemi_out = st.dots[DOT_F] + st.dots[DOT_GT] - eps * (ca + cb);
     }
     return SKNR_OK;
@@ -1633,7 +1607,7 @@ int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps, double* f_
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     int ellp = ell_pad(ell);
     WS w = make_ws(&c->lane, P, ellp, s);
     Engine E(&c->lane, P, w, s);
@@ -1646,9 +1620,7 @@ int sknr_newton_step(void* ctx, const sknr_problem* prob, double eps, double* f_
     E.newton(ell, 0);
     E.candidate(G_CHOL_OK);
     DevState st = E.read_state();
-    double ca = 0, cb = 0;
-    for (int i = 0; i < P.n; ++i) ca += P.hX[i] * std::log(P.hX[i]);
-    for (int j = 0; j < P.m; ++j) cb += P.hY[j] * std::log(P.hY[j]);
+    const double ca = P.entX, cb = P.entY;
     if (q0) *q0 = st.dots[DOT_F] + st.dots[DOT_GT] - eps * (ca + cb);
     if (q1) *q1 = st.chol_ok ? st.dots[DOT_FP] + st.dots[DOT_GP] - eps * (ca + cb) : NAN;
     if (accepted) *accepted = st.accept;
@@ -1671,7 +1643,7 @@ int sknr_newton_coef(void* ctx, const sknr_problem* prob, double eps, const doub
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     int ellp = ell_pad(ell);
     WS w = make_ws(&c->lane, P, ellp, s);
     Engine E(&c->lane, P, w, s);
@@ -1705,7 +1677,7 @@ int sknr_evaluate(void* ctx, const sknr_problem* prob, double eps, const double*
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     WS w = make_ws(&c->lane, P, 0, s);
     Engine E(&c->lane, P, w, s);
     E.eps = eps;
@@ -1735,7 +1707,7 @@ int sknr_gradient(void* ctx, const sknr_problem* prob, double eps, const double*
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     REQUIRE(!(grad_x || grad_y) || P.kind == SKNR_COST_SQEUCLID, "point gradients need a squared-Euclidean problem");
     WS w = make_ws(&c->lane, P, 32, s);
     Engine E(&c->lane, P, w, s);
@@ -1789,7 +1761,7 @@ int sknr_coupling(void* ctx, const sknr_problem* prob, double eps, const double*
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     WS w = make_ws(&c->lane, P, 0, s);
     Engine E(&c->lane, P, w, s);
     SweepArgs geo = E.caller_geo(prob);
@@ -1848,7 +1820,7 @@ int sknr_spectral_basis(void* ctx, const sknr_problem* prob, double eps, const d
     hipStream_t s = as_stream(stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, s, &staged);
-    Prepared P = prepare_caller_orientation(prob, s);
+    Prepared P = prepare_caller_orientation(prob, s, c->prep);
     REQUIRE(ell < std::min(P.n, P.m), "ell must be < min(n, m)");
     WS w = make_ws(&c->lane, P, ell_pad(ell), s);
     Engine E(&c->lane, P, w, s);

@@ -217,7 +217,9 @@ struct Prepared {
   std::vector<float> mu;  // centring point (bf16-rounded mean of all points)
   const double* wX;  // device FP64 weights
   const double* wY;
-  std::vector<double> hX, hY;  // host copies
+  // weight statistics (engine orientation): min, max, sum w log w
+  double wminX = 1, wmaxX = 1, wminY = 1, wmaxY = 1;
+  double entX = 0, entY = 0;
 };
 
 // A library context: the lane used by the synchronous entry points, the
@@ -226,6 +228,7 @@ struct Server;
 struct Ctx {
   int device = 0;
   uint64_t budget = 0;
+  void* prep = nullptr;  // kPrepBytes of device memory for prepare()
   // device copies of host-resident problem arrays (sknr_problem.on_host)
   char* stage = nullptr;
   size_t stage_cap = 0;
@@ -243,7 +246,12 @@ int ell_pad(int ell);
 void check_eps(double eps);
 // dmax_dev: optional device float for the stored-cost bound (null: a
 // stream-ordered allocation of 4 bytes)
-Prepared prepare(const sknr_problem* pr, hipStream_t s, float* dmax_dev = nullptr);
+// Validate a problem and gather what the solver needs about it; the input
+// checks (weights positive, finite and summing to 1, finite points or cost)
+// run on the device and come back in one read.  scratch: kPrepBytes of
+// device memory (the context's block, or the static array's tail).
+constexpr size_t kPrepBytes = 96 * 1024;
+Prepared prepare(const sknr_problem* pr, hipStream_t s, void* scratch);
 // A problem with host-resident arrays (on_host): copies them into the
 // context's staging block on stream s and returns *tmp describing the
 // device copies; any other problem is returned unchanged.

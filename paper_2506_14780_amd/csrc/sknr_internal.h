@@ -299,6 +299,12 @@ size_t sweep_part_floats(int n_out, int n_red, int ell, int cost_kind, int d, bo
                          int* nblk, bool stream_kernel);
 // split merge + scalar finishing kernels of a streaming sweep
 hipError_t launch_sweep_tail(const SweepArgs& a, hipStream_t stream);
+// input checks of prepare(): per weight vector and per point coordinate the
+// min, max, sum, bad-entry count and (weights) sum v log v, 5 doubles each,
+// (2 + 2d) records (x == nullptr: the two weight records only)
+hipError_t launch_input_stats(const double* a, int n, const double* b, int m, const float* x, const float* y, int d,
+                              double* out, hipStream_t s);
+hipError_t launch_weight_prep(const double* w, int n, float* w32, double* l64, float2* ldf, hipStream_t s);
 // The split merge (k_sweep_merge) gives each output merge_lanes(ell)
 // lanes, each merging a contiguous range of splits; a workgroup of
 // 64 * merge_lanes(ell) threads covers 64 outputs: merge_blocks(n_out)

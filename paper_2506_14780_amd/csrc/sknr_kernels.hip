@@ -1587,6 +1587,98 @@ hipError_t launch_cost_max(int cost_kind, const float* C, long long ldc, int n, 
   return hipGetLastError();
 }
 
+// Input statistics (prepare): block 0 covers the weights a (n), block 1
+// the weights b (m); with points, block 2 + k coordinate k of x and block
+// 2 + d + k coordinate k of y.  out[5 blk + 0 .. 4] = min, max, sum, the
+// count of bad entries (weights: not positive or not finite; points: not
+// finite) and, for weights, the entropy term sum v log v.  Each thread sums
+// its entries in index order, then a fixed tree (deterministic).
+__device__ __forceinline__ double block_reduce_d(double v, double* sbuf, int op) {  // op 0 sum, 1 min, 2 max
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v, off, 64);
+    v = op == 0 ? v + o : (op == 1 ? fmin(v, o) : fmax(v, o));
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sbuf[w] = v;
+  __syncthreads();
+  double r = sbuf[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = op == 0 ? r + sbuf[i] : (op == 1 ? fmin(r, sbuf[i]) : fmax(r, sbuf[i]));
+  return r;
+}
+__global__ __launch_bounds__(256) void k_input_stats(const double* a, int n, const double* b, int m, const float* x,
+                                                     const float* y, int d, double* out) {
+  __shared__ double sb[4];
+  const int blk = blockIdx.x;
+  double mn = INFINITY, mx = -INFINITY, sm = 0, bad = 0, ent = 0;
+  if (blk < 2) {
+    const double* w = blk == 0 ? a : b;
+    const int len = blk == 0 ? n : m;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+      const double v = w[i];
+      if (!(v > 0) || !isfinite(v)) {
+        bad += 1;
+      } else {
+        ent += v * log(v);
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+      }
+      sm += v;
+    }
+  } else {
+    const bool isy = blk - 2 >= d;
+    const int k = isy ? blk - 2 - d : blk - 2;
+    const float* pts = isy ? y : x;
+    const int len = isy ? m : n;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+      const double v = pts[(size_t)i * d + k];
+      if (!isfinite(v)) {
+        bad += 1;
+      } else {
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+      }
+      sm += v;
+    }
+  }
+  mn = block_reduce_d(mn, sb, 1);
+  mx = block_reduce_d(mx, sb, 2);
+  sm = block_reduce_d(sm, sb, 0);
+  bad = block_reduce_d(bad, sb, 0);
+  ent = block_reduce_d(ent, sb, 0);
+  if (threadIdx.x == 0) {
+    double* o = out + 5 * (size_t)blk;
+    o[0] = mn;
+    o[1] = mx;
+    o[2] = sm;
+    o[3] = bad;
+    o[4] = ent;
+  }
+}
+hipError_t launch_input_stats(const double* a, int n, const double* b, int m, const float* x, const float* y, int d,
+                              double* out, hipStream_t s) {
+  const int nb = 2 + (x ? 2 * d : 0);
+  hipLaunchKernelGGL(k_input_stats, dim3(nb), dim3(256), 0, s, a, n, b, m, x, y, x ? d : 1, out);
+  return hipGetLastError();
+}
+
+// weights -> FP32 copy, FP64 log and its double-float split
+__global__ void k_weight_prep(const double* w, int n, float* w32, double* l64, float2* ldf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = w[i];
+  const double l = log(v);
+  w32[i] = (float)v;
+  l64[i] = l;
+  const float hi = (float)l;
+  ldf[i] = make_float2(hi, (float)(l - (double)hi));
+}
+hipError_t launch_weight_prep(const double* w, int n, float* w32, double* l64, float2* ldf, hipStream_t s) {
+  hipLaunchKernelGGL(k_weight_prep, dim3((n + 255) / 256), dim3(256), 0, s, w, n, w32, l64, ldf);
+  return hipGetLastError();
+}
+
 __global__ void k_f32_to_f64(const float* s, double* d, long long cnt) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i < cnt) d[i] = s[i];

@@ -21,7 +21,7 @@ namespace sknr_host {
 
 namespace {
 constexpr size_t kScratchBytes = 64ull << 20;  // 64 MiB per device
-constexpr size_t kDmaxBytes = 256;             // tail: the stored-cost bound of prepare()
+constexpr size_t kTailBytes = kPrepBytes;      // tail: the scratch of prepare()
 static __device__ __align__(256) char scratch[kScratchBytes];
 
 std::mutex g_mu;
@@ -66,17 +66,17 @@ extern "C" int sknr_solve_noalloc(void* ctx, const sknr_problem* prob, const skn
     hipStream_t s = L->own;
     HIPCHK(hipEventRecord(c->order_ev, cs));
     HIPCHK(hipStreamWaitEvent(s, c->order_ev, 0));
-    // the stored-cost bound goes to the array's last bytes, the workspace
-    // below them
-    Prepared P = prepare(prob, s, reinterpret_cast<float*>(base + cap - kDmaxBytes));
+    // the scratch of prepare() goes to the array's last bytes, the
+    // workspace below them
+    Prepared P = prepare(prob, s, base + cap - kTailBytes);
     check_opts(opts, P);
     const size_t need = ws_bytes(P, ell_pad(opts->ell), nullptr);
-    if (need > cap - kDmaxBytes)
+    if (need > cap - kTailBytes)
       throw Err{SKNR_EINVAL, "workspace of " + std::to_string(need) + " bytes exceeds the " +
-                                 std::to_string((cap - kDmaxBytes) >> 20) +
+                                 std::to_string((cap - kTailBytes) >> 20) +
                                  " MiB limit of the allocation-free solve (use sknr_solve)"};
     L->arena.base = base;
-    L->arena.cap = cap - kDmaxBytes;
+    L->arena.cap = cap - kTailBytes;
     L->arena.off = 0;
     L->arena_external = true;
     L->use_graphs = false;  // graph instantiation may allocate

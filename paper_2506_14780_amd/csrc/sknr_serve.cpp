@@ -578,7 +578,7 @@ int sknr_submit(void* ctx, const sknr_problem* prob, const sknr_opts* opts, uint
     hipStream_t cs = as_stream(opts->stream);
     sknr_problem staged;
     prob = stage_problem(c, prob, cs, &staged);
-    Prepared P = prepare(prob, cs);
+    Prepared P = prepare(prob, cs, c->prep);
     check_opts(opts, P);
     Server* S = ensure_server(c);
     Request* r = new Request();
@@ -590,8 +590,10 @@ int sknr_submit(void* ctx, const sknr_problem* prob, const sknr_opts* opts, uint
       r->opts.eps = r->eps.data();
       r->opts.stream = nullptr;
       const size_t n0 = (size_t)P.n0, m0 = (size_t)P.m0;
-      r->ha = P.transposed ? P.hY : P.hX;
-      r->hb = P.transposed ? P.hX : P.hY;
+      r->ha.resize(n0);
+      r->hb.resize(m0);
+      HIPCHK(hipMemcpyAsync(r->ha.data(), prob->a, 8 * n0, hipMemcpyDeviceToHost, cs));
+      HIPCHK(hipMemcpyAsync(r->hb.data(), prob->b, 8 * m0, hipMemcpyDeviceToHost, cs));
       r->in_bytes = al(8 * n0) + al(8 * m0);
       if (prob->kind == SKNR_COST_STORED) {
         r->hC.resize(n0 * m0);
