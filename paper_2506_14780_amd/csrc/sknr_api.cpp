@@ -74,7 +74,7 @@ struct WS {
 // split partials of the fused single-read pass (floats), 0 when not eligible
 size_t fused_part_floats(const Prepared& P) {
   if (P.kind != SKNR_COST_STORED || P.ctrans || !fused_stored_ok(P.n, P.m, P.ldc, P.C)) return 0;
-  return (size_t)fused_stored_splits(P.n, P.m) * 3 * (size_t)P.m;
+  return (size_t)fused_stored_splits(P.n, P.m) * 2 * (size_t)P.m;  // one double per column and split
 }
 
 int ell_pad(int ell) { return ell <= 0 ? 0 : (ell <= 8 ? 8 : (ell <= 16 ? 16 : 32)); }
@@ -646,6 +646,8 @@ struct Engine {
     a.nblk = merge_blocks(P.m, 0);
     a.gate = G_NOT_DONE;
     a.flags = F_CHECK | F_COUNT | F_GSEL;
+    const char* all = getenv("SKNR_FUSED_EXACT_ALL");
+    if (all && all[0] == '1') a.flags |= F_EXACT_ALL;
     a.gsel_val = p;
     hipEvent_t e0 = nullptr, em = nullptr, e1 = nullptr;
     if (c->profile) {

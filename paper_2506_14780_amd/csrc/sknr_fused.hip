@@ -2,25 +2,37 @@
 //
 // The two-pass iteration reads C twice: g = T_c(f) by columns, then
 // f = T_r(g) by rows.  Here one pass reads each row of C once and does both
-// halves that touch it: the row's output f_i = T_r(g)_i (eq. foc_f), then,
-// with that f_i, the row's terms of the column log-sum-exp of T_c(f)
-// (eq. foc_g) for the next g.  A workgroup owns a contiguous block of rows
-// (a split of the column reduction) and keeps the running (max, S, Sc) of
-// its 4Q columns per thread in registers; the split partials then go
-// through the merge and finish kernels of the streaming column sweep, which
-// also test the pair (f, g_in) for convergence against g_out = T_c(f).
+// halves that touch it.  A workgroup owns a contiguous block of rows (a
+// split of the column reduction); each thread owns 4Q columns.
 //
-// Arithmetic of both halves is the one of the streaming sweeps: the reduce
-// side enters offset by L as a double-float (h, l) with l pre-scaled by
-// K = log2(e)/eps, the running max sigma is one of the values fl(h - C), so
-// h - sigma is exact and the exponent fma((h - sigma) - C, K, l K) is
-// rounded only relative to its own size.  The row half uses L_r from
-// max|g^|; the column half cannot know max|f^| before its rows exist and
-// uses the bound |f^_i| <= max|g^| + max|C| + eps (max|log a| + max|log b|)
-// (a c-transform lies between the extremes of g_j - C_ij), which the merge
-// kernel forms in the same order.
+// Row half: f_r = T_r(g)_r (eq. foc_f) by the arithmetic of the streaming
+// sweeps: the reduce side enters offset by L as a double-float (h, l) with
+// l pre-scaled by K = log2(e)/eps, the thread's running max sigma is one of
+// the values fl(h - C), so h - sigma is exact and the exponent
+// fma((h - sigma) - C, K, l K) is rounded only relative to its own size.
+// The terms t_rj = exp((g_j - C_rj - sigma_r)/eps) stay in the registers
+// that held the costs.
+//
+// Column half: with f_r = eps log a_r - eps log sum_j exp((g_j - C_rj)/eps),
+// the plan entry of the pair (f, g) is pi_rj = a_r t_rj / S_r (S_r the row
+// sum relative to the same max), and
+//   sum_r exp((f_r - C_rj)/eps) = exp(-g_j/eps) M_j,   M_j = sum_r pi_rj,
+// the column marginal of pi.  So the column half is one FP64 fma per
+// element: the split's M_j += (a_r / S_r) t_rj.  The merge kernel sums the
+// splits' M_j in split order and forms g'_j = g_j + eps log b_j - eps log M_j
+// (eq. foc_g) through the finalisation of the streaming sweeps, which also
+// tests the pair (f, g) for convergence (its L1 error is sum_j |M_j - b_j|).
+// M_j <= sum_r a_r = 1; an FP32 term t_rj below 2^-126 adds at most 2^-126
+// to M_j in all, so an M_j below 2^-100 is not resolved to FP32 accuracy.
+// For such a column the merge recomputes T_c(f)_j exactly from the column
+// of C and the f just written, by the online log-sum-exp of the streaming
+// sweeps.  It is rare: g = T_c(f_prev) gives a plan of (f_prev, g) with
+// column marginals b and row marginals r_i <= 1, and rescaling its rows to
+// a gives M_j = sum_i pi_ij a_i / r_i >= b_j min_i a_i, so only weights
+// whose products fall below 2^-100 take this path.
 #include "sknr_internal.h"
 #include "sknr_device.h"
+#include "sknr_sweep_tail.h"
 
 namespace sknr {
 
@@ -46,7 +58,6 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
   const EpsConst EC = eps_const(A.st);
   const float K = EC.K;
   const float Lr = sweep_offset(A.cmax, A.st->maxabs[MA_G]);
-  const float Lc = sweep_offset_bound(A, A.st->maxabs[MA_G], A.st->eps);
   const float2* G = A.Uold;
   for (int j2 = tid; j2 < (m >> 1); j2 += FT) {
     float4 u = reinterpret_cast<const float4*>(G)[j2];
@@ -59,13 +70,9 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
     sG4[j2] = make_float4(s0.x, s0.y * K, s1.x, s1.y * K);
   }
   constexpr int NC = 4 * Q;
-  float csig[NC], cS[NC], cSc[NC];
+  double cM[NC];  // this split's column sums of the plan entries
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    csig[k] = SIG0;
-    cS[k] = 0.f;
-    cSc[k] = 0.f;
-  }
+  for (int k = 0; k < NC; ++k) cM[k] = 0.0;
   const int r0 = blockIdx.x * A.rows_per_split;
   const int nr = min(A.rows_per_split, A.n_red - r0);
   for (int t = tid; t < nr; t += FT) {
@@ -122,6 +129,10 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
         const float p2 = ex2(fmaf((gb.x - tmax) - cur[4 * q + 2], K, gb.y));
         const float p3 = ex2(fmaf((gb.z - tmax) - cur[4 * q + 3], K, gb.w));
         tS += (p0 + p1) + (p2 + p3);
+        cur[4 * q] = p0;
+        cur[4 * q + 1] = p1;
+        cur[4 * q + 2] = p2;
+        cur[4 * q + 3] = p3;
       }
     }
     // wave state: the wave max, each lane's sum rescaled to it, then a
@@ -167,37 +178,13 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
     out = df_add_f(out, Lr);
     out = df_add(out, df_neg(t));
     if (tid == 0) sF[rl] = out;  // written out after the loop: no store in the loop
-    // ---- column half: this row's terms f^_r + L_c - C_rj
-    float2 hh = two_sum(Lc, out.x);
-    hh.y += out.y;
-    hh = fast_two_sum(hh.x, hh.y);
-    const float hc = hh.x, lcK = hh.y * K;
-    // a new column max is rare after the first rows: one test per row,
-    // then the rescale pass only when some lane needs it
-    bool up = false;
+    // ---- column half: pi_rj = (a_r / S_r) 2^((sigma_thread - sigma_r) K) t_rj
+    // (a thread whose max lies 2^149 below the row's adds zeros: at most
+    // 2^-149 a_r to any M_j)
+    const double wt = __hiloint2double(__float_as_int(wr.w), __float_as_int(wr.z)) / (double)rS *
+                      (double)ex2((tmax - rs) * K);
 #pragma unroll
-    for (int k = 0; k < NC; ++k) up |= hc - cur[k] > csig[k];
-    if (__any(up)) {
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const float sv = hc - cur[k];
-        const bool raise = sv > csig[k] && (FULL || 4 * (tid + FT * (k >> 2)) < m);
-        const float sc = raise ? ex2((csig[k] - sv) * K) : 1.f;
-        cS[k] *= sc;
-        cSc[k] *= sc;
-        csig[k] = raise ? sv : csig[k];
-      }
-    }
-    // S >= 1 >= p here (the split's max term is in S, every p <= 1 up to
-    // rounding), so Fast2Sum keeps the error term
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const float pk = ex2(fmaf((hc - csig[k]) - cur[k], K, lcK));
-      const float p = (FULL || 4 * (tid + FT * (k >> 2)) < m) ? pk : 0.f;
-      const float2 ts = fast_two_sum(cS[k], p);
-      cS[k] = ts.x;
-      cSc[k] += ts.y;
-    }
+    for (int k = 0; k < NC; ++k) cM[k] = fma(wt, (double)cur[k], cM[k]);
   };
   int rl = 0;
   for (; rl + 1 < nr; rl += 2) {
@@ -218,22 +205,119 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
       maxF = fmaxf(maxF, fabsf(o.x));
     }
   }
-  // split partials [split][3][m] for the merge kernel (float4 stores)
+  // split partials M[split][m] (FP64) for the merge kernel
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int j0 = 4 * (tid + FT * q);
     if (j0 < m) {
-      float* base = A.part + (size_t)blockIdx.x * 3 * m + j0;
-      *reinterpret_cast<float4*>(base) = make_float4(csig[4 * q], csig[4 * q + 1], csig[4 * q + 2], csig[4 * q + 3]);
-      *reinterpret_cast<float4*>(base + m) = make_float4(cS[4 * q], cS[4 * q + 1], cS[4 * q + 2], cS[4 * q + 3]);
-      *reinterpret_cast<float4*>(base + 2 * (size_t)m) =
-          make_float4(cSc[4 * q], cSc[4 * q + 1], cSc[4 * q + 2], cSc[4 * q + 3]);
+      double2* base = reinterpret_cast<double2*>(reinterpret_cast<double*>(A.part) + (size_t)blockIdx.x * m + j0);
+      base[0] = make_double2(cM[4 * q], cM[4 * q + 1]);
+      base[1] = make_double2(cM[4 * q + 2], cM[4 * q + 3]);
     }
   }
   if (tid == 0) {
     const_cast<double*>(A.aux_blkdot)[blockIdx.x] = dotF;
     const_cast<float*>(A.aux_blkmax)[blockIdx.x] = maxF;
   }
+}
+
+// Merge of the single-read pass: M_j = the splits' column sums in split
+// order (four lanes per column, each a contiguous range of splits, then a
+// neighbour-first shuffle tree: deterministic), then the finalisation of a
+// streaming column sweep with a fixed max.  With sigma_j = fl(L - g_j.hi)
+// (exact: |g_j| <= L/3, Sterbenz) and d_j = (sigma_j - L) + g_j.hi its exact
+// rounding error, exp((sigma_j - L)/eps) S_j = exp(-g_j/eps) M_j for
+// S_j = M_j 2^(-(d_j + g_j.lo) K), so the finalisation's
+// eps log w_j - (sigma_j - L) - eps log S_j is g'_j = T_c(f)_j (eq. foc_g).
+// A column with M_j below 2^-100 (or not finite) takes the exact path: its
+// four lanes run the online (max, sum) over contiguous row ranges of f^ + L
+// - C_rj (the streaming sweeps' arithmetic) and merge them in lane order.
+__global__ __launch_bounds__(256) void k_fused_merge(SweepArgs A) {
+  if (gate_closed(A.st, A.gate)) return;
+  constexpr int LPO = 4, OPB = 64, BATCH = 16;
+  const EpsConst EC = eps_const(A.st);
+  const float K = EC.K;
+  const int n_out = A.n_out, ns = A.nsplit;
+  const int col = blockIdx.x * OPB + (int)threadIdx.x / LPO, part = (int)threadIdx.x % LPO;
+  const int colc = min(col, n_out - 1);
+  const int per = (ns + LPO - 1) / LPO;
+  const int s0 = part * per, s1 = min(ns, s0 + per);
+  const double* pp = reinterpret_cast<const double*>(A.part) + colc;
+  double M = 0.0;
+  for (int sp0 = s0; sp0 < s1; sp0 += BATCH) {
+    double v[BATCH];
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q) v[q] = pp[(size_t)min(sp0 + q, ns - 1) * n_out];
+#pragma unroll
+    for (int q = 0; q < BATCH; ++q)
+      if (sp0 + q < s1) M += v[q];
+  }
+#pragma unroll
+  for (int off = 1; off < LPO; off <<= 1) {
+    const double o = __shfl_xor(M, off, 64);
+    M = (part & off) == 0 ? M + o : o + M;
+  }
+  const float L = sweep_offset_bound(A, A.st->maxabs[A.ma_in], A.st->eps);
+  // the same decision in the column's four lanes (same M)
+  const bool exact = (A.flags & F_EXACT_ALL) || !(M >= 0x1p-100);
+  float sg = SIG0, Ss = 0.f, Sx = 0.f;
+  if (exact && col < n_out) {
+    const int nr = A.n_red, per_r = (nr + LPO - 1) / LPO;
+    const int r0 = part * per_r, r1 = min(nr, r0 + per_r);
+    for (int r = r0; r < r1; ++r) {
+      const float2 fu = A.Uin[r];
+      float2 hh = two_sum(L, fu.x);
+      hh.y += fu.y;
+      hh = fast_two_sum(hh.x, hh.y);
+      const float c = A.C[(size_t)r * A.ldc + col];
+      const float v = hh.x - c;
+      if (v > sg) {
+        const float sc = ex2((sg - v) * K);
+        Ss *= sc;
+        Sx *= sc;
+        sg = v;
+      }
+      const float2 t = two_sum(Ss, ex2(fmaf((hh.x - sg) - c, K, hh.y * K)));
+      Ss = t.x;
+      Sx += t.y;
+    }
+  }
+  // lanes in order (every lane takes part in the shuffles)
+#pragma unroll
+  for (int off = 1; off < LPO; off <<= 1) {
+    const float sg2 = __shfl_xor(sg, off, 64), S2 = __shfl_xor(Ss, off, 64), C2 = __shfl_xor(Sx, off, 64);
+    float f1, f2;
+    if ((part & off) == 0) {
+      lse_merge(sg, Ss, Sx, sg2, S2, C2, K, f1, f2);
+    } else {
+      float t1 = sg2, t2 = S2, t3 = C2;
+      lse_merge(t1, t2, t3, sg, Ss, Sx, K, f1, f2);
+      sg = t1;
+      Ss = t2;
+      Sx = t3;
+    }
+  }
+  double err = 0, dot = 0;
+  float mxo = 0.f;
+  if (col < n_out && part == 0) {
+    if (exact) {
+      finalize_output<0>(A, EC, col, L, sg, Ss, Sx, nullptr, err, dot, mxo);
+    } else {
+      const float2 go = A.Uold[col];
+      const float sig = L - go.x;
+      const float dl = (sig - L) + go.x;
+      const double Ms = M * (double)ex2(-(dl + go.y) * K);
+      const float S = (float)Ms;
+      finalize_output<0>(A, EC, col, L, sig, S, (float)(Ms - (double)S), nullptr, err, dot, mxo);
+    }
+  }
+  __shared__ double sbd[8];
+  __shared__ float sbf[4];
+  err = block_sum_d(err, sbd);
+  dot = block_sum_d(dot, sbd + 4);
+  mxo = block_max_f(mxo, sbf);
+  write_block_scalars(A, blockIdx.x, err, dot, mxo);
+  if (arrive_last(A.st, A.nblk)) sweep_finish_body(A);
 }
 
 constexpr int kMaxRowsPerSplit = 1024;  // row outputs held in LDS until the end of the pass
@@ -260,8 +344,8 @@ size_t fused_stored_lds(int n_out, int rows_per_split) {
 template <int Q, int FT>
 static hipError_t go_fused(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
   const size_t sm = fused_stored_lds(a.n_out, a.rows_per_split);
-  // the unmasked form of the 256-register variant spills: masks there
-  const bool full = a.n_out == 4 * FT * Q && FT == 1024;
+  // the unmasked form of the 128-register 16-column variant spills: masks there
+  const bool full = a.n_out == 4 * FT * Q && FT == 1024 && Q <= 2;
   const void* fn = (const void*)k_sk_fused_stored<Q, FT, false>;
   if constexpr (FT == 1024) {
     if (full) fn = (const void*)k_sk_fused_stored<Q, FT, true>;
@@ -275,7 +359,8 @@ static hipError_t go_fused(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
     hipLaunchKernelGGL((k_sk_fused_stored<Q, FT, false>), dim3(a.nsplit), dim3(FT), sm, s, a);
   }
   if (mid) (void)hipEventRecord(mid, s);
-  return launch_sweep_tail(a, s);
+  hipLaunchKernelGGL(k_fused_merge, dim3((a.n_out + 63) / 64), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_sk_fused_stored(const SweepArgs& a, hipStream_t s, hipEvent_t mid) {
@@ -287,11 +372,10 @@ hipError_t launch_sk_fused_stored(const SweepArgs& a, hipStream_t s, hipEvent_t 
     return hipErrorInvalidValue;
   if (a.rows_per_split * (long long)(a.nsplit - 1) >= a.n_red || a.rows_per_split * (long long)a.nsplit < a.n_red)
     return hipErrorInvalidValue;
-  // 1024 threads while the columns of a thread fit in 128 registers, then
-  // 512 threads with twice the columns (256 registers)
+  // 1024 threads (four waves per SIMD) with 4, 8 or 16 columns each
   if (a.n_out <= 4096) return go_fused<1, 1024>(a, s, mid);
   if (a.n_out <= 8192) return go_fused<2, 1024>(a, s, mid);
-  return go_fused<8, 512>(a, s, mid);
+  return go_fused<4, 1024>(a, s, mid);
 }
 
 }  // namespace sknr

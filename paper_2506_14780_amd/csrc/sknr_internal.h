@@ -60,8 +60,10 @@ enum SweepFlag {
   F_CHECK = 1,       // compare the L1 error with tol and set done (col sweeps)
   F_COUNT = 2,       // count this sweep in npass
   F_GSEL = 4,        // record gsel_val into state->gsel when setting done
-  F_ACCEPT_DQ = 16    // after this sweep decide the Newton acceptance test from Q(f') - Q(f)
+  F_ACCEPT_DQ = 16,   // after this sweep decide the Newton acceptance test from Q(f') - Q(f)
                       // formed without cancellation (W_CAND sweep)
+  F_EXACT_ALL = 32    // single-read pass: take every column through the merge's exact
+                      // per-column path (the one for columns the pass cannot resolve)
 };
 // W_CAND: the sweep runs on f with the single basis column expm1((f' - f)/eps)
 // and writes the candidate T_c(f') = T_c(f) - eps log1p(w) instead of W

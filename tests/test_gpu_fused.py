@@ -78,3 +78,76 @@ def test_fused_pass_matches_two_pass_and_oracle(sk, ctx, n, m, ladder, full_orac
         d = np.abs(f1h[rows] - fr).max()
         print(f"rows: max|f - T_r(g)| = {d:.2e}", flush=True)
         assert d <= 64 * 2.0 ** -24 * ladder[-1] + 1e-12 * np.abs(f1h).max()
+
+
+@pytest.mark.parametrize("n,m", [(300, 400), (1000, 4100)])
+def test_fused_pass_exact_column_path(sk, ctx, n, m):
+    """Every column of every single-read pass through the merge's exact
+    per-column path (SKNR_FUSED_EXACT_ALL=1; in normal runs it serves only
+    columns whose plan marginal falls below 2^-100): the online log-sum-exp
+    over the column of C from the pass's f.  The loop takes the two-pass
+    iteration counts to the same optimum."""
+    C, a, b = _stored(n, m, seed=n + m + 1)
+    gp = sk.Problem(a=to_dev(a), b=to_dev(b), C=to_dev(C))
+    ladder = [5e-2, 2e-2]
+    print(f"case exact columns {n}x{m}", flush=True)
+    try:
+        os.environ["SKNR_NO_FUSED"] = "1"
+        f0, g0, r0 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=100000)
+    finally:
+        os.environ.pop("SKNR_NO_FUSED", None)
+    try:
+        os.environ["SKNR_FUSED_EXACT_ALL"] = "1"
+        f1, g1, r1 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=100000)
+    finally:
+        os.environ.pop("SKNR_FUSED_EXACT_ALL", None)
+    f2, g2, r2 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=100000)
+    it0 = [s["iters"] for s in r0["stages"]]
+    it1 = [s["iters"] for s in r1["stages"]]
+    it2 = [s["iters"] for s in r2["stages"]]
+    C64 = C.astype(np.float64)
+    f1h, g1h = f1.cpu().numpy(), g1.cpu().numpy()
+    e01 = e_pot(f0.cpu().numpy(), g0.cpu().numpy(), f1h, g1h, C64)
+    e12 = e_pot(f1h, g1h, f2.cpu().numpy(), g2.cpu().numpy(), C64)
+    print(f"two-pass {it0}, exact columns {it1}, plan sums {it2}, e_pot {e01:.2e} / {e12:.2e}", flush=True)
+    assert r1["status"] == 0 and r1["marginal_err"] < 1e-6
+    for x, y, z in zip(it1, it0, it2):
+        assert abs(x - y) <= 1 and abs(x - z) <= 1
+    assert e01 <= 1e-5 and e12 <= 1e-5
+
+
+def test_fused_pass_tiny_column_weight(sk, ctx):
+    """A column of weight 1e-40 has a plan marginal M_j near 1e-40, below
+    the 2^-100 that the pass's FP32 terms resolve: the merge computes that
+    column by its exact per-column path in every pass, and the loop
+    matches the two-pass iteration and the oracle's optimum."""
+    n, m = 300, 400
+    C, a, b = _stored(n, m, seed=77)
+    b[5] = 1e-40
+    b /= b.sum()
+    gp = sk.Problem(a=to_dev(a), b=to_dev(b), C=to_dev(C))
+    ladder = [5e-2, 2e-2]
+    print("case column weight 1e-40", flush=True)
+    try:
+        os.environ["SKNR_NO_FUSED"] = "1"
+        f0, g0, r0 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=100000)
+    finally:
+        os.environ.pop("SKNR_NO_FUSED", None)
+    f1, g1, r1 = sk.solve(ctx, gp, ladder, tol=1e-6, max_iter=100000)
+    it0 = [s["iters"] for s in r0["stages"]]
+    it1 = [s["iters"] for s in r1["stages"]]
+    C64 = C.astype(np.float64)
+    f1h, g1h = f1.cpu().numpy(), g1.cpu().numpy()
+    e01 = e_pot(f0.cpu().numpy(), g0.cpu().numpy(), f1h, g1h, C64)
+    fs, gs, _ = O.solve_schedule(C64, a, b, ladder, 1e-11, 1000000)
+    e1 = e_pot(f1h, g1h, fs, gs, C64)
+    print(f"two-pass {it0}, fused {it1}, e_pot between them {e01:.2e}, vs the oracle {e1:.2e}", flush=True)
+    assert r1["status"] == 0 and r1["marginal_err"] < 1e-6
+    for x, y in zip(it1, it0):
+        assert abs(x - y) <= 1
+    assert e01 <= 1e-5 and e1 <= 1e-5
+    # the light column itself: the two loops agree there to well within one
+    # step's change near convergence (~eps times the relative marginal error)
+    d5 = abs(g1h[5] - g0.cpu().numpy()[5])
+    print(f"light column: |g_fused - g_two_pass| = {d5:.2e}", flush=True)
+    assert np.isfinite(g1h).all() and d5 <= 1e-4 * ladder[-1]
