@@ -7,11 +7,17 @@
 //
 // Row half: f_r = T_r(g)_r (eq. foc_f) by the arithmetic of the streaming
 // sweeps: the reduce side enters offset by L as a double-float (h, l) with
-// l pre-scaled by K = log2(e)/eps, the thread's running max sigma is one of
-// the values fl(h - C), so h - sigma is exact and the exponent
-// fma((h - sigma) - C, K, l K) is rounded only relative to its own size.
-// The terms t_rj = exp((g_j - C_rj - sigma_r)/eps) stay in the registers
-// that held the costs.
+// l pre-scaled by K = log2(e)/eps, and the terms
+// t_rj = exp((g^_j + L - C_rj - sigma_r)/eps) are formed as
+// ex2(fma((h - sigma_r) - C, K, l K)), with h - sigma_r exact (both lie in
+// [L/2, 2L]), so the exponent is rounded only relative to its own size.
+// The shift needs no max pass: g = T_c(f^prev) for the previous pass's row
+// output f^prev, so every plan entry of (f^prev, g) is at most b_j, and
+// sigma_r = L - f^prev_r + eps log a_r bounds the terms by b_j / a_r while
+// their sum S_r (that plan's row marginal over a_r) is at least min_j b_j.
+// A row whose S_r falls outside [2^-24, 2^24] (extreme weights) is redone
+// with its own max as the shift.  The t_rj stay in the registers that held
+// the costs.
 //
 // Column half: with f_r = eps log a_r - eps log sum_j exp((g_j - C_rj)/eps),
 // the plan entry of the pair (f, g) is pi_rj = a_r t_rj / S_r (S_r the row
@@ -22,14 +28,15 @@
 // splits' M_j in split order and forms g'_j = g_j + eps log b_j - eps log M_j
 // (eq. foc_g) through the finalisation of the streaming sweeps, which also
 // tests the pair (f, g) for convergence (its L1 error is sum_j |M_j - b_j|).
-// M_j <= sum_r a_r = 1; an FP32 term t_rj below 2^-126 adds at most 2^-126
-// to M_j in all, so an M_j below 2^-100 is not resolved to FP32 accuracy.
+// M_j <= sum_r a_r = 1; an FP32 term t_rj below 2^-126 adds at most
+// 2^-126 a_r / S_r <= 2^-102 a_r to M_j, at most 2^-102 in all, so an M_j
+// below 2^-76 is not resolved to FP32 accuracy (relative 2^-26).
 // For such a column the merge recomputes T_c(f)_j exactly from the column
 // of C and the f just written, by the online log-sum-exp of the streaming
 // sweeps.  It is rare: g = T_c(f_prev) gives a plan of (f_prev, g) with
 // column marginals b and row marginals r_i <= 1, and rescaling its rows to
 // a gives M_j = sum_i pi_ij a_i / r_i >= b_j min_i a_i, so only weights
-// whose products fall below 2^-100 take this path.
+// whose products fall below 2^-76 take this path.
 #include "sknr_internal.h"
 #include "sknr_device.h"
 #include "sknr_sweep_tail.h"
@@ -49,9 +56,10 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
   if (gate_closed(A.st, A.gate)) return;
   extern __shared__ float4 fsm4[];
   float4* sG4 = fsm4;                                            // m/2 float4: (h, lK) pairs of g^ + L_r
-  float* xs = reinterpret_cast<float*>(fsm4 + (A.n_out >> 1));    // [2][FW][2] wave states
+  float* xs = reinterpret_cast<float*>(fsm4 + (A.n_out >> 1));    // [2][FW] wave sums, [2][FW] max-shift path
   float2* sF = reinterpret_cast<float2*>(xs + 2 * kMaxWaves * 3);  // this split's row outputs
   float4* sW = reinterpret_cast<float4*>(sF + A.rows_per_split);   // per row: (log a as double-float, a as FP64)
+  float* sP = reinterpret_cast<float*>(sW + A.rows_per_split);     // per row: the shift sigma_r
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = A.n_out;
@@ -75,10 +83,16 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
   for (int k = 0; k < NC; ++k) cM[k] = 0.0;
   const int r0 = blockIdx.x * A.rows_per_split;
   const int nr = min(A.rows_per_split, A.n_red - r0);
+  // shift of row r: L_r - f^prev_r + eps log a_r, f^prev the previous pass's
+  // row output (so g = T_c(f^prev)), kept in [L_r - max|g^| - cmax,
+  // L_r + max|g^|] (there every h - sigma is exact)
+  const float mg = A.st->maxabs[MA_G];
   for (int t = tid; t < nr; t += FT) {
     const float2 lw = A.lw_red[r0 + t];
     const double w = A.w_red64[r0 + t];
     sW[t] = make_float4(lw.x, lw.y, __int_as_float(__double2loint(w)), __int_as_float(__double2hiint(w)));
+    const float sg = (Lr - A.Uin[r0 + t].x) + (float)A.st->eps * lw.x;
+    sP[t] = fminf(fmaxf(sg, Lr - mg - A.cmax), Lr + mg);
   }
   float cv[NC], cn[NC];
   auto load_row = [&](int rl, float* dst) __attribute__((always_inline)) {
@@ -105,29 +119,20 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
     // unconditional (the last row reloads itself), so that the wait for cur
     // can count exactly the Q younger loads
     load_row(min(rl + 1, nr - 1), nxt);
-    // ---- row half: (sigma, S) of this thread's terms of row r, g^ + L_r - C
-    float tmax = SIG0;
+    // ---- row half: the terms t_rj = 2^((g^_j + L_r - C_rj - sigma_r) K) of
+    // row r and their sum S_r (fixed butterfly: the same value in every wave)
+    float sig = sP[rl];
+    float tS = 0.f;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int j2 = 2 * (tid + FT * q);
       if (FULL || 4 * (tid + FT * q) < m) {
         const float4 ga = sG4[j2];
         const float4 gb = sG4[j2 + 1];
-        tmax = fmaxf(fmaxf(fmaxf(tmax, ga.x - cur[4 * q]), ga.z - cur[4 * q + 1]),
-                     fmaxf(gb.x - cur[4 * q + 2], gb.z - cur[4 * q + 3]));
-      }
-    }
-    float tS = 0.f;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int j2 = 2 * (tid + FT * q);
-      if (FULL || 4 * (tid + FT * q) < m) {
-        float4 ga = sG4[j2];
-        float4 gb = sG4[j2 + 1];
-        const float p0 = ex2(fmaf((ga.x - tmax) - cur[4 * q], K, ga.y));
-        const float p1 = ex2(fmaf((ga.z - tmax) - cur[4 * q + 1], K, ga.w));
-        const float p2 = ex2(fmaf((gb.x - tmax) - cur[4 * q + 2], K, gb.y));
-        const float p3 = ex2(fmaf((gb.z - tmax) - cur[4 * q + 3], K, gb.w));
+        const float p0 = ex2(fmaf((ga.x - sig) - cur[4 * q], K, ga.y));
+        const float p1 = ex2(fmaf((ga.z - sig) - cur[4 * q + 1], K, ga.w));
+        const float p2 = ex2(fmaf((gb.x - sig) - cur[4 * q + 2], K, gb.y));
+        const float p3 = ex2(fmaf((gb.z - sig) - cur[4 * q + 3], K, gb.w));
         tS += (p0 + p1) + (p2 + p3);
         cur[4 * q] = p0;
         cur[4 * q + 1] = p1;
@@ -135,54 +140,84 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
         cur[4 * q + 3] = p3;
       }
     }
-    // wave state: the wave max, each lane's sum rescaled to it, then a
-    // fixed butterfly sum (all lanes end with the same values)
-    const float wmax = wave_max(tmax);
-    float S = tS * ex2((tmax - wmax) * K);
-    S = wave_sum(S);
-    float* slot = xs + (par * FW + wave) * 2;
-    if (lane == 0) {
-      slot[0] = wmax;
-      slot[1] = S;
-    }
+    const int src = lane & (FW - 1);
+    float S = wave_sum(tS);
+    if (lane == 0) xs[par * FW + wave] = S;
     // barrier on the LDS writes only: the prefetch of the next row stays in
     // flight (__syncthreads would also wait for every outstanding global load)
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    // every wave merges the FW wave states with the same FW-lane butterfly
-    // (the same result in every wave); states of the other parity are
-    // written only after the next barrier, so one barrier per row suffices
-    const float* xp = xs + par * FW * 2;
-    const int src = lane & (FW - 1);
-    const float ws = xp[2 * src];
-    float rs = ws;
-#pragma unroll
-    for (int off = FW / 2; off > 0; off >>= 1) rs = fmaxf(rs, __shfl_xor(rs, off, 64));
-    float rS = xp[2 * src + 1] * ex2((ws - rs) * K);
+    // sums of the other parity are written only after the next barrier, so
+    // one barrier per row suffices
+    float rS = xs[par * FW + src];
 #pragma unroll
     for (int off = FW / 2; off > 0; off >>= 1) rS += __shfl_xor(rS, off, 64);
-    const float rSc = 0.f;
+    // S_r = (row marginal of the plan of (f^prev, g)) / a_r >= min_j b_j and
+    // every term <= b_j / a_r; outside [2^-24, 2^24] (extreme weights, or a
+    // clamped shift) the row is redone with its own max as the shift (then
+    // S_r >= 1)
+    if (!(rS >= 0x1p-24f && rS <= 0x1p24f) || (A.flags & F_EXACT_ALL)) {
+      load_row(rl, cur);
+      float tmax = SIG0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int j2 = 2 * (tid + FT * q);
+        if (FULL || 4 * (tid + FT * q) < m) {
+          const float4 ga = sG4[j2];
+          const float4 gb = sG4[j2 + 1];
+          tmax = fmaxf(fmaxf(fmaxf(tmax, ga.x - cur[4 * q]), ga.z - cur[4 * q + 1]),
+                       fmaxf(gb.x - cur[4 * q + 2], gb.z - cur[4 * q + 3]));
+        }
+      }
+      float* xf = xs + 2 * FW;
+      const float wm = wave_max(tmax);
+      if (lane == 0) xf[wave] = wm;
+      __syncthreads();
+      sig = xf[src];
+#pragma unroll
+      for (int off = FW / 2; off > 0; off >>= 1) sig = fmaxf(sig, __shfl_xor(sig, off, 64));
+      tS = 0.f;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int j2 = 2 * (tid + FT * q);
+        if (FULL || 4 * (tid + FT * q) < m) {
+          const float4 ga = sG4[j2];
+          const float4 gb = sG4[j2 + 1];
+          const float p0 = ex2(fmaf((ga.x - sig) - cur[4 * q], K, ga.y));
+          const float p1 = ex2(fmaf((ga.z - sig) - cur[4 * q + 1], K, ga.w));
+          const float p2 = ex2(fmaf((gb.x - sig) - cur[4 * q + 2], K, gb.y));
+          const float p3 = ex2(fmaf((gb.z - sig) - cur[4 * q + 3], K, gb.w));
+          tS += (p0 + p1) + (p2 + p3);
+          cur[4 * q] = p0;
+          cur[4 * q + 1] = p1;
+          cur[4 * q + 2] = p2;
+          cur[4 * q + 3] = p3;
+        }
+      }
+      S = wave_sum(tS);
+      if (lane == 0) xf[FW + wave] = S;
+      __syncthreads();
+      rS = xf[FW + src];
+#pragma unroll
+      for (int off = FW / 2; off > 0; off >>= 1) rS += __shfl_xor(rS, off, 64);
+    }
     // f^_r = eps log a_r - eps log sum exp((g^ - C)/eps), as double-float:
-    // eps lw_r - (sigma - L_r) - eps ln2 log2(S + Sc)
+    // eps lw_r - (sigma - L_r) - eps ln2 log2(S)
     int ke;
     float mant = frexpf(rS, &ke);
     if (mant < 0.70710678f) {
       mant *= 2.f;
       ke -= 1;
     }
-    float2 l2 = fast_two_sum((float)ke, lg2(mant));
-    l2.y += (rSc / rS) * 1.4426950408889634f;
+    const float2 l2 = fast_two_sum((float)ke, lg2(mant));
     const float2 t = df_mul(EC.eln2_df, l2);
     const float4 wr = sW[rl];
     float2 out = df_mul(EC.eps_df, make_float2(wr.x, wr.y));
-    out = df_add_f(out, -rs);
+    out = df_add_f(out, -sig);
     out = df_add_f(out, Lr);
     out = df_add(out, df_neg(t));
     if (tid == 0) sF[rl] = out;  // written out after the loop: no store in the loop
-    // ---- column half: pi_rj = (a_r / S_r) 2^((sigma_thread - sigma_r) K) t_rj
-    // (a thread whose max lies 2^149 below the row's adds zeros: at most
-    // 2^-149 a_r to any M_j)
-    const double wt = __hiloint2double(__float_as_int(wr.w), __float_as_int(wr.z)) / (double)rS *
-                      (double)ex2((tmax - rs) * K);
+    // ---- column half: pi_rj = (a_r / S_r) t_rj
+    const double wt = __hiloint2double(__float_as_int(wr.w), __float_as_int(wr.z)) / (double)rS;
 #pragma unroll
     for (int k = 0; k < NC; ++k) cM[k] = fma(wt, (double)cur[k], cM[k]);
   };
@@ -229,7 +264,7 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
 // rounding error, exp((sigma_j - L)/eps) S_j = exp(-g_j/eps) M_j for
 // S_j = M_j 2^(-(d_j + g_j.lo) K), so the finalisation's
 // eps log w_j - (sigma_j - L) - eps log S_j is g'_j = T_c(f)_j (eq. foc_g).
-// A column with M_j below 2^-100 (or not finite) takes the exact path: its
+// A column with M_j below 2^-76 (or not finite) takes the exact path: its
 // four lanes run the online (max, sum) over contiguous row ranges of f^ + L
 // - C_rj (the streaming sweeps' arithmetic) and merge them in lane order.
 __global__ __launch_bounds__(256) void k_fused_merge(SweepArgs A) {
@@ -259,7 +294,7 @@ __global__ __launch_bounds__(256) void k_fused_merge(SweepArgs A) {
   }
   const float L = sweep_offset_bound(A, A.st->maxabs[A.ma_in], A.st->eps);
   // the same decision in the column's four lanes (same M)
-  const bool exact = (A.flags & F_EXACT_ALL) || !(M >= 0x1p-100);
+  const bool exact = (A.flags & F_EXACT_ALL) || !(M >= 0x1p-76);
   float sg = SIG0, Ss = 0.f, Sx = 0.f;
   if (exact && col < n_out) {
     const int nr = A.n_red, per_r = (nr + LPO - 1) / LPO;
@@ -338,7 +373,7 @@ int fused_stored_splits(int n_red, int n_out) {
 
 size_t fused_stored_lds(int n_out, int rows_per_split) {
   return (size_t)(n_out / 2) * sizeof(float4) + 2 * kMaxWaves * 3 * sizeof(float) +
-         (size_t)rows_per_split * (sizeof(float2) + sizeof(float4));
+         (size_t)rows_per_split * (sizeof(float2) + sizeof(float4) + sizeof(float));
 }
 
 template <int Q, int FT>

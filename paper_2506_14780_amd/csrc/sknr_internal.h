@@ -62,8 +62,9 @@ enum SweepFlag {
   F_GSEL = 4,        // record gsel_val into state->gsel when setting done
   F_ACCEPT_DQ = 16,   // after this sweep decide the Newton acceptance test from Q(f') - Q(f)
                       // formed without cancellation (W_CAND sweep)
-  F_EXACT_ALL = 32    // single-read pass: take every column through the merge's exact
-                      // per-column path (the one for columns the pass cannot resolve)
+  F_EXACT_ALL = 32    // single-read pass: take every row through the max-shift path and
+                      // every column through the merge's exact per-column path (the
+                      // paths for rows and columns that the fixed shifts cannot resolve)
 };
 // W_CAND: the sweep runs on f with the single basis column expm1((f' - f)/eps)
 // and writes the candidate T_c(f') = T_c(f) - eps log1p(w) instead of W

@@ -82,11 +82,12 @@ def test_fused_pass_matches_two_pass_and_oracle(sk, ctx, n, m, ladder, full_orac
 
 @pytest.mark.parametrize("n,m", [(300, 400), (1000, 4100)])
 def test_fused_pass_exact_column_path(sk, ctx, n, m):
-    """Every column of every single-read pass through the merge's exact
-    per-column path (SKNR_FUSED_EXACT_ALL=1; in normal runs it serves only
-    columns whose plan marginal falls below 2^-100): the online log-sum-exp
-    over the column of C from the pass's f.  The loop takes the two-pass
-    iteration counts to the same optimum."""
+    """Every row of every single-read pass through the max-shift path and
+    every column through the merge's exact per-column path
+    (SKNR_FUSED_EXACT_ALL=1; in normal runs they serve only rows whose sum
+    under the fixed shift leaves [2^-24, 2^24] and columns whose plan
+    marginal falls below 2^-76): the loop takes the two-pass iteration
+    counts to the same optimum."""
     C, a, b = _stored(n, m, seed=n + m + 1)
     gp = sk.Problem(a=to_dev(a), b=to_dev(b), C=to_dev(C))
     ladder = [5e-2, 2e-2]
@@ -118,7 +119,7 @@ def test_fused_pass_exact_column_path(sk, ctx, n, m):
 
 def test_fused_pass_tiny_column_weight(sk, ctx):
     """A column of weight 1e-40 has a plan marginal M_j near 1e-40, below
-    the 2^-100 that the pass's FP32 terms resolve: the merge computes that
+    the 2^-76 that the pass's FP32 terms resolve: the merge computes that
     column by its exact per-column path in every pass, and the loop
     matches the two-pass iteration and the oracle's optimum."""
     n, m = 300, 400
