@@ -62,22 +62,25 @@ def algorithmic_work(kind: str):
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the counts of a
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 GiB -> x2.0, WRITE_SIZE 1 GiB
 # -> x1.0); see profiles/.  Valid only for the kernel sources they were
-# taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip).
-TRAFFIC_KERNEL_SHA1 = "03a148350c08d6ed594616526ee26460ddff488f"
+# taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip,
+# sknr_fused.hip, sknr_sweep_tail.h).
+TRAFFIC_KERNEL_SHA1 = "6ebe7da014a7ba939b874033e3ec21ece8cd2b71"
 TRAFFIC_BYTES = {
-    "sweep_stream_points_l0:main": (243.02 * 1.9999 + 2062.17 * 1.0000) * 1024,
-    "sweep_stream_stored_l0:main": (524979.54 * 1.9999 + 6144.00 * 1.0000) * 1024,
-    "sweep_rows_stored_l0:main": (525905.74 * 1.9999 + 530.00 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x3_l0:main": (91854.47 * 1.9999 + 6223.99 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x6_l0:main": (140410.91 * 1.9999 + 6226.26 * 1.0000) * 1024,
-    "sweep_stream_points_bf16_l0:main": (25527.18 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_l0:main": (340.70 * 1.9999 + 2846.24 * 1.0000) * 1024,
+    "sweep_stream_stored_l0:main": (524971.63 * 1.9999 + 6144.00 * 1.0000) * 1024,
+    "sweep_rows_stored_l0:main": (519393.28 * 1.9999 + 694.02 * 1.0000) * 1024,
+    "sk_fused_stored:main": (524737.95 * 1.9999 + 32893.32 * 1.0000) * 1024,
+    "sk_fused_stored": ((524737.95 + 16673.19) * 1.9999 + (32893.32 + 160.02) * 1.0000) * 1024,
+    "sweep_stream_points_bf16x3_l0:main": (91039.04 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x6_l0:main": (140234.99 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_bf16_l0:main": (24415.03 * 1.9999 + 6223.96 * 1.0000) * 1024,
 }
 
 
 def kernel_traffic(name):
     import hashlib
     h = hashlib.sha1()
-    for f in ("sknr_device.h", "sknr_kernels.hip", "sknr_mfma.hip"):
+    for f in ("sknr_device.h", "sknr_kernels.hip", "sknr_mfma.hip", "sknr_fused.hip", "sknr_sweep_tail.h"):
         h.update(open(os.path.join(ROOT, "paper_2506_14780_amd", "csrc", f), "rb").read())
     if h.hexdigest() != TRAFFIC_KERNEL_SHA1:
         return None
@@ -384,14 +387,18 @@ def stored_sweep_roofline(sk, ctx, side=128, reps=10):
     # the workload's solves: cold plain SK at eps' = 1e-3, then eps = 5e-4 with
     # warm SK or warm SK-NR(16) (sequential warm start), tol 1e-6
     solves = {}
+    f_conv = None
     for name, ell in (("sk", 0), ("sknr16", 16)):
         ts, res = [], None
         for rep in range(3):
             t0 = time.perf_counter()
-            res = sk.solve(ctx, gp, [1e-3, 5e-4], tol=1e-6, max_iter=100000, ell=ell, warm_mode=sk.WARM_SEQUENTIAL)[2]
+            f_out, _, res = sk.solve(ctx, gp, [1e-3, 5e-4], tol=1e-6, max_iter=100000, ell=ell,
+                                     warm_mode=sk.WARM_SEQUENTIAL)
             torch.cuda.synchronize()
             if rep:
                 ts.append(time.perf_counter() - t0)
+        if ell == 0:
+            f_conv = f_out
         st = res["stages"]
         solves[name] = {"solves_per_s": 1.0 / float(np.median(ts)), "ms": 1e3 * float(np.median(ts)),
                         "iters_per_stage": [x["iters"] for x in st], "stage_ms": [1e3 * x["seconds"] for x in st],
@@ -399,6 +406,24 @@ def stored_sweep_roofline(sk, ctx, side=128, reps=10):
                         "marginal_err": res["marginal_err"],
                         "stage2_iters_per_s": st[1]["iters"] / st[1]["seconds"]}
     solves["speedup_sknr_vs_sk"] = solves["sknr16"]["solves_per_s"] / solves["sk"]["solves_per_s"]
+    # the single-read SK pass (one read of C per iteration: f = T_r(g) by rows
+    # and the column sums of T_c(f) from the same read, then the column
+    # merge), timed over 40 passes from the converged potentials at eps 5e-4;
+    # algorithmic bytes = 4 per cost element
+    ctx.profile(True)
+    sk.solve(ctx, gp, [5e-4], tol=1e-12, max_iter=40, f0=f_conv)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    for e in prof:
+        if e["name"] not in ("sk_fused_stored:main", "sk_fused_stored"):
+            continue
+        avg_s = e["total_ms"] / e["launches"] / 1e3
+        gbs = 4.0 * n * m / avg_s / 1e9
+        out[e["name"]] = {"avg_launch_us": avg_s * 1e6, "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": gbs / PEAK_HBM_GBS, "bytes_per_launch": 4.0 * n * m,
+                          "traffic": kernel_traffic(e["name"])}
+        if e["name"] == "sk_fused_stored":
+            out[e["name"]]["iters_per_s"] = 1.0 / avg_s
     del gp
     torch.cuda.empty_cache()
     return {"workload": f"grid_histograms {side}x{side} (n=m={side*side}), stored FP32 cost, eps 5e-4",
@@ -645,14 +670,18 @@ def main():
         out["gradient"] = {"ms": 1e3 * (time.perf_counter() - t0) / 10,
                            "what": "sknr_gradient of W_eps with respect to x, y, a, b at the solution"}
     if not args.no_stored:
+        print("bench: stored-cost leg", file=sys.stderr, flush=True)
         out["roofline_stored_cost"] = stored_sweep_roofline(sk, ctx)
     if not args.no_mfma:
+        print("bench: matrix-core cost leg", file=sys.stderr, flush=True)
         out["roofline_mfma_cost"] = mfma_sweep_roofline(sk, W, torch)
     if not args.no_stored:
         out["roofline_points_large"] = points_sweep_large(sk, W, torch)
     if not args.no_serve:
+        print("bench: serving leg", file=sys.stderr, flush=True)
         out["serving"] = serving_bench(sk, W, torch, args.serve_requests, args.serve_lanes, args.tol)
     if not args.no_paper:
+        print("bench: Sec. 5 workloads leg", file=sys.stderr, flush=True)
         out["paper_workloads"] = paper_workloads_bench(sk, W, torch, args.tol)
     if not args.no_paper:
         out["c1"] = c1_bench(sk, W, torch)
