@@ -27,6 +27,10 @@ namespace sknr_host {
 thread_local std::string g_last_error;
 
 struct WS {
+  // transposed copy of a stored cost (or null): the sweeps whose outputs
+  // run along the stored rows use the streaming kernel on it (row pitch ldx)
+  const float* X;
+  long long ldx;
   float2 *F, *Fsk, *Fp, *G[2], *Gt, *Gp;
   float* mdiff;
   float* mdiffY;  // column-side marginal differences (gradients)
@@ -204,13 +208,19 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   // weighted sweeps run l-wide (Newton) or up to 32-wide (warm start)
   const int ellw = ellp > 0 ? 32 : 0;
   // T_c (output Y), with and without weights
+  // (a stored cost may also run its rows-orientation sweeps on the
+  // streaming kernel over a transposed copy: both geometries are sized)
+  const bool both = P.kind == SKNR_COST_STORED;
   for (int e : {0, ellp > 0 ? 8 : 0, ellp > 0 ? 16 : 0, ellp, ellw}) {
-    size_t p = sweep_part_floats(m, n, e, sweep_kind(P), P.d, stream_vec(P, m), &ns, &rps, &nb, col_is_stream(P));
-    pmax = std::max(pmax, p);
-    nbmax = std::max(nbmax, nb);
-    p = sweep_part_floats(n, m, e, sweep_kind(P), P.d, stream_vec(P, n), &ns, &rps, &nb, row_is_stream(P));
-    pmax = std::max(pmax, p);
-    nbmax = std::max(nbmax, nb);
+    for (int k = 0; k < (both ? 2 : 1); ++k) {
+      const bool cs = k ? !col_is_stream(P) : col_is_stream(P), rs = k ? !row_is_stream(P) : row_is_stream(P);
+      size_t p = sweep_part_floats(m, n, e, sweep_kind(P), P.d, stream_vec(P, m), &ns, &rps, &nb, cs);
+      pmax = std::max(pmax, p);
+      nbmax = std::max(nbmax, nb);
+      p = sweep_part_floats(n, m, e, sweep_kind(P), P.d, stream_vec(P, n), &ns, &rps, &nb, rs);
+      pmax = std::max(pmax, p);
+      nbmax = std::max(nbmax, nb);
+    }
   }
   nbmax = std::max(nbmax, (std::max(n, m) + 255) / 256 + 1);
   pmax = std::max(pmax, fused_part_floats(P));
@@ -390,6 +400,34 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
   // max |log w| per side (log is monotone: at the smallest or largest weight)
   w.lwb = (float)(std::max(std::fabs(std::log(P.wminX)), std::fabs(std::log(P.wmaxX))) +
                   std::max(std::fabs(std::log(P.wminY)), std::fabs(std::log(P.wmaxY))));
+  // a large stored cost used with weighted sweeps (SK-NR, warm start): a
+  // transposed copy, so that the sweeps along its rows stream (the rows
+  // kernel re-reads the l-wide basis for every output row).  Lanes on a
+  // lent block (serving) keep the rows kernel, so a served request on a
+  // stored cost above 2^24 elements can differ from its solo run in the
+  // last bits (both within the sweeps' accuracy)
+  w.X = nullptr;
+  w.ldx = 0;
+  const char* nox = getenv("SKNR_NO_XCOST");
+  if (P.kind == SKNR_COST_STORED && ellp > 0 && !c->arena_external && (size_t)n * m >= ((size_t)1 << 24) &&
+      !(nox && nox[0] == '1')) {
+    const int rows = P.ctrans ? m : n, cols = P.ctrans ? n : m;
+    const size_t bytes = sizeof(float) * (size_t)rows * cols;
+    if (bytes > c->xcost_cap) {
+      HIPCHK(hipStreamSynchronize(s));
+      c->drop_graphs();  // captured sweeps may point at the old copy
+      if (c->xcost) HIPCHK(hipFree(c->xcost));
+      c->xcost = nullptr;
+      c->xcost_cap = 0;
+      if (hipMalloc((void**)&c->xcost, bytes) == hipSuccess) c->xcost_cap = bytes;
+      else (void)hipGetLastError();  // no copy: the rows kernel serves
+    }
+    if (c->xcost) {
+      HIPCHK(launch_transpose_cost(P.C, P.ldc, rows, cols, c->xcost, s));
+      w.X = c->xcost;
+      w.ldx = rows;
+    }
+  }
   HIPCHK(hipStreamSynchronize(s));  // host vectors go out of scope
   return w;
 }
@@ -493,6 +531,7 @@ struct Engine {
     a.gsel_val = gsel_val;
     bool st = col_is_stream(P);
     bool vec = stream_vec(P, a.n_out);
+    use_transposed(a, st, vec);
     sweep_part_floats(a.n_out, a.n_red, ell, sweep_kind(P), P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
     launch_sweep(a, st, vec, ell);
   }
@@ -532,8 +571,18 @@ struct Engine {
     a.flags = flags;
     bool st = row_is_stream(P);
     bool vec = stream_vec(P, a.n_out);
+    use_transposed(a, st, vec);
     sweep_part_floats(a.n_out, a.n_red, ell, sweep_kind(P), P.d, vec, &a.nsplit, &a.rows_per_split, &a.nblk, st);
     launch_sweep(a, st, vec, ell);
+  }
+  // a sweep whose outputs run along the stored rows streams over the
+  // transposed copy when there is one (element (r, o) = X[r ldx + o])
+  void use_transposed(SweepArgs& a, bool& st, bool& vec) const {
+    if (st || !w.X) return;
+    a.C = w.X;
+    a.ldc = w.ldx;
+    st = true;
+    vec = a.n_out % 4 == 0 && w.ldx % 4 == 0;
   }
 
   void set_consts(DevState& z) const {
@@ -813,6 +862,7 @@ struct Engine {
     key.Y = P.Y;
     key.wX = P.wX;
     key.wY = P.wY;
+    key.xcost = w.X;
     key.ldc = P.ldc;
     key.n = P.n;
     key.m = P.m;
@@ -1396,6 +1446,9 @@ void lane_release(Lane* L) {
   if (L->arena.base && !L->arena_external) (void)hipFree(L->arena.base);
   L->arena.base = nullptr;
   L->arena.cap = 0;
+  if (L->xcost) (void)hipFree(L->xcost);
+  L->xcost = nullptr;
+  L->xcost_cap = 0;
   if (L->st_host) (void)hipHostFree(L->st_host);
   L->st_host = nullptr;
   if (L->arg_pinned) (void)hipHostFree(L->arg_pinned);

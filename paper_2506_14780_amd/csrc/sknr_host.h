@@ -81,6 +81,7 @@ struct GraphKey {
   const void* Y;
   const void* wX;
   const void* wY;
+  const void* xcost;  // transposed copy of a stored cost used by the sweeps (or null)
   long long ldc;
   int n, m, d, kind, ell, ellp, iters, ctrans;
   float cscale, cmax;
@@ -131,6 +132,10 @@ struct Lane {
   hipEvent_t ev_in = nullptr, ev_done = nullptr;
   Arena arena;                   // workspace (owned, or a block lent by the serving pool)
   bool arena_external = false;   // true: never reallocated or freed here
+  // transposed copy of a large stored cost for the weighted sweeps along its
+  // rows (owned lanes only; rebuilt by every call that uses it)
+  float* xcost = nullptr;
+  size_t xcost_cap = 0;
   hipStream_t own = nullptr;     // solver stream (default priority); graphs are captured on it
   bool use_graphs = true;
   const std::atomic<int>* cancel = nullptr;  // serving: abort flag polled between chunks

@@ -290,6 +290,8 @@ struct SelectArgs {
 hipError_t launch_sweep_stream(const SweepArgs& a, int cost_kind, bool vec, hipStream_t stream,
                                hipEvent_t mid = nullptr);
 hipError_t launch_sweep_rows(const SweepArgs& a, hipStream_t stream, hipEvent_t mid = nullptr);
+// X (cols x rows, row pitch rows) = the transpose of the stored cost C (rows x cols, row pitch ldc)
+hipError_t launch_transpose_cost(const float* C, long long ldc, int rows, int cols, float* X, hipStream_t stream);
 // One SK iteration over a stored cost with a single read of C: rows of C
 // (side X, not transposed) produce f = T_r(Uold) into Uin, and each row's
 // terms join the column log-sum-exp of T_c(f); merge and finish as a

@@ -1587,6 +1587,33 @@ hipError_t launch_cost_max(int cost_kind, const float* C, long long ldc, int n, 
   return hipGetLastError();
 }
 
+// Transposed copy of a stored cost: X[j * rows + i] = C[i * ldc + j] for
+// i < rows, j < cols, through 64 x 64 LDS tiles (coalesced reads of C's
+// rows and of X's rows; the odd row pitch keeps the column reads of the
+// tile free of bank conflicts).  The weighted sweeps whose outputs run
+// along C's rows then take the streaming kernel on X.
+__global__ __launch_bounds__(256) void k_transpose_cost(const float* __restrict__ C, long long ldc, int rows, int cols,
+                                                        float* __restrict__ X) {
+  __shared__ float t[64][65];
+  const int j0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    t[r][tx] = (i < rows && j < cols) ? C[(size_t)i * ldc + j] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int j = j0 + r, i = i0 + tx;
+    if (j < cols && i < rows) X[(size_t)j * rows + i] = t[tx][r];
+  }
+}
+hipError_t launch_transpose_cost(const float* C, long long ldc, int rows, int cols, float* X, hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || ldc < cols) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose_cost, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, s, C, ldc, rows, cols,
+                     X);
+  return hipGetLastError();
+}
+
 // Input statistics (prepare): block 0 covers the weights a (n), block 1
 // the weights b (m); with points, block 2 + k coordinate k of x and block
 // 2 + d + k coordinate k of y.  out[5 blk + 0 .. 4] = min, max, sum, the
