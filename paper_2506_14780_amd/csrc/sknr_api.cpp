@@ -71,6 +71,7 @@ struct WS {
   // max|log a| + max|log b| for the bound on |f^|
   double* fz_dot;
   float* fz_max;
+  float* fz_rowmax;  // per row of the reduce side: log2 of its largest term (the pass's shift)
   float lwb;
   unsigned char* argbank;  // argument blocks of a recorded batch unit
 };
@@ -226,6 +227,7 @@ size_t ws_bytes(const Prepared& P, int ellp, int* geo) {
   pmax = std::max(pmax, fused_part_floats(P));
   add(sizeof(double) * 256);
   add(sizeof(float) * 256);
+  add(sizeof(float) * n);
   add((size_t)kMaxUnitLaunches * kMaxArgBytes);
   add(sizeof(float2) * n * 3);
   add(sizeof(float2) * m);
@@ -325,6 +327,7 @@ WS make_ws(Lane* c, const Prepared& P, int ellp, hipStream_t s) {
   pmax = std::max(pmax, fused_part_floats(P));
   w.fz_dot = (double*)A.take(sizeof(double) * 256);
   w.fz_max = (float*)A.take(sizeof(float) * 256);
+  w.fz_rowmax = (float*)A.take(sizeof(float) * n);
   w.argbank = (unsigned char*)A.take((size_t)kMaxUnitLaunches * kMaxArgBytes);
   w.part = (float*)A.take(sizeof(float) * pmax + 16);
   w.blk_err = (double*)A.take(sizeof(double) * nbmax);
@@ -676,6 +679,7 @@ struct Engine {
     a.lpad_e = w.lwb * 1.01f;
     a.aux_blkdot = w.fz_dot;
     a.aux_blkmax = w.fz_max;
+    a.rowmax = w.fz_rowmax;
     a.aux_blkddot = nullptr;
     a.aux_dot_slot = DOT_F;
     a.aux_ma_slot = MA_F;
@@ -752,6 +756,8 @@ struct Engine {
   // with one read of C per iteration.  G ends in w.G[0].
   int run_stage_fused(int max_iter, int check_every, bool* converged) {
     init_state_keep();
+    // no row maxima yet (NaN): the first pass takes each row's max as its shift
+    HIPCHK(hipMemsetAsync(w.fz_rowmax, 0xff, sizeof(float) * P.n, s));
     sweep_col(w.F, MA_F, w.G[0], w.G[1], DOT_G, MA_G, 0, nullptr, nullptr, W_NONE, G_NOT_DONE,
               F_CHECK | F_COUNT | F_GSEL, 0);
     int p = 1, launched = 0, chunk = check_every > 0 ? check_every : 4;

@@ -56,10 +56,12 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
   if (gate_closed(A.st, A.gate)) return;
   extern __shared__ float4 fsm4[];
   float4* sG4 = fsm4;                                            // m/2 float4: (h, lK) pairs of g^ + L_r
-  float* xs = reinterpret_cast<float*>(fsm4 + (A.n_out >> 1));    // [2][FW] wave sums, [2][FW] max-shift path
+  float* xs = reinterpret_cast<float*>(fsm4 + (A.n_out >> 1));    // [2][FW][2] wave (sum, max), [2][FW] max-shift path
   float2* sF = reinterpret_cast<float2*>(xs + 2 * kMaxWaves * 3);  // this split's row outputs
   float4* sW = reinterpret_cast<float4*>(sF + A.rows_per_split);   // per row: (log a as double-float, a as FP64)
   float* sP = reinterpret_cast<float*>(sW + A.rows_per_split);     // per row: the shift sigma_r
+  float* sE = sP + A.rows_per_split;                                // per row: the shift above the base (log2), NaN: none yet
+  float* sB = sE + A.rows_per_split;                                // per row: the base shift
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int m = A.n_out;
@@ -83,16 +85,24 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
   for (int k = 0; k < NC; ++k) cM[k] = 0.0;
   const int r0 = blockIdx.x * A.rows_per_split;
   const int nr = min(A.rows_per_split, A.n_red - r0);
-  // shift of row r: L_r - f^prev_r + eps log a_r, f^prev the previous pass's
-  // row output (so g = T_c(f^prev)), kept in [L_r - max|g^| - cmax,
-  // L_r + max|g^|] (there every h - sigma is exact)
+  // shift of row r: the base L_r - f^prev_r + eps log a_r (f^prev the
+  // previous pass's row output, so g = T_c(f^prev)) raised by the previous
+  // pass's log2 of the row's largest term, so that the largest terms sit
+  // near 1; kept in [L_r - max|g^| - cmax, L_r + max|g^|] (there every
+  // h - sigma is exact).  A row with no recorded maximum (NaN: the first
+  // pass of a stage) takes the max-shift path.
   const float mg = A.st->maxabs[MA_G];
+  const float eln2 = (float)(A.st->eps * 0.6931471805599453);
   for (int t = tid; t < nr; t += FT) {
     const float2 lw = A.lw_red[r0 + t];
     const double w = A.w_red64[r0 + t];
     sW[t] = make_float4(lw.x, lw.y, __int_as_float(__double2loint(w)), __int_as_float(__double2hiint(w)));
-    const float sg = (Lr - A.Uin[r0 + t].x) + (float)A.st->eps * lw.x;
-    sP[t] = fminf(fmaxf(sg, Lr - mg - A.cmax), Lr + mg);
+    const float base = (Lr - A.Uin[r0 + t].x) + (float)A.st->eps * lw.x;
+    const float e0 = A.rowmax[r0 + t];
+    const bool known = e0 == e0;
+    sB[t] = base;
+    sE[t] = known ? 0.f : __int_as_float(0x7fc00000);
+    sP[t] = fminf(fmaxf(base + (known ? e0 : 0.f) * eln2, Lr - mg - A.cmax), Lr + mg);
   }
   float cv[NC], cn[NC];
   auto load_row = [&](int rl, float* dst) __attribute__((always_inline)) {
@@ -122,17 +132,22 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
     // ---- row half: the terms t_rj = 2^((g^_j + L_r - C_rj - sigma_r) K) of
     // row r and their sum S_r (fixed butterfly: the same value in every wave)
     float sig = sP[rl];
-    float tS = 0.f;
+    // read before this row's barrier: thread 0 rewrites sE[rl] after it
+    // (every wave takes the same branch below)
+    const bool known = sE[rl] == sE[rl];
+    float tS = 0.f, tY = SIG0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int j2 = 2 * (tid + FT * q);
       if (FULL || 4 * (tid + FT * q) < m) {
         const float4 ga = sG4[j2];
         const float4 gb = sG4[j2 + 1];
-        const float p0 = ex2(fmaf((ga.x - sig) - cur[4 * q], K, ga.y));
-        const float p1 = ex2(fmaf((ga.z - sig) - cur[4 * q + 1], K, ga.w));
-        const float p2 = ex2(fmaf((gb.x - sig) - cur[4 * q + 2], K, gb.y));
-        const float p3 = ex2(fmaf((gb.z - sig) - cur[4 * q + 3], K, gb.w));
+        const float y0 = fmaf((ga.x - sig) - cur[4 * q], K, ga.y);
+        const float y1 = fmaf((ga.z - sig) - cur[4 * q + 1], K, ga.w);
+        const float y2 = fmaf((gb.x - sig) - cur[4 * q + 2], K, gb.y);
+        const float y3 = fmaf((gb.z - sig) - cur[4 * q + 3], K, gb.w);
+        tY = fmaxf(fmaxf(tY, fmaxf(y0, y1)), fmaxf(y2, y3));
+        const float p0 = ex2(y0), p1 = ex2(y1), p2 = ex2(y2), p3 = ex2(y3);
         tS += (p0 + p1) + (p2 + p3);
         cur[4 * q] = p0;
         cur[4 * q + 1] = p1;
@@ -142,20 +157,27 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
     }
     const int src = lane & (FW - 1);
     float S = wave_sum(tS);
-    if (lane == 0) xs[par * FW + wave] = S;
+    const float Y = wave_max(tY);
+    if (lane == 0) {
+      xs[(par * FW + wave) * 2] = S;
+      xs[(par * FW + wave) * 2 + 1] = Y;
+    }
     // barrier on the LDS writes only: the prefetch of the next row stays in
     // flight (__syncthreads would also wait for every outstanding global load)
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    // sums of the other parity are written only after the next barrier, so
-    // one barrier per row suffices
-    float rS = xs[par * FW + src];
+    // states of the other parity are written only after the next barrier,
+    // so one barrier per row suffices
+    float rS = xs[(par * FW + src) * 2], rY = xs[(par * FW + src) * 2 + 1];
 #pragma unroll
-    for (int off = FW / 2; off > 0; off >>= 1) rS += __shfl_xor(rS, off, 64);
+    for (int off = FW / 2; off > 0; off >>= 1) {
+      rS += __shfl_xor(rS, off, 64);
+      rY = fmaxf(rY, __shfl_xor(rY, off, 64));
+    }
     // S_r = (row marginal of the plan of (f^prev, g)) / a_r >= min_j b_j and
     // every term <= b_j / a_r; outside [2^-24, 2^24] (extreme weights, or a
     // clamped shift) the row is redone with its own max as the shift (then
     // S_r >= 1)
-    if (!(rS >= 0x1p-24f && rS <= 0x1p24f) || (A.flags & F_EXACT_ALL)) {
+    if (!known || !(rS >= 0x1p-24f && rS <= 0x1p24f) || (A.flags & F_EXACT_ALL)) {
       load_row(rl, cur);
       float tmax = SIG0;
 #pragma unroll
@@ -168,7 +190,7 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
                        fmaxf(gb.x - cur[4 * q + 2], gb.z - cur[4 * q + 3]));
         }
       }
-      float* xf = xs + 2 * FW;
+      float* xf = xs + 4 * FW;
       const float wm = wave_max(tmax);
       if (lane == 0) xf[wave] = wm;
       __syncthreads();
@@ -199,7 +221,12 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
       rS = xf[FW + src];
 #pragma unroll
       for (int off = FW / 2; off > 0; off >>= 1) rS += __shfl_xor(rS, off, 64);
+      // the largest term is now 2^(l K) ~ 1
+      rY = 0.f;
     }
+    // the next pass's shift above its base: this shift's, plus the largest
+    // term's exponent (written after the loop)
+    if (tid == 0) sE[rl] = (sig - sB[rl]) * K + rY;
     // f^_r = eps log a_r - eps log sum exp((g^ - C)/eps), as double-float:
     // eps lw_r - (sigma - L_r) - eps ln2 log2(S)
     int ke;
@@ -228,7 +255,10 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
   }
   if (rl < nr) row(rl, 0, cv, cn);
   __syncthreads();
-  for (int t = tid; t < nr; t += FT) const_cast<float2*>(A.Uin)[r0 + t] = sF[t];
+  for (int t = tid; t < nr; t += FT) {
+    const_cast<float2*>(A.Uin)[r0 + t] = sF[t];
+    A.rowmax[r0 + t] = sE[t];
+  }
   // the split's <f^, a> and max |f^.hi| in row order
   double dotF = 0;
   float maxF = 0.f;
@@ -262,7 +292,7 @@ __global__ __launch_bounds__(FT) void k_sk_fused_stored(SweepArgs A) {
 // streaming column sweep with a fixed max.  With sigma_j = fl(L - g_j.hi)
 // (exact: |g_j| <= L/3, Sterbenz) and d_j = (sigma_j - L) + g_j.hi its exact
 // rounding error, exp((sigma_j - L)/eps) S_j = exp(-g_j/eps) M_j for
-// S_j = M_j 2^(-(d_j + g_j.lo) K), so the finalisation's
+// S_j = M_j exp(-(d_j + g_j.lo)/eps) (in FP64), so the finalisation's
 // eps log w_j - (sigma_j - L) - eps log S_j is g'_j = T_c(f)_j (eq. foc_g).
 // A column with M_j below 2^-76 (or not finite) takes the exact path: its
 // four lanes run the online (max, sum) over contiguous row ranges of f^ + L
@@ -341,7 +371,10 @@ __global__ __launch_bounds__(256) void k_fused_merge(SweepArgs A) {
       const float2 go = A.Uold[col];
       const float sig = L - go.x;
       const float dl = (sig - L) + go.x;
-      const double Ms = M * (double)ex2(-(dl + go.y) * K);
+      // the factor is within ~1e-3 of 1: in FP64 (an FP32 rounding of it
+      // would put a 6e-8 relative error on every column's M_j, a floor under
+      // the L1 error)
+      const double Ms = M * exp(-((double)dl + (double)go.y) / A.st->eps);
       const float S = (float)Ms;
       finalize_output<0>(A, EC, col, L, sig, S, (float)(Ms - (double)S), nullptr, err, dot, mxo);
     }
@@ -373,7 +406,7 @@ int fused_stored_splits(int n_red, int n_out) {
 
 size_t fused_stored_lds(int n_out, int rows_per_split) {
   return (size_t)(n_out / 2) * sizeof(float4) + 2 * kMaxWaves * 3 * sizeof(float) +
-         (size_t)rows_per_split * (sizeof(float2) + sizeof(float4) + sizeof(float));
+         (size_t)rows_per_split * (sizeof(float2) + sizeof(float4) + 3 * sizeof(float));
 }
 
 template <int Q, int FT>

@@ -151,6 +151,9 @@ struct SweepArgs {
   const double* w_red64;
   float lpad_c;
   float lpad_e;
+  // fused pass: per reduce-side row, log2 of its largest term relative to
+  // L - f^ + eps log w (read for the row's shift, then rewritten)
+  float* rowmax;
 };
 
 // offset L of a sweep: 3 (cmax + bound on |Uin|), with the fused pass's
