@@ -11,17 +11,23 @@
 // t_rj = exp((g^_j + L - C_rj - sigma_r)/eps) are formed as
 // ex2(fma((h - sigma_r) - C, K, l K)), with h - sigma_r exact (both lie in
 // [L/2, 2L]), so the exponent is rounded only relative to its own size.
-// The shift needs no max pass: g = T_c(f^prev) for the previous pass's row
-// output f^prev, so every plan entry of (f^prev, g) is at most b_j, and
-// sigma_r = L - f^prev_r + eps log a_r bounds the terms by b_j / a_r while
+// The shift needs no max pass.  g = T_c(f^prev) for the previous pass's row
+// output f^prev, so every plan entry of (f^prev, g) is at most b_j, and the
+// base shift L - f^prev_r + eps log a_r bounds the terms by b_j / a_r while
 // their sum S_r (that plan's row marginal over a_r) is at least min_j b_j.
-// A row whose S_r falls outside [2^-24, 2^24] (extreme weights) is redone
-// with its own max as the shift.  The t_rj stay in the registers that held
-// the costs.
+// Each pass also records log2 of the row's largest term (one max per
+// element) and the next pass raises its base by it, so that the largest
+// terms sit near 1 and their exponents are rounded as finely as under a
+// max shift (with the base alone the exponents of a row's main terms lie
+// several binades down, and the rounding of their arguments left a 1.6e-7
+// floor on the L1 error).  A row with no recorded maximum (the first pass
+// of a stage) or whose S_r falls outside [2^-24, 2^24] is redone with its
+// own max as the shift.  The t_rj stay in the registers that held the
+// costs.
 //
 // Column half: with f_r = eps log a_r - eps log sum_j exp((g_j - C_rj)/eps),
 // the plan entry of the pair (f, g) is pi_rj = a_r t_rj / S_r (S_r the row
-// sum relative to the same max), and
+// sum relative to the same shift), and
 //   sum_r exp((f_r - C_rj)/eps) = exp(-g_j/eps) M_j,   M_j = sum_r pi_rj,
 // the column marginal of pi.  So the column half is one FP64 fma per
 // element: the split's M_j += (a_r / S_r) t_rj.  The merge kernel sums the
