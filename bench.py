@@ -64,16 +64,16 @@ def algorithmic_work(kind: str):
 # -> x1.0); see profiles/.  Valid only for the kernel sources they were
 # taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip,
 # sknr_fused.hip, sknr_sweep_tail.h).
-TRAFFIC_KERNEL_SHA1 = "6ebe7da014a7ba939b874033e3ec21ece8cd2b71"
+TRAFFIC_KERNEL_SHA1 = "2229e84be4ad6efe3ea1d9890eb8cca4ba6baf2e"
 TRAFFIC_BYTES = {
-    "sweep_stream_points_l0:main": (340.70 * 1.9999 + 2846.24 * 1.0000) * 1024,
-    "sweep_stream_stored_l0:main": (524971.63 * 1.9999 + 6144.00 * 1.0000) * 1024,
-    "sweep_rows_stored_l0:main": (519393.28 * 1.9999 + 694.02 * 1.0000) * 1024,
-    "sk_fused_stored:main": (524737.95 * 1.9999 + 32893.32 * 1.0000) * 1024,
-    "sk_fused_stored": ((524737.95 + 16673.19) * 1.9999 + (32893.32 + 160.02) * 1.0000) * 1024,
-    "sweep_stream_points_bf16x3_l0:main": (91039.04 * 1.9999 + 6223.96 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x6_l0:main": (140234.99 * 1.9999 + 6223.96 * 1.0000) * 1024,
-    "sweep_stream_points_bf16_l0:main": (24415.03 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_l0:main": (338.14 * 1.9999 + 2846.24 * 1.0000) * 1024,
+    "sweep_stream_stored_l0:main": (518398.01 * 1.9999 + 6067.04 * 1.0000) * 1024,
+    "sweep_rows_stored_l0:main": (525958.64 * 1.9999 + 640.09 * 1.0000) * 1024,
+    "sk_fused_stored:main": (525314.25 * 1.9999 + 32948.03 * 1.0000) * 1024,
+    "sk_fused_stored": ((525314.25 + 16669.99) * 1.9999 + (32948.03 + 159.97) * 1.0000) * 1024,
+    "sweep_stream_points_bf16x3_l0:main": (90826.46 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x6_l0:main": (140223.33 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_bf16_l0:main": (24560.69 * 1.9999 + 6223.96 * 1.0000) * 1024,
 }
 
 
