@@ -3,8 +3,8 @@ f = T_r(g) by rows, and each row's terms join the column log-sum-exp of
 T_c(f)) against the two-pass iteration (SKNR_NO_FUSED=1) and against the
 FP64 oracle: the same pairs are tested, so the iteration counts agree, and
 both reach the oracle's optimum.  Shapes cover one, two and four float4
-groups of columns per thread, a ragged last group, a single row per split
-and splits of unequal length."""
+groups of columns per thread, ragged last groups (4100 and 12004 columns),
+a single row per split and splits of unequal length."""
 import os
 
 import numpy as np
@@ -42,7 +42,7 @@ def _stored(n, m, seed):
 @pytest.mark.parametrize("n,m,ladder,full_oracle", [(300, 400, [5e-2, 2e-2], True),
                                                     (1000, 4100, [5e-2, 2e-2, 1e-2], True),
                                                     (4097, 8192, [5e-2, 2e-2], False), (9, 12, [1e-1, 5e-2], True),
-                                                    (700, 16384, [5e-2], False)])
+                                                    (700, 16384, [5e-2], False), (600, 12004, [5e-2], False)])
 def test_fused_pass_matches_two_pass_and_oracle(sk, ctx, n, m, ladder, full_oracle):
     C, a, b = _stored(n, m, seed=n + m)
     gp = sk.Problem(a=to_dev(a), b=to_dev(b), C=to_dev(C))
