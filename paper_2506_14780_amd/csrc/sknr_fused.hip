@@ -13,8 +13,9 @@
 // [L/2, 2L]), so the exponent is rounded only relative to its own size.
 // The shift needs no max pass.  g = T_c(f^prev) for the previous pass's row
 // output f^prev, so every plan entry of (f^prev, g) is at most b_j, and the
-// base shift L - f^prev_r + eps log a_r bounds the terms by b_j / a_r while
-// their sum S_r (that plan's row marginal over a_r) is at least min_j b_j.
+// base shift L - f^prev_r + eps log a_r bounds the terms by b_j / a_r; their
+// sum S_r (that plan's row marginal over a_r) is at least min_j b_j, since
+// f^prev is itself a row transform (true from a stage's second pass on).
 // Each pass also records log2 of the row's largest term (one max per
 // element) and the next pass raises its base by it, so that the largest
 // terms sit near 1 and their exponents are rounded as finely as under a
