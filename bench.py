@@ -64,16 +64,16 @@ def algorithmic_work(kind: str):
 # -> x1.0); see profiles/.  Valid only for the kernel sources they were
 # taken with (SHA-1 over sknr_device.h, sknr_kernels.hip, sknr_mfma.hip,
 # sknr_fused.hip, sknr_sweep_tail.h).
-TRAFFIC_KERNEL_SHA1 = "2229e84be4ad6efe3ea1d9890eb8cca4ba6baf2e"
+TRAFFIC_KERNEL_SHA1 = "a8e9d1e12731519ec171961a5e39e5d8818902fe"
 TRAFFIC_BYTES = {
     "sweep_stream_points_l0:main": (338.14 * 1.9999 + 2846.24 * 1.0000) * 1024,
-    "sweep_stream_stored_l0:main": (518398.01 * 1.9999 + 6067.04 * 1.0000) * 1024,
-    "sweep_rows_stored_l0:main": (525958.64 * 1.9999 + 640.09 * 1.0000) * 1024,
-    "sk_fused_stored:main": (525314.25 * 1.9999 + 32948.03 * 1.0000) * 1024,
-    "sk_fused_stored": ((525314.25 + 16669.99) * 1.9999 + (32948.03 + 159.97) * 1.0000) * 1024,
-    "sweep_stream_points_bf16x3_l0:main": (90826.46 * 1.9999 + 6223.96 * 1.0000) * 1024,
-    "sweep_stream_points_bf16x6_l0:main": (140223.33 * 1.9999 + 6223.96 * 1.0000) * 1024,
-    "sweep_stream_points_bf16_l0:main": (24560.69 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_stored_l0:main": (518397.07 * 1.9999 + 6067.04 * 1.0000) * 1024,
+    "sweep_rows_stored_l0:main": (525961.34 * 1.9999 + 640.09 * 1.0000) * 1024,
+    "sk_fused_stored:main": (525314.82 * 1.9999 + 32947.58 * 1.0000) * 1024,
+    "sk_fused_stored": ((525314.82 + 16669.98) * 1.9999 + (32947.58 + 159.97) * 1.0000) * 1024,
+    "sweep_stream_points_bf16x3_l0:main": (90819.55 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_bf16x6_l0:main": (140137.07 * 1.9999 + 6223.96 * 1.0000) * 1024,
+    "sweep_stream_points_bf16_l0:main": (24530.40 * 1.9999 + 6223.96 * 1.0000) * 1024,
 }
 
 
